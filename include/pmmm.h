@@ -1,0 +1,158 @@
+/*
+ * pmmm.h -- C ABI of the MI355X (gfx950) PMMM far-field library.
+ *
+ * Particle mesh multipole method (Nitadori, arXiv:1409.5981).  Given N
+ * particles with positions r_i and charges q_i in a box cut into K = n^3
+ * uniform cubic cells, the library returns the FAR-FIELD potential
+ *     Phi_i = sum over particles j outside the (2c+1)^3 cells around i of
+ *             q_j / |r_i - r_j|      (periodic: over all images, Ewald sense)
+ * and its gradient grad Phi_i, in the caller's input order (problem statement
+ * of Sec. 1 and Sec. 2.1).  The near field (the masked cells, Sec. 2.1 last
+ * paragraph) is NOT included; pmmm_near_* provides it for checking only.
+ * Electrostatics: force_i = -q_i grad Phi_i.  Gravity: pass masses and take
+ * Phi_grav = -G Phi, force_i = +G m_i grad Phi_i.
+ *
+ * Pipeline (Sec. 2.1, eq. pmmm and the FFT procedure below it):
+ *   bin -> P2M (eq. P2M) -> (p+1)^2 forward 3-D FFTs -> per-frequency M2L
+ *   with the transfer kernel G~ (eq. M2L in the real-matrix form of
+ *   eq. realmatrix) -> (p+1)^2 inverse FFTs -> periodic corrections
+ *   (App. B, correction procedure) -> L2P (eq. L2P; gradient via eq. L2L at
+ *   destination order one and eq. phigrad).
+ * Open boundaries convolve on the 2x zero-padded mesh (App. C); periodic
+ * ones use the lattice-summed kernel of App. B (eq. greenPBC).  The
+ * transfer-kernel spectra are built once, on the GPU in FP64, when the plan
+ * is created (Sec. 2.1: "performed and saved at the beginning").
+ *
+ * Memory and streams: every particle/output pointer passed to pmmm_far_*
+ * and pmmm_near_* is a DEVICE pointer owned by the caller; calls only
+ * enqueue work on the given HIP stream (hipStream_t passed as void*, NULL =
+ * default stream) and return without synchronising.  Inputs must stay
+ * alive and unmodified until the stream has completed the call.  The plan
+ * owns the transfer kernel and its workspace (device memory); a plan may be
+ * used by one stream at a time (calls on one plan must not overlap).
+ *
+ * Errors: every int-returning call returns PMMM_OK (0) or one of the codes
+ * below; pmmm_error_string() names a code and pmmm_last_error() returns the
+ * last message recorded by the calling thread.  Argument errors are
+ * detected on the host before anything is enqueued.  Open-boundary particles
+ * outside [0, b)^3 are clamped into the border cells by the kernels and
+ * raise a device flag that pmmm_plan_sync_status() reports as PMMM_EDOMAIN.
+ */
+#ifndef PMMM_H
+#define PMMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMMM_PMAX 8 /* highest expansion order compiled in */
+
+enum {
+    PMMM_OK = 0,
+    PMMM_EINVAL = 1,      /* invalid argument (null pointer, bad size or parameter) */
+    PMMM_ENOMEM = 2,      /* device allocation failed */
+    PMMM_EHIP = 3,        /* a HIP runtime call failed; see pmmm_last_error() */
+    PMMM_EDOMAIN = 4,     /* open boundary: a particle lay outside [0, b)^3 */
+    PMMM_EUNSUPPORTED = 5 /* valid by the method but not built (e.g. mesh size) */
+};
+
+enum { PMMM_OPEN = 0, PMMM_PERIODIC = 1 };
+enum { PMMM_F32 = 0, PMMM_F64 = 1 };
+enum { PMMM_MESH_M = 0, PMMM_MESH_L = 1, PMMM_MESH_GREEN = 2 };
+
+typedef struct pmmm_plan_s *pmmm_plan;
+
+/* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
+ *   nx, ny, nz  cells per axis.  This build needs nx == ny == nz == n, a
+ *               power of two with 4 <= n <= 64 (FP64: n <= 32 open,
+ *               n <= 64 periodic); other meshes return PMMM_EUNSUPPORTED.
+ *   box         edge lengths b of the box [0, b_x) x [0, b_y) x [0, b_z);
+ *               cells must be cubic (b_a / n_a equal to 1e-12 relative).
+ *   p           expansion order, 0 <= p <= PMMM_PMAX ((p+1)^2 coefficients);
+ *               at p = 0 the far-field gradient is identically zero.
+ *   cutoff      near-cell half width c: 1 (27 cells) or 2 (125 cells); 0 -> 2.
+ *               Periodic meshes need n >= 2c + 1, open meshes n >= c + 2.
+ *   boundary    PMMM_OPEN or PMMM_PERIODIC.
+ *   precision   PMMM_F32 (use pmmm_far_f32) or PMMM_F64 (pmmm_far_f64).
+ *   alpha       periodic splitting parameter of the lattice sums; 0 -> 1.5/b.
+ *   images      periodic lattice-sum radius |n| <= images; 0 -> 4.
+ *   n_max       particle capacity to allocate up front (0: grow on demand;
+ *               growing synchronises the device once). */
+typedef struct {
+    int nx, ny, nz;
+    double box[3];
+    int p;
+    int cutoff;
+    int boundary;
+    int precision;
+    double alpha;
+    int images;
+    int64_t n_max;
+} pmmm_params;
+
+/* Build a plan: validates the parameters, allocates the workspace, builds
+ * the transfer-kernel spectra on the GPU (FP64 lattice sums / harmonics and
+ * FP64 FFTs, stored in the plan's precision) on `stream`, and synchronises
+ * it.  *out receives the plan on success and NULL otherwise. */
+int pmmm_plan_create(const pmmm_params *params, void *stream, pmmm_plan *out);
+
+/* Free a plan and its device memory (synchronises the device). NULL is a no-op. */
+void pmmm_plan_destroy(pmmm_plan plan);
+
+/* Device bytes a plan with these parameters holds for n_max particles
+ * (0 if the parameters are invalid). */
+size_t pmmm_workspace_bytes(const pmmm_params *params, int64_t n_max);
+
+/* Far field for n particles, FP32 plan.  x, y, z, q: [n] device arrays;
+ * phi, gx, gy, gz: [n] device outputs (Phi and grad Phi in input order).
+ * n == 0 is a valid no-op.  Periodic positions may lie anywhere (they are
+ * wrapped into the box); open ones must lie in [0, b)^3 (PMMM_EDOMAIN via
+ * pmmm_plan_sync_status otherwise). */
+int pmmm_far_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
+                 const float *q, float *phi, float *gx, float *gy, float *gz, void *stream);
+
+/* Same as pmmm_far_f32 for an FP64 plan. */
+int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
+                 const double *z, const double *q, double *phi, double *gx, double *gy,
+                 double *gz, void *stream);
+
+/* Near field for checking only (Sec. 2.1: direct particle-particle sums over
+ * the masked (2c+1)^3 cells, no cutoff function).  Uses the binning (sorted
+ * positions and charges) of the LAST pmmm_far_* call on this plan, which must
+ * have been made with n particles on the same stream.  phi, gx, gy, gz: [n]
+ * device outputs in input order; accumulate != 0 adds into them. */
+int pmmm_near_f32(pmmm_plan plan, int64_t n, float *phi, float *gx, float *gy, float *gz,
+                  int accumulate, void *stream);
+int pmmm_near_f64(pmmm_plan plan, int64_t n, double *phi, double *gx, double *gy, double *gz,
+                  int accumulate, void *stream);
+
+/* Synchronise the plan's last stream and report a device-side condition
+ * (PMMM_EDOMAIN for an out-of-box open-boundary particle) since the last call
+ * of this function; the flag is cleared. */
+int pmmm_plan_sync_status(pmmm_plan plan);
+
+/* Copy an internal mesh to host memory for inspection (synchronises):
+ *   PMMM_MESH_M      moments of the last call, [(p+1)^2][n][n][n] (z, y, x),
+ *                    in CELL units (M_l scaled by 1/h^l), plan precision;
+ *   PMMM_MESH_L      local expansions of the last call, same layout, in cell
+ *                    units (L_l scaled by h^(l+1)), before the periodic
+ *                    corrections;
+ *   PMMM_MESH_GREEN  transfer-kernel spectra in cell units, one real value per
+ *                    component and frequency: [nf*(nf/2+1) columns (ky, kx)]
+ *                    [(2p+1)^2 components][nf (kz)], holding Re G~ for even
+ *                    orders and Im G~ for odd orders (the other part vanishes
+ *                    by the parity of the kernel).
+ * `bytes` must equal pmmm_plan_mesh_bytes(plan, which). */
+size_t pmmm_plan_mesh_bytes(pmmm_plan plan, int which);
+int pmmm_plan_copy_mesh(pmmm_plan plan, int which, void *host_dst, size_t bytes);
+
+const char *pmmm_error_string(int code);
+const char *pmmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMMM_H */

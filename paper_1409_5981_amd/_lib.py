@@ -1,0 +1,198 @@
+"""ctypes binding of libpmmm.so (the C ABI in include/pmmm.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the far-field pipeline runs in the HIP
+kernels of the library.  Importing this module raises if the library has
+not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmmm.so")
+
+PMMM_OK, PMMM_EINVAL, PMMM_ENOMEM, PMMM_EHIP, PMMM_EDOMAIN, PMMM_EUNSUPPORTED = range(6)
+PMMM_OPEN, PMMM_PERIODIC = 0, 1
+PMMM_F32, PMMM_F64 = 0, 1
+PMMM_MESH_M, PMMM_MESH_L, PMMM_MESH_GREEN = 0, 1, 2
+PMMM_PMAX = 8
+
+#: every symbol include/pmmm.h declares
+EXPORTS = [
+    "pmmm_plan_create", "pmmm_plan_destroy", "pmmm_workspace_bytes",
+    "pmmm_far_f32", "pmmm_far_f64", "pmmm_near_f32", "pmmm_near_f64",
+    "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
+    "pmmm_error_string", "pmmm_last_error",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("box", ctypes.c_double * 3),
+        ("p", ctypes.c_int), ("cutoff", ctypes.c_int), ("boundary", ctypes.c_int),
+        ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("images", ctypes.c_int),
+        ("n_max", ctypes.c_int64),
+    ]
+
+
+class PMMMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libpmmm.so and declare the prototypes (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                          "(or python paper_1409_5981_amd/build.py) first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci, cz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    L.pmmm_plan_create.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.pmmm_plan_create.restype = ci
+    L.pmmm_plan_destroy.argtypes = [vp]
+    L.pmmm_plan_destroy.restype = None
+    L.pmmm_workspace_bytes.argtypes = [ctypes.POINTER(Params), i64]
+    L.pmmm_workspace_bytes.restype = cz
+    for name in ("pmmm_far_f32", "pmmm_far_f64"):
+        f = getattr(L, name)
+        f.argtypes = [vp, i64] + [vp] * 8 + [vp]
+        f.restype = ci
+    for name in ("pmmm_near_f32", "pmmm_near_f64"):
+        f = getattr(L, name)
+        f.argtypes = [vp, i64, vp, vp, vp, vp, ci, vp]
+        f.restype = ci
+    L.pmmm_plan_sync_status.argtypes = [vp]
+    L.pmmm_plan_sync_status.restype = ci
+    L.pmmm_plan_mesh_bytes.argtypes = [vp, ci]
+    L.pmmm_plan_mesh_bytes.restype = cz
+    L.pmmm_plan_copy_mesh.argtypes = [vp, ci, vp, cz]
+    L.pmmm_plan_copy_mesh.restype = ci
+    L.pmmm_error_string.argtypes = [ci]
+    L.pmmm_error_string.restype = ctypes.c_char_p
+    L.pmmm_last_error.argtypes = []
+    L.pmmm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != PMMM_OK:
+        L = load()
+        raise PMMMError(rc, f"{L.pmmm_error_string(rc).decode()}: {L.pmmm_last_error().decode()}")
+
+
+def make_params(n: int, p: int, boundary: str, box: float = 1.0, cutoff: int = 2,
+                precision: str = "f32", alpha: float = 0.0, images: int = 0,
+                n_max: int = 0) -> Params:
+    prm = Params()
+    prm.nx = prm.ny = prm.nz = int(n)
+    for a in range(3):
+        prm.box[a] = float(box)
+    prm.p = int(p)
+    prm.cutoff = int(cutoff)
+    prm.boundary = PMMM_OPEN if boundary == "open" else PMMM_PERIODIC
+    prm.precision = PMMM_F32 if precision == "f32" else PMMM_F64
+    prm.alpha = float(alpha)
+    prm.images = int(images)
+    prm.n_max = int(n_max)
+    return prm
+
+
+def workspace_bytes(prm: Params, n_max: int) -> int:
+    return int(load().pmmm_workspace_bytes(ctypes.byref(prm), int(n_max)))
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A PMMM far-field plan (transfer kernel built on creation)."""
+
+    def __init__(self, n: int, p: int, boundary: str, box: float = 1.0, cutoff: int = 2,
+                 precision: str = "f32", alpha: float = 0.0, images: int = 0, n_max: int = 0,
+                 stream=None):
+        L = load()
+        self.params = make_params(n, p, boundary, box, cutoff, precision, alpha, images, n_max)
+        self.n, self.p, self.boundary, self.box = n, p, boundary, box
+        self.cutoff, self.precision = cutoff, precision
+        self.nf = 2 * n if boundary == "open" else n
+        self._h = ctypes.c_void_p()
+        _check(L.pmmm_plan_create(ctypes.byref(self.params), _stream_handle(stream),
+                                  ctypes.byref(self._h)))
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.precision == "f32" else torch.float64
+
+    def close(self):
+        if self._h:
+            load().pmmm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_tensors(self, *ts):
+        for t in ts:
+            if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous device tensors of the plan dtype")
+
+    def far(self, x, y, z, q, out=None, stream=None):
+        """Far-field Phi and grad Phi (input order) as four device tensors."""
+        import torch
+        self._check_tensors(x, y, z, q)
+        n = x.numel()
+        if not (y.numel() == z.numel() == q.numel() == n):
+            raise ValueError("x, y, z, q must have the same length")
+        if out is None:
+            out = tuple(torch.empty(n, dtype=self.dtype, device=x.device) for _ in range(4))
+        self._check_tensors(*out)
+        fn = load().pmmm_far_f32 if self.precision == "f32" else load().pmmm_far_f64
+        _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                  *[o.data_ptr() for o in out], _stream_handle(stream)))
+        return out
+
+    def near(self, n, out=None, accumulate=False, device="cuda", stream=None):
+        import torch
+        if out is None:
+            out = tuple(torch.zeros(n, dtype=self.dtype, device=device) for _ in range(4))
+        self._check_tensors(*out)
+        fn = load().pmmm_near_f32 if self.precision == "f32" else load().pmmm_near_f64
+        _check(fn(self._h, n, *[o.data_ptr() for o in out], int(bool(accumulate)),
+                  _stream_handle(stream)))
+        return out
+
+    def sync_status(self):
+        _check(load().pmmm_plan_sync_status(self._h))
+
+    def mesh(self, which: int) -> np.ndarray:
+        """Copy an internal mesh (PMMM_MESH_M / _L / _GREEN) to a numpy array."""
+        L = load()
+        nbytes = int(L.pmmm_plan_mesh_bytes(self._h, which))
+        dt = np.float32 if self.precision == "f32" else np.float64
+        buf = np.empty(nbytes // np.dtype(dt).itemsize, dtype=dt)
+        _check(L.pmmm_plan_copy_mesh(self._h, which, buf.ctypes.data_as(ctypes.c_void_p), nbytes))
+        P, n, nf = (self.p + 1) ** 2, self.n, self.nf
+        if which in (PMMM_MESH_M, PMMM_MESH_L):
+            return buf.reshape(P, n, n, n)
+        Q = (2 * self.p + 1) ** 2
+        return buf.reshape(nf, nf // 2 + 1, Q, nf)

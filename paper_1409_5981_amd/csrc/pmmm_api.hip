@@ -1,0 +1,509 @@
+// C ABI of the PMMM far-field library: plan objects, parameter checks,
+// workspace management and the launch sequence of one far-field call.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pmmm_internal.h"
+
+namespace pmmm {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? PMMM_ENOMEM : PMMM_EHIP;
+}
+
+// Cells denser than this go to the one-workgroup-per-cell FP64 path of P2M.
+constexpr int kDenseThreshold = 256;
+
+struct Plan {
+    pmmm_params prm;
+    int n, nf, p, P, Q, open, prec, cutoff, images;
+    int64_t K, ncol;
+    double box, h, inv_h, alpha, alpha_cell;
+    int device;
+    size_t tsize;
+    // plan-lifetime buffers
+    void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
+    int *count = nullptr, *start = nullptr, *dense_cells = nullptr, *small = nullptr;
+    double *sums = nullptr;
+    // particle buffers
+    int64_t cap = 0, last_n = -1;
+    int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr;
+    void *sorted = nullptr;
+    hipStream_t last_stream = nullptr;
+};
+
+}  // namespace pmmm
+
+struct pmmm_plan_s : pmmm::Plan {};
+
+using namespace pmmm;
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static int validate(const pmmm_params *prm, std::string &why) {
+    if (!prm) {
+        why = "params is NULL";
+        return PMMM_EINVAL;
+    }
+    if (prm->nx < 1 || prm->ny < 1 || prm->nz < 1) {
+        why = "mesh dimensions must be positive";
+        return PMMM_EINVAL;
+    }
+    if (!(prm->box[0] > 0 && prm->box[1] > 0 && prm->box[2] > 0)) {
+        why = "box lengths must be positive";
+        return PMMM_EINVAL;
+    }
+    const double h0 = prm->box[0] / prm->nx, h1 = prm->box[1] / prm->ny, h2 = prm->box[2] / prm->nz;
+    if (std::fabs(h0 - h1) > 1e-12 * h0 || std::fabs(h0 - h2) > 1e-12 * h0) {
+        why = "cells must be cubic (box[a]/n[a] equal)";
+        return PMMM_EINVAL;
+    }
+    if (prm->p < 0 || prm->p > PMMM_PMAX) {
+        why = "p outside 0..PMMM_PMAX";
+        return PMMM_EINVAL;
+    }
+    const int c = prm->cutoff == 0 ? 2 : prm->cutoff;
+    if (c != 1 && c != 2) {
+        why = "cutoff must be 1 or 2";
+        return PMMM_EINVAL;
+    }
+    if (prm->boundary != PMMM_OPEN && prm->boundary != PMMM_PERIODIC) {
+        why = "boundary must be PMMM_OPEN or PMMM_PERIODIC";
+        return PMMM_EINVAL;
+    }
+    if (prm->precision != PMMM_F32 && prm->precision != PMMM_F64) {
+        why = "precision must be PMMM_F32 or PMMM_F64";
+        return PMMM_EINVAL;
+    }
+    if (prm->alpha < 0 || prm->images < 0 || prm->n_max < 0) {
+        why = "alpha, images and n_max must be non-negative";
+        return PMMM_EINVAL;
+    }
+    const int n = prm->nx;
+    if (prm->boundary == PMMM_PERIODIC && n < 2 * c + 1) {
+        why = "periodic mesh needs n >= 2c + 1";
+        return PMMM_EINVAL;
+    }
+    if (prm->boundary == PMMM_OPEN && n < c + 2) {
+        why = "open mesh needs n >= c + 2";
+        return PMMM_EINVAL;
+    }
+    if (prm->nx != prm->ny || prm->nx != prm->nz || !is_pow2(n) || n < 4) {
+        why = "this build needs a cubic power-of-two mesh with n >= 4";
+        return PMMM_EUNSUPPORTED;
+    }
+    const int nf = prm->boundary == PMMM_OPEN ? 2 * n : n;
+    const int nfmax = prm->precision == PMMM_F32 ? 128 : 64;
+    if (nf > nfmax) {
+        why = "FFT mesh too large for this build (FP32: nf <= 128, FP64: nf <= 64)";
+        return PMMM_EUNSUPPORTED;
+    }
+    return PMMM_OK;
+}
+
+static void derive(Plan *pl, const pmmm_params *prm) {
+    pl->prm = *prm;
+    pl->n = prm->nx;
+    pl->open = prm->boundary == PMMM_OPEN;
+    pl->nf = pl->open ? 2 * pl->n : pl->n;
+    pl->p = prm->p;
+    pl->P = nreal(pl->p);
+    pl->Q = nreal(2 * pl->p);
+    pl->prec = prm->precision;
+    pl->cutoff = prm->cutoff == 0 ? 2 : prm->cutoff;
+    pl->images = prm->images == 0 ? 4 : prm->images;
+    pl->K = (int64_t)pl->n * pl->n * pl->n;
+    pl->ncol = (int64_t)pl->nf * (pl->nf / 2 + 1);
+    pl->box = prm->box[0];
+    pl->h = pl->box / pl->n;
+    pl->inv_h = pl->n / pl->box;
+    pl->alpha = prm->alpha == 0 ? 1.5 / pl->box : prm->alpha;
+    pl->alpha_cell = pl->alpha * pl->h;
+    pl->tsize = pl->prec == PMMM_F32 ? 4 : 8;
+}
+
+static size_t plan_bytes(const Plan *pl) {
+    const size_t t = pl->tsize, c = 2 * t;
+    size_t b = 0;
+    b += (size_t)pl->ncol * pl->Q * pl->nf * t;          // green
+    b += (size_t)(pl->nf / 2) * c;                       // twiddles
+    b += (size_t)(pl->P + 1) * pl->K * t;                // M
+    b += (size_t)pl->P * pl->n * pl->ncol * c;           // spectra
+    b += (size_t)pl->P * pl->K * t;                      // L
+    b += (size_t)(3 * pl->K + 1 + 8) * sizeof(int) + 8 * sizeof(double);
+    return b;
+}
+
+static size_t particle_bytes(const Plan *pl, int64_t n) {
+    return (size_t)n * (4 * sizeof(int) + 4 * pl->tsize);
+}
+
+static void free_particles(Plan *pl) {
+    hipFree(pl->cell_of);
+    hipFree(pl->slot);
+    hipFree(pl->perm);
+    hipFree(pl->scell);
+    hipFree(pl->sorted);
+    pl->cell_of = pl->slot = pl->perm = pl->scell = nullptr;
+    pl->sorted = nullptr;
+    pl->cap = 0;
+}
+
+static int ensure_capacity(Plan *pl, int64_t n) {
+    if (n <= pl->cap) return PMMM_OK;
+    if (n > (int64_t)INT32_MAX) {
+        set_error("particle count exceeds the 32-bit index range");
+        return PMMM_EINVAL;
+    }
+    PMMM_HIP(hipDeviceSynchronize());
+    free_particles(pl);
+    PMMM_HIP(hipMalloc(&pl->cell_of, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&pl->slot, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&pl->perm, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&pl->scell, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&pl->sorted, 4 * pl->tsize * n));
+    pl->cap = n;
+    return PMMM_OK;
+}
+
+static void destroy(Plan *pl) {
+    if (!pl) return;
+    hipDeviceSynchronize();
+    free_particles(pl);
+    hipFree(pl->green);
+    hipFree(pl->tw);
+    hipFree(pl->M);
+    hipFree(pl->spec);
+    hipFree(pl->L);
+    hipFree(pl->count);
+    hipFree(pl->start);
+    hipFree(pl->dense_cells);
+    hipFree(pl->small);
+    hipFree(pl->sums);
+    delete static_cast<pmmm_plan_s *>(pl);
+}
+
+template <typename T>
+static int make_twiddles(Plan *pl, hipStream_t s) {
+    const int nf = pl->nf;
+    std::vector<cplx<T>> tw(nf / 2);
+    for (int k = 0; k < nf / 2; ++k)
+        tw[k] = {T(std::cos(2.0 * M_PI * k / nf)), T(-std::sin(2.0 * M_PI * k / nf))};
+    PMMM_HIP(hipMalloc(&pl->tw, sizeof(cplx<T>) * (nf / 2)));
+    PMMM_HIP(hipMemcpyAsync(pl->tw, tw.data(), sizeof(cplx<T>) * (nf / 2), hipMemcpyHostToDevice, s));
+    return PMMM_OK;
+}
+
+static int alloc_plan(Plan *pl, hipStream_t s) {
+    const size_t t = pl->tsize, c = 2 * t;
+    PMMM_HIP(hipMalloc(&pl->green, (size_t)pl->ncol * pl->Q * pl->nf * t));
+    PMMM_HIP(hipMalloc(&pl->M, (size_t)(pl->P + 1) * pl->K * t));
+    PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
+    PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
+    PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * pl->K));
+    PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
+    PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
+    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag
+    PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
+    PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * pl->K, s));
+    PMMM_HIP(hipMemsetAsync(pl->small, 0, sizeof(int) * 8, s));
+    PMMM_HIP(hipMemsetAsync(pl->sums, 0, sizeof(double) * 8, s));
+    PMMM_HIP(hipMemsetAsync(pl->M, 0, (size_t)(pl->P + 1) * pl->K * t, s));
+    return pl->prec == PMMM_F32 ? make_twiddles<float>(pl, s) : make_twiddles<double>(pl, s);
+}
+
+static int group_for(double mean) {
+    if (mean <= 6) return 4;
+    if (mean <= 12) return 8;
+    if (mean <= 24) return 16;
+    if (mean <= 48) return 32;
+    return 64;
+}
+
+template <typename T>
+static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T *z, const T *q,
+                    T *phi, T *gx, T *gy, T *gz, void *stream) {
+    if (!pl) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    if (sizeof(T) != pl->tsize) {
+        set_error("precision of the call does not match the plan");
+        return PMMM_EINVAL;
+    }
+    if (n < 0) {
+        set_error("n must be non-negative");
+        return PMMM_EINVAL;
+    }
+    if (n > 0 && (!x || !y || !z || !q || !phi || !gx || !gy || !gz)) {
+        set_error("NULL particle or output pointer");
+        return PMMM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    PMMM_HIP(hipGetDevice(&cur));
+    if (cur != pl->device) {
+        set_error("current device differs from the plan's device");
+        return PMMM_EINVAL;
+    }
+    int rc = ensure_capacity(pl, n > 0 ? n : 1);
+    if (rc != PMMM_OK) return rc;
+    pl->last_stream = s;
+    pl->last_n = n;
+
+    BinArgs b{};
+    b.n = n;
+    b.x = x;
+    b.y = y;
+    b.z = z;
+    b.q = q;
+    b.ncell = pl->n;
+    b.inv_h = pl->inv_h;
+    b.periodic = !pl->open;
+    b.cell_of = pl->cell_of;
+    b.slot = pl->slot;
+    b.count = pl->count;
+    b.start = pl->start;
+    b.scell = pl->scell;
+    b.perm = pl->perm;
+    b.flag = pl->small + 1;
+    b.dense_cells = pl->dense_cells;
+    b.dense_count = pl->small;
+    b.dense_threshold = kDenseThreshold;
+    b.sorted = pl->sorted;
+    PMMM_HIP(launch_bin<T>(b, s));
+
+    P2MArgs m{};
+    m.p = pl->p;
+    m.ncell = pl->n;
+    m.group = group_for((double)n / (double)pl->K);
+    m.start = pl->start;
+    m.dense_cells = pl->dense_cells;
+    m.dense_count = pl->small;
+    m.dense_threshold = kDenseThreshold;
+    m.sorted = pl->sorted;
+    m.M = pl->M;
+    PMMM_HIP(launch_p2m<T>(m, s));
+
+    if (!pl->open) {
+        SumArgs sa{};
+        sa.ncell = pl->n;
+        sa.M = pl->M;
+        sa.p = pl->p;
+        sa.sums = pl->sums;
+        PMMM_HIP(launch_pbc_sums<T>(sa, s));
+    }
+
+    FFTArgs f{};
+    f.p = pl->p;
+    f.n = pl->n;
+    f.nf = pl->nf;
+    f.open = pl->open;
+    f.M = pl->M;
+    f.spec = pl->spec;
+    f.green = pl->green;
+    f.tw = pl->tw;
+    f.L = pl->L;
+    PMMM_HIP(launch_convolution<T>(f, s));
+
+    L2PArgs l{};
+    l.n = n;
+    l.p = pl->p;
+    l.ncell = pl->n;
+    l.periodic = !pl->open;
+    l.sorted = pl->sorted;
+    l.scell = pl->scell;
+    l.perm = pl->perm;
+    l.L = pl->L;
+    l.M = pl->M;
+    l.sums = pl->sums;
+    l.alpha_cell = pl->alpha_cell;
+    l.inv_h = pl->inv_h;
+    l.phi = phi;
+    l.gx = gx;
+    l.gy = gy;
+    l.gz = gz;
+    PMMM_HIP(launch_l2p<T>(l, s));
+    return PMMM_OK;
+}
+
+template <typename T>
+static int near_impl(pmmm_plan_s *pl, int64_t n, T *phi, T *gx, T *gy, T *gz, int accumulate,
+                     void *stream) {
+    if (!pl || sizeof(T) != pl->tsize) {
+        set_error("invalid plan or precision");
+        return PMMM_EINVAL;
+    }
+    if (n != pl->last_n) {
+        set_error("n differs from the last far-field call on this plan");
+        return PMMM_EINVAL;
+    }
+    if (n > 0 && (!phi || !gx || !gy || !gz)) {
+        set_error("NULL output pointer");
+        return PMMM_EINVAL;
+    }
+    NearArgs a{};
+    a.n = n;
+    a.ncell = pl->n;
+    a.cutoff = pl->cutoff;
+    a.periodic = !pl->open;
+    a.accumulate = accumulate;
+    a.start = pl->start;
+    a.scell = pl->scell;
+    a.perm = pl->perm;
+    a.sorted = pl->sorted;
+    a.inv_h = pl->inv_h;
+    a.phi = phi;
+    a.gx = gx;
+    a.gy = gy;
+    a.gz = gz;
+    PMMM_HIP(launch_near<T>(a, (hipStream_t)stream));
+    return PMMM_OK;
+}
+
+extern "C" {
+
+int pmmm_plan_create(const pmmm_params *params, void *stream, pmmm_plan *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return PMMM_EINVAL;
+    }
+    *out = nullptr;
+    std::string why;
+    int rc = validate(params, why);
+    if (rc != PMMM_OK) {
+        set_error(why);
+        return rc;
+    }
+    pmmm_plan_s *pl = new pmmm_plan_s();
+    derive(pl, params);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&pl->device);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "hipGetDevice");
+        destroy(pl);
+        return rc;
+    }
+    rc = alloc_plan(pl, s);
+    if (rc == PMMM_OK && params->n_max > 0) rc = ensure_capacity(pl, params->n_max);
+    if (rc == PMMM_OK) {
+        GreenArgs g{};
+        g.p = pl->p;
+        g.n = pl->n;
+        g.nf = pl->nf;
+        g.open = pl->open;
+        g.cutoff = pl->cutoff;
+        g.images = pl->images;
+        g.alpha_cell = pl->alpha_cell;
+        g.green_out = pl->green;
+        e = pl->prec == PMMM_F32 ? build_green<float>(g, s) : build_green<double>(g, s);
+        if (e != hipSuccess) rc = hip_fail(e, "transfer kernel build");
+    }
+    if (rc != PMMM_OK) {
+        destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return PMMM_OK;
+}
+
+void pmmm_plan_destroy(pmmm_plan plan) { destroy(plan); }
+
+size_t pmmm_workspace_bytes(const pmmm_params *params, int64_t n_max) {
+    std::string why;
+    if (validate(params, why) != PMMM_OK || n_max < 0) return 0;
+    Plan pl;
+    derive(&pl, params);
+    return plan_bytes(&pl) + particle_bytes(&pl, n_max);
+}
+
+int pmmm_far_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
+                 const float *q, float *phi, float *gx, float *gy, float *gz, void *stream) {
+    return far_impl<float>(plan, n, x, y, z, q, phi, gx, gy, gz, stream);
+}
+
+int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y, const double *z,
+                 const double *q, double *phi, double *gx, double *gy, double *gz,
+                 void *stream) {
+    return far_impl<double>(plan, n, x, y, z, q, phi, gx, gy, gz, stream);
+}
+
+int pmmm_near_f32(pmmm_plan plan, int64_t n, float *phi, float *gx, float *gy, float *gz,
+                  int accumulate, void *stream) {
+    return near_impl<float>(plan, n, phi, gx, gy, gz, accumulate, stream);
+}
+
+int pmmm_near_f64(pmmm_plan plan, int64_t n, double *phi, double *gx, double *gy, double *gz,
+                  int accumulate, void *stream) {
+    return near_impl<double>(plan, n, phi, gx, gy, gz, accumulate, stream);
+}
+
+int pmmm_plan_sync_status(pmmm_plan plan) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    PMMM_HIP(hipStreamSynchronize(plan->last_stream));
+    int flag = 0;
+    PMMM_HIP(hipMemcpy(&flag, plan->small + 1, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        const int zero = 0;
+        PMMM_HIP(hipMemcpy(plan->small + 1, &zero, sizeof(int), hipMemcpyHostToDevice));
+        set_error("open boundary: a particle lay outside [0, b)^3");
+        return PMMM_EDOMAIN;
+    }
+    return PMMM_OK;
+}
+
+size_t pmmm_plan_mesh_bytes(pmmm_plan plan, int which) {
+    if (!plan) return 0;
+    switch (which) {
+        case PMMM_MESH_M:
+        case PMMM_MESH_L:
+            return (size_t)plan->P * plan->K * plan->tsize;
+        case PMMM_MESH_GREEN:
+            return (size_t)plan->ncol * plan->Q * plan->nf * plan->tsize;
+        default:
+            return 0;
+    }
+}
+
+int pmmm_plan_copy_mesh(pmmm_plan plan, int which, void *host_dst, size_t bytes) {
+    if (!plan || !host_dst) {
+        set_error("NULL plan or destination");
+        return PMMM_EINVAL;
+    }
+    const size_t need = pmmm_plan_mesh_bytes(plan, which);
+    if (need == 0 || bytes != need) {
+        set_error("unknown mesh or wrong byte count");
+        return PMMM_EINVAL;
+    }
+    const void *src = which == PMMM_MESH_M ? plan->M : (which == PMMM_MESH_L ? plan->L : plan->green);
+    PMMM_HIP(hipStreamSynchronize(plan->last_stream));
+    PMMM_HIP(hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+    return PMMM_OK;
+}
+
+const char *pmmm_error_string(int code) {
+    switch (code) {
+        case PMMM_OK: return "PMMM_OK";
+        case PMMM_EINVAL: return "PMMM_EINVAL: invalid argument";
+        case PMMM_ENOMEM: return "PMMM_ENOMEM: device allocation failed";
+        case PMMM_EHIP: return "PMMM_EHIP: HIP runtime error";
+        case PMMM_EDOMAIN: return "PMMM_EDOMAIN: particle outside the open-boundary box";
+        case PMMM_EUNSUPPORTED: return "PMMM_EUNSUPPORTED: configuration not built";
+        default: return "unknown PMMM error code";
+    }
+}
+
+const char *pmmm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

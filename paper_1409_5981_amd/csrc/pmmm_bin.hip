@@ -1,0 +1,153 @@
+// Cell binning (Sec. 2.1: "for each cell, the set of particles inside is
+// known ... achieved in an O(N) procedure"): a counting sort by cell.
+//   k_bin_count   cell of each particle, per-cell counts (int atomics) and the
+//                 particle's slot inside its cell
+//   k_bin_scan    exclusive scan of the counts -> cell_start, resets the counts
+//                 for the next call, lists cells above the dense threshold
+//   k_bin_scatter sorted structure-of-arrays record (offset from the cell
+//                 centre in cell units, charge), permutation and cell of each
+//                 sorted slot
+// Cell index: I = floor(r n / b) per axis, clamped to [0, n-1]; periodic
+// positions are first wrapped into the box (in cell units).
+#include "pmmm_internal.h"
+
+namespace pmmm {
+
+template <typename T>
+__device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, int &ic, T &u,
+                                           int &outside) {
+    T s = v * inv_h;
+    if (periodic) {
+        s = s - T(n) * floor(s / T(n));
+    } else if (!(s >= T(0) && s < T(n))) {
+        outside = 1;
+    }
+    int i = (int)floor(s);
+    i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+    ic = i;
+    u = s - T(i) - T(0.5);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bin_count(int64_t n, const T *__restrict__ x,
+                                                   const T *__restrict__ y,
+                                                   const T *__restrict__ z, T inv_h, int nc,
+                                                   int periodic, int *__restrict__ cell_of,
+                                                   int *__restrict__ slot,
+                                                   int *__restrict__ count,
+                                                   int *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ix, iy, iz, out = 0;
+    T ux, uy, uz;
+    cell_coord(x[i], inv_h, nc, periodic, ix, ux, out);
+    cell_coord(y[i], inv_h, nc, periodic, iy, uy, out);
+    cell_coord(z[i], inv_h, nc, periodic, iz, uz, out);
+    if (out) *flag = 1;
+    const int c = (iz * nc + iy) * nc + ix;
+    cell_of[i] = c;
+    slot[i] = atomicAdd(&count[c], 1);
+}
+
+// One workgroup of 1024 threads scans all K counts in tiles of 4096.
+__global__ void __launch_bounds__(1024) k_bin_scan(int K, int *__restrict__ count,
+                                                   int *__restrict__ start, int dense_thr,
+                                                   int *__restrict__ dense_cells,
+                                                   int *__restrict__ dense_count) {
+    __shared__ int wtot[16];
+    __shared__ int carry_s;
+    __shared__ int ndense;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) {
+        carry_s = 0;
+        ndense = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < K; base += 4096) {
+        int v[4];
+        int tot = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + tid * 4 + j;
+            v[j] = idx < K ? count[idx] : 0;
+            tot += v[j];
+        }
+        // inclusive wave scan of thread totals
+        int inc = tot;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int t = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) wtot[wid] = inc;
+        __syncthreads();
+        int wpre = 0;
+        for (int w = 0; w < wid; ++w) wpre += wtot[w];
+        int run = carry_s + wpre + inc - tot;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + tid * 4 + j;
+            if (idx < K) {
+                start[idx] = run;
+                count[idx] = 0;
+                if (v[j] > dense_thr) dense_cells[atomicAdd(&ndense, 1)] = idx;
+            }
+            run += v[j];
+        }
+        __syncthreads();
+        if (tid == 1023) carry_s = run;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        start[K] = carry_s;
+        *dense_count = ndense;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bin_scatter(
+    int64_t n, const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
+    const T *__restrict__ q, T inv_h, int nc, int periodic, const int *__restrict__ cell_of,
+    const int *__restrict__ slot, const int *__restrict__ start, int *__restrict__ perm,
+    int *__restrict__ scell, particle4<T> *__restrict__ sorted) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ix, iy, iz, out = 0;
+    particle4<T> r;
+    cell_coord(x[i], inv_h, nc, periodic, ix, r.ux, out);
+    cell_coord(y[i], inv_h, nc, periodic, iy, r.uy, out);
+    cell_coord(z[i], inv_h, nc, periodic, iz, r.uz, out);
+    r.q = q[i];
+    const int c = cell_of[i];
+    const int s = start[c] + slot[i];
+    if (s < 0 || (int64_t)s >= n) return;  // only reachable with inconsistent counts
+    perm[s] = (int)i;
+    scell[s] = c;
+    sorted[s] = r;
+}
+
+template <typename T>
+hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
+    const int K = a.ncell * a.ncell * a.ncell;
+    const T inv_h = T(a.inv_h);
+    const int blocks = (int)((a.n + 255) / 256);
+    if (a.n > 0) {
+        hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks), dim3(256), 0, s, a.n,
+                           (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
+                           a.periodic, a.cell_of, a.slot, a.count, a.flag);
+    }
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, K, a.count, a.start,
+                       a.dense_threshold, a.dense_cells, a.dense_count);
+    if (a.n > 0) {
+        hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks), dim3(256), 0, s, a.n,
+                           (const T *)a.x, (const T *)a.y, (const T *)a.z, (const T *)a.q,
+                           inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, a.perm,
+                           a.scell, (particle4<T> *)a.sorted);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_bin<float>(const BinArgs &, hipStream_t);
+template hipError_t launch_bin<double>(const BinArgs &, hipStream_t);
+
+}  // namespace pmmm

@@ -1,0 +1,244 @@
+// Internal declarations shared by the HIP translation units of the PMMM
+// far-field library (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/pmmm.h"
+
+namespace pmmm {
+
+// ----------------------------------------------------------------- helpers
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a * conj(b)
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+// Sorted particle record: offsets from the cell centre in cell units and the charge.
+template <typename T>
+struct alignas(4 * sizeof(T)) particle4 {
+    T ux, uy, uz, q;
+};
+
+__host__ __device__ constexpr int nreal(int p) { return (p + 1) * (p + 1); }
+__host__ __device__ constexpr int ridx(int l, int m) { return l * (l + 1) + m; }
+
+__device__ __forceinline__ int bitrev(int v, int logn) {
+    return (int)(__builtin_bitreverse32((unsigned)v) >> (32 - logn));
+}
+
+// Regular solid harmonics R_l^m(x, y, z), 0 <= l <= P_ORD, in real storage
+// (index l(l+1)+m holds Re R_l^|m| for m >= 0 and Im R_l^|m| for m < 0).
+// Recursion of App. A.5 rewritten for R = Q/(l+m)! directly:
+//   R_m^m     = -(x + i y) / (2m) * R_{m-1}^{m-1}
+//   R_{m+1}^m = z R_m^m
+//   R_l^m     = ((2l-1) z R_{l-1}^m - r^2 R_{l-2}^m) / ((l-m)(l+m))
+// All loops have compile-time bounds so R stays in registers.
+template <int P_ORD, typename T>
+__device__ __forceinline__ void regular_harmonics(T x, T y, T z, T *R) {
+    const T r2 = x * x + y * y + z * z;
+    T cre = T(1), cim = T(0);
+#pragma unroll
+    for (int m = 0; m <= P_ORD; ++m) {
+        if (m > 0) {
+            const T f = T(-1.0 / (2.0 * m));
+            const T nre = f * (x * cre - y * cim);
+            const T nim = f * (x * cim + y * cre);
+            cre = nre;
+            cim = nim;
+        }
+        R[ridx(m, m)] = cre;
+        if (m > 0) R[ridx(m, -m)] = cim;
+        T pre = cre, pim = cim;  // R_{l-2}^m
+        T ure = T(0), uim = T(0);  // R_{l-1}^m
+        if (m + 1 <= P_ORD) {
+            ure = z * cre;
+            uim = z * cim;
+            R[ridx(m + 1, m)] = ure;
+            if (m > 0) R[ridx(m + 1, -m)] = uim;
+        }
+#pragma unroll
+        for (int l = m + 2; l <= P_ORD; ++l) {
+            const T a = T((2.0 * l - 1.0) / ((double)(l - m) * (double)(l + m)));
+            const T b = T(1.0 / ((double)(l - m) * (double)(l + m)));
+            const T nre = a * z * ure - b * r2 * pre;
+            const T nim = a * z * uim - b * r2 * pim;
+            R[ridx(l, m)] = nre;
+            if (m > 0) R[ridx(l, -m)] = nim;
+            pre = ure;
+            pim = uim;
+            ure = nre;
+            uim = nim;
+        }
+    }
+}
+
+// --------------------------------------------------------- LDS radix-2 FFT
+// `nlines` transforms of length N = 2^logn stored in LDS; element e of line
+// t lives at buf[t * lstride + e * estride].  tw[k] = exp(-2 pi i k / N)
+// (k < N/2) in LDS.  INV selects exp(+...).  Barrier after every stage.
+//
+// DIF: natural-order input, bit-reversed output.
+template <typename T, bool INV>
+__device__ void lds_fft_dif(cplx<T> *buf, int logn, int nlines, int lstride, int estride,
+                            const cplx<T> *tw, int tid, int nthr) {
+    const int N = 1 << logn;
+    const int hN = N >> 1;
+    const int total = nlines * hN;
+    for (int lh = logn - 1; lh >= 0; --lh) {  // half = 2^lh
+        const int half = 1 << lh;
+        const int twshift = logn - 1 - lh;    // twiddle step N / (2 half)
+        for (int t = tid; t < total; t += nthr) {
+            const int line = t >> (logn - 1);
+            const int k = t & (hN - 1);
+            const int j = k & (half - 1);
+            const int g = k >> lh;
+            const int i0 = (g << (lh + 1)) + j;
+            cplx<T> *base = buf + line * lstride;
+            cplx<T> a = base[i0 * estride];
+            cplx<T> b = base[(i0 + half) * estride];
+            cplx<T> w = tw[j << twshift];
+            if (INV) w.im = -w.im;
+            cplx<T> s = {a.re + b.re, a.im + b.im};
+            cplx<T> d = {a.re - b.re, a.im - b.im};
+            base[i0 * estride] = s;
+            base[(i0 + half) * estride] = cmul(d, w);
+        }
+        __syncthreads();
+    }
+}
+
+// DIT: bit-reversed input, natural-order output.
+template <typename T, bool INV>
+__device__ void lds_fft_dit(cplx<T> *buf, int logn, int nlines, int lstride, int estride,
+                            const cplx<T> *tw, int tid, int nthr) {
+    const int N = 1 << logn;
+    const int hN = N >> 1;
+    const int total = nlines * hN;
+    for (int lh = 0; lh < logn; ++lh) {
+        const int half = 1 << lh;
+        const int twshift = logn - 1 - lh;
+        for (int t = tid; t < total; t += nthr) {
+            const int line = t >> (logn - 1);
+            const int k = t & (hN - 1);
+            const int j = k & (half - 1);
+            const int g = k >> lh;
+            const int i0 = (g << (lh + 1)) + j;
+            cplx<T> *base = buf + line * lstride;
+            cplx<T> a = base[i0 * estride];
+            cplx<T> w = tw[j << twshift];
+            if (INV) w.im = -w.im;
+            cplx<T> b = cmul(base[(i0 + half) * estride], w);
+            base[i0 * estride] = {a.re + b.re, a.im + b.im};
+            base[(i0 + half) * estride] = {a.re - b.re, a.im - b.im};
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ host side
+struct Plan;  // defined in pmmm_api.hip
+
+// Error bookkeeping (thread-local message).
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define PMMM_HIP(call)                                      \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return ::pmmm::hip_fail(e_, #call); \
+    } while (0)
+
+// Launchers (each returns a HIP error code; they only enqueue).
+struct BinArgs {
+    int64_t n;
+    const void *x, *y, *z, *q;
+    int ncell;         // cells per axis
+    double inv_h;      // n / b
+    int periodic;
+    int *cell_of, *slot, *count, *start, *scell, *perm, *flag;
+    int *dense_cells, *dense_count;
+    int dense_threshold;
+    void *sorted;      // particle4<T>[n]
+};
+template <typename T>
+hipError_t launch_bin(const BinArgs &a, hipStream_t s);
+
+struct P2MArgs {
+    int p, ncell, group;            // lanes per cell in the light path
+    const int *start, *dense_cells, *dense_count;
+    int dense_threshold;
+    const void *sorted;
+    void *M;                        // [P + 1][K]: moments, then sum q |u|^2
+};
+template <typename T>
+hipError_t launch_p2m(const P2MArgs &a, hipStream_t s);
+
+struct SumArgs {
+    int ncell;
+    const void *M;                  // [P + 1][K]
+    int p;
+    double *sums;                   // [0]=sum M0, [1..3]=sum M[1..3], [4]=sum q|u|^2
+};
+template <typename T>
+hipError_t launch_pbc_sums(const SumArgs &a, hipStream_t s);
+
+struct FFTArgs {
+    int p, n, nf, open;
+    const void *M;                  // [P(+1)][n^3] real mesh
+    void *spec;                     // [P][n][nf][nf/2+1] complex
+    const void *green;              // [nf*(nf/2+1)][Q][nf]
+    const void *tw;                 // cplx<T>[nf/2]
+    void *L;                        // [P][n^3]
+};
+template <typename T>
+hipError_t launch_convolution(const FFTArgs &a, hipStream_t s);
+
+struct L2PArgs {
+    int64_t n;
+    int p, ncell, periodic;
+    const void *sorted;
+    const int *scell, *perm;
+    const void *L;                  // [P][K]
+    const void *M;                  // [P + 1][K] (self term)
+    const double *sums;
+    double alpha_cell;              // alpha h
+    double inv_h;                   // 1 / h in the caller's length unit
+    void *phi, *gx, *gy, *gz;
+};
+template <typename T>
+hipError_t launch_l2p(const L2PArgs &a, hipStream_t s);
+
+struct NearArgs {
+    int64_t n;
+    int ncell, cutoff, periodic, accumulate;
+    const int *start, *scell, *perm;
+    const void *sorted;
+    double inv_h;
+    void *phi, *gx, *gy, *gz;
+};
+template <typename T>
+hipError_t launch_near(const NearArgs &a, hipStream_t s);
+
+// Plan-time transfer kernel (FP64 on the GPU), stored in precision T.
+struct GreenArgs {
+    int p, n, nf, open, cutoff, images;
+    double alpha_cell;              // alpha h
+    void *green_out;                // [nf*(nf/2+1)][Q][nf] in T
+};
+template <typename T>
+hipError_t build_green(const GreenArgs &a, hipStream_t s);
+
+}  // namespace pmmm

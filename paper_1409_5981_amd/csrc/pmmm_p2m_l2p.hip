@@ -1,0 +1,299 @@
+// Particle <-> cell transforms, in cell units (lengths divided by h).
+//   k_p2m      eq. P2M per cell, M_l^m = sum_i q_i R_l^m(r_M - r_i), plus the
+//              per-cell sum q |r_rel|^2 used by the periodic correction.
+//              Light cells: a group of G lanes strides over the cell's sorted
+//              particles and reduces with cross-lane shuffles.  Dense cells
+//              (more than the dense threshold): one workgroup per cell with
+//              FP64 accumulation and a fixed-order block reduction.
+//   k_pbc_sums FP64 sums over all cells of M_0^0, the three order-1 moments
+//              and sum q|r_rel|^2 (App. B, correction procedure).
+//   k_l2p      eq. L2P for Phi; eq. L2L to destination order one and
+//              eq. phigrad for grad Phi; periodic corrections of App. B
+//              (dipole, self term, r^2 term, charged-system terms); results
+//              rescaled to the caller's units and scattered to input order.
+#include "pmmm_internal.h"
+
+namespace pmmm {
+
+constexpr int kDenseBlocks = 128;
+
+template <int PO, typename T, int G>
+__global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ start,
+                                             const particle4<T> *__restrict__ sorted,
+                                             int dense_thr, const int *__restrict__ dense_cells,
+                                             const int *__restrict__ dense_count,
+                                             int nlight_blocks, T *__restrict__ M) {
+    constexpr int P = nreal(PO);
+    if ((int)blockIdx.x < nlight_blocks) {
+        const int gid = blockIdx.x * 256 + threadIdx.x;
+        const int cell = gid / G;
+        const int lane = gid & (G - 1);
+        int s0 = 0, s1 = 0;
+        bool write = false;
+        if (cell < K) {
+            s0 = start[cell];
+            s1 = start[cell + 1];
+            write = (s1 - s0) <= dense_thr;
+            if (!write) s1 = s0;
+        }
+        T acc[P + 1];
+#pragma unroll
+        for (int c = 0; c <= P; ++c) acc[c] = T(0);
+        for (int s = s0 + lane; s < s1; s += G) {
+            const particle4<T> r = sorted[s];
+            T R[P];
+            regular_harmonics<PO, T>(-r.ux, -r.uy, -r.uz, R);  // R(r_M - r_i)
+#pragma unroll
+            for (int c = 0; c < P; ++c) acc[c] += r.q * R[c];
+            acc[P] += r.q * (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
+        }
+#pragma unroll
+        for (int off = G / 2; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+        }
+        if (write) {
+#pragma unroll
+            for (int c = 0; c <= P; ++c)
+                if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
+        }
+        return;
+    }
+    // dense cells
+    __shared__ double red[4][P + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nd = *dense_count;
+    const int nblk = gridDim.x - nlight_blocks;
+    for (int d = blockIdx.x - nlight_blocks; d < nd; d += nblk) {
+        const int cell = dense_cells[d];
+        const int s0 = start[cell], s1 = start[cell + 1];
+        double acc[P + 1];
+#pragma unroll
+        for (int c = 0; c <= P; ++c) acc[c] = 0.0;
+        for (int s = s0 + tid; s < s1; s += 256) {
+            const particle4<T> r = sorted[s];
+            T R[P];
+            regular_harmonics<PO, T>(-r.ux, -r.uy, -r.uz, R);
+#pragma unroll
+            for (int c = 0; c < P; ++c) acc[c] += (double)r.q * (double)R[c];
+            acc[P] += (double)r.q * ((double)r.ux * r.ux + (double)r.uy * r.uy +
+                                     (double)r.uz * r.uz);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c <= P; ++c) red[wid][c] = acc[c];
+        }
+        __syncthreads();
+        for (int c = tid; c <= P; c += 256)
+            M[(int64_t)c * K + cell] = T(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pbc_sums(int K, int P, const T *__restrict__ M,
+                                                   double *__restrict__ sums) {
+    __shared__ double red[16][5];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double a[5] = {0, 0, 0, 0, 0};
+    const int comp[5] = {0, 1, 2, 3, P};
+    for (int i = tid; i < K; i += 1024) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (j == 0 || j == 4 || P > 1) a[j] += (double)M[(int64_t)comp[j] * K + i];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) a[j] += __shfl_xor(a[j], off, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) red[wid][j] = a[j];
+    }
+    __syncthreads();
+    if (tid < 5) {
+        double s = 0;
+        for (int w = 0; w < 16; ++w) s += red[w][tid];
+        sums[tid] = s;
+    }
+}
+
+template <int PO, typename T>
+__global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
+                                             const particle4<T> *__restrict__ sorted,
+                                             const int *__restrict__ scell,
+                                             const int *__restrict__ perm,
+                                             const T *__restrict__ L, const T *__restrict__ M,
+                                             const double *__restrict__ sums, T alpha_c,
+                                             T inv_h, T *__restrict__ phi_out,
+                                             T *__restrict__ gx_out, T *__restrict__ gy_out,
+                                             T *__restrict__ gz_out) {
+    constexpr int P = nreal(PO);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const particle4<T> r = sorted[s];
+    const int c = scell[s];
+    T Lc[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) Lc[a] = L[(int64_t)a * K + c];
+    T qtot_term = T(0);
+    if (periodic) {
+        const double V = (double)K;  // box volume in cell units
+        const double pi = 3.14159265358979323846;
+        Lc[0] += T(-2.0 * (double)alpha_c / sqrt(pi)) * M[c] + T(2.0 * pi / (3.0 * V) * sums[4]);
+        if (P > 1) {
+            Lc[ridx(1, 0)] += T(4.0 * pi / (3.0 * V) * sums[2]);
+            Lc[ridx(1, 1)] += T(8.0 * pi / (3.0 * V) * sums[3]);
+            Lc[ridx(1, -1)] -= T(8.0 * pi / (3.0 * V) * sums[1]);
+        }
+        qtot_term = T(sums[0] * pi / (3.0 * V));  // Q_tot pi / (3V)
+    }
+    T R[P];
+    regular_harmonics<PO, T>(r.ux, r.uy, r.uz, R);
+    // Phi = sum_l [L_l^0 R_l^0 + 2 sum_{m>0} Re(L_l^m R_l^m)]
+    T ph = T(0);
+#pragma unroll
+    for (int l = 0; l <= PO; ++l) {
+        ph += Lc[ridx(l, 0)] * R[ridx(l, 0)];
+#pragma unroll
+        for (int m = 1; m <= l; ++m)
+            ph += T(2) * (Lc[ridx(l, m)] * R[ridx(l, m)] - Lc[ridx(l, -m)] * R[ridx(l, -m)]);
+    }
+    // L'_1^0 and L'_1^1 (eq. L2L with destination order one)
+    T d0 = T(0), d1re = T(0), d1im = T(0);
+#pragma unroll
+    for (int lam = 1; lam <= PO; ++lam) {
+        const int k = lam - 1;
+        d0 += Lc[ridx(lam, 0)] * R[ridx(k, 0)];
+#pragma unroll
+        for (int mu = 1; mu <= k; ++mu)
+            d0 += T(2) * (Lc[ridx(lam, mu)] * R[ridx(k, mu)] - Lc[ridx(lam, -mu)] * R[ridx(k, -mu)]);
+        // + sum_{mu=1..lam} L_lam^mu R_k^{mu-1}
+#pragma unroll
+        for (int mu = 1; mu <= lam; ++mu) {
+            const T lre = Lc[ridx(lam, mu)], lim = Lc[ridx(lam, -mu)];
+            const T rre = R[ridx(k, mu - 1)];
+            const T rim = (mu - 1 > 0) ? R[ridx(k, -(mu - 1))] : T(0);
+            d1re += lre * rre - lim * rim;
+            d1im += lre * rim + lim * rre;
+        }
+        // - sum_{nu=0..lam-2} conj(L_lam^nu R_k^{nu+1})
+#pragma unroll
+        for (int nu = 0; nu <= lam - 2; ++nu) {
+            const T lre = Lc[ridx(lam, nu)];
+            const T lim = (nu > 0) ? Lc[ridx(lam, -nu)] : T(0);
+            const T rre = R[ridx(k, nu + 1)], rim = R[ridx(k, -(nu + 1))];
+            d1re -= lre * rre - lim * rim;
+            d1im += lre * rim + lim * rre;  // minus the conjugate's imaginary part
+        }
+    }
+    T gx = -d1re, gy = d1im, gz = d0;
+    if (periodic) {
+        const T u2 = r.ux * r.ux + r.uy * r.uy + r.uz * r.uz;
+        ph += T(2) * qtot_term * (u2 - T(1.5) / (alpha_c * alpha_c));
+        gx += T(4) * qtot_term * r.ux;
+        gy += T(4) * qtot_term * r.uy;
+        gz += T(4) * qtot_term * r.uz;
+    }
+    const int i = perm[s];
+    const T ih2 = inv_h * inv_h;
+    phi_out[i] = ph * inv_h;
+    gx_out[i] = gx * ih2;
+    gy_out[i] = gy * ih2;
+    gz_out[i] = gz * ih2;
+}
+
+// ------------------------------------------------------------- launchers
+template <int PO, typename T>
+static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
+    const int K = a.ncell * a.ncell * a.ncell;
+    const int G = a.group;
+    const int nlight = (int)(((int64_t)K * G + 255) / 256);
+    const int grid = nlight + kDenseBlocks;
+    const int *st = a.start;
+    const particle4<T> *so = (const particle4<T> *)a.sorted;
+    T *M = (T *)a.M;
+#define PMMM_P2M_G(GG)                                                                    \
+    case GG:                                                                              \
+        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(grid), dim3(256), 0, s, K, st, so,     \
+                           a.dense_threshold, a.dense_cells, a.dense_count, nlight, M);    \
+        break;
+    switch (G) {
+        PMMM_P2M_G(4)
+        PMMM_P2M_G(8)
+        PMMM_P2M_G(16)
+        PMMM_P2M_G(32)
+        PMMM_P2M_G(64)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef PMMM_P2M_G
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_p2m(const P2MArgs &a, hipStream_t s) {
+    switch (a.p) {
+        case 0: return p2m_dispatch_g<0, T>(a, s);
+        case 1: return p2m_dispatch_g<1, T>(a, s);
+        case 2: return p2m_dispatch_g<2, T>(a, s);
+        case 3: return p2m_dispatch_g<3, T>(a, s);
+        case 4: return p2m_dispatch_g<4, T>(a, s);
+        case 5: return p2m_dispatch_g<5, T>(a, s);
+        case 6: return p2m_dispatch_g<6, T>(a, s);
+        case 7: return p2m_dispatch_g<7, T>(a, s);
+        case 8: return p2m_dispatch_g<8, T>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_pbc_sums(const SumArgs &a, hipStream_t s) {
+    const int K = a.ncell * a.ncell * a.ncell;
+    hipLaunchKernelGGL(k_pbc_sums<T>, dim3(1), dim3(1024), 0, s, K, nreal(a.p),
+                       (const T *)a.M, a.sums);
+    return hipGetLastError();
+}
+
+template <int PO, typename T>
+static hipError_t l2p_launch(const L2PArgs &a, hipStream_t s) {
+    const int K = a.ncell * a.ncell * a.ncell;
+    const int blocks = (int)((a.n + 255) / 256);
+    hipLaunchKernelGGL((k_l2p<PO, T>), dim3(blocks), dim3(256), 0, s, a.n, K, a.periodic,
+                       (const particle4<T> *)a.sorted, a.scell, a.perm, (const T *)a.L,
+                       (const T *)a.M, a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
+                       (T *)a.gx, (T *)a.gy, (T *)a.gz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_l2p(const L2PArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    switch (a.p) {
+        case 0: return l2p_launch<0, T>(a, s);
+        case 1: return l2p_launch<1, T>(a, s);
+        case 2: return l2p_launch<2, T>(a, s);
+        case 3: return l2p_launch<3, T>(a, s);
+        case 4: return l2p_launch<4, T>(a, s);
+        case 5: return l2p_launch<5, T>(a, s);
+        case 6: return l2p_launch<6, T>(a, s);
+        case 7: return l2p_launch<7, T>(a, s);
+        case 8: return l2p_launch<8, T>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_p2m<float>(const P2MArgs &, hipStream_t);
+template hipError_t launch_p2m<double>(const P2MArgs &, hipStream_t);
+template hipError_t launch_pbc_sums<float>(const SumArgs &, hipStream_t);
+template hipError_t launch_pbc_sums<double>(const SumArgs &, hipStream_t);
+template hipError_t launch_l2p<float>(const L2PArgs &, hipStream_t);
+template hipError_t launch_l2p<double>(const L2PArgs &, hipStream_t);
+
+}  // namespace pmmm

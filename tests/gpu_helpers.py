@@ -1,0 +1,59 @@
+"""Helpers shared by the GPU tests: run the HIP far field through the C ABI
+binding on numpy inputs, and convert oracle meshes to the library's cell
+units and layouts."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import pmmm as opm
+from oracle.harmonics import nreal
+
+
+def gpu_far(ps, precision="f32", cutoff=2, near=False, plan=None, alpha=0.0, images=0):
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    dt = torch.float32 if precision == "f32" else torch.float64
+    npdt = np.float32 if precision == "f32" else np.float64
+    if plan is None:
+        plan = Plan(ps.n_cells, ps.p, ps.boundary, box=ps.box, cutoff=cutoff,
+                    precision=precision, alpha=alpha, images=images)
+    dev = "cuda"
+    x, y, z, q = (torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).to(dev)
+                  for a in (ps.x, ps.y, ps.z, ps.q))
+    phi, gx, gy, gz = plan.far(x, y, z, q)
+    out = {"phi": phi, "grad": torch.stack([gx, gy, gz], dim=1)}
+    if near:
+        nphi, nx, ny, nz = plan.near(ps.n)
+        out["near_phi"] = nphi
+        out["near_grad"] = torch.stack([nx, ny, nz], dim=1)
+    torch.cuda.synchronize()
+    res = {k: v.double().cpu().numpy() for k, v in out.items()}
+    plan.sync_status()
+    return res, plan
+
+
+def oracle_cfg(ps, cutoff=2):
+    return opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=cutoff)
+
+
+def cell_unit_mesh(mesh, cfg, kind):
+    """Physical-unit oracle mesh [P, n, n, n] -> cell units (M_l / h^l or
+    L_l h^(l+1))."""
+    sm, sl = opm.mesh_scales(cfg)
+    s = sm if kind == "M" else sl
+    return mesh * s[:, None, None, None]
+
+
+def folded_green(cfg):
+    """Oracle transfer-kernel spectra in cell units, folded like the library:
+    [ky, kx, Q, kz] holding Re (even order) or Im (odd order)."""
+    Gt = opm.spectra(opm.green(cfg))        # [Q, kz, ky, kx] physical units
+    p2 = 2 * cfg.p
+    Q = nreal(p2)
+    out = np.empty(Gt.shape[2:] + (Q, Gt.shape[1]))
+    for k in range(p2 + 1):
+        scale = cfg.h ** (k + 1)            # S_k(delta h) h^(k+1) = S_k(delta)
+        for j in range(k * k, (k + 1) * (k + 1)):
+            v = Gt[j].imag if k % 2 else Gt[j].real
+            out[:, :, j, :] = np.transpose(v, (1, 2, 0)) * scale
+    return out

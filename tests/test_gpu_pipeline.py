@@ -1,0 +1,163 @@
+"""GPU parity of the HIP far-field path (through the C ABI) against the FP64
+oracle, on seeded inputs.  Tolerances: FP64 plans 1e-12 relative RMS, FP32
+plans 1e-6 relative RMS of grad Phi (the stated accuracy target) and of Phi.
+Stage meshes (moments, transfer spectra, local expansions) are compared too
+so that a failure names its stage."""
+import numpy as np
+import pytest
+
+from gpu_helpers import cell_unit_mesh, folded_green, gpu_far, oracle_cfg
+from oracle import exact
+from oracle import pmmm as opm
+from paper_1409_5981_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-6, "f64": 1e-12}
+# Periodic FP64 kernels are lattice sums from which the near image S(d) is
+# subtracted (App. B); the cancellation leaves a rounding floor near 1e-12 of
+# the largest kernel value that depends on summation order, so GPU and oracle
+# agree to about 1e-12 relative, not better.
+TOL_F64_PERIODIC = 1e-11
+
+
+def _small(n, n_cells, p, boundary, seed, dtype, neutral=True):
+    rng = np.random.default_rng(seed)
+    x, y, z = (rng.random(n).astype(dtype) for _ in range(3))
+    if neutral:
+        q = inputs.neutral_pm1(rng, n, dtype)
+    else:
+        q = (rng.random(n) / n).astype(dtype)
+    return inputs.ParticleSet(x, y, z, q, n_cells, p, boundary)
+
+
+def _compare(ps, precision, cutoff=2, tol=None):
+    if tol is None:
+        tol = TOL_F64_PERIODIC if (precision == "f64" and ps.boundary == "periodic") else TOL[precision]
+    res, plan = gpu_far(ps, precision, cutoff=cutoff)
+    cfg = oracle_cfg(ps, cutoff)
+    ref = opm.far_field(ps.pos, ps.q.astype(np.float64), cfg)
+    eg = exact.rel_rms(res["grad"], ref.grad)
+    ep = exact.rel_rms(res["phi"], ref.phi)
+    print(f"{ps.boundary} n={ps.n_cells} p={ps.p} N={ps.n} {precision}: "
+          f"rel-RMS grad {eg:.3e} phi {ep:.3e}", flush=True)
+    assert eg <= tol, eg
+    assert ep <= tol, ep
+    return res, ref, plan, cfg
+
+
+@pytest.mark.parametrize("boundary,n_cells,p", [("open", 4, 3), ("periodic", 8, 3),
+                                                ("open", 8, 5), ("periodic", 8, 6)])
+def test_small_f64(boundary, n_cells, p):
+    ps = _small(1500, n_cells, p, boundary, 11, np.float64)
+    _compare(ps, "f64")
+
+
+@pytest.mark.parametrize("boundary,n_cells,p,cutoff", [("open", 4, 2, 1), ("open", 8, 4, 2),
+                                                       ("periodic", 8, 4, 2), ("periodic", 4, 5, 1),
+                                                       ("periodic", 16, 7, 2), ("open", 16, 6, 2)])
+def test_small_f32(boundary, n_cells, p, cutoff):
+    ps = _small(6000, n_cells, p, boundary, 12, np.float32)
+    _compare(ps, "f32", cutoff=cutoff)
+
+
+def test_stage_meshes_f32():
+    """Moments, transfer spectra and local meshes against the oracle's, in
+    cell units, so that a failure names its stage."""
+    ps = _small(5000, 8, 4, "periodic", 13, np.float32)
+    res, plan = gpu_far(ps, "f32")
+    from paper_1409_5981_amd._lib import PMMM_MESH_GREEN, PMMM_MESH_L, PMMM_MESH_M
+    cfg = oracle_cfg(ps)
+    M, qr2 = opm.p2m_mesh(ps.pos, ps.q.astype(np.float64), cfg)
+    L = opm.local_mesh(M, cfg)
+    Mg = plan.mesh(PMMM_MESH_M).astype(np.float64)
+    Lg = plan.mesh(PMMM_MESH_L).astype(np.float64)
+    Gg = plan.mesh(PMMM_MESH_GREEN).astype(np.float64)
+    assert exact.rel_rms(Mg, cell_unit_mesh(M, cfg, "M")) < 1e-6
+    Gref = folded_green(cfg)
+    assert exact.rel_rms(Gg, Gref) < 1e-6
+    assert exact.rel_rms(Lg, cell_unit_mesh(L, cfg, "L")) < 2e-6
+
+
+def test_stage_meshes_open_f64():
+    ps = _small(3000, 4, 3, "open", 14, np.float64)
+    res, plan = gpu_far(ps, "f64", cutoff=1)
+    from paper_1409_5981_amd._lib import PMMM_MESH_GREEN, PMMM_MESH_L, PMMM_MESH_M
+    cfg = oracle_cfg(ps, cutoff=1)
+    M, _ = opm.p2m_mesh(ps.pos, ps.q, cfg)
+    L = opm.local_mesh(M, cfg)
+    assert exact.rel_rms(plan.mesh(PMMM_MESH_M), cell_unit_mesh(M, cfg, "M")) < 1e-13
+    assert exact.rel_rms(plan.mesh(PMMM_MESH_GREEN), folded_green(cfg)) < 1e-13
+    assert exact.rel_rms(plan.mesh(PMMM_MESH_L), cell_unit_mesh(L, cfg, "L")) < 1e-12
+
+
+def test_open_equal_mass_n4096_f64():
+    """Open boundary, N=4096, equal masses, 8^3 cells, p=4, FP64 throughout;
+    the method error against the direct sum is reported and must be small."""
+    ps = inputs.open_equal_mass()
+    res, ref, plan, cfg = _compare(ps, "f64")
+    nphi, ng = exact.near(ps.pos, ps.q, cfg)
+    dphi, dg = exact.direct(ps.pos, ps.q)
+    e = exact.rel_rms(res["grad"] + ng, dg)
+    print(f"method error vs direct sum (grad): {e:.3e}")
+    assert e < 1e-3
+
+
+def test_periodic_pm1_n32768_f32():
+    """Periodic, N=32768 neutral +/-1, 16^3 cells, p=5, FP32 vs FP64 oracle."""
+    ps = inputs.periodic_pm1()
+    _compare(ps, "f32")
+
+
+def test_near_field_matches_oracle():
+    ps = _small(4000, 8, 3, "periodic", 15, np.float32)
+    res, plan = gpu_far(ps, "f32", near=True)
+    cfg = oracle_cfg(ps)
+    nphi, ng = exact.near(ps.pos, ps.q.astype(np.float64), cfg)
+    assert exact.rel_rms(res["near_grad"], ng) < 1e-5
+    assert exact.rel_rms(res["near_phi"], nphi) < 1e-5
+
+
+def test_zero_and_single_particle():
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    plan = Plan(8, 3, "periodic")
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    out = plan.far(e, e, e, e)
+    assert all(o.numel() == 0 for o in out)
+    one = torch.tensor([0.3], dtype=torch.float32, device="cuda")
+    phi, gx, gy, gz = plan.far(one, one, one, torch.tensor([1.0], device="cuda"))
+    torch.cuda.synchronize()
+    ps = inputs.ParticleSet(np.array([0.3], np.float32), np.array([0.3], np.float32),
+                            np.array([0.3], np.float32), np.array([1.0], np.float32), 8, 3,
+                            "periodic")
+    ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+    assert abs(phi.item() - ref.phi[0]) < 1e-5 * abs(ref.phi[0])
+
+
+def test_two_calls_in_a_row_and_determinism():
+    """A second call with a smaller input reuses the plan correctly, and
+    repeated calls give identical results to rounding."""
+    import torch
+    ps = _small(8000, 8, 4, "open", 16, np.float32, neutral=False)
+    res1, plan = gpu_far(ps, "f32")
+    small = ps.subset(np.arange(3000))
+    res2, _ = gpu_far(small, "f32", plan=plan)
+    cfg = oracle_cfg(ps)
+    ref2 = opm.far_field(small.pos, small.q.astype(np.float64), cfg)
+    assert exact.rel_rms(res2["grad"], ref2.grad) < 1e-6
+    res3, _ = gpu_far(ps, "f32", plan=plan)
+    assert exact.rel_rms(res3["grad"], res1["grad"]) < 1e-6
+
+
+def test_open_domain_flag():
+    import torch
+    from paper_1409_5981_amd._lib import PMMM_EDOMAIN, Plan, PMMMError
+    plan = Plan(8, 2, "open")
+    x = torch.tensor([0.5, 1.2], dtype=torch.float32, device="cuda")
+    q = torch.ones(2, dtype=torch.float32, device="cuda")
+    plan.far(x, x * 0.5, x * 0.5, q)
+    with pytest.raises(PMMMError) as ei:
+        plan.sync_status()
+    assert ei.value.code == PMMM_EDOMAIN
+    plan.sync_status()   # flag cleared
