@@ -67,8 +67,9 @@ typedef struct pmmm_plan_s *pmmm_plan;
 
 /* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
  *   nx, ny, nz  cells per axis.  This build needs nx == ny == nz == n, a
- *               power of two with 4 <= n <= 64 (FP64: n <= 32 open,
- *               n <= 64 periodic); other meshes return PMMM_EUNSUPPORTED.
+ *               power of two with n >= 4 and an FFT mesh nf (2n open, n
+ *               periodic) of at most 128 (FP32) or 64 (FP64); other meshes
+ *               return PMMM_EUNSUPPORTED.
  *   box         edge lengths b of the box [0, b_x) x [0, b_y) x [0, b_z);
  *               cells must be cubic (b_a / n_a equal to 1e-12 relative).
  *   p           expansion order, 0 <= p <= PMMM_PMAX ((p+1)^2 coefficients);
@@ -138,16 +139,41 @@ int pmmm_plan_sync_status(pmmm_plan plan);
  *   PMMM_MESH_M      moments of the last call, [(p+1)^2][n][n][n] (z, y, x),
  *                    in CELL units (M_l scaled by 1/h^l), plan precision;
  *   PMMM_MESH_L      local expansions of the last call, same layout, in cell
- *                    units (L_l scaled by h^(l+1)), before the periodic
- *                    corrections;
+ *                    units (L_l scaled by h^(l+1)); periodic plans include the
+ *                    uniform corrections of App. B (self, dipole and r^2
+ *                    terms) but not the per-particle terms of a charged system;
  *   PMMM_MESH_GREEN  transfer-kernel spectra in cell units, one real value per
- *                    component and frequency: [nf*(nf/2+1) columns (ky, kx)]
- *                    [(2p+1)^2 components][nf (kz)], holding Re G~ for even
+ *                    component and frequency, on the quadrant ky, kz <= nf/2
+ *                    (the rest follows from the kernel's y and z reflection
+ *                    symmetries): [nh (ky)][nh (kx)][(2p+1)^2 components]
+ *                    [nhp (kz)] with nh = nf/2 + 1 and nhp = nh rounded up to
+ *                    a multiple of 4 (padding zero), holding Re G~ for even
  *                    orders and Im G~ for odd orders (the other part vanishes
- *                    by the parity of the kernel).
+ *                    by the parity of the kernel); periodic plans carry the
+ *                    self term -2 alpha h / sqrt(pi) in component 0.
  * `bytes` must equal pmmm_plan_mesh_bytes(plan, which). */
 size_t pmmm_plan_mesh_bytes(pmmm_plan plan, int which);
 int pmmm_plan_copy_mesh(pmmm_plan plan, int which, void *host_dst, size_t bytes);
+
+/* Stage timing, a profiling aid.  A far-field call runs these stages in order: */
+enum {
+    PMMM_STAGE_BIN = 0,     /* counting sort of the particles by cell */
+    PMMM_STAGE_P2M = 1,     /* eq. P2M per cell */
+    PMMM_STAGE_FFT_FWD = 2, /* forward FFT along x and y, per z-plane */
+    PMMM_STAGE_COLUMN = 3,  /* FFT along z + wave-space M2L + inverse FFT along z */
+    PMMM_STAGE_FFT_INV = 4, /* inverse FFT along y and x, per z-plane */
+    PMMM_STAGE_L2P = 5,     /* eq. L2P and the gradient */
+    PMMM_NSTAGES = 6
+};
+/* Bit s of `mask` brackets stage s of later pmmm_far_* calls on this plan with
+ * a pair of HIP events recorded on the call's stream; 0 (the default) records
+ * nothing. */
+int pmmm_plan_set_profiling(pmmm_plan plan, unsigned mask);
+/* Synchronise on the recorded events and add their elapsed times: ms[s]
+ * receives the total milliseconds and count[s] the number of timed launches
+ * of stage s since the last reset (arrays of PMMM_NSTAGES entries, either may
+ * be NULL); reset != 0 clears the totals afterwards. */
+int pmmm_plan_read_profile(pmmm_plan plan, double *ms, int64_t *count, int reset);
 
 const char *pmmm_error_string(int code);
 const char *pmmm_last_error(void);

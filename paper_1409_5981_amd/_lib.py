@@ -26,8 +26,11 @@ EXPORTS = [
     "pmmm_plan_create", "pmmm_plan_destroy", "pmmm_workspace_bytes",
     "pmmm_far_f32", "pmmm_far_f64", "pmmm_near_f32", "pmmm_near_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
+    "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
     "pmmm_error_string", "pmmm_last_error",
 ]
+
+STAGES = ["bin", "p2m", "fft_fwd", "column", "fft_inv", "l2p"]
 
 
 class Params(ctypes.Structure):
@@ -79,6 +82,11 @@ def load():
     L.pmmm_plan_mesh_bytes.restype = cz
     L.pmmm_plan_copy_mesh.argtypes = [vp, ci, vp, cz]
     L.pmmm_plan_copy_mesh.restype = ci
+    L.pmmm_plan_set_profiling.argtypes = [vp, ctypes.c_uint]
+    L.pmmm_plan_set_profiling.restype = ci
+    L.pmmm_plan_read_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ci]
+    L.pmmm_plan_read_profile.restype = ci
     L.pmmm_error_string.argtypes = [ci]
     L.pmmm_error_string.restype = ctypes.c_char_p
     L.pmmm_last_error.argtypes = []
@@ -181,6 +189,20 @@ class Plan:
                   _stream_handle(stream)))
         return out
 
+    def set_profiling(self, stages):
+        """Enable HIP-event timing for the named stages (see STAGES)."""
+        mask = 0
+        for st in stages:
+            mask |= 1 << STAGES.index(st)
+        _check(load().pmmm_plan_set_profiling(self._h, mask))
+
+    def read_profile(self, reset=True):
+        """{stage: (total ms, launches)} accumulated since the last reset."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        _check(load().pmmm_plan_read_profile(self._h, ms, cnt, int(bool(reset))))
+        return {st: (ms[i], cnt[i]) for i, st in enumerate(STAGES)}
+
     def sync_status(self):
         _check(load().pmmm_plan_sync_status(self._h))
 
@@ -195,4 +217,6 @@ class Plan:
         if which in (PMMM_MESH_M, PMMM_MESH_L):
             return buf.reshape(P, n, n, n)
         Q = (2 * self.p + 1) ** 2
-        return buf.reshape(nf, nf // 2 + 1, Q, nf)
+        nh = nf // 2 + 1
+        nhp = (nh + 3) & ~3
+        return buf.reshape(nh, nh, Q, nhp)[..., :nh]

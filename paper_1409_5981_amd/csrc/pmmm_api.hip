@@ -25,19 +25,54 @@ constexpr int kDenseThreshold = 256;
 struct Plan {
     pmmm_params prm;
     int n, nf, p, P, Q, open, prec, cutoff, images;
-    int64_t K, ncol;
+    int64_t K, ncol, ngreen;  // ngreen: stored transfer-kernel values
     double box, h, inv_h, alpha, alpha_cell;
     int device;
     size_t tsize;
     // plan-lifetime buffers
     void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
     int *count = nullptr, *start = nullptr, *dense_cells = nullptr, *small = nullptr;
-    double *sums = nullptr;
+    double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
     int64_t cap = 0, last_n = -1;
     int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr;
     void *sorted = nullptr;
     hipStream_t last_stream = nullptr;
+    // stage timing
+    unsigned prof_mask = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[PMMM_NSTAGES];
+    double prof_ms[PMMM_NSTAGES] = {0};
+    int64_t prof_cnt[PMMM_NSTAGES] = {0};
+};
+
+// Brackets one stage of a far-field call with HIP events when profiling is on.
+struct StageTimer {
+    Plan *pl;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(Plan *pl_, int st, hipStream_t s_) : pl(pl_), stage(st), s(s_) {
+        if (!(pl->prof_mask & (1u << stage))) return;
+        a = take();
+        b = take();
+        if (a) hipEventRecord(a, s);
+    }
+    hipEvent_t take() {
+        if (!pl->ev_pool.empty()) {
+            hipEvent_t e = pl->ev_pool.back();
+            pl->ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~StageTimer() {
+        if (!a || !b) return;
+        hipEventRecord(b, s);
+        pl->ev_pending[stage].push_back({a, b});
+    }
 };
 
 }  // namespace pmmm
@@ -106,6 +141,13 @@ static int validate(const pmmm_params *prm, std::string &why) {
         why = "FFT mesh too large for this build (FP32: nf <= 128, FP64: nf <= 64)";
         return PMMM_EUNSUPPORTED;
     }
+    // the column kernel keeps the spectra and kernel tile of at least one
+    // column in LDS (160 KB per CU)
+    const size_t lds = column_shape(prm->p, nf, prm->precision == PMMM_F32 ? 4 : 8, nullptr, nullptr);
+    if (lds == 0) {
+        why = "order too high for this FFT mesh: the column kernel's tile exceeds 160 KB of LDS";
+        return PMMM_EUNSUPPORTED;
+    }
     return PMMM_OK;
 }
 
@@ -122,6 +164,10 @@ static void derive(Plan *pl, const pmmm_params *prm) {
     pl->images = prm->images == 0 ? 4 : prm->images;
     pl->K = (int64_t)pl->n * pl->n * pl->n;
     pl->ncol = (int64_t)pl->nf * (pl->nf / 2 + 1);
+    {
+        const int64_t nh = pl->nf / 2 + 1, nhp = (nh + 3) & ~3;
+        pl->ngreen = nh * nh * pl->Q * nhp;
+    }
     pl->box = prm->box[0];
     pl->h = pl->box / pl->n;
     pl->inv_h = pl->n / pl->box;
@@ -133,7 +179,7 @@ static void derive(Plan *pl, const pmmm_params *prm) {
 static size_t plan_bytes(const Plan *pl) {
     const size_t t = pl->tsize, c = 2 * t;
     size_t b = 0;
-    b += (size_t)pl->ncol * pl->Q * pl->nf * t;          // green
+    b += (size_t)pl->ngreen * t;                         // green
     b += (size_t)(pl->nf / 2) * c;                       // twiddles
     b += (size_t)(pl->P + 1) * pl->K * t;                // M
     b += (size_t)pl->P * pl->n * pl->ncol * c;           // spectra
@@ -188,6 +234,13 @@ static void destroy(Plan *pl) {
     hipFree(pl->dense_cells);
     hipFree(pl->small);
     hipFree(pl->sums);
+    hipFree(pl->qr2_partial);
+    for (hipEvent_t e : pl->ev_pool) hipEventDestroy(e);
+    for (auto &v : pl->ev_pending)
+        for (auto &pr : v) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
     delete static_cast<pmmm_plan_s *>(pl);
 }
 
@@ -204,15 +257,16 @@ static int make_twiddles(Plan *pl, hipStream_t s) {
 
 static int alloc_plan(Plan *pl, hipStream_t s) {
     const size_t t = pl->tsize, c = 2 * t;
-    PMMM_HIP(hipMalloc(&pl->green, (size_t)pl->ncol * pl->Q * pl->nf * t));
+    PMMM_HIP(hipMalloc(&pl->green, (size_t)pl->ngreen * t));
     PMMM_HIP(hipMalloc(&pl->M, (size_t)(pl->P + 1) * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
     PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * pl->K));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
     PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
-    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag
+    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] scan counter
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
+    PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
     PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * pl->K, s));
     PMMM_HIP(hipMemsetAsync(pl->small, 0, sizeof(int) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->sums, 0, sizeof(double) * 8, s));
@@ -220,11 +274,12 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     return pl->prec == PMMM_F32 ? make_twiddles<float>(pl, s) : make_twiddles<double>(pl, s);
 }
 
+// Lanes per cell in the light P2M path: about four particles per lane.
 static int group_for(double mean) {
-    if (mean <= 6) return 4;
-    if (mean <= 12) return 8;
-    if (mean <= 24) return 16;
-    if (mean <= 48) return 32;
+    if (mean <= 24) return 4;
+    if (mean <= 48) return 8;
+    if (mean <= 96) return 16;
+    if (mean <= 192) return 32;
     return 64;
 }
 
@@ -259,49 +314,45 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
     pl->last_stream = s;
     pl->last_n = n;
 
-    BinArgs b{};
-    b.n = n;
-    b.x = x;
-    b.y = y;
-    b.z = z;
-    b.q = q;
-    b.ncell = pl->n;
-    b.inv_h = pl->inv_h;
-    b.periodic = !pl->open;
-    b.cell_of = pl->cell_of;
-    b.slot = pl->slot;
-    b.count = pl->count;
-    b.start = pl->start;
-    b.scell = pl->scell;
-    b.perm = pl->perm;
-    b.flag = pl->small + 1;
-    b.dense_cells = pl->dense_cells;
-    b.dense_count = pl->small;
-    b.dense_threshold = kDenseThreshold;
-    b.sorted = pl->sorted;
-    PMMM_HIP(launch_bin<T>(b, s));
-
-    P2MArgs m{};
-    m.p = pl->p;
-    m.ncell = pl->n;
-    m.group = group_for((double)n / (double)pl->K);
-    m.start = pl->start;
-    m.dense_cells = pl->dense_cells;
-    m.dense_count = pl->small;
-    m.dense_threshold = kDenseThreshold;
-    m.sorted = pl->sorted;
-    m.M = pl->M;
-    PMMM_HIP(launch_p2m<T>(m, s));
-
-    if (!pl->open) {
-        SumArgs sa{};
-        sa.ncell = pl->n;
-        sa.M = pl->M;
-        sa.p = pl->p;
-        sa.sums = pl->sums;
-        PMMM_HIP(launch_pbc_sums<T>(sa, s));
+    {
+        StageTimer t(pl, PMMM_STAGE_BIN, s);
+        BinArgs b{};
+        b.n = n;
+        b.x = x;
+        b.y = y;
+        b.z = z;
+        b.q = q;
+        b.ncell = pl->n;
+        b.inv_h = pl->inv_h;
+        b.periodic = !pl->open;
+        b.cell_of = pl->cell_of;
+        b.slot = pl->slot;
+        b.count = pl->count;
+        b.start = pl->start;
+        b.scell = pl->scell;
+        b.perm = pl->perm;
+        b.flag = pl->small + 1;
+        b.dense_cells = pl->dense_cells;
+        b.dense_count = pl->small;
+        b.dense_threshold = kDenseThreshold;
+        b.sorted = pl->sorted;
+        PMMM_HIP(launch_bin<T>(b, s));
     }
-
+    {
+        StageTimer t(pl, PMMM_STAGE_P2M, s);
+        P2MArgs m{};
+        m.p = pl->p;
+        m.ncell = pl->n;
+        m.group = group_for((double)n / (double)pl->K);
+        m.may_have_dense = n > kDenseThreshold;
+        m.start = pl->start;
+        m.dense_cells = pl->dense_cells;
+        m.dense_count = pl->small;
+        m.dense_threshold = kDenseThreshold;
+        m.sorted = pl->sorted;
+        m.M = pl->M;
+        PMMM_HIP(launch_p2m<T>(m, s));
+    }
     FFTArgs f{};
     f.p = pl->p;
     f.n = pl->n;
@@ -312,26 +363,32 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
     f.green = pl->green;
     f.tw = pl->tw;
     f.L = pl->L;
-    PMMM_HIP(launch_convolution<T>(f, s));
-
-    L2PArgs l{};
-    l.n = n;
-    l.p = pl->p;
-    l.ncell = pl->n;
-    l.periodic = !pl->open;
-    l.sorted = pl->sorted;
-    l.scell = pl->scell;
-    l.perm = pl->perm;
-    l.L = pl->L;
-    l.M = pl->M;
-    l.sums = pl->sums;
-    l.alpha_cell = pl->alpha_cell;
-    l.inv_h = pl->inv_h;
-    l.phi = phi;
-    l.gx = gx;
-    l.gy = gy;
-    l.gz = gz;
-    PMMM_HIP(launch_l2p<T>(l, s));
+    f.qr2_partial = pl->qr2_partial;
+    f.sums = pl->sums;
+    for (int st = 0; st < 3; ++st) {
+        StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s);
+        PMMM_HIP(launch_conv_stage<T>(f, st, s));
+    }
+    {
+        StageTimer t(pl, PMMM_STAGE_L2P, s);
+        L2PArgs l{};
+        l.n = n;
+        l.p = pl->p;
+        l.ncell = pl->n;
+        l.periodic = !pl->open;
+        l.sorted = pl->sorted;
+        l.scell = pl->scell;
+        l.perm = pl->perm;
+        l.L = pl->L;
+        l.sums = pl->sums;
+        l.alpha_cell = pl->alpha_cell;
+        l.inv_h = pl->inv_h;
+        l.phi = phi;
+        l.gx = gx;
+        l.gy = gy;
+        l.gz = gz;
+        PMMM_HIP(launch_l2p<T>(l, s));
+    }
     return PMMM_OK;
 }
 
@@ -470,7 +527,7 @@ size_t pmmm_plan_mesh_bytes(pmmm_plan plan, int which) {
         case PMMM_MESH_L:
             return (size_t)plan->P * plan->K * plan->tsize;
         case PMMM_MESH_GREEN:
-            return (size_t)plan->ncol * plan->Q * plan->nf * plan->tsize;
+            return (size_t)plan->ngreen * plan->tsize;
         default:
             return 0;
     }
@@ -489,6 +546,41 @@ int pmmm_plan_copy_mesh(pmmm_plan plan, int which, void *host_dst, size_t bytes)
     const void *src = which == PMMM_MESH_M ? plan->M : (which == PMMM_MESH_L ? plan->L : plan->green);
     PMMM_HIP(hipStreamSynchronize(plan->last_stream));
     PMMM_HIP(hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+    return PMMM_OK;
+}
+
+int pmmm_plan_set_profiling(pmmm_plan plan, unsigned mask) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    plan->prof_mask = mask & ((1u << PMMM_NSTAGES) - 1);
+    return PMMM_OK;
+}
+
+int pmmm_plan_read_profile(pmmm_plan plan, double *ms, int64_t *count, int reset) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    for (int st = 0; st < PMMM_NSTAGES; ++st) {
+        for (auto &pr : plan->ev_pending[st]) {
+            PMMM_HIP(hipEventSynchronize(pr.second));
+            float t = 0.f;
+            PMMM_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+            plan->prof_ms[st] += t;
+            plan->prof_cnt[st] += 1;
+            plan->ev_pool.push_back(pr.first);
+            plan->ev_pool.push_back(pr.second);
+        }
+        plan->ev_pending[st].clear();
+        if (ms) ms[st] = plan->prof_ms[st];
+        if (count) count[st] = plan->prof_cnt[st];
+        if (reset) {
+            plan->prof_ms[st] = 0;
+            plan->prof_cnt[st] = 0;
+        }
+    }
     return PMMM_OK;
 }
 

@@ -30,12 +30,16 @@
 
 namespace pmmm {
 
+// Global loads each thread keeps in flight before writing them to LDS.
+constexpr int kLoadBatch = 8;
+
 // ------------------------------------------------------------------ planes
 template <typename T>
 __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
                                                    const T *__restrict__ M,
                                                    cplx<T> *__restrict__ spec,
-                                                   const cplx<T> *__restrict__ tw_g) {
+                                                   const cplx<T> *__restrict__ tw_g,
+                                                   int P, double *__restrict__ qr2_partial) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nf = 1 << logn, nh = nf / 2 + 1, npair = nin / 2;
     cplx<T> *tw = (cplx<T> *)lds_raw;
@@ -45,14 +49,25 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
     const T *plane = M + ((int64_t)c * nin + z) * nin * nin;
-    for (int idx = tid; idx < npair * nf; idx += nthr) {
-        const int j = idx >> logn, x = idx & (nf - 1);
-        cplx<T> v = {T(0), T(0)};
-        if (x < nin) {
-            v.re = plane[(2 * j) * nin + x];
-            v.im = plane[(2 * j + 1) * nin + x];
+    // rows are paired (2j, 2j+1) into one complex row; loads are issued in
+    // batches of kLoadBatch before their LDS stores
+    for (int base = tid; base < npair * nf; base += nthr * kLoadBatch) {
+        cplx<T> v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * nthr;
+            const int j = idx >> logn, x = idx & (nf - 1);
+            v[u] = {T(0), T(0)};
+            if (idx < npair * nf && x < nin) {
+                v[u].re = plane[(2 * j) * nin + x];
+                v[u].im = plane[(2 * j + 1) * nin + x];
+            }
         }
-        buf1[idx] = v;
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * nthr;
+            if (idx < npair * nf) buf1[idx] = v[u];
+        }
     }
     __syncthreads();
     lds_fft_dif<T, false>(buf1, logn, npair, nf, 1, tw, tid, nthr);
@@ -80,6 +95,21 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
         const int pos = idx / nh, k = idx - pos * nh;
         out[bitrev(pos, logn) * nh + k] = buf2[idx];
     }
+    if (qr2_partial != nullptr && c == 0) {
+        // sum over this plane of the per-cell q|u|^2 (component P of M),
+        // fixed-order reduction
+        __shared__ double red[256];
+        const T *pl = M + ((int64_t)P * nin + z) * nin * nin;
+        double acc = 0.0;
+        for (int idx = tid; idx < nin * nin; idx += nthr) acc += (double)pl[idx];
+        red[tid] = acc;
+        __syncthreads();
+        for (int off = 128; off >= 1; off >>= 1) {
+            if (tid < off) red[tid] += red[tid + off];
+            __syncthreads();
+        }
+        if (tid == 0) qr2_partial[z] = red[0];
+    }
 }
 
 template <typename T>
@@ -96,7 +126,19 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
     const cplx<T> *in = spec + ((int64_t)c * nout + z) * nf * nh;
-    for (int idx = tid; idx < nf * nh; idx += nthr) buf2[idx] = in[idx];
+    for (int base = tid; base < nf * nh; base += nthr * kLoadBatch) {
+        cplx<T> v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * nthr;
+            if (idx < nf * nh) v[u] = in[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * nthr;
+            if (idx < nf * nh) buf2[idx] = v[u];
+        }
+    }
     __syncthreads();
     lds_fft_dif<T, true>(buf2, logn, nh, 1, nh, tw, tid, nthr);
     for (int idx = tid; idx < npair * nf; idx += nthr) {
@@ -162,45 +204,71 @@ __device__ __forceinline__ void mac(cplx<T> &acc, T c, cplx<T> m) {
     acc.im = fma(c, m.im, acc.im);
 }
 
-// acc[a] += sum_b t_ab(g of order nn) * Mh[b] for all (l, lam) with l + lam = nn.
-template <int PO, int NN, typename T>
-__device__ __forceinline__ void m2l_order(const T *g, const cplx<T> *Mh, cplx<T> *acc) {
+// Output orders are dealt to kRowSplit subsets at compile time, largest
+// first, each to the subset with the fewest rows so far (2l+1 rows per order).
+constexpr int kRowSplit = 4;
+
+__host__ __device__ constexpr int order_subset(int PO, int RS, int l) {
+    int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int owner = 0;
+    for (int o = PO; o >= 0; --o) {
+        int best = 0;
+        for (int s = 1; s < RS; ++s)
+            if (load[s] < load[best]) best = s;
+        load[best] += 2 * o + 1;
+        if (o == l) owner = best;
+    }
+    return owner;
+}
+
+// Does subset S need the kernel values of order NN?
+__host__ __device__ constexpr bool subset_needs(int PO, int RS, int S, int NN) {
+    for (int l = 0; l <= PO; ++l)
+        if (order_subset(PO, RS, l) == S && NN - l >= 0 && NN - l <= PO) return true;
+    return false;
+}
+
+// acc[a] += sum_b t_ab(g of order NN) * M~_b over the output orders l of
+// subset S with lam = NN - l; M~ of order lam is read from LDS (column
+// `mcol`, row stride `mstride`) and pre-multiplied by i^(lam mod 2).
+template <int PO, int NN, int RS, int S, typename T>
+__device__ __forceinline__ void m2l_order(const T *g, const cplx<T> *mcol, int mstride,
+                                          cplx<T> *acc) {
     constexpr int lo = NN - PO > 0 ? NN - PO : 0;
     constexpr int hi = NN < PO ? NN : PO;
 #pragma unroll
     for (int l = lo; l <= hi; ++l) {
+        if (order_subset(PO, RS, l) != S) continue;
         const int lam = NN - l;
         const int s = ((l & 1) && (lam & 1)) ? -1 : 1;
+        cplx<T> Mh[2 * PO + 1];
+#pragma unroll
+        for (int mu = -lam; mu <= lam; ++mu) {
+            const cplx<T> v = mcol[ridx(lam, mu) * mstride];
+            Mh[mu + lam] = (lam & 1) ? cplx<T>{-v.im, v.re} : v;
+        }
 #pragma unroll
         for (int m = 0; m <= l; ++m) {
             cplx<T> are = acc[ridx(l, m)];
             cplx<T> aim = (m > 0) ? acc[ridx(l, -m)] : cplx<T>{T(0), T(0)};
-            // mu = 0 column: G^{m,0} = S_nn^{-m}
+            // mu = 0 column: G^{m,0} = S_NN^{-m}
             {
-                const cplx<T> x = Mh[ridx(lam, 0)];
-                const T A = term2(g, re_S(NN, -m), s, Term{0, 0}, 0);
-                mac(are, A, x);
-                if (m > 0) {
-                    const T B = term2(g, im_S(NN, -m), s, Term{0, 0}, 0);
-                    mac(aim, B, x);
-                }
+                const cplx<T> x = Mh[lam];
+                mac(are, term2(g, re_S(NN, -m), s, Term{0, 0}, 0), x);
+                if (m > 0) mac(aim, term2(g, im_S(NN, -m), s, Term{0, 0}, 0), x);
             }
 #pragma unroll
             for (int mu = 1; mu <= lam; ++mu) {
-                const cplx<T> xr = Mh[ridx(lam, mu)];
-                const cplx<T> xi = Mh[ridx(lam, -mu)];
+                const cplx<T> xr = Mh[lam + mu];   // Re M_lam^mu
+                const cplx<T> xi = Mh[lam - mu];   // Im M_lam^mu
                 const int sg = (mu & 1) ? -1 : 1;  // (-1)^mu of C and D
                 // Re row: (A + C) ReM - (B - D) ImM
-                const T apc = term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), s * sg);
-                const T bmd = term2(g, im_S(NN, -(m + mu)), -s, im_S(NN, -(m - mu)), s * sg);
-                mac(are, apc, xr);
-                mac(are, bmd, xi);
+                mac(are, term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), s * sg), xr);
+                mac(are, term2(g, im_S(NN, -(m + mu)), -s, im_S(NN, -(m - mu)), s * sg), xi);
                 if (m > 0) {
                     // Im row: (B + D) ReM + (A - C) ImM
-                    const T bpd = term2(g, im_S(NN, -(m + mu)), s, im_S(NN, -(m - mu)), s * sg);
-                    const T amc = term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), -s * sg);
-                    mac(aim, bpd, xr);
-                    mac(aim, amc, xi);
+                    mac(aim, term2(g, im_S(NN, -(m + mu)), s, im_S(NN, -(m - mu)), s * sg), xr);
+                    mac(aim, term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), -s * sg), xi);
                 }
             }
             acc[ridx(l, m)] = are;
@@ -209,34 +277,100 @@ __device__ __forceinline__ void m2l_order(const T *g, const cplx<T> *Mh, cplx<T>
     }
 }
 
-template <int PO, int NN, typename T>
+// Kernel values g of order NN come from the block's LDS tile (component j
+// at gcol[j * gstride]) of the stored quadrant ky, kz in [0, nf/2].  A
+// frequency with ky > nf/2 reads ky' = nf - ky and negates the Im-part
+// components (S(x, -y, z) = conj S); kz > nf/2 reads kz' = nf - kz and
+// multiplies component (n, k) by (-1)^(n+|k|) (S_n^k(x, y, -z) =
+// (-1)^(n+k) S_n^k).  flip = 1 for a mirrored ky, 2 for a mirrored kz.
+template <int PO, int NN, int RS, int S, typename T>
 struct M2LOrders {
-    __device__ static __forceinline__ void run(const T *__restrict__ gcol, int nf, int kz,
-                                               const cplx<T> *Mh, cplx<T> *acc) {
-        T g[2 * NN + 1];
+    __device__ static __forceinline__ void run(const T *gcol, int gstride, int flip,
+                                               const cplx<T> *mcol, int mstride, cplx<T> *acc) {
+        if constexpr (subset_needs(PO, RS, S, NN)) {
+            T g[2 * NN + 1];
 #pragma unroll
-        for (int k = 0; k <= 2 * NN; ++k) g[k] = gcol[(int64_t)(NN * NN + k) * nf + kz];
-        m2l_order<PO, NN, T>(g, Mh, acc);
-        M2LOrders<PO, NN + 1, T>::run(gcol, nf, kz, Mh, acc);
+            for (int k = 0; k <= 2 * NN; ++k) {
+                const int kk = k - NN;
+                const int odd_z = (NN + (kk < 0 ? -kk : kk)) & 1;
+                const int neg = ((flip & 1) && kk < 0) ^ ((flip & 2) && odd_z);
+                const T v = gcol[(NN * NN + k) * gstride];
+                g[k] = neg ? -v : v;
+            }
+            m2l_order<PO, NN, RS, S, T>(g, mcol, mstride, acc);
+            // keep the next order's loads after this one's arithmetic so that
+            // the (2p+1)^2 kernel values are never all live at once
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        M2LOrders<PO, NN + 1, RS, S, T>::run(gcol, gstride, flip, mcol, mstride, acc);
     }
 };
-template <int PO, typename T>
-struct M2LOrders<PO, 2 * PO + 1, T> {
-    __device__ static __forceinline__ void run(const T *__restrict__, int, int, const cplx<T> *,
+template <int PO, int RS, int S, typename T>
+struct M2LOrders<PO, 2 * PO + 1, RS, S, T> {
+    __device__ static __forceinline__ void run(const T *, int, int, const cplx<T> *, int,
                                                cplx<T> *) {}
 };
 
+// Uniform corrections of a periodic system at the zero frequency (added to
+// the final L~, i.e. after the i^(l mod 2) factor).  Adding c to every cell
+// of L equals adding c * nf^3 to L~(k = 0).
+struct DCCorr {
+    bool on;
+    double l00, l10, l11re, l11im;
+};
+
+// Rows of subset S: M~ read from `mcol`, L~ = i^(l mod 2) acc (plus the
+// zero-frequency corrections) written to `ocol`.
+template <int PO, int RS, int S, typename T>
+__device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
+                                           const cplx<T> *mcol, cplx<T> *ocol, int stride,
+                                           DCCorr dc) {
+    constexpr int P = nreal(PO);
+    cplx<T> acc[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) acc[a] = {T(0), T(0)};
+    M2LOrders<PO, 0, RS, S, T>::run(gcol, gstride, flip, mcol, stride, acc);
+#pragma unroll
+    for (int l = 0; l <= PO; ++l) {
+        if (order_subset(PO, RS, l) != S) continue;
+#pragma unroll
+        for (int m = -l; m <= l; ++m) {
+            const int a = ridx(l, m);
+            const cplx<T> v = acc[a];
+            cplx<T> o = (l & 1) ? cplx<T>{-v.im, v.re} : v;
+            if (dc.on) {
+                if (a == 0) o.re += T(dc.l00);
+                if (PO >= 1 && a == ridx(1, 0)) o.re += T(dc.l10);
+                if (PO >= 1 && a == ridx(1, 1)) o.re += T(dc.l11re);
+                if (PO >= 1 && a == ridx(1, -1)) o.re += T(dc.l11im);
+            }
+            ocol[a * stride] = o;
+        }
+    }
+}
+
+// Block = rs row subsets x (w columns x nf frequencies) <= 256 threads; with
+// rs < kRowSplit each thread runs kRowSplit / rs of the subsets.  LDS:
+// moment spectra buf[P][w][nf], local spectra obuf[P][w][nf] and the
+// block's transfer-kernel tile gt[Q][w][nhp] (kz' in [0, nf/2], padded).
 template <int PO, typename T>
-__global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int ncol, int ngroups,
+__global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs, int ncol,
+                                                int ngroups,
                                                 const T *__restrict__ green,
                                                 cplx<T> *__restrict__ spec,
-                                                const cplx<T> *__restrict__ tw_g) {
+                                                const cplx<T> *__restrict__ tw_g, int periodic,
+                                                const double *__restrict__ qr2_partial,
+                                                double *__restrict__ sums) {
     constexpr int P = nreal(PO);
     constexpr int Q = nreal(2 * PO);
+    constexpr int RS = kRowSplit;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn;
+    const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3;
+    const int nfreq = w * nf;
     cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *buf = tw + nf / 2;  // [P][w][nf]
+    cplx<T> *buf = tw + nf / 2;
+    cplx<T> *obuf = buf + P * nfreq;
+    T *gt = (T *)(obuf + P * nfreq);
     // XCD-aware order: consecutive column groups stay on one XCD (blocks are
     // dealt round-robin over the 8 XCDs).
     const int per_xcd = (ngroups + 7) / 8;
@@ -245,57 +379,125 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int nco
     const int col0 = grp * w;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
+    // transfer-kernel tile: reduced column (ky', kx) of each block column is a
+    // contiguous, 16-byte aligned [Q][nhp] slab; loads go out in batches
+    {
+        const int vec = 16 / (int)sizeof(T);
+        const int per_col = Q * nhp / vec;
+        const int total = w * per_col;
+        for (int base = tid; base < total; base += nthr * kLoadBatch) {
+            float4 v[kLoadBatch];
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int t = base + u * nthr;
+                const int ci = t / per_col, r = (t - ci * per_col) * vec;
+                const int col = col0 + ci;
+                if (t < total && col < ncol) {
+                    const int ky = col / nh, kx = col - ky * nh;
+                    const int kyr = ky <= nf / 2 ? ky : nf - ky;
+                    v[u] = *(const float4 *)(green + ((int64_t)(kyr * nh + kx) * Q * nhp + r));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int t = base + u * nthr;
+                const int ci = t / per_col, r = (t - ci * per_col) * vec;
+                if (t >= total || col0 + ci >= ncol) continue;
+                const int j = r / nhp, kz0 = r - j * nhp;
+                T *dst = gt + (j * w + ci) * nhp + kz0;
+                if (sizeof(T) == 4) {
+                    const float *vf = (const float *)&v[u];
+                    dst[0] = vf[0];
+                    dst[1] = vf[1];
+                    dst[2] = vf[2];
+                    dst[3] = vf[3];
+                } else {
+                    const double *vd = (const double *)&v[u];
+                    dst[0] = vd[0];
+                    dst[1] = vd[1];
+                }
+            }
+        }
+    }
     const int64_t zstride = (int64_t)ncol;
-    // load z < nz, zero the padding
-    for (int idx = tid; idx < P * nf * w; idx += nthr) {
-        const int i = idx % w;
-        const int rest = idx / w;
-        const int zz = rest & (nf - 1);
-        const int b = rest >> logn;
-        const int col = col0 + i;
-        cplx<T> v = {T(0), T(0)};
-        if (zz < nz && col < ncol) v = spec[((int64_t)b * nz + zz) * zstride + col];
-        buf[(b * w + i) * nf + zz] = v;
+    // spectra of z < nz; the rest of the padded column is zero
+    for (int base = tid; base < P * nf * w; base += nthr * kLoadBatch) {
+        cplx<T> v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * nthr;
+            const int i = idx % w;
+            const int rest = idx / w;
+            const int zz = rest & (nf - 1);
+            const int b = rest >> logn;
+            const int col = col0 + i;
+            v[u] = {T(0), T(0)};
+            if (idx < P * nf * w && zz < nz && col < ncol)
+                v[u] = spec[((int64_t)b * nz + zz) * zstride + col];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * nthr;
+            if (idx >= P * nf * w) continue;
+            const int i = idx % w;
+            const int rest = idx / w;
+            const int zz = rest & (nf - 1);
+            const int b = rest >> logn;
+            buf[(b * w + i) * nf + zz] = v[u];
+        }
     }
     __syncthreads();
     lds_fft_dif<T, false>(buf, logn, P * w, nf, 1, tw, tid, nthr);
-    // M2L, one thread per frequency of the block's columns
-    for (int t = tid; t < w * nf; t += nthr) {
-        const int i = t >> logn, pos = t & (nf - 1);
-        const int col = col0 + i;
-        if (col >= ncol) continue;
-        const int kz = bitrev(pos, logn);
-        cplx<T> Mh[P], acc[P];
-#pragma unroll
-        for (int lam = 0; lam <= PO; ++lam) {
-#pragma unroll
-            for (int mu = -lam; mu <= lam; ++mu) {
-                const int b = ridx(lam, mu);
-                const cplx<T> v = buf[(b * w + i) * nf + pos];
-                Mh[b] = (lam & 1) ? cplx<T>{-v.im, v.re} : v;  // i^(lam mod 2) M~
-                acc[b] = {T(0), T(0)};
-            }
-        }
-        M2LOrders<PO, 0, T>::run(green + (int64_t)col * Q * nf, nf, kz, Mh, acc);
-#pragma unroll
-        for (int l = 0; l <= PO; ++l) {
-#pragma unroll
-            for (int m = -l; m <= l; ++m) {
-                const int a = ridx(l, m);
-                const cplx<T> v = acc[a];
-                buf[(a * w + i) * nf + pos] = (l & 1) ? cplx<T>{-v.im, v.re} : v;
+    // M2L: thread = (row subset, frequency)
+    const int sub = tid / nfreq, f = tid - sub * nfreq;
+    const int i = f >> logn, pos = f & (nf - 1);
+    const int col = col0 + i;
+    const int kz = bitrev(pos, logn);
+    DCCorr dcc = {false, 0.0, 0.0, 0.0, 0.0};
+    if (periodic && col == 0 && kz == 0) {
+        // zero frequency: M~_c(0) = sum over cells of M_c (real)
+        const cplx<T> *m0 = buf + i * nf + pos;
+        const double V = (double)nf * nf * nf;  // box volume in cell units (nf = n)
+        const double pi = 3.14159265358979323846;
+        double qr2 = 0.0;
+        for (int z = 0; z < nz; ++z) qr2 += qr2_partial[z];
+        const double m10 = PO >= 1 ? (double)m0[ridx(1, 0) * nfreq].re : 0.0;
+        const double m11 = PO >= 1 ? (double)m0[ridx(1, 1) * nfreq].re : 0.0;
+        const double m1m1 = PO >= 1 ? (double)m0[ridx(1, -1) * nfreq].re : 0.0;
+        // per-cell constants of the correction procedure, times nf^3 (= V)
+        dcc.l00 = 2.0 * pi / (3.0 * V) * qr2 * V;
+        dcc.l10 = 4.0 * pi / (3.0 * V) * m10 * V;
+        dcc.l11re = 8.0 * pi / (3.0 * V) * m11 * V;
+        dcc.l11im = -8.0 * pi / (3.0 * V) * m1m1 * V;
+        dcc.on = true;
+        if (sub == 0) sums[0] = (double)m0[0].re;  // total charge
+    }
+    if (col < ncol) {
+        const int ky = col / nh;
+        const int kzr = kz <= nf / 2 ? kz : nf - kz;
+        const int flip = (ky > nf / 2 ? 1 : 0) | (kz > nf / 2 ? 2 : 0);
+        const T *gp = gt + i * nhp + kzr;
+        const int gstride = w * nhp;
+        const cplx<T> *mp = buf + i * nf + pos;
+        cplx<T> *op = obuf + i * nf + pos;
+        for (int ss = sub; ss < RS; ss += rs) {
+            switch (ss) {
+                case 0: m2l_subset<PO, RS, 0, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
+                case 1: m2l_subset<PO, RS, 1, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
+                case 2: m2l_subset<PO, RS, 2, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
+                default: m2l_subset<PO, RS, 3, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
             }
         }
     }
     __syncthreads();
-    lds_fft_dit<T, true>(buf, logn, P * w, nf, 1, tw, tid, nthr);
+    lds_fft_dit<T, true>(obuf, logn, P * w, nf, 1, tw, tid, nthr);
     for (int idx = tid; idx < P * nz * w; idx += nthr) {
-        const int i = idx % w;
+        const int ii = idx % w;
         const int rest = idx / w;
         const int zz = rest % nz;
         const int a = rest / nz;
-        const int col = col0 + i;
-        if (col < ncol) spec[((int64_t)a * nz + zz) * zstride + col] = buf[(a * w + i) * nf + zz];
+        const int cc = col0 + ii;
+        if (cc < ncol) spec[((int64_t)a * nz + zz) * zstride + cc] = obuf[(a * w + ii) * nf + zz];
     }
 }
 
@@ -315,53 +517,51 @@ static hipError_t ensure_lds(Kern k, size_t bytes) {
 
 template <int PO, typename T>
 static hipError_t column_launch(const FFTArgs &a, hipStream_t s) {
-    constexpr int P = nreal(PO);
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, ncol = nf * nh;
-    const size_t csz = sizeof(cplx<T>);
-    const size_t budget = 80 * 1024;
-    int w = 256 / nf;
-    if (w < 1) w = 1;
-    while (w > 1 && (size_t)P * w * nf * csz + nf / 2 * csz > budget) w >>= 1;
-    // prefer more, narrower blocks while the mesh has few columns
-    while (w > 1 && (ncol + w - 1) / w < 512) w >>= 1;
-    const int threads = (w * nf < 64) ? 64 : (w * nf > 256 ? 256 : w * nf);
+    int w = 1, rs = 1;
+    const size_t lds = column_shape(PO, nf, sizeof(T), &w, &rs);
+    if (lds == 0) return hipErrorInvalidValue;
+    const int threads = rs * w * nf;
     const int ngroups = (ncol + w - 1) / w;
     const int grid = ((ngroups + 7) / 8) * 8;
-    const size_t lds = (size_t)P * w * nf * csz + nf / 2 * csz;
     hipError_t e = ensure_lds(k_column<PO, T>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_column<PO, T>), dim3(grid), dim3(threads), lds, s, a.n, logn, w, ncol,
-                       ngroups, (const T *)a.green, (cplx<T> *)a.spec,
-                       (const cplx<T> *)a.tw);
+    hipLaunchKernelGGL((k_column<PO, T>), dim3(grid), dim3(threads), lds, s, a.n, logn, w, rs,
+                       ncol, ngroups, (const T *)a.green, (cplx<T> *)a.spec,
+                       (const cplx<T> *)a.tw, a.open ? 0 : 1, a.qr2_partial, a.sums);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_convolution(const FFTArgs &a, hipStream_t s) {
+hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const int P = nreal(a.p);
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, n = a.n;
     const size_t csz = sizeof(cplx<T>);
     const size_t lds_plane = (size_t)(nf / 2 + (n / 2) * nf + nf * nh) * csz;
-    hipError_t e = ensure_lds(k_plane_fwd<T>, lds_plane);
-    if (e != hipSuccess) return e;
-    e = ensure_lds(k_plane_inv<T>, lds_plane);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, P), dim3(256), lds_plane, s, n, logn,
-                       (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    switch (a.p) {
-        case 0: e = column_launch<0, T>(a, s); break;
-        case 1: e = column_launch<1, T>(a, s); break;
-        case 2: e = column_launch<2, T>(a, s); break;
-        case 3: e = column_launch<3, T>(a, s); break;
-        case 4: e = column_launch<4, T>(a, s); break;
-        case 5: e = column_launch<5, T>(a, s); break;
-        case 6: e = column_launch<6, T>(a, s); break;
-        case 7: e = column_launch<7, T>(a, s); break;
-        case 8: e = column_launch<8, T>(a, s); break;
-        default: return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if (stage == 0) {
+        e = ensure_lds(k_plane_fwd<T>, lds_plane);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, P), dim3(256), lds_plane, s, n, logn,
+                           (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
+                           a.open ? nullptr : a.qr2_partial);
+        return hipGetLastError();
     }
+    if (stage == 1) {
+        switch (a.p) {
+            case 0: return column_launch<0, T>(a, s);
+            case 1: return column_launch<1, T>(a, s);
+            case 2: return column_launch<2, T>(a, s);
+            case 3: return column_launch<3, T>(a, s);
+            case 4: return column_launch<4, T>(a, s);
+            case 5: return column_launch<5, T>(a, s);
+            case 6: return column_launch<6, T>(a, s);
+            case 7: return column_launch<7, T>(a, s);
+            case 8: return column_launch<8, T>(a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    e = ensure_lds(k_plane_inv<T>, lds_plane);
     if (e != hipSuccess) return e;
     const T scale = T(1.0 / ((double)nf * nf * nf));
     hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P), dim3(256), lds_plane, s, n, logn,
@@ -369,7 +569,7 @@ hipError_t launch_convolution(const FFTArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template hipError_t launch_convolution<float>(const FFTArgs &, hipStream_t);
-template hipError_t launch_convolution<double>(const FFTArgs &, hipStream_t);
+template hipError_t launch_conv_stage<float>(const FFTArgs &, int, hipStream_t);
+template hipError_t launch_conv_stage<double>(const FFTArgs &, int, hipStream_t);
 
 }  // namespace pmmm

@@ -12,8 +12,8 @@
 //                     left out; for 0 < max|offset| <= c the image covered by
 //                     the near field, S(offset), is subtracted (App. B).
 //   k_line_fft        FP64 complex FFT of mesh lines (LDS, radix 2)
-//   k_fold            keeps Re G~ (even order) or Im G~ (odd order), rounds
-//                     to the plan precision, layout [col = ky*(nf/2+1)+kx][Q][kz]
+//   k_fold            keeps Re G~ (even order) or Im G~ (odd order) on the
+//                     quadrant ky, kz <= nf/2, rounded to the plan precision
 // Singular harmonics use the order recursion (derived from App. A.5 with
 // S_l^m = (-1)^(l+m) (l-m)! Q_l^m / r^(2l+1)):
 //   S_m^m = -(2m-1) (x+iy)/r^2 S_{m-1}^{m-1},  S_{m+1}^m = -(2m+1) z/r^2 S_m^m,
@@ -230,22 +230,33 @@ __global__ void __launch_bounds__(64) k_line_fft(cplx<double> *__restrict__ data
     }
 }
 
+// Keeps Re G~ (even order) or Im G~ (odd order) for ky, kz in [0, nf/2]
+// (the other quadrants follow from the y and z reflection symmetries of
+// S_n^k), layout [ky' * nh + kx][Q][nhp] with nh = nf/2 + 1 and nhp = nh
+// rounded up to 4 (padding zero).  self_shift is added to component 0 at
+// every frequency: a kernel weight at offset zero, i.e. the self term
+// -(2 alpha/sqrt(pi)) M_0^0(cell) of the periodic correction procedure
+// (App. B) applied inside the convolution.
 template <typename T>
 __global__ void k_fold(int nf, int Q, int j0, int jcount, const cplx<double> *__restrict__ Gc,
-                       T *__restrict__ out) {
-    const int nh = nf / 2 + 1;
-    const int64_t total = (int64_t)nf * nh * jcount * nf;
+                       double self_shift, T *__restrict__ out) {
+    const int nh = nf / 2 + 1, nhp = (nh + 3) & ~3;
+    const int64_t total = (int64_t)nh * nh * jcount * nhp;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const int kz = (int)(i % nf);
-    const int jl = (int)((i / nf) % jcount);
-    const int64_t col = i / ((int64_t)nf * jcount);
-    const int ky = (int)(col / nh), kx = (int)(col % nh);
+    const int kz = (int)(i % nhp);
+    const int jl = (int)((i / nhp) % jcount);
+    const int64_t colr = i / ((int64_t)nhp * jcount);
+    const int ky = (int)(colr / nh), kx = (int)(colr % nh);
     const int j = j0 + jl;
     int order = 0;
     while ((order + 1) * (order + 1) <= j) ++order;
-    const cplx<double> v = Gc[(((int64_t)jl * nf + kz) * nf + ky) * nf + kx];
-    out[(col * Q + j) * nf + kz] = T((order & 1) ? v.im : v.re);
+    double g = 0.0;
+    if (kz < nh) {
+        const cplx<double> v = Gc[(((int64_t)jl * nf + kz) * nf + ky) * nf + kx];
+        g = (order & 1) ? v.im : v.re + (j == 0 ? self_shift : 0.0);
+    }
+    out[(colr * Q + j) * nhp + kz] = T(g);
 }
 
 static int ilog2i(int v) {
@@ -322,9 +333,11 @@ hipError_t build_green(const GreenArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(k_line_fft, dim3((unsigned)((nlines + lpb - 1) / lpb)), dim3(64),
                                lds, s, Gc, logn, nlines, stride, lpb, tw);
         }
-        const int64_t tot = (int64_t)nf * (nf / 2 + 1) * jc * nf;
+        const int nhp = ((nf / 2 + 1) + 3) & ~3;
+        const int64_t tot = (int64_t)(nf / 2 + 1) * (nf / 2 + 1) * jc * nhp;
+        const double shift = a.open ? 0.0 : -2.0 * a.alpha_cell / std::sqrt(M_PI);
         hipLaunchKernelGGL(k_fold<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nf, Q,
-                           j0, jc, Gc, (T *)a.green_out);
+                           j0, jc, Gc, shift, (T *)a.green_out);
         e = hipGetLastError();
     }
     hipError_t e2 = hipStreamSynchronize(s);

@@ -85,6 +85,48 @@ __device__ __forceinline__ void regular_harmonics(T x, T y, T z, T *R) {
     }
 }
 
+// acc[c] += q * R_c(x, y, z) for the real-storage components c of orders
+// <= P_ORD, with the same recursion as regular_harmonics; each value is
+// consumed as soon as it is produced, so no R array stays live.
+template <int P_ORD, typename T>
+__device__ __forceinline__ void accumulate_regular(T x, T y, T z, T q, T *acc) {
+    const T r2 = x * x + y * y + z * z;
+    T cre = q, cim = T(0);  // q R_m^m
+#pragma unroll
+    for (int m = 0; m <= P_ORD; ++m) {
+        if (m > 0) {
+            const T f = T(-1.0 / (2.0 * m));
+            const T nre = f * (x * cre - y * cim);
+            const T nim = f * (x * cim + y * cre);
+            cre = nre;
+            cim = nim;
+        }
+        acc[ridx(m, m)] += cre;
+        if (m > 0) acc[ridx(m, -m)] += cim;
+        T pre = cre, pim = cim;
+        T ure = T(0), uim = T(0);
+        if (m + 1 <= P_ORD) {
+            ure = z * cre;
+            uim = z * cim;
+            acc[ridx(m + 1, m)] += ure;
+            if (m > 0) acc[ridx(m + 1, -m)] += uim;
+        }
+#pragma unroll
+        for (int l = m + 2; l <= P_ORD; ++l) {
+            const T a = T((2.0 * l - 1.0) / ((double)(l - m) * (double)(l + m)));
+            const T b = T(1.0 / ((double)(l - m) * (double)(l + m)));
+            const T nre = a * z * ure - b * r2 * pre;
+            const T nim = a * z * uim - b * r2 * pim;
+            acc[ridx(l, m)] += nre;
+            if (m > 0) acc[ridx(l, -m)] += nim;
+            pre = ure;
+            pim = uim;
+            ure = nre;
+            uim = nim;
+        }
+    }
+}
+
 // --------------------------------------------------------- LDS radix-2 FFT
 // `nlines` transforms of length N = 2^logn stored in LDS; element e of line
 // t lives at buf[t * lstride + e * estride].  tw[k] = exp(-2 pi i k / N)
@@ -151,6 +193,27 @@ __device__ void lds_fft_dit(cplx<T> *buf, int logn, int nlines, int lstride, int
 // ------------------------------------------------------------ host side
 struct Plan;  // defined in pmmm_api.hip
 
+// Shape of the column kernel: w columns of nf frequencies per block and rs
+// row subsets (rs * w * nf <= 256 threads); LDS holds moment and local
+// spectra [P][w][nf] and the kernel tile [Q][w][nhp].  Returns the LDS
+// bytes, or 0 if no shape fits the 160 KB of one CU.
+inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out) {
+    const size_t P = (size_t)(p + 1) * (p + 1), Q = (size_t)(2 * p + 1) * (2 * p + 1);
+    const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
+    int w = nf >= 64 ? 1 : 64 / nf;
+    for (;;) {
+        const size_t lds = 2 * P * w * nf * 2 * tsize + Q * w * nhp * tsize + (size_t)nf / 2 * 2 * tsize;
+        if (lds <= 160 * 1024) {
+            const int rs = 256 / (w * nf) < 4 ? 256 / (w * nf) : 4;
+            if (w_out) *w_out = w;
+            if (rs_out) *rs_out = rs;
+            return lds;
+        }
+        if (w == 1) return 0;
+        w >>= 1;
+    }
+}
+
 // Error bookkeeping (thread-local message).
 void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
@@ -178,6 +241,7 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s);
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path
+    int may_have_dense;             // n exceeds the dense threshold: launch the dense path
     const int *start, *dense_cells, *dense_count;
     int dense_threshold;
     const void *sorted;
@@ -186,25 +250,19 @@ struct P2MArgs {
 template <typename T>
 hipError_t launch_p2m(const P2MArgs &a, hipStream_t s);
 
-struct SumArgs {
-    int ncell;
-    const void *M;                  // [P + 1][K]
-    int p;
-    double *sums;                   // [0]=sum M0, [1..3]=sum M[1..3], [4]=sum q|u|^2
-};
-template <typename T>
-hipError_t launch_pbc_sums(const SumArgs &a, hipStream_t s);
-
 struct FFTArgs {
     int p, n, nf, open;
+    double *qr2_partial;            // [n] per-plane sums of q|u|^2 (periodic)
+    double *sums;                   // [0] = total charge (periodic, for L2P)
     const void *M;                  // [P(+1)][n^3] real mesh
     void *spec;                     // [P][n][nf][nf/2+1] complex
     const void *green;              // [nf*(nf/2+1)][Q][nf]
     const void *tw;                 // cplx<T>[nf/2]
     void *L;                        // [P][n^3]
 };
+// stage 0: forward plane FFTs, 1: column FFT + M2L + inverse, 2: inverse planes
 template <typename T>
-hipError_t launch_convolution(const FFTArgs &a, hipStream_t s);
+hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s);
 
 struct L2PArgs {
     int64_t n;
@@ -212,8 +270,7 @@ struct L2PArgs {
     const void *sorted;
     const int *scell, *perm;
     const void *L;                  // [P][K]
-    const void *M;                  // [P + 1][K] (self term)
-    const double *sums;
+    const double *sums;             // [0] = total charge
     double alpha_cell;              // alpha h
     double inv_h;                   // 1 / h in the caller's length unit
     void *phi, *gx, *gy, *gz;

@@ -5,12 +5,11 @@
 //              particles and reduces with cross-lane shuffles.  Dense cells
 //              (more than the dense threshold): one workgroup per cell with
 //              FP64 accumulation and a fixed-order block reduction.
-//   k_pbc_sums FP64 sums over all cells of M_0^0, the three order-1 moments
-//              and sum q|r_rel|^2 (App. B, correction procedure).
 //   k_l2p      eq. L2P for Phi; eq. L2L to destination order one and
-//              eq. phigrad for grad Phi; periodic corrections of App. B
-//              (dipole, self term, r^2 term, charged-system terms); results
-//              rescaled to the caller's units and scattered to input order.
+//              eq. phigrad for grad Phi; the per-particle terms of a charged
+//              periodic system (App. B, correction procedure; the uniform
+//              corrections are already in L); results rescaled to the
+//              caller's units and scattered to input order.
 #include "pmmm_internal.h"
 
 namespace pmmm {
@@ -20,51 +19,52 @@ constexpr int kDenseBlocks = 128;
 template <int PO, typename T, int G>
 __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ start,
                                              const particle4<T> *__restrict__ sorted,
-                                             int dense_thr, const int *__restrict__ dense_cells,
-                                             const int *__restrict__ dense_count,
-                                             int nlight_blocks, T *__restrict__ M) {
+                                             int dense_thr, T *__restrict__ M) {
     constexpr int P = nreal(PO);
-    if ((int)blockIdx.x < nlight_blocks) {
-        const int gid = blockIdx.x * 256 + threadIdx.x;
-        const int cell = gid / G;
-        const int lane = gid & (G - 1);
-        int s0 = 0, s1 = 0;
-        bool write = false;
-        if (cell < K) {
-            s0 = start[cell];
-            s1 = start[cell + 1];
-            write = (s1 - s0) <= dense_thr;
-            if (!write) s1 = s0;
-        }
-        T acc[P + 1];
-#pragma unroll
-        for (int c = 0; c <= P; ++c) acc[c] = T(0);
-        for (int s = s0 + lane; s < s1; s += G) {
-            const particle4<T> r = sorted[s];
-            T R[P];
-            regular_harmonics<PO, T>(-r.ux, -r.uy, -r.uz, R);  // R(r_M - r_i)
-#pragma unroll
-            for (int c = 0; c < P; ++c) acc[c] += r.q * R[c];
-            acc[P] += r.q * (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
-        }
-#pragma unroll
-        for (int off = G / 2; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-        }
-        if (write) {
-#pragma unroll
-            for (int c = 0; c <= P; ++c)
-                if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
-        }
-        return;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int cell = gid / G;
+    const int lane = gid & (G - 1);
+    int s0 = 0, s1 = 0;
+    bool write = false;
+    if (cell < K) {
+        s0 = start[cell];
+        s1 = start[cell + 1];
+        write = (s1 - s0) <= dense_thr;
+        if (!write) s1 = s0;
     }
-    // dense cells
+    T acc[P + 1];
+#pragma unroll
+    for (int c = 0; c <= P; ++c) acc[c] = T(0);
+    for (int s = s0 + lane; s < s1; s += G) {
+        const particle4<T> r = sorted[s];
+        accumulate_regular<PO, T>(-r.ux, -r.uy, -r.uz, r.q, acc);  // q R(r_M - r_i)
+        acc[P] += r.q * (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    if (write) {
+#pragma unroll
+        for (int c = 0; c <= P; ++c)
+            if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
+    }
+}
+
+// Dense cells: one workgroup per listed cell, FP64 accumulation and a
+// fixed-order reduction (waves in order).
+template <int PO, typename T>
+__global__ void __launch_bounds__(256) k_p2m_dense(int K, const int *__restrict__ start,
+                                                   const particle4<T> *__restrict__ sorted,
+                                                   const int *__restrict__ dense_cells,
+                                                   const int *__restrict__ dense_count,
+                                                   T *__restrict__ M) {
+    constexpr int P = nreal(PO);
     __shared__ double red[4][P + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nd = *dense_count;
-    const int nblk = gridDim.x - nlight_blocks;
-    for (int d = blockIdx.x - nlight_blocks; d < nd; d += nblk) {
+    for (int d = blockIdx.x; d < nd; d += gridDim.x) {
         const int cell = dense_cells[d];
         const int s0 = start[cell], s1 = start[cell + 1];
         double acc[P + 1];
@@ -72,10 +72,8 @@ __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ star
         for (int c = 0; c <= P; ++c) acc[c] = 0.0;
         for (int s = s0 + tid; s < s1; s += 256) {
             const particle4<T> r = sorted[s];
-            T R[P];
-            regular_harmonics<PO, T>(-r.ux, -r.uy, -r.uz, R);
-#pragma unroll
-            for (int c = 0; c < P; ++c) acc[c] += (double)r.q * (double)R[c];
+            accumulate_regular<PO, double>(-(double)r.ux, -(double)r.uy, -(double)r.uz,
+                                           (double)r.q, acc);
             acc[P] += (double)r.q * ((double)r.ux * r.ux + (double)r.uy * r.uy +
                                      (double)r.uz * r.uz);
         }
@@ -95,41 +93,12 @@ __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ star
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_pbc_sums(int K, int P, const T *__restrict__ M,
-                                                   double *__restrict__ sums) {
-    __shared__ double red[16][5];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    double a[5] = {0, 0, 0, 0, 0};
-    const int comp[5] = {0, 1, 2, 3, P};
-    for (int i = tid; i < K; i += 1024) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-            if (j == 0 || j == 4 || P > 1) a[j] += (double)M[(int64_t)comp[j] * K + i];
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j) a[j] += __shfl_xor(a[j], off, 64);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j) red[wid][j] = a[j];
-    }
-    __syncthreads();
-    if (tid < 5) {
-        double s = 0;
-        for (int w = 0; w < 16; ++w) s += red[w][tid];
-        sums[tid] = s;
-    }
-}
-
 template <int PO, typename T>
 __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
                                              const particle4<T> *__restrict__ sorted,
                                              const int *__restrict__ scell,
                                              const int *__restrict__ perm,
-                                             const T *__restrict__ L, const T *__restrict__ M,
+                                             const T *__restrict__ L,
                                              const double *__restrict__ sums, T alpha_c,
                                              T inv_h, T *__restrict__ phi_out,
                                              T *__restrict__ gx_out, T *__restrict__ gy_out,
@@ -142,18 +111,9 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
     T Lc[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) Lc[a] = L[(int64_t)a * K + c];
-    T qtot_term = T(0);
-    if (periodic) {
-        const double V = (double)K;  // box volume in cell units
-        const double pi = 3.14159265358979323846;
-        Lc[0] += T(-2.0 * (double)alpha_c / sqrt(pi)) * M[c] + T(2.0 * pi / (3.0 * V) * sums[4]);
-        if (P > 1) {
-            Lc[ridx(1, 0)] += T(4.0 * pi / (3.0 * V) * sums[2]);
-            Lc[ridx(1, 1)] += T(8.0 * pi / (3.0 * V) * sums[3]);
-            Lc[ridx(1, -1)] -= T(8.0 * pi / (3.0 * V) * sums[1]);
-        }
-        qtot_term = T(sums[0] * pi / (3.0 * V));  // Q_tot pi / (3V)
-    }
+    // charged periodic system: Phi += 2 pi/(3V) Q (|u|^2 - 3/(2 alpha^2)),
+    // grad += 4 pi/(3V) Q u, with V = K in cell units
+    const T qtot_term = periodic ? T(sums[0] * 3.14159265358979323846 / (3.0 * (double)K)) : T(0);
     T R[P];
     regular_harmonics<PO, T>(r.ux, r.uy, r.uz, R);
     // Phi = sum_l [L_l^0 R_l^0 + 2 sum_{m>0} Re(L_l^m R_l^m)]
@@ -215,14 +175,13 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const int G = a.group;
     const int nlight = (int)(((int64_t)K * G + 255) / 256);
-    const int grid = nlight + kDenseBlocks;
     const int *st = a.start;
     const particle4<T> *so = (const particle4<T> *)a.sorted;
     T *M = (T *)a.M;
-#define PMMM_P2M_G(GG)                                                                    \
-    case GG:                                                                              \
-        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(grid), dim3(256), 0, s, K, st, so,     \
-                           a.dense_threshold, a.dense_cells, a.dense_count, nlight, M);    \
+#define PMMM_P2M_G(GG)                                                                     \
+    case GG:                                                                               \
+        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(nlight), dim3(256), 0, s, K, st, so,    \
+                           a.dense_threshold, M);                                          \
         break;
     switch (G) {
         PMMM_P2M_G(4)
@@ -234,6 +193,10 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
             return hipErrorInvalidValue;
     }
 #undef PMMM_P2M_G
+    if (a.may_have_dense) {
+        hipLaunchKernelGGL((k_p2m_dense<PO, T>), dim3(kDenseBlocks), dim3(256), 0, s, K, st, so,
+                           a.dense_cells, a.dense_count, M);
+    }
     return hipGetLastError();
 }
 
@@ -253,21 +216,13 @@ hipError_t launch_p2m(const P2MArgs &a, hipStream_t s) {
     }
 }
 
-template <typename T>
-hipError_t launch_pbc_sums(const SumArgs &a, hipStream_t s) {
-    const int K = a.ncell * a.ncell * a.ncell;
-    hipLaunchKernelGGL(k_pbc_sums<T>, dim3(1), dim3(1024), 0, s, K, nreal(a.p),
-                       (const T *)a.M, a.sums);
-    return hipGetLastError();
-}
-
 template <int PO, typename T>
 static hipError_t l2p_launch(const L2PArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const int blocks = (int)((a.n + 255) / 256);
     hipLaunchKernelGGL((k_l2p<PO, T>), dim3(blocks), dim3(256), 0, s, a.n, K, a.periodic,
                        (const particle4<T> *)a.sorted, a.scell, a.perm, (const T *)a.L,
-                       (const T *)a.M, a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
+                       a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
                        (T *)a.gx, (T *)a.gy, (T *)a.gz);
     return hipGetLastError();
 }
@@ -291,8 +246,6 @@ hipError_t launch_l2p(const L2PArgs &a, hipStream_t s) {
 
 template hipError_t launch_p2m<float>(const P2MArgs &, hipStream_t);
 template hipError_t launch_p2m<double>(const P2MArgs &, hipStream_t);
-template hipError_t launch_pbc_sums<float>(const SumArgs &, hipStream_t);
-template hipError_t launch_pbc_sums<double>(const SumArgs &, hipStream_t);
 template hipError_t launch_l2p<float>(const L2PArgs &, hipStream_t);
 template hipError_t launch_l2p<double>(const L2PArgs &, hipStream_t);
 

@@ -46,7 +46,8 @@ def cell_unit_mesh(mesh, cfg, kind):
 
 def folded_green(cfg):
     """Oracle transfer-kernel spectra in cell units, folded like the library:
-    [ky, kx, Q, kz] holding Re (even order) or Im (odd order)."""
+    [ky, kx, Q, kz] on ky, kz <= nf/2, holding Re (even order) or Im (odd
+    order)."""
     Gt = opm.spectra(opm.green(cfg))        # [Q, kz, ky, kx] physical units
     p2 = 2 * cfg.p
     Q = nreal(p2)
@@ -56,4 +57,10 @@ def folded_green(cfg):
         for j in range(k * k, (k + 1) * (k + 1)):
             v = Gt[j].imag if k % 2 else Gt[j].real
             out[:, :, j, :] = np.transpose(v, (1, 2, 0)) * scale
+    nh = Gt.shape[1] // 2 + 1
+    out = out[:nh, :, :, :nh]
+    if cfg.boundary == "periodic":
+        # the library folds the self term -(2 alpha/sqrt(pi)) M_0^0 of the
+        # correction procedure into component 0 (cell units: alpha h)
+        out[:, :, 0, :] += -2.0 * cfg.a * cfg.h / np.sqrt(np.pi)
     return out

@@ -1,0 +1,60 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every
+function include/pmmm.h declares, and validates parameters on the host
+(pmmm_workspace_bytes makes no GPU call)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1409_5981_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1409_5981_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "pmmm.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmmm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1409_5981_amd import _lib
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_parameter_validation_on_host(lib):
+    from paper_1409_5981_amd._lib import make_params, workspace_bytes
+    ok = make_params(16, 5, "periodic")
+    assert workspace_bytes(ok, 32768) > 0
+    assert workspace_bytes(make_params(16, 5, "periodic", cutoff=3), 10) == 0      # bad cutoff
+    assert workspace_bytes(make_params(4, 3, "periodic", cutoff=2), 10) == 0       # n < 2c+1
+    assert workspace_bytes(make_params(8, 9, "open"), 10) == 0                     # p > PMAX
+    assert workspace_bytes(make_params(12, 3, "periodic"), 10) == 0                # not 2^k
+    assert workspace_bytes(make_params(128, 3, "open"), 10) == 0                   # nf > 128
+    assert workspace_bytes(make_params(64, 3, "open", precision="f64"), 10) == 0   # nf > 64 (FP64)
+    prm = make_params(8, 3, "open")
+    prm.box[1] = 2.0                                                              # non-cubic cells
+    assert workspace_bytes(prm, 10) == 0
+
+
+def test_workspace_grows_with_particles(lib):
+    from paper_1409_5981_amd._lib import make_params, workspace_bytes
+    prm = make_params(32, 7, "periodic")
+    assert workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0) == (1 << 20) * 32
+
+
+def test_error_strings(lib):
+    for code in range(6):
+        assert lib.pmmm_error_string(code).startswith(b"PMMM_")
