@@ -148,6 +148,10 @@ def main():
     plan = Plan(n, p, boundary, cutoff=2, precision=prec, n_max=N)
     tdt = torch.float32 if prec == "f32" else torch.float64
     out = tuple(torch.empty(N, dtype=tdt, device=dev) for _ in range(4))
+    # a dedicated stream (the legacy default stream adds implicit synchronisation)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(stream)
 
     # warm-up; the second half also times every stage to pick the dominant kernel
     half = max(1, args.warmup // 2)

@@ -345,6 +345,8 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         m.ncell = pl->n;
         m.group = group_for((double)n / (double)pl->K);
         m.may_have_dense = n > kDenseThreshold;
+        // meshes scanned inside the scatter kernel reset their counts here
+        m.zero_count = (n > 0 && pl->K <= 4096) ? pl->count : nullptr;
         m.start = pl->start;
         m.dense_cells = pl->dense_cells;
         m.dense_count = pl->small;

@@ -4,6 +4,8 @@
 //                 particle's slot inside its cell
 //   k_bin_scan    exclusive scan of the counts -> cell_start, resets the counts
 //                 for the next call, lists cells above the dense threshold
+//                 (meshes up to 16^3 skip it: each scatter block scans the
+//                 counts itself and the P2M kernel resets them)
 //   k_bin_scatter sorted structure-of-arrays record (offset from the cell
 //                 centre in cell units, charge), permutation and cell of each
 //                 sorted slot
@@ -104,12 +106,71 @@ __global__ void __launch_bounds__(1024) k_bin_scan(int K, int *__restrict__ coun
     }
 }
 
+// Exclusive scan of K <= kInBlockScanMax counts by one 256-thread block into
+// LDS (s_start[0..K]); block 0 also publishes start[] and the dense list.
+constexpr int kInBlockScanMax = 4096;
+
+__device__ void block_scan_small(int K, const int *__restrict__ count, int *s_start,
+                                 int publish, int *__restrict__ start, int dense_thr,
+                                 int *__restrict__ dense_cells, int *__restrict__ dense_count) {
+    __shared__ int wtot[4];
+    __shared__ int ndense;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int PER = kInBlockScanMax / 256;  // 16 counts per thread
+    int v[PER], tot = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = tid * PER + j;
+        v[j] = idx < K ? count[idx] : 0;
+        tot += v[j];
+    }
+    int inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) wtot[wid] = inc;
+    if (tid == 0) ndense = 0;
+    __syncthreads();
+    int run = inc - tot;
+    for (int w = 0; w < wid; ++w) run += wtot[w];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = tid * PER + j;
+        if (idx < K) {
+            s_start[idx] = run;
+            if (publish) {
+                start[idx] = run;
+                if (v[j] > dense_thr) dense_cells[atomicAdd(&ndense, 1)] = idx;
+            }
+        }
+        run += v[j];
+    }
+    if (tid == 255) {
+        s_start[K] = run;
+        if (publish) start[K] = run;
+    }
+    __syncthreads();
+    if (publish && tid == 0) *dense_count = ndense;
+}
+
+// Scatter into the sorted structure-of-arrays record.  With inblock, every
+// block scans the counts itself (small meshes), else start[] comes from the
+// scan kernel.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_scatter(
     int64_t n, const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
     const T *__restrict__ q, T inv_h, int nc, int periodic, const int *__restrict__ cell_of,
-    const int *__restrict__ slot, const int *__restrict__ start, int *__restrict__ perm,
-    int *__restrict__ scell, particle4<T> *__restrict__ sorted) {
+    const int *__restrict__ slot, int *__restrict__ start, int *__restrict__ perm,
+    int *__restrict__ scell, particle4<T> *__restrict__ sorted, int inblock,
+    const int *__restrict__ count, int dense_thr, int *__restrict__ dense_cells,
+    int *__restrict__ dense_count) {
+    __shared__ int s_start[kInBlockScanMax + 1];
+    const int K = nc * nc * nc;
+    if (inblock)
+        block_scan_small(K, count, s_start, blockIdx.x == 0, start, dense_thr, dense_cells,
+                         dense_count);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int ix, iy, iz, out = 0;
@@ -119,7 +180,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     cell_coord(z[i], inv_h, nc, periodic, iz, r.uz, out);
     r.q = q[i];
     const int c = cell_of[i];
-    const int s = start[c] + slot[i];
+    const int s = (inblock ? s_start[c] : start[c]) + slot[i];
     if (s < 0 || (int64_t)s >= n) return;  // only reachable with inconsistent counts
     perm[s] = (int)i;
     scell[s] = c;
@@ -131,18 +192,22 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const T inv_h = T(a.inv_h);
     const int blocks = (int)((a.n + 255) / 256);
+    const int inblock = K <= kInBlockScanMax ? 1 : 0;
     if (a.n > 0) {
         hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks), dim3(256), 0, s, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
                            a.periodic, a.cell_of, a.slot, a.count, a.flag);
     }
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, K, a.count, a.start,
-                       a.dense_threshold, a.dense_cells, a.dense_count);
+    if (!inblock || a.n == 0) {
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, K, a.count, a.start,
+                           a.dense_threshold, a.dense_cells, a.dense_count);
+    }
     if (a.n > 0) {
         hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks), dim3(256), 0, s, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, (const T *)a.q,
                            inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, a.perm,
-                           a.scell, (particle4<T> *)a.sorted);
+                           a.scell, (particle4<T> *)a.sorted, inblock, a.count,
+                           a.dense_threshold, a.dense_cells, a.dense_count);
     }
     return hipGetLastError();
 }

@@ -241,7 +241,8 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s);
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path
-    int may_have_dense;             // n exceeds the dense threshold: launch the dense path
+    int may_have_dense;             // n exceeds the dense threshold: add the dense blocks
+    int *zero_count;                // counts to reset for the next binning (or null)
     const int *start, *dense_cells, *dense_count;
     int dense_threshold;
     const void *sorted;

@@ -3,8 +3,9 @@
 //              per-cell sum q |r_rel|^2 used by the periodic correction.
 //              Light cells: a group of G lanes strides over the cell's sorted
 //              particles and reduces with cross-lane shuffles.  Dense cells
-//              (more than the dense threshold): one workgroup per cell with
-//              FP64 accumulation and a fixed-order block reduction.
+//              (more than the dense threshold): extra workgroups of the same
+//              launch, one per cell, with FP64 accumulation and a fixed-order
+//              block reduction.
 //   k_l2p      eq. L2P for Phi; eq. L2L to destination order one and
 //              eq. phigrad for grad Phi; the per-particle terms of a charged
 //              periodic system (App. B, correction procedure; the uniform
@@ -16,55 +17,55 @@ namespace pmmm {
 
 constexpr int kDenseBlocks = 128;
 
+// Blocks [0, nlight) run the light path (G lanes per cell); the remaining
+// kDenseBlocks handle the listed dense cells, one workgroup per cell with
+// FP64 accumulation and a fixed-order reduction.  zero_count (when not
+// null) is reset for the next binning.
 template <int PO, typename T, int G>
 __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ start,
                                              const particle4<T> *__restrict__ sorted,
-                                             int dense_thr, T *__restrict__ M) {
+                                             int dense_thr, const int *__restrict__ dense_cells,
+                                             const int *__restrict__ dense_count, int nlight,
+                                             T *__restrict__ M, int *__restrict__ zero_count) {
     constexpr int P = nreal(PO);
-    const int gid = blockIdx.x * 256 + threadIdx.x;
-    const int cell = gid / G;
-    const int lane = gid & (G - 1);
-    int s0 = 0, s1 = 0;
-    bool write = false;
-    if (cell < K) {
-        s0 = start[cell];
-        s1 = start[cell + 1];
-        write = (s1 - s0) <= dense_thr;
-        if (!write) s1 = s0;
-    }
-    T acc[P + 1];
+    if ((int)blockIdx.x < nlight) {
+        const int gid = blockIdx.x * 256 + threadIdx.x;
+        if (zero_count != nullptr && gid < K) zero_count[gid] = 0;
+        const int cell = gid / G;
+        const int lane = gid & (G - 1);
+        int s0 = 0, s1 = 0;
+        bool write = false;
+        if (cell < K) {
+            s0 = start[cell];
+            s1 = start[cell + 1];
+            write = (s1 - s0) <= dense_thr;
+            if (!write) s1 = s0;
+        }
+        T acc[P + 1];
 #pragma unroll
-    for (int c = 0; c <= P; ++c) acc[c] = T(0);
-    for (int s = s0 + lane; s < s1; s += G) {
-        const particle4<T> r = sorted[s];
-        accumulate_regular<PO, T>(-r.ux, -r.uy, -r.uz, r.q, acc);  // q R(r_M - r_i)
-        acc[P] += r.q * (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
-    }
+        for (int c = 0; c <= P; ++c) acc[c] = T(0);
+        for (int s = s0 + lane; s < s1; s += G) {
+            const particle4<T> r = sorted[s];
+            accumulate_regular<PO, T>(-r.ux, -r.uy, -r.uz, r.q, acc);  // q R(r_M - r_i)
+            acc[P] += r.q * (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
+        }
 #pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) {
+        for (int off = G / 2; off >= 1; off >>= 1) {
 #pragma unroll
-        for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-    }
-    if (write) {
+            for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+        }
+        if (write) {
 #pragma unroll
-        for (int c = 0; c <= P; ++c)
-            if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
+            for (int c = 0; c <= P; ++c)
+                if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
+        }
+        return;
     }
-}
-
-// Dense cells: one workgroup per listed cell, FP64 accumulation and a
-// fixed-order reduction (waves in order).
-template <int PO, typename T>
-__global__ void __launch_bounds__(256) k_p2m_dense(int K, const int *__restrict__ start,
-                                                   const particle4<T> *__restrict__ sorted,
-                                                   const int *__restrict__ dense_cells,
-                                                   const int *__restrict__ dense_count,
-                                                   T *__restrict__ M) {
-    constexpr int P = nreal(PO);
     __shared__ double red[4][P + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nd = *dense_count;
-    for (int d = blockIdx.x; d < nd; d += gridDim.x) {
+    const int nblk = gridDim.x - nlight;
+    for (int d = blockIdx.x - nlight; d < nd; d += nblk) {
         const int cell = dense_cells[d];
         const int s0 = start[cell], s1 = start[cell + 1];
         double acc[P + 1];
@@ -174,14 +175,17 @@ template <int PO, typename T>
 static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const int G = a.group;
-    const int nlight = (int)(((int64_t)K * G + 255) / 256);
+    int nlight = (int)(((int64_t)K * G + 255) / 256);
+    if (a.zero_count && nlight * 256 < K) nlight = (K + 255) / 256;
+    const int grid = nlight + (a.may_have_dense ? kDenseBlocks : 0);
     const int *st = a.start;
     const particle4<T> *so = (const particle4<T> *)a.sorted;
     T *M = (T *)a.M;
 #define PMMM_P2M_G(GG)                                                                     \
     case GG:                                                                               \
-        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(nlight), dim3(256), 0, s, K, st, so,    \
-                           a.dense_threshold, M);                                          \
+        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(grid), dim3(256), 0, s, K, st, so,      \
+                           a.dense_threshold, a.dense_cells, a.dense_count, nlight, M,      \
+                           a.zero_count);                                                  \
         break;
     switch (G) {
         PMMM_P2M_G(4)
@@ -193,10 +197,6 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
             return hipErrorInvalidValue;
     }
 #undef PMMM_P2M_G
-    if (a.may_have_dense) {
-        hipLaunchKernelGGL((k_p2m_dense<PO, T>), dim3(kDenseBlocks), dim3(256), 0, s, K, st, so,
-                           a.dense_cells, a.dense_count, M);
-    }
     return hipGetLastError();
 }
 
