@@ -26,6 +26,8 @@
 // s = -1 when l and lam are both odd, the moments are pre-multiplied by
 // i^(lam mod 2), accumulated with real coefficients, and the outputs of odd
 // order l are post-multiplied by i.
+#include <type_traits>
+
 #include "pmmm_internal.h"
 
 namespace pmmm {
@@ -41,10 +43,10 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
                                                    const cplx<T> *__restrict__ tw_g,
                                                    int P, double *__restrict__ qr2_partial) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn, nh = nf / 2 + 1, npair = nin / 2;
+    const int nf = 1 << logn, nh = nf / 2 + 1, npair = nin / 2, ls = lds_line(nf);
     cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *buf1 = tw + nf / 2;           // [npair][nf]
-    cplx<T> *buf2 = buf1 + npair * nf;     // [nf][nh]
+    cplx<T> *buf1 = tw + nf / 2;           // [npair][ls] row pairs
+    cplx<T> *buf2 = buf1 + npair * ls;     // [nf][nh]
     const int z = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
@@ -66,18 +68,18 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * nthr;
-            if (idx < npair * nf) buf1[idx] = v[u];
+            if (idx < npair * nf) buf1[(idx >> logn) * ls + (idx & (nf - 1))] = v[u];
         }
     }
     __syncthreads();
-    lds_fft_dif<T, false>(buf1, logn, npair, nf, 1, tw, tid, nthr);
+    fft_lines<T, false>(buf1, logn, npair, ls, 1, tw, tid, nthr);
     for (int idx = tid; idx < nf * nh; idx += nthr) {
         const int y = idx / nh, k = idx - y * nh;
         cplx<T> v = {T(0), T(0)};
         if (y < nin) {
-            const cplx<T> *row = buf1 + (y >> 1) * nf;
-            const cplx<T> zk = row[bitrev(k & (nf - 1), logn)];
-            const cplx<T> zm = row[bitrev((nf - k) & (nf - 1), logn)];
+            const cplx<T> *row = buf1 + (y >> 1) * ls;
+            const cplx<T> zk = row[k & (nf - 1)];
+            const cplx<T> zm = row[(nf - k) & (nf - 1)];
             if ((y & 1) == 0) {
                 v.re = T(0.5) * (zk.re + zm.re);
                 v.im = T(0.5) * (zk.im - zm.im);
@@ -89,12 +91,9 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
         buf2[idx] = v;
     }
     __syncthreads();
-    lds_fft_dif<T, false>(buf2, logn, nh, 1, nh, tw, tid, nthr);
+    fft_lines<T, false>(buf2, logn, nh, 1, nh, tw, tid, nthr);
     cplx<T> *out = spec + ((int64_t)c * nin + z) * nf * nh;
-    for (int idx = tid; idx < nf * nh; idx += nthr) {
-        const int pos = idx / nh, k = idx - pos * nh;
-        out[bitrev(pos, logn) * nh + k] = buf2[idx];
-    }
+    for (int idx = tid; idx < nf * nh; idx += nthr) out[idx] = buf2[idx];
     if (qr2_partial != nullptr && c == 0) {
         // sum over this plane of the per-cell q|u|^2 (component P of M),
         // fixed-order reduction
@@ -118,10 +117,10 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
                                                    T *__restrict__ L,
                                                    const cplx<T> *__restrict__ tw_g, T scale) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn, nh = nf / 2 + 1, npair = nout / 2;
+    const int nf = 1 << logn, nh = nf / 2 + 1, npair = nout / 2, ls = lds_line(nf);
     cplx<T> *tw = (cplx<T> *)lds_raw;
     cplx<T> *buf2 = tw + nf / 2;           // [nf][nh]
-    cplx<T> *buf1 = buf2 + nf * nh;        // [npair][nf]
+    cplx<T> *buf1 = buf2 + nf * nh;        // [npair][ls]
     const int z = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
@@ -140,11 +139,11 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
         }
     }
     __syncthreads();
-    lds_fft_dif<T, true>(buf2, logn, nh, 1, nh, tw, tid, nthr);
+    fft_lines<T, true>(buf2, logn, nh, 1, nh, tw, tid, nthr);
     for (int idx = tid; idx < npair * nf; idx += nthr) {
         const int j = idx >> logn, k = idx & (nf - 1);
-        const cplx<T> *ra = buf2 + bitrev(2 * j, logn) * nh;
-        const cplx<T> *rb = buf2 + bitrev(2 * j + 1, logn) * nh;
+        const cplx<T> *ra = buf2 + (2 * j) * nh;
+        const cplx<T> *rb = buf2 + (2 * j + 1) * nh;
         cplx<T> A, B;
         if (k <= nf / 2) {
             A = ra[k];
@@ -155,14 +154,14 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
             A.im = -A.im;
             B.im = -B.im;
         }
-        buf1[idx] = {A.re - B.im, A.im + B.re};
+        buf1[j * ls + k] = {A.re - B.im, A.im + B.re};
     }
     __syncthreads();
-    lds_fft_dif<T, true>(buf1, logn, npair, nf, 1, tw, tid, nthr);
+    fft_lines<T, true>(buf1, logn, npair, ls, 1, tw, tid, nthr);
     T *plane = L + ((int64_t)c * nout + z) * nout * nout;
     for (int idx = tid; idx < nout * nout; idx += nthr) {
         const int y = idx / nout, x = idx - y * nout;
-        const cplx<T> v = buf1[(y >> 1) * nf + bitrev(x, logn)];
+        const cplx<T> v = buf1[(y >> 1) * ls + x];
         plane[idx] = ((y & 1) ? v.im : v.re) * scale;
     }
 }
@@ -230,51 +229,55 @@ __host__ __device__ constexpr bool subset_needs(int PO, int RS, int S, int NN) {
 
 // acc[a] += sum_b t_ab(g of order NN) * M~_b over the output orders l of
 // subset S with lam = NN - l; M~ of order lam is read from LDS (column
-// `mcol`, row stride `mstride`) and pre-multiplied by i^(lam mod 2).
+// `mcol`, row stride `mstride`) and pre-multiplied by i^(lam mod 2).  Every
+// index is a compile-time constant (static_for), so acc, Mh and g stay in
+// registers.
 template <int PO, int NN, int RS, int S, typename T>
 __device__ __forceinline__ void m2l_order(const T *g, const cplx<T> *mcol, int mstride,
                                           cplx<T> *acc) {
     constexpr int lo = NN - PO > 0 ? NN - PO : 0;
     constexpr int hi = NN < PO ? NN : PO;
-#pragma unroll
-    for (int l = lo; l <= hi; ++l) {
-        if (order_subset(PO, RS, l) != S) continue;
-        const int lam = NN - l;
-        const int s = ((l & 1) && (lam & 1)) ? -1 : 1;
-        cplx<T> Mh[2 * PO + 1];
-#pragma unroll
-        for (int mu = -lam; mu <= lam; ++mu) {
-            const cplx<T> v = mcol[ridx(lam, mu) * mstride];
-            Mh[mu + lam] = (lam & 1) ? cplx<T>{-v.im, v.re} : v;
-        }
-#pragma unroll
-        for (int m = 0; m <= l; ++m) {
-            cplx<T> are = acc[ridx(l, m)];
-            cplx<T> aim = (m > 0) ? acc[ridx(l, -m)] : cplx<T>{T(0), T(0)};
-            // mu = 0 column: G^{m,0} = S_NN^{-m}
-            {
-                const cplx<T> x = Mh[lam];
-                mac(are, term2(g, re_S(NN, -m), s, Term{0, 0}, 0), x);
-                if (m > 0) mac(aim, term2(g, im_S(NN, -m), s, Term{0, 0}, 0), x);
-            }
-#pragma unroll
-            for (int mu = 1; mu <= lam; ++mu) {
-                const cplx<T> xr = Mh[lam + mu];   // Re M_lam^mu
-                const cplx<T> xi = Mh[lam - mu];   // Im M_lam^mu
-                const int sg = (mu & 1) ? -1 : 1;  // (-1)^mu of C and D
-                // Re row: (A + C) ReM - (B - D) ImM
-                mac(are, term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), s * sg), xr);
-                mac(are, term2(g, im_S(NN, -(m + mu)), -s, im_S(NN, -(m - mu)), s * sg), xi);
-                if (m > 0) {
-                    // Im row: (B + D) ReM + (A - C) ImM
-                    mac(aim, term2(g, im_S(NN, -(m + mu)), s, im_S(NN, -(m - mu)), s * sg), xr);
-                    mac(aim, term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), -s * sg), xi);
+    static_for<lo, hi + 1>([&](auto il) {
+        constexpr int l = decltype(il)::value;
+        if constexpr (order_subset(PO, RS, l) == S) {
+            constexpr int lam = NN - l;
+            constexpr int s = ((l & 1) && (lam & 1)) ? -1 : 1;
+            cplx<T> Mh[2 * lam + 1];
+            static_for<0, 2 * lam + 1>([&](auto ik) {
+                constexpr int k = decltype(ik)::value;
+                constexpr int mu = k - lam;
+                const cplx<T> v = mcol[ridx(lam, mu) * mstride];
+                Mh[k] = (lam & 1) ? cplx<T>{-v.im, v.re} : v;
+            });
+            static_for<0, l + 1>([&](auto im) {
+                constexpr int m = decltype(im)::value;
+                cplx<T> are = acc[ridx(l, m)];
+                cplx<T> aim = (m > 0) ? acc[ridx(l, -m)] : cplx<T>{T(0), T(0)};
+                // mu = 0 column: G^{m,0} = S_NN^{-m}
+                {
+                    const cplx<T> x = Mh[lam];
+                    mac(are, term2(g, re_S(NN, -m), s, Term{0, 0}, 0), x);
+                    if constexpr (m > 0) mac(aim, term2(g, im_S(NN, -m), s, Term{0, 0}, 0), x);
                 }
-            }
-            acc[ridx(l, m)] = are;
-            if (m > 0) acc[ridx(l, -m)] = aim;
+                static_for<1, lam + 1>([&](auto iu) {
+                    constexpr int mu = decltype(iu)::value;
+                    const cplx<T> xr = Mh[lam + mu];   // Re M_lam^mu
+                    const cplx<T> xi = Mh[lam - mu];   // Im M_lam^mu
+                    constexpr int sg = (mu & 1) ? -1 : 1;  // (-1)^mu of C and D
+                    // Re row: (A + C) ReM - (B - D) ImM
+                    mac(are, term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), s * sg), xr);
+                    mac(are, term2(g, im_S(NN, -(m + mu)), -s, im_S(NN, -(m - mu)), s * sg), xi);
+                    if constexpr (m > 0) {
+                        // Im row: (B + D) ReM + (A - C) ImM
+                        mac(aim, term2(g, im_S(NN, -(m + mu)), s, im_S(NN, -(m - mu)), s * sg), xr);
+                        mac(aim, term2(g, re_S(NN, -(m + mu)), s, re_S(NN, -(m - mu)), -s * sg), xi);
+                    }
+                });
+                acc[ridx(l, m)] = are;
+                if constexpr (m > 0) acc[ridx(l, -m)] = aim;
+            });
         }
-    }
+    });
 }
 
 // Kernel values g of order NN come from the block's LDS tile (component j
@@ -289,14 +292,14 @@ struct M2LOrders {
                                                const cplx<T> *mcol, int mstride, cplx<T> *acc) {
         if constexpr (subset_needs(PO, RS, S, NN)) {
             T g[2 * NN + 1];
-#pragma unroll
-            for (int k = 0; k <= 2 * NN; ++k) {
-                const int kk = k - NN;
-                const int odd_z = (NN + (kk < 0 ? -kk : kk)) & 1;
+            static_for<0, 2 * NN + 1>([&](auto ik) {
+                constexpr int k = decltype(ik)::value;
+                constexpr int kk = k - NN;
+                constexpr int odd_z = (NN + (kk < 0 ? -kk : kk)) & 1;
                 const int neg = ((flip & 1) && kk < 0) ^ ((flip & 2) && odd_z);
                 const T v = gcol[(NN * NN + k) * gstride];
                 g[k] = neg ? -v : v;
-            }
+            });
             m2l_order<PO, NN, RS, S, T>(g, mcol, mstride, acc);
             // keep the next order's loads after this one's arithmetic so that
             // the (2p+1)^2 kernel values are never all live at once
@@ -327,26 +330,26 @@ __device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
                                            DCCorr dc) {
     constexpr int P = nreal(PO);
     cplx<T> acc[P];
-#pragma unroll
-    for (int a = 0; a < P; ++a) acc[a] = {T(0), T(0)};
+    static_for<0, P>([&](auto ia) { acc[decltype(ia)::value] = {T(0), T(0)}; });
     M2LOrders<PO, 0, RS, S, T>::run(gcol, gstride, flip, mcol, stride, acc);
-#pragma unroll
-    for (int l = 0; l <= PO; ++l) {
-        if (order_subset(PO, RS, l) != S) continue;
-#pragma unroll
-        for (int m = -l; m <= l; ++m) {
-            const int a = ridx(l, m);
-            const cplx<T> v = acc[a];
-            cplx<T> o = (l & 1) ? cplx<T>{-v.im, v.re} : v;
-            if (dc.on) {
-                if (a == 0) o.re += T(dc.l00);
-                if (PO >= 1 && a == ridx(1, 0)) o.re += T(dc.l10);
-                if (PO >= 1 && a == ridx(1, 1)) o.re += T(dc.l11re);
-                if (PO >= 1 && a == ridx(1, -1)) o.re += T(dc.l11im);
-            }
-            ocol[a * stride] = o;
+    static_for<0, PO + 1>([&](auto il) {
+        constexpr int l = decltype(il)::value;
+        if constexpr (order_subset(PO, RS, l) == S) {
+            static_for<-l, l + 1>([&](auto im) {
+                constexpr int m = decltype(im)::value;
+                constexpr int a = ridx(l, m);
+                const cplx<T> v = acc[a];
+                cplx<T> o = (l & 1) ? cplx<T>{-v.im, v.re} : v;
+                if (dc.on) {
+                    if constexpr (a == 0) o.re += T(dc.l00);
+                    if constexpr (PO >= 1 && a == ridx(1, 0)) o.re += T(dc.l10);
+                    if constexpr (PO >= 1 && a == ridx(1, 1)) o.re += T(dc.l11re);
+                    if constexpr (PO >= 1 && a == ridx(1, -1)) o.re += T(dc.l11im);
+                }
+                ocol[a * stride] = o;
+            });
         }
-    }
+    });
 }
 
 // Block = rs row subsets x (w columns x nf frequencies) <= 256 threads; with
@@ -365,12 +368,13 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
     constexpr int Q = nreal(2 * PO);
     constexpr int RS = kRowSplit;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3;
+    const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ls = lds_line(nf);
     const int nfreq = w * nf;
+    const int cstride = w * ls;                 // component stride in buf / obuf
     cplx<T> *tw = (cplx<T> *)lds_raw;
     cplx<T> *buf = tw + nf / 2;
-    cplx<T> *obuf = buf + P * nfreq;
-    T *gt = (T *)(obuf + P * nfreq);
+    cplx<T> *obuf = buf + P * cstride;
+    T *gt = (T *)(obuf + P * cstride);
     // XCD-aware order: consecutive column groups stay on one XCD (blocks are
     // dealt round-robin over the 8 XCDs).
     const int per_xcd = (ngroups + 7) / 8;
@@ -443,27 +447,27 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
             const int rest = idx / w;
             const int zz = rest & (nf - 1);
             const int b = rest >> logn;
-            buf[(b * w + i) * nf + zz] = v[u];
+            buf[(b * w + i) * ls + zz] = v[u];
         }
     }
     __syncthreads();
-    lds_fft_dif<T, false>(buf, logn, P * w, nf, 1, tw, tid, nthr);
+    fft_lines<T, false>(buf, logn, P * w, ls, 1, tw, tid, nthr);
     // M2L: thread = (row subset, frequency)
     const int sub = tid / nfreq, f = tid - sub * nfreq;
     const int i = f >> logn, pos = f & (nf - 1);
     const int col = col0 + i;
-    const int kz = bitrev(pos, logn);
+    const int kz = pos;
     DCCorr dcc = {false, 0.0, 0.0, 0.0, 0.0};
     if (periodic && col == 0 && kz == 0) {
         // zero frequency: M~_c(0) = sum over cells of M_c (real)
-        const cplx<T> *m0 = buf + i * nf + pos;
+        const cplx<T> *m0 = buf + i * ls + pos;
         const double V = (double)nf * nf * nf;  // box volume in cell units (nf = n)
         const double pi = 3.14159265358979323846;
         double qr2 = 0.0;
         for (int z = 0; z < nz; ++z) qr2 += qr2_partial[z];
-        const double m10 = PO >= 1 ? (double)m0[ridx(1, 0) * nfreq].re : 0.0;
-        const double m11 = PO >= 1 ? (double)m0[ridx(1, 1) * nfreq].re : 0.0;
-        const double m1m1 = PO >= 1 ? (double)m0[ridx(1, -1) * nfreq].re : 0.0;
+        const double m10 = PO >= 1 ? (double)m0[ridx(1, 0) * cstride].re : 0.0;
+        const double m11 = PO >= 1 ? (double)m0[ridx(1, 1) * cstride].re : 0.0;
+        const double m1m1 = PO >= 1 ? (double)m0[ridx(1, -1) * cstride].re : 0.0;
         // per-cell constants of the correction procedure, times nf^3 (= V)
         dcc.l00 = 2.0 * pi / (3.0 * V) * qr2 * V;
         dcc.l10 = 4.0 * pi / (3.0 * V) * m10 * V;
@@ -478,26 +482,26 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
         const int flip = (ky > nf / 2 ? 1 : 0) | (kz > nf / 2 ? 2 : 0);
         const T *gp = gt + i * nhp + kzr;
         const int gstride = w * nhp;
-        const cplx<T> *mp = buf + i * nf + pos;
-        cplx<T> *op = obuf + i * nf + pos;
+        const cplx<T> *mp = buf + i * ls + pos;
+        cplx<T> *op = obuf + i * ls + pos;
         for (int ss = sub; ss < RS; ss += rs) {
             switch (ss) {
-                case 0: m2l_subset<PO, RS, 0, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
-                case 1: m2l_subset<PO, RS, 1, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
-                case 2: m2l_subset<PO, RS, 2, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
-                default: m2l_subset<PO, RS, 3, T>(gp, gstride, flip, mp, op, nfreq, dcc); break;
+                case 0: m2l_subset<PO, RS, 0, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
+                case 1: m2l_subset<PO, RS, 1, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
+                case 2: m2l_subset<PO, RS, 2, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
+                default: m2l_subset<PO, RS, 3, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
             }
         }
     }
     __syncthreads();
-    lds_fft_dit<T, true>(obuf, logn, P * w, nf, 1, tw, tid, nthr);
+    fft_lines<T, true>(obuf, logn, P * w, ls, 1, tw, tid, nthr);
     for (int idx = tid; idx < P * nz * w; idx += nthr) {
         const int ii = idx % w;
         const int rest = idx / w;
         const int zz = rest % nz;
         const int a = rest / nz;
         const int cc = col0 + ii;
-        if (cc < ncol) spec[((int64_t)a * nz + zz) * zstride + cc] = obuf[(a * w + ii) * nf + zz];
+        if (cc < ncol) spec[((int64_t)a * nz + zz) * zstride + cc] = obuf[(a * w + ii) * ls + zz];
     }
 }
 
@@ -537,7 +541,7 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const int P = nreal(a.p);
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, n = a.n;
     const size_t csz = sizeof(cplx<T>);
-    const size_t lds_plane = (size_t)(nf / 2 + (n / 2) * nf + nf * nh) * csz;
+    const size_t lds_plane = (size_t)(nf / 2 + (n / 2) * lds_line(nf) + nf * nh) * csz;
     hipError_t e = hipSuccess;
     if (stage == 0) {
         e = ensure_lds(k_plane_fwd<T>, lds_plane);

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <type_traits>
 
 #include "../../include/pmmm.h"
 
@@ -190,6 +191,151 @@ __device__ void lds_fft_dit(cplx<T> *buf, int logn, int nlines, int lstride, int
     }
 }
 
+// ------------------------------------------------- register / LDS FFTs
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+__host__ __device__ constexpr int brevc(int v, int bits) {
+    return bits == 0 ? 0 : ((v & 1) << (bits - 1)) | brevc(v >> 1, bits - 1);
+}
+
+// exp(-+ 2 pi i k / 16) for 0 <= k < 8 (forward: minus sign).
+template <typename T, bool INV, int K>
+__device__ __forceinline__ cplx<T> w16() {
+    constexpr double C1 = 0.92387953251128674, S1 = 0.38268343236508978, R2 = 0.70710678118654752;
+    constexpr double c[8] = {1.0, C1, R2, S1, 0.0, -S1, -R2, -C1};
+    constexpr double sn[8] = {0.0, S1, R2, C1, 1.0, C1, R2, S1};
+    return {T(c[K]), INV ? T(sn[K]) : T(-sn[K])};
+}
+
+// In-register FFT of R = 1..16 points, natural order in and out (radix-2
+// decimation in time on the bit-reversed copy), unnormalised.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void fft_reg(cplx<T> *v) {
+    if constexpr (R > 1) {
+        constexpr int LG = ilog2c(R);
+        cplx<T> a[R];
+        static_for<0, R>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            a[brevc(i, LG)] = v[i];
+        });
+        static_for<0, LG>([&](auto is) {
+            constexpr int half = 1 << decltype(is)::value;
+            constexpr int span = 2 * half;
+            static_for<0, half>([&](auto ij) {
+                constexpr int j = decltype(ij)::value;
+                constexpr int k16 = j * (16 / span);
+                static_for<0, R / span>([&](auto ig) {
+                    constexpr int i0 = decltype(ig)::value * span + j, i1 = i0 + half;
+                    cplx<T> b = a[i1];
+                    if constexpr (k16 != 0) b = cmul(b, w16<T, INV, k16>());
+                    a[i1] = {a[i0].re - b.re, a[i0].im - b.im};
+                    a[i0] = {a[i0].re + b.re, a[i0].im + b.im};
+                });
+            });
+        });
+        static_for<0, R>([&](auto ii) { v[decltype(ii)::value] = a[decltype(ii)::value]; });
+    }
+}
+
+// In-place FFTs of `nlines` lines of N points in LDS, natural order in and
+// out; element e of line t at buf[t * lstride + e * estride].  tw[k] =
+// exp(-2 pi i k / N), k < N/2, in LDS.  N <= 16: one thread per line in
+// registers.  N = 16 N2 (N2 = 2, 4, 8): four-step scheme, 16-point register
+// FFTs over n1 for each t2 (x[n1 N2 + t2]), twiddle W_N^(t2 k1), then N2-point
+// FFTs over t2; X[k1 + 16 k2] ends at position k1 + 16 k2.  nthr must be a
+// multiple of 64.  Ends with a barrier.
+template <typename T, bool INV, int N>
+__device__ void fft_lines_n(cplx<T> *buf, int nlines, int lstride, int estride,
+                            const cplx<T> *tw, int tid, int nthr) {
+    if constexpr (N <= 16) {
+        for (int line = tid; line < nlines; line += nthr) {
+            cplx<T> *b = buf + line * lstride;
+            cplx<T> v[N];
+            static_for<0, N>([&](auto ie) { v[decltype(ie)::value] = b[decltype(ie)::value * estride]; });
+            fft_reg<N, INV, T>(v);
+            static_for<0, N>([&](auto ie) { b[decltype(ie)::value * estride] = v[decltype(ie)::value]; });
+        }
+        __syncthreads();
+    } else {
+        constexpr int N2 = N / 16;
+        const int items = nlines * N2;
+        const int rounds = (items + nthr - 1) / nthr;
+        for (int r = 0; r < rounds; ++r) {
+            const int it = r * nthr + tid;
+            const bool act = it < items;
+            const int line = it / N2, t2 = it - line * N2;
+            cplx<T> *b = buf + line * lstride;
+            cplx<T> v[16];
+            if (act) {
+                static_for<0, 16>([&](auto in) {
+                    constexpr int n1 = decltype(in)::value;
+                    v[n1] = b[(n1 * N2 + t2) * estride];
+                });
+                fft_reg<16, INV, T>(v);
+                static_for<1, 16>([&](auto ik) {
+                    constexpr int k1 = decltype(ik)::value;
+                    const int e = t2 * k1;  // < N
+                    cplx<T> w = e < N / 2 ? tw[e] : tw[e - N / 2];
+                    if (e >= N / 2) {
+                        w.re = -w.re;
+                        w.im = -w.im;
+                    }
+                    if (INV) w.im = -w.im;
+                    v[k1] = cmul(v[k1], w);
+                });
+            }
+            __syncthreads();  // every load of this round's lines is done
+            if (act) {
+                static_for<0, 16>([&](auto ik) {
+                    constexpr int k1 = decltype(ik)::value;
+                    b[(t2 * 16 + k1) * estride] = v[k1];
+                });
+            }
+        }
+        __syncthreads();
+        for (int it = tid; it < nlines * 16; it += nthr) {
+            const int line = it >> 4, k1 = it & 15;
+            cplx<T> *b = buf + line * lstride;
+            cplx<T> u[N2];
+            static_for<0, N2>([&](auto it2) {
+                constexpr int t2 = decltype(it2)::value;
+                u[t2] = b[(t2 * 16 + k1) * estride];
+            });
+            fft_reg<N2, INV, T>(u);
+            static_for<0, N2>([&](auto ik2) {
+                constexpr int k2 = decltype(ik2)::value;
+                b[(k2 * 16 + k1) * estride] = u[k2];
+            });
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, bool INV>
+__device__ void fft_lines(cplx<T> *buf, int logn, int nlines, int lstride, int estride,
+                          const cplx<T> *tw, int tid, int nthr) {
+    switch (logn) {
+        case 2: fft_lines_n<T, INV, 4>(buf, nlines, lstride, estride, tw, tid, nthr); break;
+        case 3: fft_lines_n<T, INV, 8>(buf, nlines, lstride, estride, tw, tid, nthr); break;
+        case 4: fft_lines_n<T, INV, 16>(buf, nlines, lstride, estride, tw, tid, nthr); break;
+        case 5: fft_lines_n<T, INV, 32>(buf, nlines, lstride, estride, tw, tid, nthr); break;
+        case 6: fft_lines_n<T, INV, 64>(buf, nlines, lstride, estride, tw, tid, nthr); break;
+        default: fft_lines_n<T, INV, 128>(buf, nlines, lstride, estride, tw, tid, nthr); break;
+    }
+}
+
+// Line stride in LDS for lines of n complex values: one thread per line for
+// n <= 16, so pad by one element to spread the lines over the LDS banks.
+__host__ __device__ constexpr int lds_line(int n) { return n <= 16 ? n + 1 : n; }
+
 // ------------------------------------------------------------ host side
 struct Plan;  // defined in pmmm_api.hip
 
@@ -202,7 +348,8 @@ inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out)
     const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
     int w = nf >= 64 ? 1 : 64 / nf;
     for (;;) {
-        const size_t lds = 2 * P * w * nf * 2 * tsize + Q * w * nhp * tsize + (size_t)nf / 2 * 2 * tsize;
+        const size_t lds = 2 * P * w * (size_t)lds_line(nf) * 2 * tsize + Q * w * nhp * tsize +
+                           (size_t)nf / 2 * 2 * tsize;
         if (lds <= 160 * 1024) {
             const int rs = 256 / (w * nf) < 4 ? 256 / (w * nf) : 4;
             if (w_out) *w_out = w;
