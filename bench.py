@@ -31,6 +31,9 @@ METRIC = "particles/s, PMMM far field (P2M+FFT M2L+L2P) at rel. RMS force err <=
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector
 FP64_PEAK = 78.6e12
+BF16_PEAK = 2.5e15           # FLOP/s, MI355X dense BF16 matrix cores
+MULTI_METRIC = ("particle x charge-set evaluations/s, PMMM far field of many charge sets "
+                "on one mesh (M2L on BF16 matrix cores, split operands)")
 
 
 def stage_work(stage, N, n, p, nf, open_bc, tsize=4):
@@ -56,6 +59,36 @@ def stage_work(stage, N, n, p, nf, open_bc, tsize=4):
         return c * P * spec + tsize * P * K, 5 * P * n * nf * (nf // 2 + 1) * 2 * lg
     if stage == "l2p":
         return tsize * P * K + 4 * tsize * N + 2 * 4 * N + 4 * tsize * N, (harm + 14 * P) * N
+    raise KeyError(stage)
+
+
+def multi_stage_work(stage, N, S, n, p, nprod):
+    """Algorithmic HBM bytes, useful FP32 flops and executed matrix-core
+    flops of one launch of a multi-charge stage (S charge sets, periodic
+    n^3 mesh, FP32 storage)."""
+    P, Q = (p + 1) ** 2, (2 * p + 1) ** 2
+    PD = p * p
+    K = n ** 3
+    nh = n // 2 + 1
+    ncol = n * nh
+    F = ncol * n
+    lg = n.bit_length() - 1
+    harm = 4 * (p + 1) * (p + 2)
+    spec = 8 * S * P * F                    # split-z spectra, complex FP32
+    if stage == "bin":
+        return 4 * 3 * N + 16 * N + 4 * 4 * N + 3 * 4 * K, 10 * N, 0
+    if stage == "p2m":
+        return 20 * N + 4 * S * N + 4 * S * (P + 1) * K, (harm + 2 * S * (P + 1)) * N, 0
+    if stage == "fft_fwd":
+        return 4 * S * (P + 1) * K + spec, 5 * S * P * K * 2 * lg, 0
+    if stage == "column":
+        rt, ks = -(-P // 16) * 16, -(-P // 32) * 32
+        mfma = nprod * 2 * rt * ks * (-(-2 * S // 16) * 16) * F
+        return 2 * spec + 4 * Q * nh * nh * ((nh + 3) & ~3), 4 * P * P * S * F, mfma
+    if stage == "fft_inv":
+        return spec + 4 * S * P * K, 5 * S * P * K * 2 * lg, 0
+    if stage == "l2p":
+        return 4 * S * P * K + 20 * N + 16 * S * N, (harm + 2 * S * (P + 3 * PD)) * N, 0
     raise KeyError(stage)
 
 
@@ -113,6 +146,7 @@ WORKLOADS = {
     "open_n4096_m8_p4_f64": ("open_equal_mass", "open", "f64"),
     "periodic_n1048576_m32_p7": ("periodic_pm1_blocks", "periodic", "f32"),
     "open_plummer_n4194304_m64_p6": ("plummer_sphere", "open", "f32"),
+    "multi_periodic_n1048576_m32_p6_s64": ("multi_charge_sets", "periodic", "f32"),
 }
 
 
@@ -126,6 +160,9 @@ def main():
     ap.add_argument("--workload", default="periodic_n32768_m16_p5", choices=sorted(WORKLOADS),
                     help="default: the headline workload; the others are the remaining "
                          "single-GPU configurations")
+    ap.add_argument("--split", default="f32", choices=["f32", "bf16x3"],
+                    help="multi-charge workload: three-term (f32) or two-term (bf16x3) "
+                         "bf16 splits in the M2L product")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -139,6 +176,8 @@ def main():
     from paper_1409_5981_amd._lib import Plan, STAGES
 
     workload = args.workload
+    if workload.startswith("multi_"):
+        return bench_multi(args, workload)
     gen, boundary, prec = WORKLOADS[workload]
     ps = getattr(inputs, gen)()
     N, n, p = ps.n, ps.n_cells, ps.p
@@ -219,6 +258,114 @@ def main():
                    "cells": f"{n}^3", "fft_mesh": f"{nf}^3", "p": p, "cutoff": 2,
                    "parallelism": "single GPU"},
         "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def _roofline(t_k, bytes_k, flops_k, peak_flops, mfma_flops=0):
+    t_hbm = bytes_k / HBM_PEAK
+    t_alu = flops_k / peak_flops
+    t_mfma = mfma_flops / BF16_PEAK
+    if t_mfma > max(t_hbm, t_alu):
+        roof = {"bound": "mfma", "achieved": mfma_flops / t_k / 1e12, "peak": BF16_PEAK / 1e12,
+                "unit": "TFLOP/s"}
+    elif t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": bytes_k / t_k / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops_k / t_k / 1e12, "peak": peak_flops / 1e12,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    return roof
+
+
+def bench_multi(args, workload):
+    """Multi-charge workload: 2^20 uniform positions, 64 neutral +/-1 charge
+    sets, periodic 32^3 mesh, p = 6; one step is one pmmm_far_multi_f32 call
+    (binning once, then P2M, split-z FFTs, M2L on the matrix cores, inverse
+    FFTs and L2P for every set)."""
+    import torch
+    from paper_1409_5981_amd import inputs
+    from paper_1409_5981_amd._lib import Plan, STAGES
+
+    ps, qs = inputs.multi_charge_sets()
+    N, S, n, p = ps.n, qs.shape[0], ps.n_cells, ps.p
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    x, y, z = (torch.from_numpy(a).to(dev) for a in (ps.x, ps.y, ps.z))
+    q = torch.from_numpy(qs.T.copy()).to(dev)
+    plan = Plan(n, p, "periodic", cutoff=2, precision=args.split, n_max=N)
+    out = tuple(torch.empty(N, S, dtype=torch.float32, device=dev) for _ in range(4))
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(stream)
+    warm = max(2, args.warmup)
+    half = max(1, warm // 2)
+    for i in range(warm):
+        if i == half:
+            plan.set_profiling(STAGES)
+        plan.far_multi(x, y, z, q, out=out)
+    torch.cuda.synchronize()
+    prof = plan.read_profile(reset=True)
+    means = {st: (ms / c if c else 0.0) for st, (ms, c) in prof.items()}
+    dominant = max(means, key=means.get)
+    print("stage means: " + ", ".join(f"{k}={v*1e3:.1f}us" for k, v in means.items()),
+          file=sys.stderr)
+    plan.set_profiling([dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.far_multi(x, y, z, q, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.sync_status()
+    prof = plan.read_profile(reset=True)
+    plan.set_profiling([])
+    ms_k, cnt = prof[dominant]
+    t_k = ms_k / cnt / 1e3
+    nprod = 6 if args.split == "f32" else 3
+    bytes_k, flops_k, mfma_k = multi_stage_work(dominant, N, S, n, p, nprod)
+    roof = _roofline(t_k, bytes_k, flops_k, FP32_PEAK, mfma_k)
+    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash())
+    roof["kernel"] = dominant
+    roof["kernel_us"] = t_k * 1e6
+    roof["algorithmic_bytes"] = bytes_k
+    roof["algorithmic_flops"] = flops_k
+    # matrix-core share of the column stage (mean over the warm-up profile)
+    t_col = means.get("column", 0.0) / 1e3
+    col_bytes, col_flops, col_mfma = multi_stage_work("column", N, S, n, p, nprod)
+    stages = {st: {"us": means[st] * 1e3} for st in STAGES}
+    for st in STAGES:
+        b_, f_, m_ = multi_stage_work(st, N, S, n, p, nprod)
+        if means[st] > 0:
+            stages[st]["hbm_frac"] = b_ / (means[st] / 1e3) / HBM_PEAK
+            if m_:
+                stages[st]["mfma_frac"] = m_ / (means[st] / 1e3) / BF16_PEAK
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(ps, args.cpu_seconds)
+        cpu["unit"] = "particle x charge-set evaluations/s"
+        cpu["sample"] += "; one charge set per pass"
+    rec = {
+        "metric": MULTI_METRIC,
+        "value": N * S * args.steps / el,
+        "unit": "particle x charge-set evaluations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": warm,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.split == "f32" else "f32+bf16x3",
+        "data": "synthetic",
+        "config": {"workload": workload, "boundary": "periodic", "n_particles": N,
+                   "charge_sets": S, "cells": f"{n}^3", "fft_mesh": f"{n}^3", "p": p,
+                   "cutoff": 2, "m2l_products": nprod, "positions_per_s": N * args.steps / el,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "stages": stages,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

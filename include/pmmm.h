@@ -60,7 +60,7 @@ enum {
 };
 
 enum { PMMM_OPEN = 0, PMMM_PERIODIC = 1 };
-enum { PMMM_F32 = 0, PMMM_F64 = 1 };
+enum { PMMM_F32 = 0, PMMM_F64 = 1, PMMM_BF16X3 = 2 };
 enum { PMMM_MESH_M = 0, PMMM_MESH_L = 1, PMMM_MESH_GREEN = 2 };
 
 typedef struct pmmm_plan_s *pmmm_plan;
@@ -78,6 +78,11 @@ typedef struct pmmm_plan_s *pmmm_plan;
  *               Periodic meshes need n >= 2c + 1, open meshes n >= c + 2.
  *   boundary    PMMM_OPEN or PMMM_PERIODIC.
  *   precision   PMMM_F32 (use pmmm_far_f32) or PMMM_F64 (pmmm_far_f64).
+ *               PMMM_BF16X3 is an FP32 plan whose multi-charge M2L product
+ *               (pmmm_far_multi_f32) keeps two bf16 terms of each operand
+ *               (three products, about 16 bits); FP32 plans keep three
+ *               terms (six products, FP32-level rounding).  pmmm_far_f32
+ *               runs the same FP32 pipeline for both.
  *   alpha       periodic splitting parameter of the lattice sums; 0 -> 1.5/b.
  *   images      periodic lattice-sum radius |n| <= images; 0 -> 4.
  *   n_max       particle capacity to allocate up front (0: grow on demand;
@@ -119,6 +124,27 @@ int pmmm_far_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, cons
 int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
                  const double *z, const double *q, double *phi, double *gx, double *gy,
                  double *gz, void *stream);
+
+/* Far field of nsets charge sets on the same n positions (Sec. 2.1 for each
+ * set: every step is linear in the charges, so the binning, the particles'
+ * harmonics and the transfer kernel are shared).  At each frequency the M2L
+ * of eq. realmatrix for all sets is one real (P x P) by (P x 2 nsets)
+ * product, computed on the BF16 matrix cores with split FP32 operands and
+ * FP32 accumulation (two terms for PMMM_BF16X3 plans, three for PMMM_F32).
+ * Periodic FP32 / BF16X3 plans with an FFT mesh of 4 to 32 cells per axis
+ * only (PMMM_EUNSUPPORTED otherwise).
+ *   x, y, z    [n] device positions;
+ *   q          [n][nsets] device charges, the set index fastest
+ *              (q[i * nsets + s] is the charge of particle i in set s);
+ *   phi, gx, gy, gz  [n][nsets] device outputs in the same layout, input
+ *              order of the particles.
+ * Sets are processed in chunks of at most 64; the plan grows its multi-set
+ * workspace (about 16 P n^3 bytes per set of a chunk) on the first call that
+ * needs it, which synchronises the device once.  nsets >= 1; n == 0 is a
+ * valid no-op.  pmmm_near_* after this call uses zero charges. */
+int pmmm_far_multi_f32(pmmm_plan plan, int64_t n, const float *x, const float *y,
+                       const float *z, int nsets, const float *q, float *phi, float *gx,
+                       float *gy, float *gz, void *stream);
 
 /* Near field for checking only (Sec. 2.1: direct particle-particle sums over
  * the masked (2c+1)^3 cells, no cutoff function).  Uses the binning (sorted

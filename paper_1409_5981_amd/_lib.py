@@ -17,14 +17,15 @@ LIB_PATH = os.path.join(HERE, "libpmmm.so")
 
 PMMM_OK, PMMM_EINVAL, PMMM_ENOMEM, PMMM_EHIP, PMMM_EDOMAIN, PMMM_EUNSUPPORTED = range(6)
 PMMM_OPEN, PMMM_PERIODIC = 0, 1
-PMMM_F32, PMMM_F64 = 0, 1
+PMMM_F32, PMMM_F64, PMMM_BF16X3 = 0, 1, 2
 PMMM_MESH_M, PMMM_MESH_L, PMMM_MESH_GREEN = 0, 1, 2
 PMMM_PMAX = 8
 
 #: every symbol include/pmmm.h declares
 EXPORTS = [
     "pmmm_plan_create", "pmmm_plan_destroy", "pmmm_workspace_bytes",
-    "pmmm_far_f32", "pmmm_far_f64", "pmmm_near_f32", "pmmm_near_f64",
+    "pmmm_far_f32", "pmmm_far_f64", "pmmm_far_multi_f32",
+    "pmmm_near_f32", "pmmm_near_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
     "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
     "pmmm_error_string", "pmmm_last_error",
@@ -72,6 +73,8 @@ def load():
         f = getattr(L, name)
         f.argtypes = [vp, i64] + [vp] * 8 + [vp]
         f.restype = ci
+    L.pmmm_far_multi_f32.argtypes = [vp, i64, vp, vp, vp, ci] + [vp] * 5 + [vp]
+    L.pmmm_far_multi_f32.restype = ci
     for name in ("pmmm_near_f32", "pmmm_near_f64"):
         f = getattr(L, name)
         f.argtypes = [vp, i64, vp, vp, vp, vp, ci, vp]
@@ -111,7 +114,7 @@ def make_params(n: int, p: int, boundary: str, box: float = 1.0, cutoff: int = 2
     prm.p = int(p)
     prm.cutoff = int(cutoff)
     prm.boundary = PMMM_OPEN if boundary == "open" else PMMM_PERIODIC
-    prm.precision = PMMM_F32 if precision == "f32" else PMMM_F64
+    prm.precision = {"f32": PMMM_F32, "f64": PMMM_F64, "bf16x3": PMMM_BF16X3}[precision]
     prm.alpha = float(alpha)
     prm.images = int(images)
     prm.n_max = int(n_max)
@@ -146,7 +149,7 @@ class Plan:
     @property
     def dtype(self):
         import torch
-        return torch.float32 if self.precision == "f32" else torch.float64
+        return torch.float64 if self.precision == "f64" else torch.float32
 
     def close(self):
         if self._h:
@@ -174,9 +177,28 @@ class Plan:
         if out is None:
             out = tuple(torch.empty(n, dtype=self.dtype, device=x.device) for _ in range(4))
         self._check_tensors(*out)
-        fn = load().pmmm_far_f32 if self.precision == "f32" else load().pmmm_far_f64
+        fn = load().pmmm_far_f64 if self.precision == "f64" else load().pmmm_far_f32
         _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
                   *[o.data_ptr() for o in out], _stream_handle(stream)))
+        return out
+
+    def far_multi(self, x, y, z, q, out=None, stream=None):
+        """Far field of several charge sets on the same positions.  q is
+        [n, nsets] (set index fastest); returns Phi, gx, gy, gz as [n, nsets]
+        device tensors in input order."""
+        import torch
+        self._check_tensors(x, y, z, q)
+        n = x.numel()
+        if q.dim() != 2 or q.shape[0] != n or not (y.numel() == z.numel() == n):
+            raise ValueError("x, y, z must have length n and q shape [n, nsets]")
+        nsets = int(q.shape[1])
+        if out is None:
+            out = tuple(torch.empty(n, nsets, dtype=self.dtype, device=x.device)
+                        for _ in range(4))
+        self._check_tensors(*out)
+        _check(load().pmmm_far_multi_f32(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                                         nsets, q.data_ptr(), *[o.data_ptr() for o in out],
+                                         _stream_handle(stream)))
         return out
 
     def near(self, n, out=None, accumulate=False, device="cuda", stream=None):
@@ -184,7 +206,7 @@ class Plan:
         if out is None:
             out = tuple(torch.zeros(n, dtype=self.dtype, device=device) for _ in range(4))
         self._check_tensors(*out)
-        fn = load().pmmm_near_f32 if self.precision == "f32" else load().pmmm_near_f64
+        fn = load().pmmm_near_f64 if self.precision == "f64" else load().pmmm_near_f32
         _check(fn(self._h, n, *[o.data_ptr() for o in out], int(bool(accumulate)),
                   _stream_handle(stream)))
         return out
@@ -210,7 +232,7 @@ class Plan:
         """Copy an internal mesh (PMMM_MESH_M / _L / _GREEN) to a numpy array."""
         L = load()
         nbytes = int(L.pmmm_plan_mesh_bytes(self._h, which))
-        dt = np.float32 if self.precision == "f32" else np.float64
+        dt = np.float64 if self.precision == "f64" else np.float32
         buf = np.empty(nbytes // np.dtype(dt).itemsize, dtype=dt)
         _check(L.pmmm_plan_copy_mesh(self._h, which, buf.ctypes.data_as(ctypes.c_void_p), nbytes))
         P, n, nf = (self.p + 1) ** 2, self.n, self.nf

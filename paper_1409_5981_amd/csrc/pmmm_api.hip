@@ -38,6 +38,12 @@ struct Plan {
     int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr;
     void *sorted = nullptr;
     hipStream_t last_stream = nullptr;
+    // multi-charge workspace (chunks of up to kMultiMaxSets sets)
+    int mcap_sets = 0;
+    float *mM = nullptr;          // [S][P+1][K] moments, then [S][P][K] local expansions
+    void *mX = nullptr;           // split-z spectra
+    unsigned *mtmap = nullptr;    // t-matrix map in MFMA fragment order
+    double *mqr2 = nullptr, *mqtot = nullptr;
     // stage timing
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -114,8 +120,9 @@ static int validate(const pmmm_params *prm, std::string &why) {
         why = "boundary must be PMMM_OPEN or PMMM_PERIODIC";
         return PMMM_EINVAL;
     }
-    if (prm->precision != PMMM_F32 && prm->precision != PMMM_F64) {
-        why = "precision must be PMMM_F32 or PMMM_F64";
+    if (prm->precision != PMMM_F32 && prm->precision != PMMM_F64 &&
+        prm->precision != PMMM_BF16X3) {
+        why = "precision must be PMMM_F32, PMMM_F64 or PMMM_BF16X3";
         return PMMM_EINVAL;
     }
     if (prm->alpha < 0 || prm->images < 0 || prm->n_max < 0) {
@@ -136,14 +143,14 @@ static int validate(const pmmm_params *prm, std::string &why) {
         return PMMM_EUNSUPPORTED;
     }
     const int nf = prm->boundary == PMMM_OPEN ? 2 * n : n;
-    const int nfmax = prm->precision == PMMM_F32 ? 128 : 64;
+    const int nfmax = prm->precision == PMMM_F64 ? 64 : 128;
     if (nf > nfmax) {
         why = "FFT mesh too large for this build (FP32: nf <= 128, FP64: nf <= 64)";
         return PMMM_EUNSUPPORTED;
     }
     // the column kernel keeps the spectra and kernel tile of at least one
     // column in LDS (160 KB per CU)
-    const size_t lds = column_shape(prm->p, nf, prm->precision == PMMM_F32 ? 4 : 8, nullptr, nullptr);
+    const size_t lds = column_shape(prm->p, nf, prm->precision == PMMM_F64 ? 8 : 4, nullptr, nullptr);
     if (lds == 0) {
         why = "order too high for this FFT mesh: the column kernel's tile exceeds 160 KB of LDS";
         return PMMM_EUNSUPPORTED;
@@ -173,7 +180,7 @@ static void derive(Plan *pl, const pmmm_params *prm) {
     pl->inv_h = pl->n / pl->box;
     pl->alpha = prm->alpha == 0 ? 1.5 / pl->box : prm->alpha;
     pl->alpha_cell = pl->alpha * pl->h;
-    pl->tsize = pl->prec == PMMM_F32 ? 4 : 8;
+    pl->tsize = pl->prec == PMMM_F64 ? 8 : 4;
 }
 
 static size_t plan_bytes(const Plan *pl) {
@@ -235,6 +242,11 @@ static void destroy(Plan *pl) {
     hipFree(pl->small);
     hipFree(pl->sums);
     hipFree(pl->qr2_partial);
+    hipFree(pl->mM);
+    hipFree(pl->mX);
+    hipFree(pl->mtmap);
+    hipFree(pl->mqr2);
+    hipFree(pl->mqtot);
     for (hipEvent_t e : pl->ev_pool) hipEventDestroy(e);
     for (auto &v : pl->ev_pending)
         for (auto &pr : v) {
@@ -271,7 +283,7 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMemsetAsync(pl->small, 0, sizeof(int) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->sums, 0, sizeof(double) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->M, 0, (size_t)(pl->P + 1) * pl->K * t, s));
-    return pl->prec == PMMM_F32 ? make_twiddles<float>(pl, s) : make_twiddles<double>(pl, s);
+    return pl->prec == PMMM_F64 ? make_twiddles<double>(pl, s) : make_twiddles<float>(pl, s);
 }
 
 // Lanes per cell in the light P2M path: about four particles per lane.
@@ -428,6 +440,147 @@ static int near_impl(pmmm_plan_s *pl, int64_t n, T *phi, T *gx, T *gy, T *gz, in
     return PMMM_OK;
 }
 
+static int ensure_multi(Plan *pl, int sets, hipStream_t s) {
+    if (pl->mtmap == nullptr) {
+        std::vector<unsigned> map(multi_map_entries(pl->p));
+        build_multi_map(pl->p, map.data());
+        PMMM_HIP(hipMalloc(&pl->mtmap, map.size() * sizeof(unsigned)));
+        PMMM_HIP(hipMemcpyAsync(pl->mtmap, map.data(), map.size() * sizeof(unsigned),
+                                hipMemcpyHostToDevice, s));
+        PMMM_HIP(hipStreamSynchronize(s));
+    }
+    if (sets <= pl->mcap_sets) return PMMM_OK;
+    PMMM_HIP(hipDeviceSynchronize());
+    hipFree(pl->mM);
+    hipFree(pl->mX);
+    hipFree(pl->mqr2);
+    hipFree(pl->mqtot);
+    pl->mM = nullptr;
+    pl->mX = nullptr;
+    pl->mqr2 = pl->mqtot = nullptr;
+    pl->mcap_sets = 0;
+    const size_t P = pl->P, K = pl->K;
+    PMMM_HIP(hipMalloc(&pl->mM, (size_t)sets * (P + 1) * K * sizeof(float)));
+    PMMM_HIP(hipMalloc(&pl->mX, (size_t)sets * P * pl->nf * pl->ncol * 2 * sizeof(float)));
+    PMMM_HIP(hipMalloc(&pl->mqr2, (size_t)sets * kMultiZA * sizeof(double)));
+    PMMM_HIP(hipMalloc(&pl->mqtot, (size_t)sets * sizeof(double)));
+    pl->mcap_sets = sets;
+    return PMMM_OK;
+}
+
+// Sets per column-GEMM block: the largest multiple of 8 (at most the chunk,
+// rounded up) whose tile fits the LDS of one CU.
+static int multi_set_tile(const Plan *pl, int split, int sets) {
+    int st = ((sets + 7) / 8) * 8;
+    if (st > kMultiMaxSets) st = kMultiMaxSets;
+    while (st > 8 && multi_column_lds(pl->p, split, st) == 0) st -= 8;
+    return multi_column_lds(pl->p, split, st) ? st : 0;
+}
+
+static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y,
+                      const float *z, int nsets, const float *q, float *phi, float *gx,
+                      float *gy, float *gz, void *stream) {
+    if (!pl) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    if (pl->tsize != sizeof(float)) {
+        set_error("multi-charge calls need a PMMM_F32 or PMMM_BF16X3 plan");
+        return PMMM_EINVAL;
+    }
+    if (n < 0 || nsets < 1) {
+        set_error("n must be non-negative and nsets positive");
+        return PMMM_EINVAL;
+    }
+    if (n > 0 && (!x || !y || !z || !q || !phi || !gx || !gy || !gz)) {
+        set_error("NULL particle or output pointer");
+        return PMMM_EINVAL;
+    }
+    if (pl->open || pl->nf % kMultiZA != 0 || pl->nf > 32) {
+        set_error("multi-charge calls are built for periodic meshes of 4 to 32 cells per axis");
+        return PMMM_EUNSUPPORTED;
+    }
+    const int split = pl->prec == PMMM_BF16X3 ? 2 : 3;
+    const int chunk = nsets < kMultiMaxSets ? nsets : kMultiMaxSets;
+    if (multi_set_tile(pl, split, 8) == 0) {
+        set_error("order too high for the multi-charge column tile");
+        return PMMM_EUNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    PMMM_HIP(hipGetDevice(&cur));
+    if (cur != pl->device) {
+        set_error("current device differs from the plan's device");
+        return PMMM_EINVAL;
+    }
+    int rc = ensure_capacity(pl, n > 0 ? n : 1);
+    if (rc != PMMM_OK) return rc;
+    rc = ensure_multi(pl, chunk, s);
+    if (rc != PMMM_OK) return rc;
+    pl->last_stream = s;
+    pl->last_n = n;
+    {
+        StageTimer t(pl, PMMM_STAGE_BIN, s);
+        BinArgs b{};
+        b.n = n;
+        b.x = x;
+        b.y = y;
+        b.z = z;
+        b.q = nullptr;            // sorted charges stay zero; the sets are read by P2M
+        b.ncell = pl->n;
+        b.inv_h = pl->inv_h;
+        b.periodic = 1;
+        b.cell_of = pl->cell_of;
+        b.slot = pl->slot;
+        b.count = pl->count;
+        b.start = pl->start;
+        b.scell = pl->scell;
+        b.perm = pl->perm;
+        b.flag = pl->small + 1;
+        b.dense_cells = pl->dense_cells;
+        b.dense_count = pl->small;
+        b.dense_threshold = kDenseThreshold;
+        b.sorted = pl->sorted;
+        PMMM_HIP(launch_bin<float>(b, s));
+    }
+    for (int s0 = 0; s0 < nsets; s0 += kMultiMaxSets) {
+        const int S = nsets - s0 < kMultiMaxSets ? nsets - s0 : kMultiMaxSets;
+        MultiArgs a{};
+        a.p = pl->p;
+        a.n = pl->n;
+        a.nsets = S;
+        a.split = split;
+        a.set_tile = multi_set_tile(pl, split, S);
+        a.np = n;
+        a.ld = nsets;
+        a.start = pl->start;
+        a.perm = pl->perm;
+        a.zero_count = (s0 == 0 && n > 0 && pl->K <= 4096) ? pl->count : nullptr;
+        a.sorted = pl->sorted;
+        a.q = q + s0;
+        a.M = pl->mM;
+        a.X = pl->mX;
+        a.green = (const float *)pl->green;
+        a.tw = pl->tw;
+        a.tmap = pl->mtmap;
+        a.qr2_partial = pl->mqr2;
+        a.qtot = pl->mqtot;
+        a.alpha_cell = pl->alpha_cell;
+        a.inv_h = pl->inv_h;
+        a.phi = phi + s0;
+        a.gx = gx + s0;
+        a.gy = gy + s0;
+        a.gz = gz + s0;
+        static const int stage_of[5] = {PMMM_STAGE_P2M, PMMM_STAGE_FFT_FWD, PMMM_STAGE_COLUMN,
+                                        PMMM_STAGE_FFT_INV, PMMM_STAGE_L2P};
+        for (int st = 0; st < 5; ++st) {
+            StageTimer t(pl, stage_of[st], s);
+            PMMM_HIP(launch_multi_stage(a, st, s));
+        }
+    }
+    return PMMM_OK;
+}
+
 extern "C" {
 
 int pmmm_plan_create(const pmmm_params *params, void *stream, pmmm_plan *out) {
@@ -463,7 +616,7 @@ int pmmm_plan_create(const pmmm_params *params, void *stream, pmmm_plan *out) {
         g.images = pl->images;
         g.alpha_cell = pl->alpha_cell;
         g.green_out = pl->green;
-        e = pl->prec == PMMM_F32 ? build_green<float>(g, s) : build_green<double>(g, s);
+        e = pl->prec == PMMM_F64 ? build_green<double>(g, s) : build_green<float>(g, s);
         if (e != hipSuccess) rc = hip_fail(e, "transfer kernel build");
     }
     if (rc != PMMM_OK) {
@@ -493,6 +646,12 @@ int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y, co
                  const double *q, double *phi, double *gx, double *gy, double *gz,
                  void *stream) {
     return far_impl<double>(plan, n, x, y, z, q, phi, gx, gy, gz, stream);
+}
+
+int pmmm_far_multi_f32(pmmm_plan plan, int64_t n, const float *x, const float *y,
+                       const float *z, int nsets, const float *q, float *phi, float *gx,
+                       float *gy, float *gz, void *stream) {
+    return multi_impl(plan, n, x, y, z, nsets, q, phi, gx, gy, gz, stream);
 }
 
 int pmmm_near_f32(pmmm_plan plan, int64_t n, float *phi, float *gx, float *gy, float *gz,

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     cell_coord(x[i], inv_h, nc, periodic, ix, r.ux, out);
     cell_coord(y[i], inv_h, nc, periodic, iy, r.uy, out);
     cell_coord(z[i], inv_h, nc, periodic, iz, r.uz, out);
-    r.q = q[i];
+    r.q = q != nullptr ? q[i] : T(0);
     const int c = cell_of[i];
     const int s = (inblock ? s_start[c] : start[c]) + slot[i];
     if (s < 0 || (int64_t)s >= n) return;  // only reachable with inconsistent counts

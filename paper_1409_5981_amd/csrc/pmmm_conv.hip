@@ -167,24 +167,6 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
 }
 
 // ---------------------------------------------------------------- columns
-// Value of Re S_n^k and Im S_n^k (any k) as sign * g[n + idx] where g holds
-// the stored components of order n at offsets k + n (k = -n..n): offset n+k
-// (k >= 0) is Re S_n^k, offset n-k (k > 0) is Im S_n^k.  sign 0 = zero.
-struct Term {
-    int off;
-    int sgn;
-};
-__host__ __device__ constexpr Term re_S(int n, int k) {
-    return (k > n || k < -n) ? Term{0, 0}
-           : (k >= 0)        ? Term{n + k, 1}
-                             : Term{n - k, ((-k) & 1) ? -1 : 1};
-}
-__host__ __device__ constexpr Term im_S(int n, int k) {
-    return (k > n || k < -n || k == 0) ? Term{0, 0}
-           : (k > 0)                   ? Term{n - k, 1}
-                                       : Term{n + k, ((-k) & 1) ? 1 : -1};
-}
-
 template <typename T>
 __device__ __forceinline__ T term2(const T *g, Term a, int sa, Term b, int sb) {
     // sa * a + sb * b with compile-time signs after unrolling

@@ -336,6 +336,25 @@ __device__ void fft_lines(cplx<T> *buf, int logn, int nlines, int lstride, int e
 // n <= 16, so pad by one element to spread the lines over the LDS banks.
 __host__ __device__ constexpr int lds_line(int n) { return n <= 16 ? n + 1 : n; }
 
+// ------------------------------------------------- transfer-kernel terms
+// Value of Re S_n^k and Im S_n^k (any k) as sign * g[n + idx] where g holds
+// the stored components of order n at offsets k + n (k = -n..n): offset n+k
+// (k >= 0) is Re S_n^k, offset n-k (k > 0) is Im S_n^k.  sign 0 = zero.
+struct Term {
+    int off;
+    int sgn;
+};
+__host__ __device__ constexpr Term re_S(int n, int k) {
+    return (k > n || k < -n) ? Term{0, 0}
+           : (k >= 0)        ? Term{n + k, 1}
+                             : Term{n - k, ((-k) & 1) ? -1 : 1};
+}
+__host__ __device__ constexpr Term im_S(int n, int k) {
+    return (k > n || k < -n || k == 0) ? Term{0, 0}
+           : (k > 0)                   ? Term{n - k, 1}
+                                       : Term{n + k, ((-k) & 1) ? 1 : -1};
+}
+
 // ------------------------------------------------------------ host side
 struct Plan;  // defined in pmmm_api.hip
 
@@ -445,5 +464,44 @@ struct GreenArgs {
 };
 template <typename T>
 hipError_t build_green(const GreenArgs &a, hipStream_t s);
+
+// Multi-charge periodic pipeline (FP32 storage; M2L on the BF16 matrix
+// cores).  nf = 4 B; the z transform is split between the slab kernels
+// (B-point stage over the planes z1 + 4 j) and the column kernel (4-point
+// stage over z1).
+constexpr int kMultiZA = 4;     // z frequencies per column-GEMM block
+constexpr int kMultiMaxSets = 64;
+
+// t-matrix map of one (P x P) real M2L matrix in MFMA A-fragment order:
+// [RT][KS][64 lanes][8] codes, RT = ceil(P/16), KS = ceil(P/32).  Code bits
+// 0-8: index of the first kernel value, 9-10: its sign (0 none, 1 +, 2 -),
+// 11-19 and 20-21: the second.
+size_t multi_map_entries(int p);
+void build_multi_map(int p, unsigned *out);
+
+struct MultiArgs {
+    int p, n, nsets;                // n = nf (periodic)
+    int split;                      // bf16 terms per operand: 2 or 3
+    int set_tile;                   // sets per column-GEMM block
+    int64_t np;                     // particles
+    int64_t ld;                     // row stride of q and the outputs (sets)
+    const int *start, *perm;
+    int *zero_count;                // counts to reset for the next binning (or null)
+    const void *sorted;             // particle4<float>[np]
+    const float *q;                 // [np][ld], this chunk's first set at column 0
+    float *M;                       // [S][P+1][K] moments and q|u|^2; then L [S][P][K]
+    void *X;                        // cplx<float>[B][ncol][4][S*P]
+    const float *green;             // [nh][nh][Q][nhp]
+    const void *tw;                 // cplx<float>[nf/2]
+    const unsigned *tmap;           // build_multi_map(p)
+    double *qr2_partial;            // [S][4]
+    double *qtot;                   // [S]
+    double alpha_cell, inv_h;
+    float *phi, *gx, *gy, *gz;      // [np][ld]
+};
+// stage 0: P2M, 1: slab forward, 2: column GEMM, 3: slab inverse, 4: L2P
+hipError_t launch_multi_stage(const MultiArgs &a, int stage, hipStream_t s);
+// LDS bytes of the column-GEMM block for a set tile (0 if it does not fit).
+size_t multi_column_lds(int p, int split, int set_tile);
 
 }  // namespace pmmm

@@ -29,7 +29,36 @@ JOBS = {
 }
 
 
+MULTI = {
+    # name -> (generator, sets evaluated)
+    "multi_periodic_n1048576_m32_p6_s64": (inputs.multi_charge_sets, [0, 21, 42, 63]),
+}
+
+
+def make_multi(name: str) -> str:
+    t0 = time.time()
+    gen, sets = MULTI[name]
+    ps, qs = gen()
+    cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=2)
+    rng = np.random.Generator(np.random.PCG64(1234))
+    idx = np.sort(rng.choice(ps.n, size=SAMPLE, replace=False))
+    phis, grads = [], []
+    for s in sets:
+        res = opm.far_field(ps.pos, qs[s].astype(np.float64), cfg, eval_idx=idx)
+        phis.append(res.phi)
+        grads.append(res.grad)
+        print(f"{name}: set {s} done at {time.time() - t0:.0f} s", flush=True)
+    path = os.path.join(HERE, f"ref_{name}.npz")
+    np.savez_compressed(path, idx=idx, sets=np.array(sets), phi=np.stack(phis),
+                        grad=np.stack(grads), n=ps.n, n_sets=qs.shape[0],
+                        n_cells=ps.n_cells, p=ps.p, boundary=ps.boundary)
+    print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
+    return path
+
+
 def make(name: str) -> str:
+    if name in MULTI:
+        return make_multi(name)
     t0 = time.time()
     ps = JOBS[name]()
     cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=2)
@@ -44,5 +73,5 @@ def make(name: str) -> str:
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or list(JOBS)):
+    for nm in (sys.argv[1:] or list(JOBS) + list(MULTI)):
         make(nm)
