@@ -40,8 +40,8 @@ struct Plan {
     hipStream_t last_stream = nullptr;
     // multi-charge workspace (chunks of up to kMultiMaxSets sets)
     int mcap_sets = 0;
-    float *mM = nullptr;          // [S][P+1][K] moments, then [S][P][K] local expansions
-    void *mX = nullptr;           // split-z spectra
+    float *mM = nullptr;          // [K][P+1][S] moments, then [K][P][S] local expansions
+    void *mY = nullptr;           // [nf][nf][nf/2+1][P S] spectra
     unsigned *mtmap = nullptr;    // t-matrix map in MFMA fragment order
     double *mqr2 = nullptr, *mqtot = nullptr;
     // stage timing
@@ -243,7 +243,7 @@ static void destroy(Plan *pl) {
     hipFree(pl->sums);
     hipFree(pl->qr2_partial);
     hipFree(pl->mM);
-    hipFree(pl->mX);
+    hipFree(pl->mY);
     hipFree(pl->mtmap);
     hipFree(pl->mqr2);
     hipFree(pl->mqtot);
@@ -452,29 +452,21 @@ static int ensure_multi(Plan *pl, int sets, hipStream_t s) {
     if (sets <= pl->mcap_sets) return PMMM_OK;
     PMMM_HIP(hipDeviceSynchronize());
     hipFree(pl->mM);
-    hipFree(pl->mX);
+    hipFree(pl->mY);
     hipFree(pl->mqr2);
     hipFree(pl->mqtot);
     pl->mM = nullptr;
-    pl->mX = nullptr;
+    pl->mY = nullptr;
     pl->mqr2 = pl->mqtot = nullptr;
     pl->mcap_sets = 0;
     const size_t P = pl->P, K = pl->K;
     PMMM_HIP(hipMalloc(&pl->mM, (size_t)sets * (P + 1) * K * sizeof(float)));
-    PMMM_HIP(hipMalloc(&pl->mX, (size_t)sets * P * pl->nf * pl->ncol * 2 * sizeof(float)));
-    PMMM_HIP(hipMalloc(&pl->mqr2, (size_t)sets * kMultiZA * sizeof(double)));
+    // spectra: one slice of P sets complex values (padded to even) per frequency
+    PMMM_HIP(hipMalloc(&pl->mY, ((size_t)sets * P + 1) * pl->nf * pl->ncol * 2 * sizeof(float)));
+    PMMM_HIP(hipMalloc(&pl->mqr2, (size_t)sets * pl->nf * sizeof(double)));
     PMMM_HIP(hipMalloc(&pl->mqtot, (size_t)sets * sizeof(double)));
     pl->mcap_sets = sets;
     return PMMM_OK;
-}
-
-// Sets per column-GEMM block: the largest multiple of 8 (at most the chunk,
-// rounded up) whose tile fits the LDS of one CU.
-static int multi_set_tile(const Plan *pl, int split, int sets) {
-    int st = ((sets + 7) / 8) * 8;
-    if (st > kMultiMaxSets) st = kMultiMaxSets;
-    while (st > 8 && multi_column_lds(pl->p, split, st) == 0) st -= 8;
-    return multi_column_lds(pl->p, split, st) ? st : 0;
 }
 
 static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y,
@@ -496,16 +488,13 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         set_error("NULL particle or output pointer");
         return PMMM_EINVAL;
     }
-    if (pl->open || pl->nf % kMultiZA != 0 || pl->nf > 32) {
-        set_error("multi-charge calls are built for periodic meshes of 4 to 32 cells per axis");
+    if (pl->open || !multi_supported(pl->p, pl->nf)) {
+        set_error("multi-charge calls are built for periodic meshes of 4, 8, 16 or 32 cells "
+                  "per axis (p <= 7 at 32)");
         return PMMM_EUNSUPPORTED;
     }
     const int split = pl->prec == PMMM_BF16X3 ? 2 : 3;
     const int chunk = nsets < kMultiMaxSets ? nsets : kMultiMaxSets;
-    if (multi_set_tile(pl, split, 8) == 0) {
-        set_error("order too high for the multi-charge column tile");
-        return PMMM_EUNSUPPORTED;
-    }
     hipStream_t s = (hipStream_t)stream;
     int cur = 0;
     PMMM_HIP(hipGetDevice(&cur));
@@ -550,7 +539,6 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         a.n = pl->n;
         a.nsets = S;
         a.split = split;
-        a.set_tile = multi_set_tile(pl, split, S);
         a.np = n;
         a.ld = nsets;
         a.start = pl->start;
@@ -559,7 +547,7 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         a.sorted = pl->sorted;
         a.q = q + s0;
         a.M = pl->mM;
-        a.X = pl->mX;
+        a.Y = pl->mY;
         a.green = (const float *)pl->green;
         a.tw = pl->tw;
         a.tmap = pl->mtmap;

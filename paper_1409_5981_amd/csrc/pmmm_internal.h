@@ -206,16 +206,19 @@ __host__ __device__ constexpr int brevc(int v, int bits) {
     return bits == 0 ? 0 : ((v & 1) << (bits - 1)) | brevc(v >> 1, bits - 1);
 }
 
-// exp(-+ 2 pi i k / 16) for 0 <= k < 8 (forward: minus sign).
+// exp(-+ 2 pi i k / 32) for 0 <= k < 16 (forward: minus sign).
 template <typename T, bool INV, int K>
-__device__ __forceinline__ cplx<T> w16() {
-    constexpr double C1 = 0.92387953251128674, S1 = 0.38268343236508978, R2 = 0.70710678118654752;
-    constexpr double c[8] = {1.0, C1, R2, S1, 0.0, -S1, -R2, -C1};
-    constexpr double sn[8] = {0.0, S1, R2, C1, 1.0, C1, R2, S1};
+__device__ __forceinline__ cplx<T> w32() {
+    constexpr double C1 = 0.98078528040323044913, S1 = 0.19509032201612826785;  // pi/16
+    constexpr double C2 = 0.92387953251128674, S2 = 0.38268343236508978;          // pi/8
+    constexpr double C3 = 0.83146961230254523708, S3 = 0.55557023301960222474;  // 3 pi/16
+    constexpr double R2 = 0.70710678118654752;
+    constexpr double c[16] = {1.0, C1, C2, C3, R2, S3, S2, S1, 0.0, -S1, -S2, -S3, -R2, -C3, -C2, -C1};
+    constexpr double sn[16] = {0.0, S1, S2, S3, R2, C3, C2, C1, 1.0, C1, C2, C3, R2, S3, S2, S1};
     return {T(c[K]), INV ? T(sn[K]) : T(-sn[K])};
 }
 
-// In-register FFT of R = 1..16 points, natural order in and out (radix-2
+// In-register FFT of R = 1..32 points, natural order in and out (radix-2
 // decimation in time on the bit-reversed copy), unnormalised.
 template <int R, bool INV, typename T>
 __device__ __forceinline__ void fft_reg(cplx<T> *v) {
@@ -231,11 +234,11 @@ __device__ __forceinline__ void fft_reg(cplx<T> *v) {
             constexpr int span = 2 * half;
             static_for<0, half>([&](auto ij) {
                 constexpr int j = decltype(ij)::value;
-                constexpr int k16 = j * (16 / span);
+                constexpr int k32 = j * (32 / span);
                 static_for<0, R / span>([&](auto ig) {
                     constexpr int i0 = decltype(ig)::value * span + j, i1 = i0 + half;
                     cplx<T> b = a[i1];
-                    if constexpr (k16 != 0) b = cmul(b, w16<T, INV, k16>());
+                    if constexpr (k32 != 0) b = cmul(b, w32<T, INV, k32>());
                     a[i1] = {a[i0].re - b.re, a[i0].im - b.im};
                     a[i0] = {a[i0].re + b.re, a[i0].im + b.im};
                 });
@@ -466,11 +469,13 @@ template <typename T>
 hipError_t build_green(const GreenArgs &a, hipStream_t s);
 
 // Multi-charge periodic pipeline (FP32 storage; M2L on the BF16 matrix
-// cores).  nf = 4 B; the z transform is split between the slab kernels
-// (B-point stage over the planes z1 + 4 j) and the column kernel (4-point
-// stage over z1).
-constexpr int kMultiZA = 4;     // z frequencies per column-GEMM block
+// cores).  Meshes are point-major with the set index fastest: component b of
+// set s at point x lives at [x][b S + s], so the particle kernels (one lane
+// per set) and the FFT kernels (tiles of consecutive components) both make
+// contiguous accesses.
 constexpr int kMultiMaxSets = 64;
+constexpr int kMultiSetTile = 8;       // sets per column-GEMM block
+constexpr int kMultiCompTile = 16;     // components per plane-FFT block
 
 // t-matrix map of one (P x P) real M2L matrix in MFMA A-fragment order:
 // [RT][KS][64 lanes][8] codes, RT = ceil(P/16), KS = ceil(P/32).  Code bits
@@ -482,26 +487,26 @@ void build_multi_map(int p, unsigned *out);
 struct MultiArgs {
     int p, n, nsets;                // n = nf (periodic)
     int split;                      // bf16 terms per operand: 2 or 3
-    int set_tile;                   // sets per column-GEMM block
     int64_t np;                     // particles
     int64_t ld;                     // row stride of q and the outputs (sets)
     const int *start, *perm;
     int *zero_count;                // counts to reset for the next binning (or null)
     const void *sorted;             // particle4<float>[np]
     const float *q;                 // [np][ld], this chunk's first set at column 0
-    float *M;                       // [S][P+1][K] moments and q|u|^2; then L [S][P][K]
-    void *X;                        // cplx<float>[B][ncol][4][S*P]
+    float *M;                       // [K][P+1][S] moments and q|u|^2; then L [K][P][S]
+    void *Y;                        // cplx<float>[nf][nf][nf/2+1][P S (+1: even)] spectra
     const float *green;             // [nh][nh][Q][nhp]
     const void *tw;                 // cplx<float>[nf/2]
     const unsigned *tmap;           // build_multi_map(p)
-    double *qr2_partial;            // [S][4]
+    double *qr2_partial;            // [nf][S] per-plane sums of q|u|^2
     double *qtot;                   // [S]
     double alpha_cell, inv_h;
     float *phi, *gx, *gy, *gz;      // [np][ld]
 };
-// stage 0: P2M, 1: slab forward, 2: column GEMM, 3: slab inverse, 4: L2P
+// stage 0: P2M, 1: forward x-y FFTs, 2: column (z FFT, M2L GEMM, inverse z
+// FFT), 3: inverse y-x FFTs, 4: L2P
 hipError_t launch_multi_stage(const MultiArgs &a, int stage, hipStream_t s);
-// LDS bytes of the column-GEMM block for a set tile (0 if it does not fit).
-size_t multi_column_lds(int p, int split, int set_tile);
+// Orders and meshes the multi-charge kernels are built for.
+bool multi_supported(int p, int nf);
 
 }  // namespace pmmm

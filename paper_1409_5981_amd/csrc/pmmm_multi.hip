@@ -10,33 +10,31 @@
 // products) keep about 16 bits of each operand; three terms (six products)
 // keep all 24.
 //
+// Meshes are point-major with the set index fastest (component b of set s at
+// point x is element [x][b S + s]): the particle kernels give each set one
+// lane, the FFT kernels take tiles of consecutive components, and all their
+// global accesses are contiguous runs.
 //   k_p2m_multi     one wave per cell, one lane per set: eq. P2M with the
 //                   harmonics R(r_M - r_i) of the cell's particles staged in
 //                   LDS and read by every lane.
-//   k_slab_fwd      one component of one set and the B planes z1 + 4 j:
-//                   x and y FFTs, then the first z stage.
-//   k_column_multi  one (ky, kx) column, one z residue r and a tile of sets:
-//                   last z stage, the M2L product at the four frequencies
-//                   kz = B q + r, inverse z stage.
-//   k_slab_inv      inverse of k_slab_fwd, scaled by 1/nf^3.
+//   k_xy_fwd        one z-plane and 16 components: real FFT along x (two
+//                   rows per complex transform) and FFT along y, in
+//                   registers, through one LDS transpose.
+//   k_z_fft         FFT along z (forward or inverse), one thread per
+//                   (column, component) line, in registers.
+//   k_m2l_gemm      one frequency: t (eq. realmatrix) built once in MFMA
+//                   fragments and applied to all sets at once.
+//   k_xy_inv        inverse of k_xy_fwd, scaled by 1/nf^3.
 //   k_l2p_multi     one wave per cell, one lane per set: eq. L2P and the
 //                   order-one eq. L2L of eq. phigrad, with the cell's local
 //                   expansion folded into per-set coefficient vectors.
-//
-// Split z transform, nf = 4 B, z = z1 + 4 j, kz = B q + r:
-//   M~(B q + r) = sum_z1 W_4^(z1 q) W_nf^(z1 r) sum_j W_B^(j r) M(z1 + 4 j)
-//   L(z1 + 4 j) = sum_r W_B^(-j r) W_nf^(-z1 r) sum_q W_4^(-z1 q) L~(B q + r)
-// Between the slab and column kernels the spectra live as
-// X[r][col][z1][s P + b] (col = ky (nf/2+1) + kx), so one column block reads
-// and writes one contiguous range per z1.
 #include "pmmm_internal.h"
 
 namespace pmmm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kZA = kMultiZA;
 
 // LDS written by some lanes of a wave and read by others of the same wave:
 // the wave's LDS operations complete in order, so a wave-scope fence and a
@@ -53,13 +51,9 @@ __host__ __device__ constexpr int order_of(int a) {
     return l;
 }
 
-// exp(-2 pi i e / nf) from the half table tw[k] = exp(-2 pi i k / nf).
-__device__ __forceinline__ cplx<float> tw_at(const cplx<float> *tw, int e, int nf) {
-    e &= nf - 1;
-    if (e < nf / 2) return tw[e];
-    const cplx<float> w = tw[e - nf / 2];
-    return {-w.re, -w.im};
-}
+// Order of real component a (a < 2^20) without a loop: sqrt(a + 1/2) lies
+// strictly between l and l + 1.
+__device__ __forceinline__ int order_fast(int a) { return (int)__builtin_sqrtf((float)a + 0.5f); }
 
 // ------------------------------------------------------------------- P2M
 // Row stride of the staged harmonics (16-byte rows for vector LDS reads).
@@ -123,7 +117,7 @@ __global__ void __launch_bounds__(256) k_p2m_multi(int K, int cells_per_block,
         }
         if (lane < S) {
 #pragma unroll
-            for (int a = 0; a <= P; ++a) M[((int64_t)lane * (P + 1) + a) * K + c] = acc[a];
+            for (int a = 0; a <= P; ++a) M[((int64_t)c * (P + 1) + a) * S + lane] = acc[a];
         }
     }
 }
@@ -204,7 +198,7 @@ __global__ void __launch_bounds__(256) k_l2p_multi(int K, int cells_per_block,
         if (lane < S) {
             float Lc[P];
 #pragma unroll
-            for (int a = 0; a < P; ++a) Lc[a] = L[((int64_t)lane * P + a) * K + c];
+            for (int a = 0; a < P; ++a) Lc[a] = L[((int64_t)c * P + a) * S + lane];
             l2p_vectors<PO>(Lc, lh, vx, vy, vz);
             // charged periodic system: Phi += 2 pi/(3V) Q (|u|^2 - 3/(2 alpha^2)),
             // grad += 4 pi/(3V) Q u, V = K in cell units
@@ -256,176 +250,164 @@ __global__ void __launch_bounds__(256) k_l2p_multi(int K, int cells_per_block,
     }
 }
 
-// ----------------------------------------------------------------- slabs
-// Block -> (z1, component): each XCD (blocks are dealt round-robin over the
-// 8 XCDs) takes a contiguous range, so the blocks that run together on one
-// XCD share z1 and hold neighbouring components; their 8-byte stores to
-// X[r][col][z1][.] then meet in the same L2 lines.
-__device__ __forceinline__ int slab_block(int nblk) {
+// ------------------------------------------------------- x-y plane FFTs
+// Block -> (z-plane, component tile) with the tile fastest; each XCD (blocks
+// are dealt round-robin over the 8 XCDs) takes a contiguous range, so
+// neighbouring tiles, which share cache lines, run on one XCD.
+__device__ __forceinline__ int xcd_block(int nblk) {
     const int per_xcd = (nblk + 7) / 8;
     return (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
 }
 
-template <int B>
-__global__ void __launch_bounds__(256) k_slab_fwd(int logn, int S, int P,
-                                                  const float *__restrict__ M,
-                                                  cplx<float> *__restrict__ X,
-                                                  const cplx<float> *__restrict__ tw_g,
-                                                  double *__restrict__ qr2_partial) {
+template <int NF>
+__global__ void __launch_bounds__(256) k_xy_fwd(int S, int P, const float *__restrict__ M,
+                                                cplx<float> *__restrict__ Y,
+                                                double *__restrict__ qr2_partial) {
+    constexpr int NH = NF / 2 + 1, CT = kMultiCompTile, NPAIR = NF / 2;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn, nh = nf / 2 + 1, npair = nf / 2, ls = lds_line(nf);
-    const int ncol = nf * nh, SP = S * P;
-    const int64_t K = (int64_t)nf * nf * nf;
-    cplx<float> *tw = (cplx<float> *)lds_raw;
-    cplx<float> *rows = tw + nf / 2;                 // [B][npair][ls]
-    cplx<float> *slab = rows + B * npair * ls;       // [nf y][B j][nh kx]
-    const int v = slab_block(kZA * SP);
-    if (v >= kZA * SP) return;
-    const int z1 = v / SP, c = v - z1 * SP;
-    const int s = c / P, b = c - s * P;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
-    const float *comp = M + ((int64_t)s * (P + 1) + b) * K;
-    // planes z = z1 + 4 j as pairs of real rows packed into complex rows
-    const int nrow = B * npair * nf;
-    for (int base = tid; base < nrow; base += nthr * 8) {
-        cplx<float> vv[8];
+    cplx<float> *Z = (cplx<float> *)lds_raw;          // [NF y][NH kx][CT]
+    const int SP = S * P, SP1 = S * (P + 1), sps = (SP + 1) & ~1;
+    const int ntile = (SP + CT - 1) / CT;
+    const int v = xcd_block(NF * ntile);
+    if (v >= NF * ntile) return;
+    const int z = v / ntile, tile = v - z * ntile;
+    const int c0 = tile * CT;
+    const int tid = threadIdx.x;
+    const float *plane = M + (int64_t)z * NF * NF * SP1;
+    // x transforms: rows 2jj and 2jj+1 as the real and imaginary parts
+    for (int item = tid; item < NPAIR * CT; item += 256) {
+        const int jj = item / CT, ct = item - jj * CT, c = c0 + ct;
+        const bool ok = c < SP;
+        cplx<float> w[NF];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = base + u * nthr;
-            if (idx < nrow) {
-                const int j = idx / (npair * nf), rem = idx - j * npair * nf;
-                const int jj = rem >> logn, x = rem & (nf - 1);
-                const float *pl = comp + (int64_t)(z1 + kZA * j) * nf * nf;
-                vv[u].re = pl[(2 * jj) * nf + x];
-                vv[u].im = pl[(2 * jj + 1) * nf + x];
-            }
+        for (int x = 0; x < NF; ++x) {
+            w[x].re = ok ? plane[((int64_t)(2 * jj) * NF + x) * SP1 + c] : 0.f;
+            w[x].im = ok ? plane[((int64_t)(2 * jj + 1) * NF + x) * SP1 + c] : 0.f;
         }
+        fft_reg<NF, false, float>(w);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = base + u * nthr;
-            if (idx < nrow) {
-                const int j = idx / (npair * nf), rem = idx - j * npair * nf;
-                const int jj = rem >> logn, x = rem & (nf - 1);
-                rows[(j * npair + jj) * ls + x] = vv[u];
-            }
+        for (int k = 0; k < NH; ++k) {
+            const cplx<float> zk = w[k], zm = w[(NF - k) & (NF - 1)];
+            Z[((2 * jj) * NH + k) * CT + ct] = {0.5f * (zk.re + zm.re), 0.5f * (zk.im - zm.im)};
+            Z[((2 * jj + 1) * NH + k) * CT + ct] = {0.5f * (zk.im + zm.im), -0.5f * (zk.re - zm.re)};
         }
     }
     __syncthreads();
-    fft_lines<float, false>(rows, logn, B * npair, ls, 1, tw, tid, nthr);
-    for (int idx = tid; idx < B * nf * nh; idx += nthr) {
-        const int j = idx / (nf * nh), rem = idx - j * nf * nh;
-        const int y = rem / nh, k = rem - y * nh;
-        const cplx<float> *row = rows + (j * npair + (y >> 1)) * ls;
-        const cplx<float> zk = row[k & (nf - 1)];
-        const cplx<float> zm = row[(nf - k) & (nf - 1)];
-        cplx<float> o;
-        if ((y & 1) == 0) {
-            o.re = 0.5f * (zk.re + zm.re);
-            o.im = 0.5f * (zk.im - zm.im);
-        } else {
-            o.re = 0.5f * (zk.im + zm.im);
-            o.im = -0.5f * (zk.re - zm.re);
-        }
-        slab[(y * B + j) * nh + k] = o;
-    }
-    __syncthreads();
-    // y transforms: line (j, kx) starts at j nh + kx, elements B nh apart
-    fft_lines<float, false>(slab, logn, B * nh, 1, B * nh, tw, tid, nthr);
-    // first z stage: B-point DFT over j, twiddle W_nf^(z1 r)
-    for (int pt = tid; pt < ncol; pt += nthr) {
-        const int y = pt / nh, kx = pt - y * nh;
-        cplx<float> w8[B];
+    // y transforms, written straight to the spectra
+    for (int item = tid; item < NH * CT; item += 256) {
+        const int kx = item / CT, ct = item - kx * CT, c = c0 + ct;
+        cplx<float> w[NF];
 #pragma unroll
-        for (int j = 0; j < B; ++j) w8[j] = slab[(y * B + j) * nh + kx];
-        fft_reg<B, false, float>(w8);
+        for (int y = 0; y < NF; ++y) w[y] = Z[(y * NH + kx) * CT + ct];
+        fft_reg<NF, false, float>(w);
+        if (c < SP) {
 #pragma unroll
-        for (int r = 0; r < B; ++r) {
-            const cplx<float> o = r == 0 ? w8[0] : cmul(w8[r], tw_at(tw, z1 * r, nf));
-            X[(((int64_t)r * ncol + pt) * kZA + z1) * SP + c] = o;
+            for (int ky = 0; ky < NF; ++ky) Y[((int64_t)(z * NF + ky) * NH + kx) * sps + c] = w[ky];
         }
     }
-    if (b == 0) {
-        // this set's sum of q|u|^2 over the block's planes (component P of M),
+    if (c0 < S) {
+        // sum over this plane of q|u|^2 (component P) for the sets [c0, c0 + CT),
         // fixed-order reduction
-        __shared__ double red[256];
-        const float *pq = M + ((int64_t)s * (P + 1) + P) * K;
-        double acc = 0.0;
-        for (int idx = tid; idx < B * nf * nf; idx += nthr) {
-            const int j = idx / (nf * nf), rem = idx - j * nf * nf;
-            acc += (double)pq[(int64_t)(z1 + kZA * j) * nf * nf + rem];
-        }
-        red[tid] = acc;
+        constexpr int PARTS = 256 / CT;
         __syncthreads();
-        for (int off = 128; off >= 1; off >>= 1) {
-            if (tid < off) red[tid] += red[tid + off];
-            __syncthreads();
+        double *red = (double *)lds_raw;
+        const int ct = tid % CT, part = tid / CT, s = c0 + ct;
+        double acc = 0.0;
+        if (s < S)
+            for (int cell = part; cell < NF * NF; cell += PARTS)
+                acc += (double)plane[(int64_t)cell * SP1 + SP + s];
+        red[part * CT + ct] = acc;
+        __syncthreads();
+        if (tid < CT && c0 + tid < S) {
+            double t = 0.0;
+            for (int pp = 0; pp < PARTS; ++pp) t += red[pp * CT + tid];
+            qr2_partial[(int64_t)z * S + c0 + tid] = t;
         }
-        if (tid == 0) qr2_partial[s * kZA + z1] = red[0];
     }
 }
 
-template <int B>
-__global__ void __launch_bounds__(256) k_slab_inv(int logn, int S, int P,
-                                                  const cplx<float> *__restrict__ X,
-                                                  float *__restrict__ L,
-                                                  const cplx<float> *__restrict__ tw_g,
-                                                  float scale) {
+template <int NF>
+__global__ void __launch_bounds__(256) k_xy_inv(int S, int P, const cplx<float> *__restrict__ Y,
+                                                float *__restrict__ L, float scale) {
+    constexpr int NH = NF / 2 + 1, CT = kMultiCompTile, NPAIR = NF / 2;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn, nh = nf / 2 + 1, npair = nf / 2, ls = lds_line(nf);
-    const int ncol = nf * nh, SP = S * P;
-    const int64_t K = (int64_t)nf * nf * nf;
-    cplx<float> *tw = (cplx<float> *)lds_raw;
-    cplx<float> *rows = tw + nf / 2;
-    cplx<float> *slab = rows + B * npair * ls;
-    const int v = slab_block(kZA * SP);
-    if (v >= kZA * SP) return;
-    const int z1 = v / SP, c = v - z1 * SP;
-    const int s = c / P, b = c - s * P;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
-    // last z stage: B-point inverse DFT over r into the planes z1 + 4 j
-    for (int pt = tid; pt < ncol; pt += nthr) {
-        cplx<float> w8[B];
+    cplx<float> *Z = (cplx<float> *)lds_raw;          // [NF y][NH kx][CT]
+    const int SP = S * P, sps = (SP + 1) & ~1;
+    const int ntile = (SP + CT - 1) / CT;
+    const int v = xcd_block(NF * ntile);
+    if (v >= NF * ntile) return;
+    const int z = v / ntile, tile = v - z * ntile;
+    const int c0 = tile * CT;
+    const int tid = threadIdx.x;
+    for (int item = tid; item < NH * CT; item += 256) {
+        const int kx = item / CT, ct = item - kx * CT, c = c0 + ct;
+        const bool ok = c < SP;
+        cplx<float> w[NF];
 #pragma unroll
-        for (int r = 0; r < B; ++r) w8[r] = X[(((int64_t)r * ncol + pt) * kZA + z1) * SP + c];
-        fft_reg<B, true, float>(w8);
-        const int y = pt / nh, kx = pt - y * nh;
+        for (int ky = 0; ky < NF; ++ky)
+            w[ky] = ok ? Y[((int64_t)(z * NF + ky) * NH + kx) * sps + c] : cplx<float>{0.f, 0.f};
+        fft_reg<NF, true, float>(w);
 #pragma unroll
-        for (int j = 0; j < B; ++j) slab[(y * B + j) * nh + kx] = w8[j];
+        for (int y = 0; y < NF; ++y) Z[(y * NH + kx) * CT + ct] = w[y];
     }
     __syncthreads();
-    fft_lines<float, true>(slab, logn, B * nh, 1, B * nh, tw, tid, nthr);
-    // C2R along x: rows 2jj and 2jj+1 of a plane packed into one complex row
-    for (int idx = tid; idx < B * npair * nf; idx += nthr) {
-        const int j = idx / (npair * nf), rem = idx - j * npair * nf;
-        const int jj = rem >> logn, k = rem & (nf - 1);
-        const cplx<float> *ra = slab + ((2 * jj) * B + j) * nh;
-        const cplx<float> *rb = slab + ((2 * jj + 1) * B + j) * nh;
-        cplx<float> A, Bv;
-        if (k <= nf / 2) {
-            A = ra[k];
-            Bv = rb[k];
-        } else {
-            A = ra[nf - k];
-            Bv = rb[nf - k];
-            A.im = -A.im;
-            Bv.im = -Bv.im;
+    // C2R along x: rows 2jj and 2jj+1 packed into one complex transform
+    for (int item = tid; item < NPAIR * CT; item += 256) {
+        const int jj = item / CT, ct = item - jj * CT, c = c0 + ct;
+        cplx<float> w[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const int kk = k <= NF / 2 ? k : NF - k;
+            cplx<float> A = Z[((2 * jj) * NH + kk) * CT + ct];
+            cplx<float> B = Z[((2 * jj + 1) * NH + kk) * CT + ct];
+            if (k > NF / 2) {
+                A.im = -A.im;
+                B.im = -B.im;
+            }
+            w[k] = {A.re - B.im, A.im + B.re};
         }
-        rows[(j * npair + jj) * ls + k] = {A.re - Bv.im, A.im + Bv.re};
-    }
-    __syncthreads();
-    fft_lines<float, true>(rows, logn, B * npair, ls, 1, tw, tid, nthr);
-    float *comp = L + ((int64_t)s * P + b) * K;
-    for (int idx = tid; idx < B * nf * nf; idx += nthr) {
-        const int j = idx / (nf * nf), rem = idx - j * nf * nf;
-        const int y = rem / nf, x = rem - y * nf;
-        const cplx<float> o = rows[(j * npair + (y >> 1)) * ls + x];
-        comp[(int64_t)(z1 + kZA * j) * nf * nf + rem] = ((y & 1) ? o.im : o.re) * scale;
+        fft_reg<NF, true, float>(w);
+        if (c < SP) {
+            float *r0 = L + ((int64_t)(z * NF + 2 * jj) * NF) * SP + c;
+#pragma unroll
+            for (int x = 0; x < NF; ++x) {
+                r0[(int64_t)x * SP] = w[x].re * scale;
+                r0[(int64_t)(NF + x) * SP] = w[x].im * scale;
+            }
+        }
     }
 }
 
 // ----------------------------------------------------------- column GEMM
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two values at once: h[i] holds term i of both (one packed conversion per
+// term).
+template <int NS>
+__device__ __forceinline__ void split_pair(float a, float b, bf16x2 (&h)[NS]) {
+    f32x2 v = {a, b};
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        h[i] = __builtin_convertvector(v, bf16x2);
+        if (i + 1 < NS) v = v - __builtin_convertvector(h[i], f32x2);
+    }
+}
+
+// Eight values (in pairs) into the NS bf16x8 fragments of their terms.
+template <int NS>
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8 (&fr)[NS]) {
+    bf16x2 h[4][NS];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) split_pair<NS>(v[2 * q], v[2 * q + 1], h[q]);
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp) {
+        const bf16x4v lo = __builtin_shufflevector(h[0][sp], h[1][sp], 0, 1, 2, 3);
+        const bf16x4v hi = __builtin_shufflevector(h[2][sp], h[3][sp], 0, 1, 2, 3);
+        fr[sp] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+}
+
 template <int NS>
 __device__ __forceinline__ void split_bf16(float v, __bf16 (&h)[NS]) {
 #pragma unroll
@@ -442,253 +424,266 @@ __device__ __forceinline__ float decode_term(const float *g, unsigned code) {
     return f1 * g[code & 511u] + f2 * g[(code >> 11) & 511u];
 }
 
+// z transforms of the spectra, in place: one thread per (column, component)
+// line, in registers; consecutive threads hold consecutive components.  The
+// forward transform leaves component b multiplied by i^(lam mod 2) (lam the
+// order of b), the form the M2L product takes.
+template <int NF, bool INV>
+__global__ void __launch_bounds__(256) k_z_fft(int SP, int S, cplx<float> *__restrict__ Y) {
+    constexpr int NH = NF / 2 + 1, NCOL = NF * NH;
+    const int nchunk = (SP + 255) / 256;
+    const int v = xcd_block(NCOL * nchunk);
+    if (v >= NCOL * nchunk) return;
+    const int col = v / nchunk, chunk = v - col * nchunk;
+    const int c = chunk * 256 + threadIdx.x;
+    if (c >= SP) return;
+    const int sps = (SP + 1) & ~1;
+    cplx<float> *base = Y + (int64_t)col * sps + c;
+    const int64_t zs = (int64_t)NCOL * sps;
+    cplx<float> w[NF];
+#pragma unroll
+    for (int z = 0; z < NF; ++z) w[z] = base[z * zs];
+    fft_reg<NF, INV, float>(w);
+    if (!INV && (order_fast(c / S) & 1)) {
+        // forward: pre-multiply component b = c / S by i^(lam mod 2) for the
+        // real form of the M2L product
+#pragma unroll
+        for (int z = 0; z < NF; ++z) w[z] = {-w[z].im, w[z].re};
+    }
+#pragma unroll
+    for (int z = 0; z < NF; ++z) base[z * zs] = w[z];
+}
+
 template <int PO, int NS>
-struct ColumnMultiShape {
+struct GemmShape {
     static constexpr int P = nreal(PO), Q = nreal(2 * PO);
     static constexpr int RT = (P + 15) / 16, KS = (P + 31) / 32;
-    static constexpr int ITEMS = RT * KS * 64;          // A fragments of one split
-    static constexpr int NIT = (ITEMS + 255) / 256;     // per thread
-    static constexpr size_t abuf_bytes = (size_t)NS * ITEMS * 16;
-    static constexpr size_t gq_bytes = ((size_t)kZA * Q * 4 + 15) & ~(size_t)15;
-    static size_t lds(int st) {
-        return abuf_bytes + gq_bytes + (size_t)st * 4 * 4 + (size_t)kZA * st * P * 8;
-    }
+    static constexpr int NT = (2 * kMultiMaxSets) / 16;           // column tiles at most
+    // spectra / results in LDS: component rows of 2S + 1 floats (the odd
+    // stride puts rows 8 apart in different banks)
+    static constexpr size_t raw_bytes = (size_t)P * (2 * kMultiMaxSets + 1) * 4;
+    static constexpr size_t abuf_bytes = (size_t)NS * RT * KS * 64 * 16;
+    static constexpr size_t raw_al = (raw_bytes + 15) / 16 * 16;
+    static constexpr size_t lds = raw_al + abuf_bytes + ((size_t)Q * 4 + 15) / 16 * 16 +
+                                  (size_t)kMultiMaxSets * 16;
 };
 
-// Block: 256 threads, one (ky, kx) column, one residue r and sets
-// [st0, st0 + ST).  LDS: A fragments of the current frequency (every split),
-// the kernel values of the four frequencies, the zero-frequency moments for
-// the corrections, and xb[q][s P + b] (moment spectra, then local spectra).
+constexpr int kGemmThreads = 512;
+
+// One frequency per block (512 threads): L~_a = i^(l mod 2) sum_b t_ab
+// i^(lam mod 2) M~_b for every set at once, as the real product of t (rows
+// a, columns b) and the (P x 2S) matrix of the sets' real and imaginary
+// parts.  The frequency's P S spectra (contiguous) come in with one batch of
+// 16-byte loads into LDS; the waves build the A fragments of t together;
+// wave w then owns column tile w (8 sets): it splits its own B fragments
+// from LDS, multiplies every row tile, and writes the results over its own
+// columns, which no other wave reads.  The results leave with 16-byte
+// stores.  (The spectra of the frequency are read into LDS before any
+// result is written back to the same place.)
 template <int PO, int NS>
-__global__ void __launch_bounds__(256) k_column_multi(int logn, int S, int ST,
-                                                      const float *__restrict__ green,
-                                                      cplx<float> *__restrict__ X,
-                                                      const cplx<float> *__restrict__ tw_g,
-                                                      const unsigned *__restrict__ tmap,
-                                                      const double *__restrict__ qr2_partial,
-                                                      double *__restrict__ qtot) {
-    using Sh = ColumnMultiShape<PO, NS>;
-    constexpr int P = Sh::P, Q = Sh::Q, RT = Sh::RT, KS = Sh::KS;
-    constexpr int ITEMS = Sh::ITEMS, NIT = Sh::NIT;
+__global__ void __launch_bounds__(kGemmThreads, PO >= 8 ? 2 : 6) k_m2l_gemm(int logn, int S,
+                                                           const float *__restrict__ green,
+                                                           cplx<float> *__restrict__ Y,
+                                                           const unsigned *__restrict__ tmap,
+                                                           const double *__restrict__ qr2_partial,
+                                                           double *__restrict__ qtot) {
+    using Sh = GemmShape<PO, NS>;
+    constexpr int P = Sh::P, Q = Sh::Q, RT = Sh::RT, KS = Sh::KS, NTM = Sh::NT;
+    constexpr int NTH = kGemmThreads, NW = NTH / 64;
+    constexpr int AITEMS = RT * KS * 64, AIT = (AITEMS + NTH - 1) / NTH;
+    constexpr int MAXV4 = (P * kMultiMaxSets / 2 + NTH - 1) / NTH;   // float4 loads per thread
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    bf16x8 *abuf = (bf16x8 *)lds_raw;                                   // [NS][RT][KS][64]
-    float *gq = (float *)(lds_raw + Sh::abuf_bytes);                    // [4][Q]
-    float *dcm = (float *)(lds_raw + Sh::abuf_bytes + Sh::gq_bytes);    // [ST][4]
-    cplx<float> *xb = (cplx<float> *)(dcm + ST * 4);                   // [4][ST P]
+    float *rawf = (float *)lds_raw;                                    // [P][2S+1]
+    bf16x8 *abuf = (bf16x8 *)(lds_raw + Sh::raw_al);                   // [NS][RT][KS][64]
+    float *gq = (float *)(lds_raw + Sh::raw_al + Sh::abuf_bytes);      // [Q]
+    float *dcm = gq + (Q + 3) / 4 * 4;                                 // [64][4]
     const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ncol = nf * nh;
-    const int B = nf / kZA;
-    const int SP = S * P, STP = ST * P;
-    const int nst = (S + ST - 1) / ST;
-    const int nblk = B * ncol * nst;
-    const int per_xcd = (nblk + 7) / 8;
-    const int v = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (v >= nblk) return;
-    const int tile = v % nst, rest = v / nst;
-    const int r = rest % B, col = rest / B;
-    const int st0 = tile * ST, stc = min(ST, S - st0);
+    const int SP = S * P, rsf = 2 * S + 1;
+    const int NT = (2 * S + 15) / 16;
+    const int nfreq = nf * ncol;
+    const int f = xcd_block(nfreq);
+    if (f >= nfreq) return;
+    const int kz = f / ncol, col = f - kz * ncol;
     const int ky = col / nh, kx = col - ky * nh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const bool dc_block = (r == 0 && col == 0);
-
-    // kernel values of kz = B q + r from the stored quadrant, mirrored
-    // (ky > nf/2: Im-part components negate; kz > nf/2: (n, k) times
-    // (-1)^(n+|k|))
+    const bool dc = f == 0;
+    // frequency slices are padded to an even number of complex values, so
+    // each starts 16-byte aligned
+    const int sps = (SP + 1) & ~1;
+    cplx<float> *Yf = Y + (int64_t)f * sps;
+    // every global load of the block goes out first: the spectra, this
+    // thread's t-map codes and the kernel values
+    const int nv4 = sps / 2;                      // float4 = two complex values
+    f32x4 rv[MAXV4];
+#pragma unroll
+    for (int u = 0; u < MAXV4; ++u) rv[u] = ((const f32x4 *)Yf)[min(tid + u * NTH, nv4 - 1)];
+    uint4 cd[AIT][2];
+#pragma unroll
+    for (int it = 0; it < AIT; ++it) {
+        const int item = min(tid + it * NTH, AITEMS - 1);
+        cd[it][0] = ((const uint4 *)tmap)[item * 2];
+        cd[it][1] = ((const uint4 *)tmap)[item * 2 + 1];
+    }
+    constexpr int GIT = (Q + NTH - 1) / NTH;
+    float gv[GIT];
     {
         const int kyr = ky <= nf / 2 ? ky : nf - ky;
+        const int kzr = kz <= nf / 2 ? kz : nf - kz;
         const float *gcol = green + (int64_t)(kyr * nh + kx) * Q * nhp;
-        for (int idx = tid; idx < kZA * Q; idx += 256) {
-            const int qq = idx / Q, j = idx - qq * Q;
-            const int kz = B * qq + r;
-            const int kzr = kz <= nf / 2 ? kz : nf - kz;
-            const int nn = order_of(j), kk = j - nn * nn - nn;
+#pragma unroll
+        for (int it = 0; it < GIT; ++it) gv[it] = gcol[min(tid + it * NTH, Q - 1) * nhp + kzr];
+    }
+    // keep the loads in flight together: the empty statements below need
+    // every value here, so no load is sunk next to its LDS store
+#pragma unroll
+    for (int u = 0; u < MAXV4; ++u) asm volatile("" : "+v"(rv[u]));
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) asm volatile("" : "+v"(gv[it]));
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+        const int j = tid + it * NTH;
+        if (j < Q) {
+            const int nn = order_fast(j), kk = j - nn * nn - nn;
             const int ak = kk < 0 ? -kk : kk;
+            // mirrors: ky > nf/2 negates the Im-part components, kz > nf/2
+            // multiplies (n, k) by (-1)^(n+|k|)
             const bool neg = ((ky > nf / 2) && kk < 0) != ((kz > nf / 2) && ((nn + ak) & 1));
-            const float gv = gcol[j * nhp + kzr];
-            gq[idx] = neg ? -gv : gv;
+            gq[j] = neg ? -gv[it] : gv[it];
         }
     }
-    // moment spectra of this tile, four z1 rows
-    {
-        const cplx<float> *src = X + ((int64_t)r * ncol + col) * kZA * SP + (int64_t)st0 * P;
-        const int tot = kZA * stc * P, rowlen = stc * P;
-        for (int base = tid; base < tot; base += 256 * 8) {
-            cplx<float> vv[8];
+    // spectra into padded rows: complex 2i and 2i+1 of the slice
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int idx = base + u * 256;
-                if (idx < tot) {
-                    const int z1 = idx / rowlen, i = idx - z1 * rowlen;
-                    vv[u] = src[(int64_t)z1 * SP + i];
-                }
+    for (int u = 0; u < MAXV4; ++u) {
+        const int i = tid + u * NTH;
+        if (i < nv4) {
+            const int c0 = 2 * i, k0 = c0 / S, s0 = c0 - k0 * S;
+            const int c1 = c0 + 1, k1 = s0 + 1 < S ? k0 : k0 + 1, s1 = s0 + 1 < S ? s0 + 1 : 0;
+            rawf[k0 * rsf + 2 * s0] = rv[u][0];
+            rawf[k0 * rsf + 2 * s0 + 1] = rv[u][1];
+            if (c1 < SP) {
+                rawf[k1 * rsf + 2 * s1] = rv[u][2];
+                rawf[k1 * rsf + 2 * s1 + 1] = rv[u][3];
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int idx = base + u * 256;
-                if (idx < tot) {
-                    const int z1 = idx / rowlen, i = idx - z1 * rowlen;
-                    xb[z1 * STP + i] = vv[u];
-                }
-            }
-        }
-    }
-    // this thread's t-map codes (the same at every frequency)
-    unsigned tm[NIT][8];
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int item = tid + it * 256;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) tm[it][e] = item < ITEMS ? tmap[item * 8 + e] : 0u;
-    }
-    __syncthreads();
-    // last forward z stage (4-point DFT over z1), pre-multiply by i^(lam mod 2)
-    for (int i = tid; i < stc * P; i += 256) {
-        cplx<float> w4[kZA];
-#pragma unroll
-        for (int z1 = 0; z1 < kZA; ++z1) w4[z1] = xb[z1 * STP + i];
-        fft_reg<kZA, false, float>(w4);
-        const int sl = i / P, bb = i - sl * P;
-        if (dc_block) {
-            // zero frequency: M~_b(0) = sum over cells of M_b
-            const int slot = bb == 0 ? 0 : bb == ridx(1, 0) ? 1 : bb == ridx(1, 1) ? 2
-                             : bb == ridx(1, -1) ? 3 : -1;
-            if (slot >= 0) dcm[sl * 4 + slot] = w4[0].re;
-        }
-        const bool odd = order_of(bb) & 1;
-#pragma unroll
-        for (int qq = 0; qq < kZA; ++qq) {
-            const cplx<float> o = odd ? cplx<float>{-w4[qq].im, w4[qq].re} : w4[qq];
-            xb[qq * STP + i] = o;
         }
     }
     __syncthreads();
-    const double pi = 3.14159265358979323846;
-    const int ntile = (2 * stc + 15) / 16;                // 16-column tiles of this block
-    for (int qq = 0; qq < kZA; ++qq) {
-        // A fragments of t(kz = B qq + r), every split
-        const float *g = gq + qq * Q;
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int item = tid + it * 256;
-            if (item < ITEMS) {
-                bf16x8 fr[NS];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    __bf16 h[NS];
-                    split_bf16<NS>(decode_term(g, tm[it][e]), h);
-#pragma unroll
-                    for (int sp = 0; sp < NS; ++sp) fr[sp][e] = h[sp];
-                }
-#pragma unroll
-                for (int sp = 0; sp < NS; ++sp) abuf[sp * ITEMS + item] = fr[sp];
-            }
+    if (dc) {
+        // zero frequency: M~_b(0) = sum over cells of M_b (real); the order-one
+        // components arrive multiplied by i, so their value is the Im part
+        for (int s = tid; s < S; s += NTH) {
+            dcm[s * 4 + 0] = rawf[2 * s];
+            dcm[s * 4 + 1] = PO >= 1 ? rawf[ridx(1, 0) * rsf + 2 * s + 1] : 0.f;
+            dcm[s * 4 + 2] = PO >= 1 ? rawf[ridx(1, 1) * rsf + 2 * s + 1] : 0.f;
+            dcm[s * 4 + 3] = PO >= 1 ? rawf[ridx(1, -1) * rsf + 2 * s + 1] : 0.f;
         }
-        __syncthreads();
-        cplx<float> *xq = xb + qq * STP;
-        for (int nt = wv; nt < ntile; nt += 4) {
-            const int n = nt * 16 + (lane & 15);
-            const int sl = n >> 1, part = n & 1;
-            const bool colok = sl < stc;
-            // B fragments: rows k = ks 32 + (lane/16) 8 + e, column n
-            bf16x8 bfr[KS][NS];
+    }
+    // A fragments of t at this frequency
+#pragma unroll
+    for (int it = 0; it < AIT; ++it) {
+        const int item = tid + it * NTH;
+        if (item < AITEMS) {
+            const unsigned codes[8] = {cd[it][0].x, cd[it][0].y, cd[it][0].z, cd[it][0].w,
+                                       cd[it][1].x, cd[it][1].y, cd[it][1].z, cd[it][1].w};
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = decode_term(gq, codes[e]);
+            bf16x8 fr[NS];
+            split8<NS>(v, fr);
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) abuf[sp * AITEMS + item] = fr[sp];
+        }
+    }
+    __syncthreads();
+    if (dc) {
+        for (int s = tid; s < S; s += NTH) qtot[s] = (double)dcm[s * 4];
+    }
+    // wave w: column tile nt = w (columns n = 16 nt + lane % 16 = 2 s + part);
+    // B fragments (the spectra arrive pre-multiplied by i^(lam mod 2)): rows
+    // k = ks 32 + (lane/16) 8 + e
+    const int n0 = lane & 15, part = n0 & 1;
+    for (int nt = wv; nt < NT; nt += NW) {
+        const int s = nt * 8 + (n0 >> 1);
+        const bool sok = s < S;
+        const float *rp = rawf + 2 * min(s, S - 1) + part;
+        bf16x8 bfr[KS][NS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = ks * 32 + (lane >> 4) * 8 + e;
+                const float x = rp[min(k, P - 1) * rsf];
+                v[e] = (sok && k < P) ? x : 0.f;
+            }
+            split8<NS>(v, bfr[ks]);
+        }
+        f32x4 acc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
+                bf16x8 afr[NS];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = ks * 32 + (lane >> 4) * 8 + e;
-                    float val = 0.f;
-                    if (colok && k < P) {
-                        const cplx<float> m = xq[sl * P + k];
-                        val = part ? m.im : m.re;
-                    }
-                    __bf16 h[NS];
-                    split_bf16<NS>(val, h);
+                for (int sp = 0; sp < NS; ++sp) afr[sp] = abuf[(sp * RT + rt) * KS * 64 + ks * 64 + lane];
+                // smallest products first
 #pragma unroll
-                    for (int sp = 0; sp < NS; ++sp) bfr[ks][sp][e] = h[sp];
+                for (int d = NS - 1; d >= 0; --d) {
+#pragma unroll
+                    for (int i = d; i >= 0; --i)
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[i], bfr[ks][d - i],
+                                                                       acc[rt], 0, 0, 0);
                 }
             }
-            f32x4 acc[RT];
+        }
+        // D rows a = rt 16 + (lane/16) 4 + i over this wave's own columns
+        if (sok) {
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    bf16x8 afr[NS];
-#pragma unroll
-                    for (int sp = 0; sp < NS; ++sp) afr[sp] = abuf[sp * ITEMS + (rt * KS + ks) * 64 + lane];
-                    // smallest products first
-#pragma unroll
-                    for (int d = NS - 1; d >= 0; --d) {
-#pragma unroll
-                        for (int i = d; i >= 0; --i) {
-                            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[i], bfr[ks][d - i],
-                                                                           acc[rt], 0, 0, 0);
-                        }
+                for (int i = 0; i < 4; ++i) {
+                    const int a = rt * 16 + (lane >> 4) * 4 + i;
+                    if (a >= P) continue;
+                    float val = acc[rt][i];
+                    int dst = part;                      // 0: Re, 1: Im
+                    if (order_fast(a) & 1) {
+                        dst = part ^ 1;
+                        if (part) val = -val;
                     }
+                    rawf[a * rsf + 2 * s + dst] = val;
                 }
             }
-            // D rows a = rt 16 + (lane/16) 4 + i, column n; L~_a = i^(l mod 2) acc
-            if (colok) {
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int a = rt * 16 + (lane >> 4) * 4 + i;
-                        if (a < P) {
-                            const bool odd = order_of(a) & 1;
-                            float val = acc[rt][i];
-                            int dst;                      // 0: Re, 1: Im
-                            if (!odd) {
-                                dst = part;
-                            } else {
-                                dst = part ^ 1;
-                                if (part) val = -val;
-                            }
-                            if (dc_block && qq == 0 && dst == 0) {
-                                // uniform corrections of App. B at k = 0 (times nf^3)
-                                const float *dm = dcm + sl * 4;
-                                double add = 0.0;
-                                if (a == 0) {
-                                    double qr2 = 0.0;
-                                    for (int z1 = 0; z1 < kZA; ++z1)
-                                        qr2 += qr2_partial[(st0 + sl) * kZA + z1];
-                                    add = 2.0 * pi / 3.0 * qr2;
-                                } else if (PO >= 1 && a == ridx(1, 0)) {
-                                    add = 4.0 * pi / 3.0 * (double)dm[1];
-                                } else if (PO >= 1 && a == ridx(1, 1)) {
-                                    add = 8.0 * pi / 3.0 * (double)dm[2];
-                                } else if (PO >= 1 && a == ridx(1, -1)) {
-                                    add = -8.0 * pi / 3.0 * (double)dm[3];
-                                }
-                                val += (float)add;
-                            }
-                            float *pv = (float *)(xq + sl * P + a);
-                            pv[dst] = val;
-                        }
-                    }
-                }
+        }
+    }
+    __syncthreads();
+    if (dc) {
+        // uniform corrections of App. B at k = 0 (times nf^3)
+        const double pi = 3.14159265358979323846;
+        for (int s = tid; s < S; s += NTH) {
+            double qr2 = 0.0;
+            for (int z = 0; z < nf; ++z) qr2 += qr2_partial[(int64_t)z * S + s];
+            rawf[2 * s] += (float)(2.0 * pi / 3.0 * qr2);
+            if (PO >= 1) {
+                rawf[ridx(1, 0) * rsf + 2 * s] += (float)(4.0 * pi / 3.0 * (double)dcm[s * 4 + 1]);
+                rawf[ridx(1, 1) * rsf + 2 * s] += (float)(8.0 * pi / 3.0 * (double)dcm[s * 4 + 2]);
+                rawf[ridx(1, -1) * rsf + 2 * s] += (float)(-8.0 * pi / 3.0 * (double)dcm[s * 4 + 3]);
             }
         }
         __syncthreads();
     }
-    if (dc_block) {
-        for (int sl = tid; sl < stc; sl += 256) qtot[st0 + sl] = (double)dcm[sl * 4];
-    }
-    // inverse z stage over q, twiddle W_nf^(-z1 r), back to X
-    cplx<float> *dst = X + ((int64_t)r * ncol + col) * kZA * SP + (int64_t)st0 * P;
-    for (int i = tid; i < stc * P; i += 256) {
-        cplx<float> w4[kZA];
+    // results out, complex 2i and 2i+1 per 16-byte store
 #pragma unroll
-        for (int qq = 0; qq < kZA; ++qq) w4[qq] = xb[qq * STP + i];
-        fft_reg<kZA, true, float>(w4);
-#pragma unroll
-        for (int z1 = 0; z1 < kZA; ++z1) {
-            cplx<float> o = w4[z1];
-            if (z1 * r != 0) {
-                cplx<float> wt = tw_at(tw_g, z1 * r, nf);
-                wt.im = -wt.im;
-                o = cmul(o, wt);
-            }
-            dst[(int64_t)z1 * SP + i] = o;
+    for (int u = 0; u < MAXV4; ++u) {
+        const int i = tid + u * NTH;
+        if (i < nv4) {
+            const int c0 = 2 * i, k0 = c0 / S, s0 = c0 - k0 * S;
+            const int c1 = c0 + 1, k1 = s0 + 1 < S ? k0 : k0 + 1, s1 = s0 + 1 < S ? s0 + 1 : 0;
+            f32x4 o;
+            o[0] = rawf[k0 * rsf + 2 * s0];
+            o[1] = rawf[k0 * rsf + 2 * s0 + 1];
+            o[2] = c1 < SP ? rawf[k1 * rsf + 2 * s1] : 0.f;
+            o[3] = c1 < SP ? rawf[k1 * rsf + 2 * s1 + 1] : 0.f;
+            ((f32x4 *)Yf)[i] = o;
         }
     }
 }
@@ -751,26 +746,9 @@ void build_multi_map(int p, unsigned *out) {
                 }
 }
 
-template <int PO>
-static size_t column_lds_po(int split, int st) {
-    return split == 2 ? ColumnMultiShape<PO, 2>::lds(st) : ColumnMultiShape<PO, 3>::lds(st);
-}
-
-size_t multi_column_lds(int p, int split, int st) {
-    size_t b = 0;
-    switch (p) {
-        case 0: b = column_lds_po<0>(split, st); break;
-        case 1: b = column_lds_po<1>(split, st); break;
-        case 2: b = column_lds_po<2>(split, st); break;
-        case 3: b = column_lds_po<3>(split, st); break;
-        case 4: b = column_lds_po<4>(split, st); break;
-        case 5: b = column_lds_po<5>(split, st); break;
-        case 6: b = column_lds_po<6>(split, st); break;
-        case 7: b = column_lds_po<7>(split, st); break;
-        case 8: b = column_lds_po<8>(split, st); break;
-        default: return 0;
-    }
-    return b <= 160 * 1024 ? b : 0;
+bool multi_supported(int p, int nf) {
+    if (nf != 4 && nf != 8 && nf != 16 && nf != 32) return false;
+    return p >= 0 && p <= PMMM_PMAX;
 }
 
 template <typename Kern>
@@ -808,18 +786,14 @@ static hipError_t multi_particles(const MultiArgs &a, int stage, hipStream_t s) 
 
 template <int PO, int NS>
 static hipError_t multi_column(const MultiArgs &a, hipStream_t s) {
-    const int nf = a.n, logn = ilog2i(nf), nh = nf / 2 + 1, ncol = nf * nh, B = nf / kZA;
-    const int ST = a.set_tile;
-    const size_t lds = ColumnMultiShape<PO, NS>::lds(ST);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = lds_attr(k_column_multi<PO, NS>, lds);
+    const int nf = a.n, logn = ilog2i(nf), ncol = nf * (nf / 2 + 1);
+    const size_t lds = GemmShape<PO, NS>::lds;
+    hipError_t e = lds_attr(k_m2l_gemm<PO, NS>, lds);
     if (e != hipSuccess) return e;
-    const int nst = (a.nsets + ST - 1) / ST;
-    const int nblk = B * ncol * nst;
+    const int nblk = nf * ncol;
     const int grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_column_multi<PO, NS>), dim3(grid), dim3(256), lds, s, logn, a.nsets, ST,
-                       a.green, (cplx<float> *)a.X, (const cplx<float> *)a.tw, a.tmap,
-                       a.qr2_partial, a.qtot);
+    hipLaunchKernelGGL((k_m2l_gemm<PO, NS>), dim3(grid), dim3(kGemmThreads), lds, s, logn, a.nsets,
+                       a.green, (cplx<float> *)a.Y, a.tmap, a.qr2_partial, a.qtot);
     return hipGetLastError();
 }
 
@@ -828,26 +802,37 @@ static hipError_t multi_column_po(const MultiArgs &a, hipStream_t s) {
     return a.split == 2 ? multi_column<PO, 2>(a, s) : multi_column<PO, 3>(a, s);
 }
 
-template <int B>
-static hipError_t multi_slab(const MultiArgs &a, int inverse, hipStream_t s) {
-    const int nf = a.n, logn = ilog2i(nf), nh = nf / 2 + 1, P = nreal(a.p);
-    const size_t lds = (size_t)(nf / 2 + B * (nf / 2) * lds_line(nf) + nf * B * nh) *
-                       sizeof(cplx<float>);
-    const int nblk = kZA * a.nsets * P;
+template <int NF>
+static hipError_t multi_planes(const MultiArgs &a, int inverse, hipStream_t s) {
+    const int P = nreal(a.p), SP = a.nsets * P;
+    // spectra tile, also the 256-double reduction buffer of the forward kernel
+    size_t lds = (size_t)NF * (NF / 2 + 1) * kMultiCompTile * sizeof(cplx<float>);
+    if (lds < 256 * sizeof(double)) lds = 256 * sizeof(double);
+    const int ntile = (SP + kMultiCompTile - 1) / kMultiCompTile;
+    const int nblk = NF * ntile;
     const int grid = ((nblk + 7) / 8) * 8;
+    const int zblk = NF * (NF / 2 + 1) * ((SP + 255) / 256);
+    const int zgrid = ((zblk + 7) / 8) * 8;
     hipError_t e;
     if (!inverse) {
-        e = lds_attr(k_slab_fwd<B>, lds);
+        e = lds_attr(k_xy_fwd<NF>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_slab_fwd<B>, dim3(grid), dim3(256), lds, s, logn, a.nsets, P,
-                           (const float *)a.M, (cplx<float> *)a.X, (const cplx<float> *)a.tw,
-                           a.qr2_partial);
+        hipLaunchKernelGGL(k_xy_fwd<NF>, dim3(grid), dim3(256), lds, s, a.nsets, P,
+                           (const float *)a.M, (cplx<float> *)a.Y, a.qr2_partial);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_z_fft<NF, false>), dim3(zgrid), dim3(256), 0, s, SP, a.nsets,
+                           (cplx<float> *)a.Y);
     } else {
-        e = lds_attr(k_slab_inv<B>, lds);
+        hipLaunchKernelGGL((k_z_fft<NF, true>), dim3(zgrid), dim3(256), 0, s, SP, a.nsets,
+                           (cplx<float> *)a.Y);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const float scale = (float)(1.0 / ((double)nf * nf * nf));
-        hipLaunchKernelGGL(k_slab_inv<B>, dim3(grid), dim3(256), lds, s, logn, a.nsets, P,
-                           (const cplx<float> *)a.X, a.M, (const cplx<float> *)a.tw, scale);
+        e = lds_attr(k_xy_inv<NF>, lds);
+        if (e != hipSuccess) return e;
+        const float scale = (float)(1.0 / ((double)NF * NF * NF));
+        hipLaunchKernelGGL(k_xy_inv<NF>, dim3(grid), dim3(256), lds, s, a.nsets, P,
+                           (const cplx<float> *)a.Y, a.M, scale);
     }
     return hipGetLastError();
 }
@@ -868,11 +853,11 @@ hipError_t launch_multi_stage(const MultiArgs &a, int stage, hipStream_t s) {
         }
     }
     if (stage == 1 || stage == 3) {
-        switch (a.n / kZA) {
-            case 1: return multi_slab<1>(a, stage == 3, s);
-            case 2: return multi_slab<2>(a, stage == 3, s);
-            case 4: return multi_slab<4>(a, stage == 3, s);
-            case 8: return multi_slab<8>(a, stage == 3, s);
+        switch (a.n) {
+            case 4: return multi_planes<4>(a, stage == 3, s);
+            case 8: return multi_planes<8>(a, stage == 3, s);
+            case 16: return multi_planes<16>(a, stage == 3, s);
+            case 32: return multi_planes<32>(a, stage == 3, s);
             default: return hipErrorInvalidValue;
         }
     }
