@@ -147,6 +147,7 @@ WORKLOADS = {
     "periodic_n1048576_m32_p7": ("periodic_pm1_blocks", "periodic", "f32"),
     "open_plummer_n4194304_m64_p6": ("plummer_sphere", "open", "f32"),
     "multi_periodic_n1048576_m32_p6_s64": ("multi_charge_sets", "periodic", "f32"),
+    "batch_periodic_256sys": ("batched_systems", "periodic", "f32"),
 }
 
 
@@ -178,6 +179,8 @@ def main():
     workload = args.workload
     if workload.startswith("multi_"):
         return bench_multi(args, workload)
+    if workload.startswith("batch_"):
+        return bench_batch(args, workload)
     gen, boundary, prec = WORKLOADS[workload]
     ps = getattr(inputs, gen)()
     N, n, p = ps.n, ps.n_cells, ps.p
@@ -366,6 +369,67 @@ def bench_multi(args, workload):
                    "parallelism": "single GPU"},
         "roofline": roof,
         "stages": stages,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_batch(args, workload):
+    """Batched workload: 256 independent periodic systems (N uniform in
+    [2048, 65536], meshes 8^3/16^3/32^3, p in {4, 5, 6}, neutral +/-1); one
+    step is one pmmm_batch_far_f32 call over all of them (graph replay after
+    the second call)."""
+    import numpy as np
+    import torch
+    from paper_1409_5981_amd import inputs
+    from paper_1409_5981_amd._lib import Batch
+
+    systems = inputs.batched_systems()
+    offs = np.zeros(len(systems) + 1, dtype=np.int64)
+    for i, ps in enumerate(systems):
+        offs[i + 1] = offs[i] + ps.n
+    N = int(offs[-1])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    x, y, z, q = (torch.from_numpy(np.concatenate([getattr(ps, a) for ps in systems])).to(dev)
+                  for a in ("x", "y", "z", "q"))
+    batch = Batch([{"n": ps.n_cells, "p": ps.p, "boundary": "periodic"} for ps in systems])
+    out = tuple(torch.empty(N, dtype=torch.float32, device=dev) for _ in range(4))
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(stream)
+    for _ in range(max(3, args.warmup)):
+        batch.far(offs, x, y, z, q, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.far(offs, x, y, z, q, out=out, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    batch.sync_status()
+    cpu = None
+    if not args.no_cpu_baseline:
+        big = max(systems, key=lambda ps: ps.n)
+        cpu = cpu_baseline(big, args.cpu_seconds)
+        cpu["sample"] += "; the largest system of the batch"
+    meshes = {m: sum(1 for ps in systems if ps.n_cells == m) for m in (8, 16, 32)}
+    rec = {
+        "metric": "particles/s over a batch of independent periodic systems, PMMM far field",
+        "value": N * args.steps / el,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(3, args.warmup),
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "systems": len(systems), "n_particles": N,
+                   "classes": batch.classes, "meshes": meshes, "cutoff": 2,
+                   "parallelism": "single GPU"},
+        "roofline": None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -64,6 +64,7 @@ enum { PMMM_F32 = 0, PMMM_F64 = 1, PMMM_BF16X3 = 2 };
 enum { PMMM_MESH_M = 0, PMMM_MESH_L = 1, PMMM_MESH_GREEN = 2 };
 
 typedef struct pmmm_plan_s *pmmm_plan;
+typedef struct pmmm_batch_s *pmmm_batch;
 
 /* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
  *   nx, ny, nz  cells per axis.  This build needs nx == ny == nz == n, a
@@ -145,6 +146,34 @@ int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
 int pmmm_far_multi_f32(pmmm_plan plan, int64_t n, const float *x, const float *y,
                        const float *z, int nsets, const float *q, float *phi, float *gx,
                        float *gy, float *gz, void *stream);
+
+/* Batches of independent systems (Sec. 2.1 for each; the paper notes that
+ * many small FFTs can run independently in place of one large one).  Each
+ * system has its own parameters; systems whose parameters agree (mesh, box,
+ * order, cutoff, boundary, alpha, images) share one transfer kernel and run
+ * every stage in one launch for all of them, and a call whose arguments
+ * repeat the previous call's replays the previous launches as one HIP graph
+ * (captured on the second identical call; not for the NULL stream).
+ *   pmmm_batch_create   validates every system (PMMM_F32 or PMMM_BF16X3
+ *                       only), builds the transfer kernels on `stream` and
+ *                       synchronises it.
+ *   pmmm_batch_far_f32  far field of all systems: offsets is a HOST array of
+ *                       nsys + 1 non-decreasing values with offsets[0] = 0;
+ *                       system s owns particles [offsets[s], offsets[s+1]) of
+ *                       the device arrays x, y, z, q and of the outputs phi,
+ *                       gx, gy, gz (same meaning as pmmm_far_f32).  A call
+ *                       with new offsets synchronises the stream once.
+ *   pmmm_batch_classes  number of distinct parameter sets.
+ *   pmmm_batch_set_graphs  enable (default) or disable the graph replay.
+ *   pmmm_batch_sync_status  as pmmm_plan_sync_status, for the batch. */
+int pmmm_batch_create(int nsys, const pmmm_params *per_sys, void *stream, pmmm_batch *out);
+void pmmm_batch_destroy(pmmm_batch batch);
+int pmmm_batch_far_f32(pmmm_batch batch, const int64_t *offsets, const float *x, const float *y,
+                       const float *z, const float *q, float *phi, float *gx, float *gy,
+                       float *gz, void *stream);
+int pmmm_batch_classes(pmmm_batch batch);
+int pmmm_batch_set_graphs(pmmm_batch batch, int enable);
+int pmmm_batch_sync_status(pmmm_batch batch);
 
 /* Near field for checking only (Sec. 2.1: direct particle-particle sums over
  * the masked (2c+1)^3 cells, no cutoff function).  Uses the binning (sorted

@@ -28,6 +28,8 @@ EXPORTS = [
     "pmmm_near_f32", "pmmm_near_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
     "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
+    "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
+    "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
     "pmmm_error_string", "pmmm_last_error",
 ]
 
@@ -90,6 +92,18 @@ def load():
     L.pmmm_plan_read_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64), ci]
     L.pmmm_plan_read_profile.restype = ci
+    L.pmmm_batch_create.argtypes = [ci, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.pmmm_batch_create.restype = ci
+    L.pmmm_batch_destroy.argtypes = [vp]
+    L.pmmm_batch_destroy.restype = None
+    L.pmmm_batch_far_f32.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)] + [vp] * 8 + [vp]
+    L.pmmm_batch_far_f32.restype = ci
+    L.pmmm_batch_classes.argtypes = [vp]
+    L.pmmm_batch_classes.restype = ci
+    L.pmmm_batch_set_graphs.argtypes = [vp, ci]
+    L.pmmm_batch_set_graphs.restype = ci
+    L.pmmm_batch_sync_status.argtypes = [vp]
+    L.pmmm_batch_sync_status.restype = ci
     L.pmmm_error_string.argtypes = [ci]
     L.pmmm_error_string.restype = ctypes.c_char_p
     L.pmmm_last_error.argtypes = []
@@ -242,3 +256,61 @@ class Plan:
         nh = nf // 2 + 1
         nhp = (nh + 3) & ~3
         return buf.reshape(nh, nh, Q, nhp)[..., :nh]
+
+
+class Batch:
+    """Independent systems in one call (pmmm_batch_*).  `systems` is a list
+    of dicts with the Plan arguments (n, p, boundary, box, cutoff, alpha,
+    images); every system runs the FP32 pipeline."""
+
+    def __init__(self, systems, stream=None):
+        L = load()
+        self.nsys = len(systems)
+        arr = (Params * self.nsys)()
+        for i, sy in enumerate(systems):
+            arr[i] = make_params(sy["n"], sy["p"], sy.get("boundary", "periodic"),
+                                 sy.get("box", 1.0), sy.get("cutoff", 2), "f32",
+                                 sy.get("alpha", 0.0), sy.get("images", 0))
+        self._params = arr
+        self._h = ctypes.c_void_p()
+        _check(L.pmmm_batch_create(self.nsys, arr, _stream_handle(stream), ctypes.byref(self._h)))
+
+    @property
+    def classes(self) -> int:
+        return int(load().pmmm_batch_classes(self._h))
+
+    def set_graphs(self, enable: bool):
+        _check(load().pmmm_batch_set_graphs(self._h, int(bool(enable))))
+
+    def close(self):
+        if self._h:
+            load().pmmm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def far(self, offsets, x, y, z, q, out=None, stream=None):
+        """offsets: nsys + 1 particle offsets (host); x, y, z, q: concatenated
+        float32 device tensors.  Returns Phi, gx, gy, gz (device, input order)."""
+        import torch
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if offs.shape != (self.nsys + 1,):
+            raise ValueError("offsets must have nsys + 1 entries")
+        n = int(offs[-1])
+        for t in (x, y, z, q):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("x, y, z, q must be contiguous float32 device tensors of length offsets[-1]")
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(4))
+        self._offs = offs
+        _check(load().pmmm_batch_far_f32(self._h, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                                         *[o.data_ptr() for o in out], _stream_handle(stream)))
+        return out
+
+    def sync_status(self):
+        _check(load().pmmm_batch_sync_status(self._h))

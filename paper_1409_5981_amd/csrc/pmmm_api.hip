@@ -2,8 +2,11 @@
 // workspace management and the launch sequence of one far-field call.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "pmmm_internal.h"
@@ -13,6 +16,18 @@ namespace pmmm {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+hipError_t set_max_lds(const void *kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find(kernel);
+    if (it != done.end() && it->second >= bytes) return hipSuccess;
+    const hipError_t e =
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done[kernel] = bytes;
+    return e;
+}
 
 int hip_fail(hipError_t e, const char *what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -569,6 +584,289 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
     return PMMM_OK;
 }
 
+// ------------------------------------------------------------------ batches
+// Systems with equal method parameters (mesh, box, order, cutoff, boundary,
+// splitting, images) form a class: one transfer kernel, one launch per stage
+// for all of them (blockIdx.y / .z selects the system), per-system meshes at
+// fixed strides in the class workspace.
+struct BatchClass {
+    pmmm_plan_s *plan = nullptr;    // transfer kernel, twiddles, constants
+    std::vector<int> members;       // system indices in the caller's order
+    int *count = nullptr, *start = nullptr, *dense = nullptr, *small = nullptr;
+    void *M = nullptr, *spec = nullptr, *L = nullptr;
+    double *qr2 = nullptr, *sums = nullptr;
+    int64_t *d_prange = nullptr;    // [2 members]
+    int64_t max_np = 0, tot_np = 0;
+};
+
+struct pmmm_batch_s {
+    int nsys = 0, device = 0;
+    std::vector<BatchClass> cls;
+    int64_t cap = 0;
+    int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr;
+    void *sorted = nullptr;
+    int *flag = nullptr;
+    int64_t *h_prange = nullptr;    // pinned staging [2 nsys]
+    std::vector<int64_t> offsets;   // of the last call
+    hipStream_t last_stream = nullptr;
+    // the last call's launches as a graph, replayed while the arguments repeat
+    int use_graph = 1;
+    std::vector<const void *> key;
+    int key_hits = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+static bool same_class(const pmmm_params &a, const pmmm_params &b) {
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.box[0] == b.box[0] &&
+           a.box[1] == b.box[1] && a.box[2] == b.box[2] && a.p == b.p &&
+           (a.cutoff == 0 ? 2 : a.cutoff) == (b.cutoff == 0 ? 2 : b.cutoff) &&
+           a.boundary == b.boundary && a.alpha == b.alpha && a.images == b.images;
+}
+
+static void drop_graph(pmmm_batch_s *b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->key.clear();
+    b->key_hits = 0;
+}
+
+static void batch_destroy(pmmm_batch_s *b) {
+    if (!b) return;
+    hipDeviceSynchronize();
+    drop_graph(b);
+    for (auto &c : b->cls) {
+        hipFree(c.count);
+        hipFree(c.start);
+        hipFree(c.dense);
+        hipFree(c.small);
+        hipFree(c.M);
+        hipFree(c.spec);
+        hipFree(c.L);
+        hipFree(c.qr2);
+        hipFree(c.sums);
+        hipFree(c.d_prange);
+        destroy(c.plan);
+    }
+    hipFree(b->cell_of);
+    hipFree(b->slot);
+    hipFree(b->perm);
+    hipFree(b->scell);
+    hipFree(b->sorted);
+    hipFree(b->flag);
+    if (b->h_prange) hipHostFree(b->h_prange);
+    delete b;
+}
+
+static int batch_alloc_class(BatchClass &c, hipStream_t s) {
+    const Plan *pl = c.plan;
+    const size_t ns = c.members.size(), K = pl->K, P = pl->P, t = pl->tsize;
+    PMMM_HIP(hipMalloc(&c.count, sizeof(int) * K * ns));
+    PMMM_HIP(hipMalloc(&c.start, sizeof(int) * (K + 1) * ns));
+    PMMM_HIP(hipMalloc(&c.dense, sizeof(int) * K * ns));
+    PMMM_HIP(hipMalloc(&c.small, sizeof(int) * 8 * ns));
+    PMMM_HIP(hipMalloc(&c.M, t * (P + 1) * K * ns));
+    PMMM_HIP(hipMalloc(&c.spec, 2 * t * P * pl->n * pl->ncol * ns));
+    PMMM_HIP(hipMalloc(&c.L, t * P * K * ns));
+    PMMM_HIP(hipMalloc(&c.qr2, sizeof(double) * pl->n * ns));
+    PMMM_HIP(hipMalloc(&c.sums, sizeof(double) * 8 * ns));
+    PMMM_HIP(hipMalloc(&c.d_prange, sizeof(int64_t) * 2 * ns));
+    PMMM_HIP(hipMemsetAsync(c.count, 0, sizeof(int) * K * ns, s));
+    PMMM_HIP(hipMemsetAsync(c.small, 0, sizeof(int) * 8 * ns, s));
+    PMMM_HIP(hipMemsetAsync(c.M, 0, t * (P + 1) * K * ns, s));
+    return PMMM_OK;
+}
+
+static int batch_capacity(pmmm_batch_s *b, int64_t n) {
+    if (n <= b->cap) return PMMM_OK;
+    if (n > (int64_t)INT32_MAX) {
+        set_error("particle count exceeds the 32-bit index range");
+        return PMMM_EINVAL;
+    }
+    PMMM_HIP(hipDeviceSynchronize());
+    drop_graph(b);
+    hipFree(b->cell_of);
+    hipFree(b->slot);
+    hipFree(b->perm);
+    hipFree(b->scell);
+    hipFree(b->sorted);
+    b->cap = 0;
+    PMMM_HIP(hipMalloc(&b->cell_of, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&b->slot, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&b->perm, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&b->scell, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&b->sorted, sizeof(float) * 4 * n));
+    b->cap = n;
+    return PMMM_OK;
+}
+
+// Every launch of one batched far-field call, class by class.
+static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const float *z,
+                         const float *q, float *phi, float *gx, float *gy, float *gz,
+                         hipStream_t s) {
+    for (auto &c : b->cls) {
+        const Plan *pl = c.plan;
+        const int ns = (int)c.members.size();
+        BinArgs bn{};
+        bn.n = 0;
+        bn.x = x;
+        bn.y = y;
+        bn.z = z;
+        bn.q = q;
+        bn.ncell = pl->n;
+        bn.inv_h = pl->inv_h;
+        bn.periodic = !pl->open;
+        bn.cell_of = b->cell_of;
+        bn.slot = b->slot;
+        bn.count = c.count;
+        bn.start = c.start;
+        bn.scell = b->scell;
+        bn.perm = b->perm;
+        bn.flag = b->flag;
+        bn.dense_cells = c.dense;
+        bn.dense_count = c.small;
+        bn.dense_threshold = kDenseThreshold;
+        bn.sorted = b->sorted;
+        bn.prange = c.d_prange;
+        bn.nsys = ns;
+        bn.max_np = c.max_np;
+        PMMM_HIP(launch_bin<float>(bn, s));
+        P2MArgs m{};
+        m.p = pl->p;
+        m.ncell = pl->n;
+        m.group = group_for((double)c.tot_np / ((double)pl->K * ns));
+        m.may_have_dense = c.max_np > kDenseThreshold;
+        m.zero_count = (c.max_np > 0 && pl->K <= 4096) ? c.count : nullptr;
+        m.start = c.start;
+        m.dense_cells = c.dense;
+        m.dense_count = c.small;
+        m.dense_threshold = kDenseThreshold;
+        m.sorted = b->sorted;
+        m.M = c.M;
+        m.prange = c.d_prange;
+        m.nsys = ns;
+        PMMM_HIP(launch_p2m<float>(m, s));
+        FFTArgs f{};
+        f.p = pl->p;
+        f.n = pl->n;
+        f.nf = pl->nf;
+        f.open = pl->open;
+        f.M = c.M;
+        f.spec = c.spec;
+        f.green = pl->green;
+        f.tw = pl->tw;
+        f.L = c.L;
+        f.qr2_partial = c.qr2;
+        f.sums = c.sums;
+        f.nsys = ns;
+        for (int st = 0; st < 3; ++st) PMMM_HIP(launch_conv_stage<float>(f, st, s));
+        L2PArgs l{};
+        l.n = 0;
+        l.p = pl->p;
+        l.ncell = pl->n;
+        l.periodic = !pl->open;
+        l.sorted = b->sorted;
+        l.scell = b->scell;
+        l.perm = b->perm;
+        l.L = c.L;
+        l.sums = c.sums;
+        l.alpha_cell = pl->alpha_cell;
+        l.inv_h = pl->inv_h;
+        l.phi = phi;
+        l.gx = gx;
+        l.gy = gy;
+        l.gz = gz;
+        l.prange = c.d_prange;
+        l.nsys = ns;
+        l.max_np = c.max_np;
+        PMMM_HIP(launch_l2p<float>(l, s));
+    }
+    return PMMM_OK;
+}
+
+static int batch_far(pmmm_batch_s *b, const int64_t *offsets, const float *x, const float *y,
+                     const float *z, const float *q, float *phi, float *gx, float *gy,
+                     float *gz, void *stream) {
+    if (!b || !offsets) {
+        set_error("NULL batch or offsets");
+        return PMMM_EINVAL;
+    }
+    if (offsets[0] != 0) {
+        set_error("offsets[0] must be 0");
+        return PMMM_EINVAL;
+    }
+    for (int i = 0; i < b->nsys; ++i) {
+        if (offsets[i + 1] < offsets[i]) {
+            set_error("offsets must be non-decreasing");
+            return PMMM_EINVAL;
+        }
+    }
+    const int64_t total = offsets[b->nsys];
+    if (total > 0 && (!x || !y || !z || !q || !phi || !gx || !gy || !gz)) {
+        set_error("NULL particle or output pointer");
+        return PMMM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    PMMM_HIP(hipGetDevice(&cur));
+    if (cur != b->device) {
+        set_error("current device differs from the batch's device");
+        return PMMM_EINVAL;
+    }
+    int rc = batch_capacity(b, total > 0 ? total : 1);
+    if (rc != PMMM_OK) return rc;
+    b->last_stream = s;
+    if (b->offsets.size() != (size_t)b->nsys + 1 ||
+        !std::equal(b->offsets.begin(), b->offsets.end(), offsets)) {
+        // new particle ranges: restage them for every class (pinned buffer,
+        // synchronised before it is reused)
+        drop_graph(b);
+        PMMM_HIP(hipStreamSynchronize(s));
+        int64_t *h = b->h_prange;
+        for (auto &c : b->cls) {
+            c.max_np = 0;
+            c.tot_np = 0;
+            for (size_t k = 0; k < c.members.size(); ++k) {
+                const int m = c.members[k];
+                h[2 * k] = offsets[m];
+                h[2 * k + 1] = offsets[m + 1];
+                const int64_t np = offsets[m + 1] - offsets[m];
+                c.max_np = np > c.max_np ? np : c.max_np;
+                c.tot_np += np;
+            }
+            PMMM_HIP(hipMemcpyAsync(c.d_prange, h, sizeof(int64_t) * 2 * c.members.size(),
+                                    hipMemcpyHostToDevice, s));
+            PMMM_HIP(hipStreamSynchronize(s));
+        }
+        b->offsets.assign(offsets, offsets + b->nsys + 1);
+    }
+    const std::vector<const void *> key = {x, y, z, q, phi, gx, gy, gz, (const void *)s};
+    const bool graphs = b->use_graph && s != nullptr;
+    if (graphs && key == b->key) {
+        if (b->gexec == nullptr) {
+            // second call with these arguments: capture the launches once
+            PMMM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            rc = batch_enqueue(b, x, y, z, q, phi, gx, gy, gz, s);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &g);
+            if (rc != PMMM_OK) {
+                if (g) hipGraphDestroy(g);
+                return rc;
+            }
+            PMMM_HIP(e);
+            b->graph = g;
+            PMMM_HIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+        }
+        PMMM_HIP(hipGraphLaunch(b->gexec, s));
+        return PMMM_OK;
+    }
+    drop_graph(b);
+    b->key = key;
+    return batch_enqueue(b, x, y, z, q, phi, gx, gy, gz, s);
+}
+
 extern "C" {
 
 int pmmm_plan_create(const pmmm_params *params, void *stream, pmmm_plan *out) {
@@ -650,6 +948,105 @@ int pmmm_near_f32(pmmm_plan plan, int64_t n, float *phi, float *gx, float *gy, f
 int pmmm_near_f64(pmmm_plan plan, int64_t n, double *phi, double *gx, double *gy, double *gz,
                   int accumulate, void *stream) {
     return near_impl<double>(plan, n, phi, gx, gy, gz, accumulate, stream);
+}
+
+int pmmm_batch_create(int nsys, const pmmm_params *per_sys, void *stream, pmmm_batch *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return PMMM_EINVAL;
+    }
+    *out = nullptr;
+    if (nsys < 1 || !per_sys) {
+        set_error("nsys must be positive and per_sys non-NULL");
+        return PMMM_EINVAL;
+    }
+    for (int i = 0; i < nsys; ++i) {
+        std::string why;
+        const int rc = validate(&per_sys[i], why);
+        if (rc != PMMM_OK) {
+            set_error("system " + std::to_string(i) + ": " + why);
+            return rc;
+        }
+        if (per_sys[i].precision == PMMM_F64) {
+            set_error("batches run the FP32 pipeline (PMMM_F32 or PMMM_BF16X3 systems)");
+            return PMMM_EINVAL;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    pmmm_batch_s *b = new pmmm_batch_s();
+    b->nsys = nsys;
+    int rc = PMMM_OK;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) rc = hip_fail(e, "hipGetDevice");
+    for (int i = 0; i < nsys && rc == PMMM_OK; ++i) {
+        size_t k = 0;
+        while (k < b->cls.size() && !same_class(b->cls[k].plan->prm, per_sys[i])) ++k;
+        if (k == b->cls.size()) {
+            BatchClass c;
+            pmmm_params prm = per_sys[i];
+            prm.precision = PMMM_F32;
+            prm.n_max = 0;
+            rc = pmmm_plan_create(&prm, stream, &c.plan);
+            if (rc != PMMM_OK) break;
+            b->cls.push_back(c);
+        }
+        b->cls[k].members.push_back(i);
+    }
+    for (auto &c : b->cls) {
+        if (rc != PMMM_OK) break;
+        rc = batch_alloc_class(c, s);
+    }
+    if (rc == PMMM_OK) {
+        e = hipMalloc(&b->flag, sizeof(int));
+        if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), s);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_prange, sizeof(int64_t) * 2 * nsys);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "batch workspace");
+    }
+    if (rc != PMMM_OK) {
+        batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PMMM_OK;
+}
+
+void pmmm_batch_destroy(pmmm_batch batch) { batch_destroy(batch); }
+
+int pmmm_batch_far_f32(pmmm_batch batch, const int64_t *offsets, const float *x, const float *y,
+                       const float *z, const float *q, float *phi, float *gx, float *gy,
+                       float *gz, void *stream) {
+    return batch_far(batch, offsets, x, y, z, q, phi, gx, gy, gz, stream);
+}
+
+int pmmm_batch_classes(pmmm_batch batch) { return batch ? (int)batch->cls.size() : 0; }
+
+int pmmm_batch_set_graphs(pmmm_batch batch, int enable) {
+    if (!batch) {
+        set_error("batch is NULL");
+        return PMMM_EINVAL;
+    }
+    PMMM_HIP(hipDeviceSynchronize());
+    drop_graph(batch);
+    batch->use_graph = enable != 0;
+    return PMMM_OK;
+}
+
+int pmmm_batch_sync_status(pmmm_batch batch) {
+    if (!batch) {
+        set_error("batch is NULL");
+        return PMMM_EINVAL;
+    }
+    PMMM_HIP(hipStreamSynchronize(batch->last_stream));
+    int flag = 0;
+    PMMM_HIP(hipMemcpy(&flag, batch->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        const int zero = 0;
+        PMMM_HIP(hipMemcpy(batch->flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+        set_error("open boundary: a particle lay outside [0, b)^3");
+        return PMMM_EDOMAIN;
+    }
+    return PMMM_OK;
 }
 
 int pmmm_plan_sync_status(pmmm_plan plan) {

@@ -11,6 +11,11 @@
 //                 sorted slot
 // Cell index: I = floor(r n / b) per axis, clamped to [0, n-1]; periodic
 // positions are first wrapped into the box (in cell units).
+//
+// Batches: blockIdx.y selects one of several independent systems on meshes of
+// the same size; prange[2s], prange[2s+1] bound system s's particles in the
+// caller's arrays (null: one system, particles [0, n)), and its cell arrays
+// sit at fixed strides (count K, start K + 1, dense list K, small 8).
 #include "pmmm_internal.h"
 
 namespace pmmm {
@@ -31,15 +36,20 @@ __device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, in
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_bin_count(int64_t n, const T *__restrict__ x,
+__global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ prange, int64_t n,
+                                                   const T *__restrict__ x,
                                                    const T *__restrict__ y,
                                                    const T *__restrict__ z, T inv_h, int nc,
                                                    int periodic, int *__restrict__ cell_of,
                                                    int *__restrict__ slot,
                                                    int *__restrict__ count,
                                                    int *__restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    int64_t p0, np;
+    sys_range(prange, n, p0, np);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    const int64_t i = p0 + j;
+    count += (int64_t)blockIdx.y * nc * nc * nc;
     int ix, iy, iz, out = 0;
     T ux, uy, uz;
     cell_coord(x[i], inv_h, nc, periodic, ix, ux, out);
@@ -51,11 +61,18 @@ __global__ void __launch_bounds__(256) k_bin_count(int64_t n, const T *__restric
     slot[i] = atomicAdd(&count[c], 1);
 }
 
-// One workgroup of 1024 threads scans all K counts in tiles of 4096.
+// One workgroup of 1024 threads per system scans its K counts in tiles of 4096.
 __global__ void __launch_bounds__(1024) k_bin_scan(int K, int *__restrict__ count,
                                                    int *__restrict__ start, int dense_thr,
                                                    int *__restrict__ dense_cells,
                                                    int *__restrict__ dense_count) {
+    {
+        const int64_t sy = blockIdx.y;
+        count += sy * K;
+        start += sy * (K + 1);
+        dense_cells += sy * K;
+        dense_count += sy * 8;
+    }
     __shared__ int wtot[16];
     __shared__ int carry_s;
     __shared__ int ndense;
@@ -158,21 +175,33 @@ __device__ void block_scan_small(int K, const int *__restrict__ count, int *s_st
 // Scatter into the sorted structure-of-arrays record.  With inblock, every
 // block scans the counts itself (small meshes), else start[] comes from the
 // scan kernel.
+// Sorted slot g of system s is p0 + start[c] + slot: perm[g] holds the
+// particle's index in the caller's arrays, scell[g] its cell.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bin_scatter(
-    int64_t n, const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
-    const T *__restrict__ q, T inv_h, int nc, int periodic, const int *__restrict__ cell_of,
-    const int *__restrict__ slot, int *__restrict__ start, int *__restrict__ perm,
-    int *__restrict__ scell, particle4<T> *__restrict__ sorted, int inblock,
-    const int *__restrict__ count, int dense_thr, int *__restrict__ dense_cells,
-    int *__restrict__ dense_count) {
+    const int64_t *__restrict__ prange, int64_t n, const T *__restrict__ x,
+    const T *__restrict__ y, const T *__restrict__ z, const T *__restrict__ q, T inv_h, int nc,
+    int periodic, const int *__restrict__ cell_of, const int *__restrict__ slot,
+    int *__restrict__ start, int *__restrict__ perm, int *__restrict__ scell,
+    particle4<T> *__restrict__ sorted, int inblock, const int *__restrict__ count,
+    int dense_thr, int *__restrict__ dense_cells, int *__restrict__ dense_count) {
     __shared__ int s_start[kInBlockScanMax + 1];
     const int K = nc * nc * nc;
+    {
+        const int64_t sy = blockIdx.y;
+        count += sy * K;
+        start += sy * (K + 1);
+        dense_cells += sy * K;
+        dense_count += sy * 8;
+    }
+    int64_t p0, np;
+    sys_range(prange, n, p0, np);
     if (inblock)
         block_scan_small(K, count, s_start, blockIdx.x == 0, start, dense_thr, dense_cells,
                          dense_count);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    const int64_t i = p0 + j;
     int ix, iy, iz, out = 0;
     particle4<T> r;
     cell_coord(x[i], inv_h, nc, periodic, ix, r.ux, out);
@@ -181,29 +210,32 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     r.q = q != nullptr ? q[i] : T(0);
     const int c = cell_of[i];
     const int s = (inblock ? s_start[c] : start[c]) + slot[i];
-    if (s < 0 || (int64_t)s >= n) return;  // only reachable with inconsistent counts
-    perm[s] = (int)i;
-    scell[s] = c;
-    sorted[s] = r;
+    if (s < 0 || (int64_t)s >= np) return;  // only reachable with inconsistent counts
+    const int64_t g = p0 + s;
+    perm[g] = (int)i;
+    scell[g] = c;
+    sorted[g] = r;
 }
 
 template <typename T>
 hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const T inv_h = T(a.inv_h);
-    const int blocks = (int)((a.n + 255) / 256);
+    const int nsys = a.nsys > 0 ? a.nsys : 1;
+    const int64_t maxn = a.prange ? a.max_np : a.n;
+    const int blocks = (int)((maxn + 255) / 256);
     const int inblock = K <= kInBlockScanMax ? 1 : 0;
-    if (a.n > 0) {
-        hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks), dim3(256), 0, s, a.n,
+    if (maxn > 0) {
+        hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
                            a.periodic, a.cell_of, a.slot, a.count, a.flag);
     }
-    if (!inblock || a.n == 0) {
-        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, K, a.count, a.start,
+    if (!inblock || maxn == 0) {
+        hipLaunchKernelGGL(k_bin_scan, dim3(1, nsys), dim3(1024), 0, s, K, a.count, a.start,
                            a.dense_threshold, a.dense_cells, a.dense_count);
     }
-    if (a.n > 0) {
-        hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks), dim3(256), 0, s, a.n,
+    if (maxn > 0) {
+        hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, (const T *)a.q,
                            inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, a.perm,
                            a.scell, (particle4<T> *)a.sorted, inblock, a.count,

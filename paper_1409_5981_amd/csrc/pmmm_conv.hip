@@ -49,6 +49,13 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
     cplx<T> *buf2 = buf1 + npair * ls;     // [nf][nh]
     const int z = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    {
+        // system blockIdx.z of a batch: meshes at fixed strides
+        const int64_t sy = blockIdx.z, K = (int64_t)nin * nin * nin;
+        M += sy * (P + 1) * K;
+        spec += sy * P * nin * nf * nh;
+        if (qr2_partial != nullptr) qr2_partial += sy * nin;
+    }
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
     const T *plane = M + ((int64_t)c * nin + z) * nin * nin;
     // rows are paired (2j, 2j+1) into one complex row; loads are issued in
@@ -116,6 +123,13 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
                                                    const cplx<T> *__restrict__ spec,
                                                    T *__restrict__ L,
                                                    const cplx<T> *__restrict__ tw_g, T scale) {
+    {
+        // system blockIdx.z of a batch: meshes at fixed strides
+        const int64_t sy = blockIdx.z, P = gridDim.y;
+        const int nf_ = 1 << logn;
+        spec += sy * P * nout * nf_ * (nf_ / 2 + 1);
+        L += sy * P * nout * nout * nout;
+    }
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nf = 1 << logn, nh = nf / 2 + 1, npair = nout / 2, ls = lds_line(nf);
     cplx<T> *tw = (cplx<T> *)lds_raw;
@@ -362,6 +376,13 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
     const int per_xcd = (ngroups + 7) / 8;
     const int grp = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (grp >= ngroups) return;
+    {
+        // system blockIdx.y of a batch: spectra and sums at fixed strides
+        const int64_t sy = blockIdx.y;
+        spec += sy * P * nz * ncol;
+        qr2_partial += sy * nz;
+        sums += sy * 8;
+    }
     const int col0 = grp * w;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
@@ -497,8 +518,7 @@ static int ilog2(int v) {
 template <typename Kern>
 static hipError_t ensure_lds(Kern k, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    return set_max_lds((const void *)k, bytes);
 }
 
 template <int PO, typename T>
@@ -512,7 +532,7 @@ static hipError_t column_launch(const FFTArgs &a, hipStream_t s) {
     const int grid = ((ngroups + 7) / 8) * 8;
     hipError_t e = ensure_lds(k_column<PO, T>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_column<PO, T>), dim3(grid), dim3(threads), lds, s, a.n, logn, w, rs,
+    hipLaunchKernelGGL((k_column<PO, T>), dim3(grid, a.nsys > 0 ? a.nsys : 1), dim3(threads), lds, s, a.n, logn, w, rs,
                        ncol, ngroups, (const T *)a.green, (cplx<T> *)a.spec,
                        (const cplx<T> *)a.tw, a.open ? 0 : 1, a.qr2_partial, a.sums);
     return hipGetLastError();
@@ -522,13 +542,14 @@ template <typename T>
 hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const int P = nreal(a.p);
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, n = a.n;
+    const int nsys = a.nsys > 0 ? a.nsys : 1;
     const size_t csz = sizeof(cplx<T>);
     const size_t lds_plane = (size_t)(nf / 2 + (n / 2) * lds_line(nf) + nf * nh) * csz;
     hipError_t e = hipSuccess;
     if (stage == 0) {
         e = ensure_lds(k_plane_fwd<T>, lds_plane);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, P), dim3(256), lds_plane, s, n, logn,
+        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, P, nsys), dim3(256), lds_plane, s, n, logn,
                            (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
                            a.open ? nullptr : a.qr2_partial);
         return hipGetLastError();
@@ -550,7 +571,7 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     e = ensure_lds(k_plane_inv<T>, lds_plane);
     if (e != hipSuccess) return e;
     const T scale = T(1.0 / ((double)nf * nf * nf));
-    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P), dim3(256), lds_plane, s, n, logn,
+    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P, nsys), dim3(256), lds_plane, s, n, logn,
                        (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw, scale);
     return hipGetLastError();
 }

@@ -358,6 +358,20 @@ __host__ __device__ constexpr Term im_S(int n, int k) {
                                        : Term{n + k, ((-k) & 1) ? 1 : -1};
 }
 
+// Particle range of a block's system in a batch (blockIdx.y selects the
+// system; prange[2s], prange[2s+1] bound its particles in the caller's
+// arrays).  Without a batch (prange null) the one system holds [0, n).
+__device__ __forceinline__ void sys_range(const int64_t *prange, int64_t n, int64_t &p0,
+                                          int64_t &np) {
+    if (prange == nullptr) {
+        p0 = 0;
+        np = n;
+    } else {
+        p0 = prange[2 * blockIdx.y];
+        np = prange[2 * blockIdx.y + 1] - p0;
+    }
+}
+
 // ------------------------------------------------------------ host side
 struct Plan;  // defined in pmmm_api.hip
 
@@ -383,6 +397,10 @@ inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out)
     }
 }
 
+// Raise a kernel's dynamic-LDS limit once (later calls with no larger size
+// make no runtime call, so they are safe while a stream is being captured).
+hipError_t set_max_lds(const void *kernel, size_t bytes);
+
 // Error bookkeeping (thread-local message).
 void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
@@ -404,6 +422,10 @@ struct BinArgs {
     int *dense_cells, *dense_count;
     int dense_threshold;
     void *sorted;      // particle4<T>[n]
+    // batch of nsys systems on this mesh (prange null: one system of n)
+    const int64_t *prange;
+    int nsys;
+    int64_t max_np;
 };
 template <typename T>
 hipError_t launch_bin(const BinArgs &a, hipStream_t s);
@@ -416,6 +438,8 @@ struct P2MArgs {
     int dense_threshold;
     const void *sorted;
     void *M;                        // [P + 1][K]: moments, then sum q |u|^2
+    const int64_t *prange;          // batch (see BinArgs)
+    int nsys;
 };
 template <typename T>
 hipError_t launch_p2m(const P2MArgs &a, hipStream_t s);
@@ -429,6 +453,7 @@ struct FFTArgs {
     const void *green;              // [nf*(nf/2+1)][Q][nf]
     const void *tw;                 // cplx<T>[nf/2]
     void *L;                        // [P][n^3]
+    int nsys;                       // batch of systems at fixed strides (1: one)
 };
 // stage 0: forward plane FFTs, 1: column FFT + M2L + inverse, 2: inverse planes
 template <typename T>
@@ -444,6 +469,9 @@ struct L2PArgs {
     double alpha_cell;              // alpha h
     double inv_h;                   // 1 / h in the caller's length unit
     void *phi, *gx, *gy, *gz;
+    const int64_t *prange;          // batch (see BinArgs)
+    int nsys;
+    int64_t max_np;
 };
 template <typename T>
 hipError_t launch_l2p(const L2PArgs &a, hipStream_t s);

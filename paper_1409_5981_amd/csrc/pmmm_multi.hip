@@ -754,8 +754,7 @@ bool multi_supported(int p, int nf) {
 template <typename Kern>
 static hipError_t lds_attr(Kern k, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    return set_max_lds((const void *)k, bytes);
 }
 
 static int ilog2i(int v) {

@@ -26,8 +26,19 @@ __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ star
                                              const particle4<T> *__restrict__ sorted,
                                              int dense_thr, const int *__restrict__ dense_cells,
                                              const int *__restrict__ dense_count, int nlight,
-                                             T *__restrict__ M, int *__restrict__ zero_count) {
+                                             T *__restrict__ M, int *__restrict__ zero_count,
+                                             const int64_t *__restrict__ prange) {
     constexpr int P = nreal(PO);
+    {
+        // system blockIdx.y of a batch: its cell arrays and sorted particles
+        const int64_t sy = blockIdx.y;
+        start += sy * (K + 1);
+        dense_cells += sy * K;
+        dense_count += sy * 8;
+        M += sy * (P + 1) * K;
+        if (zero_count != nullptr) zero_count += sy * K;
+        if (prange != nullptr) sorted += prange[2 * sy];
+    }
     if ((int)blockIdx.x < nlight) {
         const int gid = blockIdx.x * 256 + threadIdx.x;
         if (zero_count != nullptr && gid < K) zero_count[gid] = 0;
@@ -103,10 +114,16 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
                                              const double *__restrict__ sums, T alpha_c,
                                              T inv_h, T *__restrict__ phi_out,
                                              T *__restrict__ gx_out, T *__restrict__ gy_out,
-                                             T *__restrict__ gz_out) {
+                                             T *__restrict__ gz_out,
+                                             const int64_t *__restrict__ prange) {
     constexpr int P = nreal(PO);
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
+    int64_t p0, np;
+    sys_range(prange, n, p0, np);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    const int64_t s = p0 + j;                 // sorted slot (caller-array numbering)
+    L += (int64_t)blockIdx.y * P * K;
+    sums += (int64_t)blockIdx.y * 8;
     const particle4<T> r = sorted[s];
     const int c = scell[s];
     T Lc[P];
@@ -178,14 +195,15 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
     int nlight = (int)(((int64_t)K * G + 255) / 256);
     if (a.zero_count && nlight * 256 < K) nlight = (K + 255) / 256;
     const int grid = nlight + (a.may_have_dense ? kDenseBlocks : 0);
+    const int nsys = a.nsys > 0 ? a.nsys : 1;
     const int *st = a.start;
     const particle4<T> *so = (const particle4<T> *)a.sorted;
     T *M = (T *)a.M;
 #define PMMM_P2M_G(GG)                                                                     \
     case GG:                                                                               \
-        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(grid), dim3(256), 0, s, K, st, so,      \
+        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(grid, nsys), dim3(256), 0, s, K, st, so,\
                            a.dense_threshold, a.dense_cells, a.dense_count, nlight, M,      \
-                           a.zero_count);                                                  \
+                           a.zero_count, a.prange);                                        \
         break;
     switch (G) {
         PMMM_P2M_G(4)
@@ -219,17 +237,19 @@ hipError_t launch_p2m(const P2MArgs &a, hipStream_t s) {
 template <int PO, typename T>
 static hipError_t l2p_launch(const L2PArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
-    const int blocks = (int)((a.n + 255) / 256);
-    hipLaunchKernelGGL((k_l2p<PO, T>), dim3(blocks), dim3(256), 0, s, a.n, K, a.periodic,
+    const int64_t maxn = a.prange ? a.max_np : a.n;
+    const int blocks = (int)((maxn + 255) / 256);
+    const int nsys = a.nsys > 0 ? a.nsys : 1;
+    hipLaunchKernelGGL((k_l2p<PO, T>), dim3(blocks, nsys), dim3(256), 0, s, a.n, K, a.periodic,
                        (const particle4<T> *)a.sorted, a.scell, a.perm, (const T *)a.L,
                        a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
-                       (T *)a.gx, (T *)a.gy, (T *)a.gz);
+                       (T *)a.gx, (T *)a.gy, (T *)a.gz, a.prange);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_l2p(const L2PArgs &a, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
+    if ((a.prange ? a.max_np : a.n) == 0) return hipSuccess;
     switch (a.p) {
         case 0: return l2p_launch<0, T>(a, s);
         case 1: return l2p_launch<1, T>(a, s);

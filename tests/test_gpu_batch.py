@@ -1,0 +1,152 @@
+"""GPU parity of batched independent systems (pmmm_batch_far_f32): every
+system of a mixed batch against the FP64 oracle run on that system alone,
+at the FP32 bound of 1e-6 relative RMS; the eager launches, the captured
+graph and its replays; new offsets; and the full 256-system workload on a
+sample of systems."""
+import numpy as np
+import pytest
+
+from gpu_helpers import oracle_cfg
+from oracle import exact
+from oracle import pmmm as opm
+from paper_1409_5981_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def _concat(systems):
+    offs = np.zeros(len(systems) + 1, dtype=np.int64)
+    for i, ps in enumerate(systems):
+        offs[i + 1] = offs[i] + ps.n
+    cat = [np.concatenate([getattr(ps, a) for ps in systems]).astype(np.float32)
+           if offs[-1] else np.zeros(0, np.float32) for a in ("x", "y", "z", "q")]
+    return offs, cat
+
+
+def _run(batch, systems, offs=None, cat=None):
+    import torch
+    if offs is None:
+        offs, cat = _concat(systems)
+    t = [torch.from_numpy(a).cuda() for a in cat]
+    phi, gx, gy, gz = batch.far(offs, *t)
+    torch.cuda.synchronize()
+    batch.sync_status()
+    return offs, phi.double().cpu().numpy(), torch.stack([gx, gy, gz], 1).double().cpu().numpy()
+
+
+def _check(systems, offs, phi, grad, which=None, sample=None):
+    for i in (range(len(systems)) if which is None else which):
+        ps = systems[i]
+        if ps.n == 0:
+            continue
+        a, b = offs[i], offs[i + 1]
+        idx = None if sample is None or ps.n <= sample else np.sort(
+            np.random.default_rng(i).choice(ps.n, sample, replace=False))
+        ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps), eval_idx=idx)
+        gp, gg = phi[a:b], grad[a:b]
+        if idx is not None:
+            gp, gg = gp[idx], gg[idx]
+        eg, ep = exact.rel_rms(gg, ref.grad), exact.rel_rms(gp, ref.phi)
+        print(f"system {i} ({ps.boundary} n={ps.n_cells} p={ps.p} N={ps.n}): "
+              f"rel-RMS grad {eg:.3e} phi {ep:.3e}", flush=True)
+        assert eg <= TOL and ep <= TOL, (i, eg, ep)
+
+
+def _mixed(seed=31):
+    rng = np.random.default_rng(seed)
+    systems = []
+    specs = [(8, 3, "periodic"), (16, 4, "periodic"), (8, 3, "periodic"), (16, 5, "periodic"),
+             (8, 4, "open"), (8, 3, "periodic"), (16, 4, "periodic"), (8, 5, "periodic"),
+             (8, 3, "periodic"), (16, 4, "periodic")]
+    for k, (n, p, bc) in enumerate(specs):
+        npart = 0 if k == 5 else int(rng.integers(300, 3000)) & ~1
+        x, y, z = (rng.random(npart).astype(np.float32) for _ in range(3))
+        q = inputs.neutral_pm1(rng, npart) if npart else np.zeros(0, np.float32)
+        systems.append(inputs.ParticleSet(x, y, z, q, n, p, bc))
+    return systems
+
+
+def _batch(systems):
+    from paper_1409_5981_amd._lib import Batch
+    return Batch([{"n": ps.n_cells, "p": ps.p, "boundary": ps.boundary} for ps in systems])
+
+
+def test_batch_mixed_against_oracle():
+    systems = _mixed()
+    batch = _batch(systems)
+    assert batch.classes == 5
+    offs, phi, grad = _run(batch, systems)
+    _check(systems, offs, phi, grad)
+
+
+def test_batch_matches_single_system_path():
+    from gpu_helpers import gpu_far
+    systems = _mixed(32)
+    batch = _batch(systems)
+    offs, phi, grad = _run(batch, systems)
+    for i in (0, 3, 4):
+        res, _ = gpu_far(systems[i], "f32")
+        a, b = offs[i], offs[i + 1]
+        assert exact.rel_rms(grad[a:b], res["grad"]) < 1e-6
+        assert exact.rel_rms(phi[a:b], res["phi"]) < 1e-6
+
+
+def test_batch_graph_capture_and_replay():
+    """Eager call, captured call, two replays (with eager work and
+    synchronisations in between), then new offsets: every result against
+    the oracle's."""
+    import torch
+    systems = _mixed(33)
+    batch = _batch(systems)
+    offs, cat = _concat(systems)
+    t = [torch.from_numpy(a).cuda() for a in cat]
+    out = tuple(torch.empty(int(offs[-1]), dtype=torch.float32, device="cuda") for _ in range(4))
+    stream = torch.cuda.Stream()
+    results = []
+    with torch.cuda.stream(stream):
+        for it in range(4):
+            for o in out:
+                o.fill_(float("nan"))
+            batch.far(offs, *t, out=out, stream=stream)
+            stream.synchronize()
+            results.append((out[0].double().cpu().numpy(),
+                            torch.stack(out[1:], 1).double().cpu().numpy()))
+            _ = (t[0] * 2).sum().item()        # unrelated eager work between replays
+    _check(systems, offs, *results[0])
+    for phi, grad in results[1:]:
+        assert np.all(np.isfinite(phi))
+        assert exact.rel_rms(grad, results[0][1]) < 1e-6
+        assert exact.rel_rms(phi, results[0][0]) < 1e-6
+    # new offsets: drop the first 100 particles of system 0
+    sub = list(systems)
+    sub[0] = systems[0].subset(np.arange(100, systems[0].n))
+    offs2, phi2, grad2 = _run(batch, sub)
+    _check(sub, offs2, phi2, grad2, which=[0, 1, 4])
+
+
+def test_batch_errors():
+    import torch
+    from paper_1409_5981_amd._lib import PMMM_EINVAL, Batch, PMMMError
+    batch = Batch([{"n": 8, "p": 3}, {"n": 8, "p": 3}])
+    e = torch.zeros(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(PMMMError) as ei:
+        batch.far(np.array([0, 3, 2]), e[:2], e[:2], e[:2], e[:2])
+    assert ei.value.code == PMMM_EINVAL
+    with pytest.raises(PMMMError):
+        Batch([{"n": 12, "p": 3}])           # not a power of two
+
+
+def test_batch_full_workload_sampled():
+    """The 256-system workload (N uniform in [2048, 65536], meshes 8/16/32,
+    p in {4, 5, 6}) in the benchmark's launch configuration; one system of
+    each mesh size is checked against the oracle on 1024 sampled particles
+    (moments from all of the system's particles)."""
+    systems = inputs.batched_systems()
+    batch = _batch(systems)
+    offs, phi, grad = _run(batch, systems)
+    pick = []
+    for n in (8, 16, 32):
+        pick.append(next(i for i, ps in enumerate(systems) if ps.n_cells == n))
+    _check(systems, offs, phi, grad, which=pick, sample=1024)
