@@ -54,7 +54,9 @@ def stage_work(stage, N, n, p, nf, open_bc, tsize=4):
     if stage == "fft_fwd":
         return tsize * P * K + c * P * spec, 5 * P * n * nf * (nf // 2 + 1) * 2 * lg
     if stage == "column":
-        return 2 * c * P * spec + tsize * Q * F, 4 * P * P * F + 2 * 5 * P * ncol * nf * lg
+        nh = nf // 2 + 1
+        green = tsize * Q * nh * nh * ((nh + 3) & ~3)      # stored quadrant of the kernel
+        return 2 * c * P * spec + green, 4 * P * P * F + 2 * 5 * P * ncol * nf * lg
     if stage == "fft_inv":
         return c * P * spec + tsize * P * K, 5 * P * n * nf * (nf // 2 + 1) * 2 * lg
     if stage == "l2p":
@@ -161,6 +163,9 @@ def main():
     ap.add_argument("--workload", default="periodic_n32768_m16_p5", choices=sorted(WORKLOADS),
                     help="default: the headline workload; the others are the remaining "
                          "single-GPU configurations")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB before the "
+                         "benchmark (calibration of the HBM traffic counters)")
     ap.add_argument("--split", default="f32", choices=["f32", "bf16x3"],
                     help="multi-charge workload: three-term (f32) or two-term (bf16x3) "
                          "bf16 splits in the M2L product")
@@ -176,6 +181,13 @@ def main():
     from paper_1409_5981_amd import inputs
     from paper_1409_5981_amd._lib import Plan, STAGES
 
+    if args.copy_mb > 0:
+        # a plain copy kernel of known size: reads and writes copy_mb MiB once
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     workload = args.workload
     if workload.startswith("multi_"):
         return bench_multi(args, workload)
