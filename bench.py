@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--workload", default="periodic_n32768_m16_p5", choices=sorted(WORKLOADS),
                     help="default: the headline workload; the others are the remaining "
                          "single-GPU configurations")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the plan-time launch-shape autotuner (single-system workloads)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "benchmark (calibration of the HBM traffic counters)")
@@ -206,6 +208,10 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
     torch.cuda.set_stream(stream)
+    tuning = None
+    if not args.no_autotune:
+        # plan-time choice of launch shapes on this workload (not timed)
+        tuning = plan.autotune(x, y, z, q, out=out)
 
     # warm-up; the second half also times every stage to pick the dominant kernel
     half = max(1, args.warmup // 2)
@@ -271,6 +277,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "boundary": boundary, "n_particles": N,
                    "cells": f"{n}^3", "fft_mesh": f"{nf}^3", "p": p, "cutoff": 2,
+                   "tuning": {"column_width": tuning[0], "p2m_lanes": tuning[1]} if tuning else None,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -28,6 +28,7 @@ EXPORTS = [
     "pmmm_near_f32", "pmmm_near_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
     "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
+    "pmmm_plan_autotune", "pmmm_plan_get_tuning",
     "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
     "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
     "pmmm_error_string", "pmmm_last_error",
@@ -92,6 +93,10 @@ def load():
     L.pmmm_plan_read_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64), ci]
     L.pmmm_plan_read_profile.restype = ci
+    L.pmmm_plan_autotune.argtypes = [vp, i64] + [vp] * 8 + [vp]
+    L.pmmm_plan_autotune.restype = ci
+    L.pmmm_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.pmmm_plan_get_tuning.restype = ci
     L.pmmm_batch_create.argtypes = [ci, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     L.pmmm_batch_create.restype = ci
     L.pmmm_batch_destroy.argtypes = [vp]
@@ -214,6 +219,24 @@ class Plan:
                                          nsets, q.data_ptr(), *[o.data_ptr() for o in out],
                                          _stream_handle(stream)))
         return out
+
+    def autotune(self, x, y, z, q, out=None, stream=None):
+        """Time the candidate launch shapes on these particles and keep the
+        fastest; returns (column width, P2M lanes per cell)."""
+        import torch
+        self._check_tensors(x, y, z, q)
+        n = x.numel()
+        if out is None:
+            out = tuple(torch.empty(n, dtype=self.dtype, device=x.device) for _ in range(4))
+        _check(load().pmmm_plan_autotune(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                                         q.data_ptr(), *[o.data_ptr() for o in out],
+                                         _stream_handle(stream)))
+        return self.tuning()
+
+    def tuning(self):
+        w, g = ctypes.c_int(), ctypes.c_int()
+        _check(load().pmmm_plan_get_tuning(self._h, ctypes.byref(w), ctypes.byref(g)))
+        return w.value, g.value
 
     def near(self, n, out=None, accumulate=False, device="cuda", stream=None):
         import torch

@@ -59,6 +59,8 @@ struct Plan {
     void *mY = nullptr;           // [nf][nf][nf/2+1][P S] spectra
     unsigned *mtmap = nullptr;    // t-matrix map in MFMA fragment order
     double *mqr2 = nullptr, *mqtot = nullptr;
+    // tuned launch shapes (0: defaults)
+    int tune_col_w = 0, tune_group = 0;
     // stage timing
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -370,7 +372,7 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         P2MArgs m{};
         m.p = pl->p;
         m.ncell = pl->n;
-        m.group = group_for((double)n / (double)pl->K);
+        m.group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
         m.may_have_dense = n > kDenseThreshold;
         // meshes scanned inside the scatter kernel reset their counts here
         m.zero_count = (n > 0 && pl->K <= 4096) ? pl->count : nullptr;
@@ -394,6 +396,7 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
     f.L = pl->L;
     f.qr2_partial = pl->qr2_partial;
     f.sums = pl->sums;
+    f.col_w = pl->tune_col_w;
     for (int st = 0; st < 3; ++st) {
         StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s);
         PMMM_HIP(launch_conv_stage<T>(f, st, s));
@@ -582,6 +585,57 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         }
     }
     return PMMM_OK;
+}
+
+// Autotuner: times the far-field call on the caller's particles for each
+// candidate launch shape (column-kernel width w from the widest that fits
+// down to a quarter of it; P2M lanes per cell 4..32) and keeps the fastest.
+template <typename T>
+static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T *z,
+                         const T *q, T *phi, T *gx, T *gy, T *gz, hipStream_t s) {
+    int wmax = 1, rs = 1;
+    if (column_shape(pl->p, pl->nf, pl->tsize, &wmax, &rs) == 0) return PMMM_EUNSUPPORTED;
+    std::vector<int> ws = {wmax};
+    if (wmax >= 2) ws.push_back(wmax / 2);
+    if (wmax >= 4) ws.push_back(wmax / 4);
+    const int gs[4] = {4, 8, 16, 32};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PMMM_HIP(hipEventCreate(&e0));
+    PMMM_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bw = 0, bg = 0, rc = PMMM_OK;
+    for (int w : ws) {
+        for (int g : gs) {
+            pl->tune_col_w = w;
+            pl->tune_group = g;
+            for (int it = 0; it < 2 && rc == PMMM_OK; ++it)
+                rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
+            if (rc != PMMM_OK) break;
+            hipEventRecord(e0, s);
+            constexpr int kReps = 5;
+            for (int it = 0; it < kReps && rc == PMMM_OK; ++it)
+                rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
+            hipEventRecord(e1, s);
+            if (rc != PMMM_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = PMMM_EHIP;
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bw = w;
+                bg = g;
+            }
+        }
+        if (rc != PMMM_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    pl->tune_col_w = rc == PMMM_OK ? bw : 0;
+    pl->tune_group = rc == PMMM_OK ? bg : 0;
+    return rc;
 }
 
 // ------------------------------------------------------------------ batches
@@ -1046,6 +1100,32 @@ int pmmm_batch_sync_status(pmmm_batch batch) {
         set_error("open boundary: a particle lay outside [0, b)^3");
         return PMMM_EDOMAIN;
     }
+    return PMMM_OK;
+}
+
+int pmmm_plan_autotune(pmmm_plan plan, int64_t n, const void *x, const void *y, const void *z,
+                       const void *q, void *phi, void *gx, void *gy, void *gz, void *stream) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->tsize == sizeof(double))
+        return autotune_impl<double>(plan, n, (const double *)x, (const double *)y,
+                                     (const double *)z, (const double *)q, (double *)phi,
+                                     (double *)gx, (double *)gy, (double *)gz, s);
+    return autotune_impl<float>(plan, n, (const float *)x, (const float *)y, (const float *)z,
+                                (const float *)q, (float *)phi, (float *)gx, (float *)gy,
+                                (float *)gz, s);
+}
+
+int pmmm_plan_get_tuning(pmmm_plan plan, int *column_width, int *p2m_lanes) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    if (column_width) *column_width = plan->tune_col_w;
+    if (p2m_lanes) *p2m_lanes = plan->tune_group;
     return PMMM_OK;
 }
 

@@ -525,8 +525,14 @@ template <int PO, typename T>
 static hipError_t column_launch(const FFTArgs &a, hipStream_t s) {
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, ncol = nf * nh;
     int w = 1, rs = 1;
-    const size_t lds = column_shape(PO, nf, sizeof(T), &w, &rs);
+    size_t lds = column_shape(PO, nf, sizeof(T), &w, &rs);
     if (lds == 0) return hipErrorInvalidValue;
+    if (a.col_w > 0 && a.col_w < w) {
+        // a narrower tuned shape (always fits when the widest one does)
+        w = a.col_w;
+        lds = column_lds_w(PO, nf, sizeof(T), w, &rs);
+        if (lds == 0) return hipErrorInvalidValue;
+    }
     const int threads = rs * w * nf;
     const int ngroups = (ncol + w - 1) / w;
     const int grid = ((ngroups + 7) / 8) * 8;

@@ -379,6 +379,18 @@ struct Plan;  // defined in pmmm_api.hip
 // row subsets (rs * w * nf <= 256 threads); LDS holds moment and local
 // spectra [P][w][nf] and the kernel tile [Q][w][nhp].  Returns the LDS
 // bytes, or 0 if no shape fits the 160 KB of one CU.
+// LDS bytes of the column kernel for w columns per block (0 if over 160 KB),
+// and its row subsets rs.
+inline size_t column_lds_w(int p, int nf, size_t tsize, int w, int *rs_out) {
+    const size_t P = (size_t)(p + 1) * (p + 1), Q = (size_t)(2 * p + 1) * (2 * p + 1);
+    const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
+    const size_t lds = 2 * P * w * (size_t)lds_line(nf) * 2 * tsize + Q * w * nhp * tsize +
+                       (size_t)nf / 2 * 2 * tsize;
+    if (w < 1 || (size_t)w * nf > 256 || lds > 160 * 1024) return 0;
+    if (rs_out) *rs_out = 256 / (w * nf) < 4 ? 256 / (w * nf) : 4;
+    return lds;
+}
+
 inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out) {
     const size_t P = (size_t)(p + 1) * (p + 1), Q = (size_t)(2 * p + 1) * (2 * p + 1);
     const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
@@ -454,6 +466,7 @@ struct FFTArgs {
     const void *tw;                 // cplx<T>[nf/2]
     void *L;                        // [P][n^3]
     int nsys;                       // batch of systems at fixed strides (1: one)
+    int col_w;                      // columns per column-kernel block (0: largest that fits)
 };
 // stage 0: forward plane FFTs, 1: column FFT + M2L + inverse, 2: inverse planes
 template <typename T>

@@ -181,3 +181,20 @@ def test_full_size_sampled(name, gen):
     print(f"{name}: sampled rel-RMS grad {eg:.3e} phi {ep:.3e}", flush=True)
     assert eg <= TOL["f32"], eg
     assert ep <= TOL["f32"], ep
+
+
+def test_autotune_keeps_parity():
+    """The launch-shape autotuner picks a column width and P2M lane count; the
+    far field computed with the kept shape still matches the oracle."""
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    ps = _small(20000, 16, 5, "periodic", 17, np.float32)
+    plan = Plan(16, 5, "periodic")
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (ps.x, ps.y, ps.z, ps.q)]
+    w, g = plan.autotune(*t)
+    assert w in (1, 2, 4) and g in (4, 8, 16, 32), (w, g)
+    print(f"autotune: column width {w}, P2M lanes {g}")
+    res, _ = gpu_far(ps, "f32", plan=plan)
+    ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+    assert exact.rel_rms(res["grad"], ref.grad) <= TOL["f32"]
+    assert exact.rel_rms(res["phi"], ref.phi) <= TOL["f32"]
