@@ -47,6 +47,7 @@ struct Plan {
     // plan-lifetime buffers
     void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
     int *count = nullptr, *start = nullptr, *dense_cells = nullptr, *small = nullptr;
+    int *tile_sums = nullptr;
     double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
     int64_t cap = 0, last_n = -1;
@@ -256,6 +257,7 @@ static void destroy(Plan *pl) {
     hipFree(pl->count);
     hipFree(pl->start);
     hipFree(pl->dense_cells);
+    hipFree(pl->tile_sums);
     hipFree(pl->small);
     hipFree(pl->sums);
     hipFree(pl->qr2_partial);
@@ -293,6 +295,7 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * pl->K));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
     PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
+    PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * scan_tiles(pl->K)));
     PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] scan counter
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
     PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
@@ -363,6 +366,7 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         b.flag = pl->small + 1;
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
+        b.tile_sums = pl->tile_sums;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         PMMM_HIP(launch_bin<T>(b, s));
@@ -546,6 +550,7 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         b.flag = pl->small + 1;
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
+        b.tile_sums = pl->tile_sums;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         PMMM_HIP(launch_bin<float>(b, s));
@@ -647,6 +652,7 @@ struct BatchClass {
     pmmm_plan_s *plan = nullptr;    // transfer kernel, twiddles, constants
     std::vector<int> members;       // system indices in the caller's order
     int *count = nullptr, *start = nullptr, *dense = nullptr, *small = nullptr;
+    int *tile_sums = nullptr;
     void *M = nullptr, *spec = nullptr, *L = nullptr;
     double *qr2 = nullptr, *sums = nullptr;
     int64_t *d_prange = nullptr;    // [2 members]
@@ -695,6 +701,7 @@ static void batch_destroy(pmmm_batch_s *b) {
         hipFree(c.count);
         hipFree(c.start);
         hipFree(c.dense);
+        hipFree(c.tile_sums);
         hipFree(c.small);
         hipFree(c.M);
         hipFree(c.spec);
@@ -720,6 +727,7 @@ static int batch_alloc_class(BatchClass &c, hipStream_t s) {
     PMMM_HIP(hipMalloc(&c.count, sizeof(int) * K * ns));
     PMMM_HIP(hipMalloc(&c.start, sizeof(int) * (K + 1) * ns));
     PMMM_HIP(hipMalloc(&c.dense, sizeof(int) * K * ns));
+    PMMM_HIP(hipMalloc(&c.tile_sums, sizeof(int) * scan_tiles(K) * ns));
     PMMM_HIP(hipMalloc(&c.small, sizeof(int) * 8 * ns));
     PMMM_HIP(hipMalloc(&c.M, t * (P + 1) * K * ns));
     PMMM_HIP(hipMalloc(&c.spec, 2 * t * P * pl->n * pl->ncol * ns));
@@ -781,6 +789,7 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         bn.flag = b->flag;
         bn.dense_cells = c.dense;
         bn.dense_count = c.small;
+        bn.tile_sums = c.tile_sums;
         bn.dense_threshold = kDenseThreshold;
         bn.sorted = b->sorted;
         bn.prange = c.d_prange;

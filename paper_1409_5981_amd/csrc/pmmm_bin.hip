@@ -2,10 +2,11 @@
 // known ... achieved in an O(N) procedure"): a counting sort by cell.
 //   k_bin_count   cell of each particle, per-cell counts (int atomics) and the
 //                 particle's slot inside its cell
-//   k_bin_scan    exclusive scan of the counts -> cell_start, resets the counts
-//                 for the next call, lists cells above the dense threshold
-//                 (meshes up to 16^3 skip it: each scatter block scans the
-//                 counts itself and the P2M kernel resets them)
+//   k_bin_tile_sums, k_bin_scan_tiles
+//                 exclusive scan of the counts -> cell_start in tiles of 4096
+//                 cells, resets the counts for the next call, lists cells above
+//                 the dense threshold (meshes up to 16^3 skip it: each scatter
+//                 block scans the counts itself and the P2M kernel resets them)
 //   k_bin_scatter sorted structure-of-arrays record (offset from the cell
 //                 centre in cell units, charge), permutation and cell of each
 //                 sorted slot
@@ -50,77 +51,119 @@ __global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ p
     if (j >= np) return;
     const int64_t i = p0 + j;
     count += (int64_t)blockIdx.y * nc * nc * nc;
+    // the three loads are issued together, ahead of the branches below
+    const T xv = x[i], yv = y[i], zv = z[i];
+    asm volatile("" ::"v"(xv), "v"(yv), "v"(zv));
     int ix, iy, iz, out = 0;
     T ux, uy, uz;
-    cell_coord(x[i], inv_h, nc, periodic, ix, ux, out);
-    cell_coord(y[i], inv_h, nc, periodic, iy, uy, out);
-    cell_coord(z[i], inv_h, nc, periodic, iz, uz, out);
+    cell_coord(xv, inv_h, nc, periodic, ix, ux, out);
+    cell_coord(yv, inv_h, nc, periodic, iy, uy, out);
+    cell_coord(zv, inv_h, nc, periodic, iz, uz, out);
     if (out) *flag = 1;
     const int c = (iz * nc + iy) * nc + ix;
     cell_of[i] = c;
     slot[i] = atomicAdd(&count[c], 1);
 }
 
-// One workgroup of 1024 threads per system scans its K counts in tiles of 4096.
-__global__ void __launch_bounds__(1024) k_bin_scan(int K, int *__restrict__ count,
-                                                   int *__restrict__ start, int dense_thr,
-                                                   int *__restrict__ dense_cells,
-                                                   int *__restrict__ dense_count) {
+// Exclusive scan of the counts in tiles of kScanTile, one 1024-thread block
+// per tile: k_bin_tile_sums adds up every tile, then k_bin_scan_tiles scans
+// its tile starting from the sum of the tiles before it, resets the counts
+// for the next call and lists the cells above the dense threshold (in no
+// particular order: each dense cell is reduced by one block in a fixed order).
+constexpr int kScanTile = 4096;
+
+__global__ void __launch_bounds__(1024) k_bin_tile_sums(int K, const int *__restrict__ count,
+                                                        int *__restrict__ tile_sums,
+                                                        int *__restrict__ dense_count) {
+    const int ntiles = gridDim.x;
     {
         const int64_t sy = blockIdx.y;
         count += sy * K;
+        tile_sums += sy * ntiles;
+        dense_count += sy * 8;
+    }
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // K = n^3 with n >= 4 is a multiple of 64: four counts per thread, 16-byte aligned
+    const int idx = blockIdx.x * kScanTile + tid * 4;
+    int v = 0;
+    if (idx < K) {
+        const int4 c4 = *(const int4 *)(count + idx);
+        v = (c4.x + c4.y) + (c4.z + c4.w);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) wsum[wid] = v;
+    __syncthreads();
+    if (tid == 0) {
+        int t = 0;
+        for (int w = 0; w < 16; ++w) t += wsum[w];
+        tile_sums[blockIdx.x] = t;
+        if (blockIdx.x == 0) *dense_count = 0;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int *__restrict__ count,
+                                                         const int *__restrict__ tile_sums,
+                                                         int *__restrict__ start, int dense_thr,
+                                                         int *__restrict__ dense_cells,
+                                                         int *__restrict__ dense_count) {
+    const int ntiles = gridDim.x, t = blockIdx.x;
+    {
+        const int64_t sy = blockIdx.y;
+        count += sy * K;
+        tile_sums += sy * ntiles;
         start += sy * (K + 1);
         dense_cells += sy * K;
         dense_count += sy * 8;
     }
     __shared__ int wtot[16];
-    __shared__ int carry_s;
-    __shared__ int ndense;
+    __shared__ int pre_s;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int idx = t * kScanTile + tid * 4;
+    int v[4] = {0, 0, 0, 0};
+    if (idx < K) {
+        const int4 c4 = *(const int4 *)(count + idx);
+        v[0] = c4.x;
+        v[1] = c4.y;
+        v[2] = c4.z;
+        v[3] = c4.w;
+    }
+    // sum of the tiles before this one
+    int pre = 0;
+    for (int k = tid; k < t; k += 1024) pre += tile_sums[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) pre += __shfl_xor(pre, off, 64);
+    if (lane == 0) wtot[wid] = pre;
+    __syncthreads();
     if (tid == 0) {
-        carry_s = 0;
-        ndense = 0;
+        int a = 0;
+        for (int w = 0; w < 16; ++w) a += wtot[w];
+        pre_s = a;
     }
     __syncthreads();
-    for (int base = 0; base < K; base += 4096) {
-        int v[4];
-        int tot = 0;
+    // in-tile exclusive scan: wave scan of the thread totals, then the waves
+    const int tot = (v[0] + v[1]) + (v[2] + v[3]);
+    int inc = tot;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int idx = base + tid * 4 + j;
-            v[j] = idx < K ? count[idx] : 0;
-            tot += v[j];
-        }
-        // inclusive wave scan of thread totals
-        int inc = tot;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            int t = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += t;
-        }
-        if (lane == 63) wtot[wid] = inc;
-        __syncthreads();
-        int wpre = 0;
-        for (int w = 0; w < wid; ++w) wpre += wtot[w];
-        int run = carry_s + wpre + inc - tot;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int idx = base + tid * 4 + j;
-            if (idx < K) {
-                start[idx] = run;
-                count[idx] = 0;
-                if (v[j] > dense_thr) dense_cells[atomicAdd(&ndense, 1)] = idx;
-            }
-            run += v[j];
-        }
-        __syncthreads();
-        if (tid == 1023) carry_s = run;
-        __syncthreads();
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += u;
     }
-    if (tid == 0) {
-        start[K] = carry_s;
-        *dense_count = ndense;
+    if (lane == 63) wtot[wid] = inc;
+    __syncthreads();
+    int run = pre_s + inc - tot;
+    for (int w = 0; w < wid; ++w) run += wtot[w];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (idx + j < K) {
+            start[idx + j] = run;
+            if (v[j] > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = idx + j;
+        }
+        run += v[j];
     }
+    if (idx < K) *(int4 *)(count + idx) = make_int4(0, 0, 0, 0);
+    if (t == ntiles - 1 && tid == 1023) start[K] = run;
 }
 
 // Exclusive scan of K <= kInBlockScanMax counts by one 256-thread block into
@@ -196,20 +239,33 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     }
     int64_t p0, np;
     sys_range(prange, n, p0, np);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // The particle's inputs are read first (clamped index, so unconditional):
+    // their loads overlap those of the in-block scan.
+    const int64_t i = p0 + (j < np ? j : np - 1);
+    T xv = T(0), yv = T(0), zv = T(0), qv = T(0);
+    int c = 0, sl = 0;
+    if (np > 0) {
+        const T *qp = q != nullptr ? q : x;
+        xv = x[i];
+        yv = y[i];
+        zv = z[i];
+        qv = qp[i];
+        c = cell_of[i];
+        sl = slot[i];
+    }
     if (inblock)
         block_scan_small(K, count, s_start, blockIdx.x == 0, start, dense_thr, dense_cells,
                          dense_count);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= np) return;
-    const int64_t i = p0 + j;
+    asm volatile("" ::"v"(xv), "v"(yv), "v"(zv), "v"(qv), "v"(c), "v"(sl));
     int ix, iy, iz, out = 0;
     particle4<T> r;
-    cell_coord(x[i], inv_h, nc, periodic, ix, r.ux, out);
-    cell_coord(y[i], inv_h, nc, periodic, iy, r.uy, out);
-    cell_coord(z[i], inv_h, nc, periodic, iz, r.uz, out);
-    r.q = q != nullptr ? q[i] : T(0);
-    const int c = cell_of[i];
-    const int s = (inblock ? s_start[c] : start[c]) + slot[i];
+    cell_coord(xv, inv_h, nc, periodic, ix, r.ux, out);
+    cell_coord(yv, inv_h, nc, periodic, iy, r.uy, out);
+    cell_coord(zv, inv_h, nc, periodic, iz, r.uz, out);
+    r.q = q != nullptr ? qv : T(0);
+    const int s = (inblock ? s_start[c] : start[c]) + sl;
     if (s < 0 || (int64_t)s >= np) return;  // only reachable with inconsistent counts
     const int64_t g = p0 + s;
     perm[g] = (int)i;
@@ -231,8 +287,12 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
                            a.periodic, a.cell_of, a.slot, a.count, a.flag);
     }
     if (!inblock || maxn == 0) {
-        hipLaunchKernelGGL(k_bin_scan, dim3(1, nsys), dim3(1024), 0, s, K, a.count, a.start,
-                           a.dense_threshold, a.dense_cells, a.dense_count);
+        const int ntiles = (K + kScanTile - 1) / kScanTile;
+        hipLaunchKernelGGL(k_bin_tile_sums, dim3(ntiles, nsys), dim3(1024), 0, s, K, a.count,
+                           a.tile_sums, a.dense_count);
+        hipLaunchKernelGGL(k_bin_scan_tiles, dim3(ntiles, nsys), dim3(1024), 0, s, K, a.count,
+                           a.tile_sums, a.start, a.dense_threshold, a.dense_cells,
+                           a.dense_count);
     }
     if (maxn > 0) {
         hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,

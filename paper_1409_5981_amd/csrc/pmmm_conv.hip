@@ -56,7 +56,22 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
         spec += sy * P * nin * nf * nh;
         if (qr2_partial != nullptr) qr2_partial += sy * nin;
     }
-    for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
+    if (c == P) {
+        // blocks of the extra component row: sum over plane z of the per-cell
+        // q|u|^2 (component P of M), fixed-order reduction
+        __shared__ double red[4];
+        const T *pl = M + ((int64_t)P * nin + z) * nin * nin;
+        double acc = 0.0;
+        for (int idx = tid; idx < nin * nin; idx += nthr) acc += (double)pl[idx];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) qr2_partial[z] = ((red[0] + red[1]) + red[2]) + red[3];
+        return;
+    }
+    // twiddle load in flight together with the plane's loads (nf/2 <= blockDim.x)
+    const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];
     const T *plane = M + ((int64_t)c * nin + z) * nin * nin;
     // rows are paired (2j, 2j+1) into one complex row; loads are issued in
     // batches of kLoadBatch before their LDS stores
@@ -78,6 +93,8 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
             if (idx < npair * nf) buf1[(idx >> logn) * ls + (idx & (nf - 1))] = v[u];
         }
     }
+    asm volatile("" ::"v"(twv.re), "v"(twv.im));   // keeps the load above this point
+    if (tid < nf / 2) tw[tid] = twv;
     __syncthreads();
     fft_lines<T, false>(buf1, logn, npair, ls, 1, tw, tid, nthr);
     for (int idx = tid; idx < nf * nh; idx += nthr) {
@@ -101,21 +118,6 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
     fft_lines<T, false>(buf2, logn, nh, 1, nh, tw, tid, nthr);
     cplx<T> *out = spec + ((int64_t)c * nin + z) * nf * nh;
     for (int idx = tid; idx < nf * nh; idx += nthr) out[idx] = buf2[idx];
-    if (qr2_partial != nullptr && c == 0) {
-        // sum over this plane of the per-cell q|u|^2 (component P of M),
-        // fixed-order reduction
-        __shared__ double red[256];
-        const T *pl = M + ((int64_t)P * nin + z) * nin * nin;
-        double acc = 0.0;
-        for (int idx = tid; idx < nin * nin; idx += nthr) acc += (double)pl[idx];
-        red[tid] = acc;
-        __syncthreads();
-        for (int off = 128; off >= 1; off >>= 1) {
-            if (tid < off) red[tid] += red[tid + off];
-            __syncthreads();
-        }
-        if (tid == 0) qr2_partial[z] = red[0];
-    }
 }
 
 template <typename T>
@@ -137,21 +139,27 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
     cplx<T> *buf1 = buf2 + nf * nh;        // [npair][ls]
     const int z = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
+    // twiddle load in flight together with the spectrum's (nf/2 <= blockDim.x)
+    const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];
     const cplx<T> *in = spec + ((int64_t)c * nout + z) * nf * nh;
     for (int base = tid; base < nf * nh; base += nthr * kLoadBatch) {
         cplx<T> v[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
+            // clamped, unconditional loads: the whole batch is issued at once
             const int idx = base + u * nthr;
-            if (idx < nf * nh) v[u] = in[idx];
+            v[u] = in[idx < nf * nh ? idx : nf * nh - 1];
         }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) asm volatile("" ::"v"(v[u].re), "v"(v[u].im));
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * nthr;
             if (idx < nf * nh) buf2[idx] = v[u];
         }
     }
+    asm volatile("" ::"v"(twv.re), "v"(twv.im));
+    if (tid < nf / 2) tw[tid] = twv;
     __syncthreads();
     fft_lines<T, true>(buf2, logn, nh, 1, nh, tw, tid, nthr);
     for (int idx = tid; idx < npair * nf; idx += nthr) {
@@ -181,6 +189,13 @@ __global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
 }
 
 // ---------------------------------------------------------------- columns
+// floor(t / d) for 0 <= t < 2^22 - 1 and 1 <= d < 2^24 from inv_d = fl(1/d):
+// x = (t + 1/2) / d lies at least 1/(2d) from an integer, and the two FP32
+// roundings move it by at most x 2^-23 (1 + 2^-24) < 1/(2d).
+__device__ __forceinline__ int small_div(int t, float inv_d) {
+    return (int)(((float)t + 0.5f) * inv_d);
+}
+
 template <typename T>
 __device__ __forceinline__ T term2(const T *g, Term a, int sa, Term b, int sb) {
     // sa * a + sb * b with compile-time signs after unrolling
@@ -351,7 +366,7 @@ __device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
 // Block = rs row subsets x (w columns x nf frequencies) <= 256 threads; with
 // rs < kRowSplit each thread runs kRowSplit / rs of the subsets.  LDS:
 // moment spectra buf[P][w][nf], local spectra obuf[P][w][nf] and the
-// block's transfer-kernel tile gt[Q][w][nhp] (kz' in [0, nf/2], padded).
+// block's transfer-kernel tile gt[w][Q][nhp] (kz' in [0, nf/2], padded).
 template <int PO, typename T>
 __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs, int ncol,
                                                 int ngroups,
@@ -385,73 +400,98 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
     }
     const int col0 = grp * w;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int k = tid; k < nf / 2; k += nthr) tw[k] = tw_g[k];
-    // transfer-kernel tile: reduced column (ky', kx) of each block column is a
-    // contiguous, 16-byte aligned [Q][nhp] slab; loads go out in batches
+    // Global reads: the twiddles, the transfer-kernel tile (reduced column
+    // (ky', kx) of each block column is a contiguous, 16-byte aligned
+    // [Q][nhp] slab) and the moment spectra of z < nz (the rest of the padded
+    // column is zero).  Indices are clamped so that every load is
+    // unconditional; the first batch of each kind is issued before any LDS
+    // store, so small meshes take one round trip to HBM.
+    const int logw = __builtin_ctz(w);          // w and nf are powers of two
+    const int vec = 16 / (int)sizeof(T);
+    const int slab = Q * nhp;                   // one column's tile
+    const int per_col = slab / vec;
+    const float inv_per_col = 1.0f / (float)per_col, inv_nh = 1.0f / (float)nh;
+    const int gtotal = w * per_col;
+    const float4 *green4 = (const float4 *)green;
+    // tile element t: float4 r4 of block column ci; returns its index in the
+    // stored transfer kernel and sets its LDS offset (clamped duplicates
+    // rewrite the same value; columns past ncol fill slots never read)
+    auto g_at = [&](int t, int &loff) {
+        const int tc = t < gtotal ? t : gtotal - 1;
+        const int ci = small_div(tc, inv_per_col), r4 = tc - ci * per_col;
+        const int col = col0 + ci < ncol ? col0 + ci : ncol - 1;
+        const int ky = small_div(col, inv_nh), kx = col - ky * nh;
+        const int kyr = ky <= nf / 2 ? ky : nf - ky;
+        loff = ci * slab + r4 * vec;
+        return (kyr * nh + kx) * per_col + r4;
+    };
+    auto g_put = [&](int loff, float4 v) {
+        T *dst = gt + loff;
+        if (sizeof(T) == 4) {
+            const float *vf = (const float *)&v;
+            dst[0] = vf[0];
+            dst[1] = vf[1];
+            dst[2] = vf[2];
+            dst[3] = vf[3];
+        } else {
+            const double *vd = (const double *)&v;
+            dst[0] = vd[0];
+            dst[1] = vd[1];
+        }
+    };
+    // spectra: blockDim.x = rs * w * nf, so the elements of a thread share
+    // block column s_i and z; the component advances by s_db per element
+    const int s_i = tid & (w - 1);
+    const int s_z = (tid >> logw) & (nf - 1);
+    const int s_b0 = tid >> (logw + logn);
+    const int s_db = nthr >> (logw + logn);
+    const bool s_live = s_z < nz && col0 + s_i < ncol;
+    const int s_g = (s_z < nz ? s_z : nz - 1) * ncol + (col0 + s_i < ncol ? col0 + s_i : ncol - 1);
+    auto s_comp = [&](int u) { return s_b0 + u * s_db < P ? s_b0 + u * s_db : P - 1; };
+    auto s_load = [&](int u) { return spec[s_comp(u) * nz * ncol + s_g]; };
+    auto s_store = [&](int u, cplx<T> v) {
+        buf[(s_comp(u) * w + s_i) * ls + s_z] = cplx<T>{s_live ? v.re : T(0), s_live ? v.im : T(0)};
+    };
+    constexpr int GB = kLoadBatch, SB = 2 * kLoadBatch;
     {
-        const int vec = 16 / (int)sizeof(T);
-        const int per_col = Q * nhp / vec;
-        const int total = w * per_col;
-        for (int base = tid; base < total; base += nthr * kLoadBatch) {
-            float4 v[kLoadBatch];
+        const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];   // nf/2 <= blockDim.x
+        float4 gv[GB];
+        int gl[GB];
+        cplx<T> sv[SB];
 #pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u) {
-                const int t = base + u * nthr;
-                const int ci = t / per_col, r = (t - ci * per_col) * vec;
-                const int col = col0 + ci;
-                if (t < total && col < ncol) {
-                    const int ky = col / nh, kx = col - ky * nh;
-                    const int kyr = ky <= nf / 2 ? ky : nf - ky;
-                    v[u] = *(const float4 *)(green + ((int64_t)(kyr * nh + kx) * Q * nhp + r));
-                }
-            }
+        for (int u = 0; u < GB; ++u) gv[u] = green4[g_at(tid + u * nthr, gl[u])];
 #pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u) {
-                const int t = base + u * nthr;
-                const int ci = t / per_col, r = (t - ci * per_col) * vec;
-                if (t >= total || col0 + ci >= ncol) continue;
-                const int j = r / nhp, kz0 = r - j * nhp;
-                T *dst = gt + (j * w + ci) * nhp + kz0;
-                if (sizeof(T) == 4) {
-                    const float *vf = (const float *)&v[u];
-                    dst[0] = vf[0];
-                    dst[1] = vf[1];
-                    dst[2] = vf[2];
-                    dst[3] = vf[3];
-                } else {
-                    const double *vd = (const double *)&v[u];
-                    dst[0] = vd[0];
-                    dst[1] = vd[1];
-                }
-            }
-        }
+        for (int u = 0; u < SB; ++u) sv[u] = s_load(u);
+        asm volatile("" ::"v"(twv.re), "v"(twv.im));
+#pragma unroll
+        for (int u = 0; u < GB; ++u) asm volatile("" ::"v"(gv[u].x), "v"(gv[u].y), "v"(gv[u].z), "v"(gv[u].w));
+#pragma unroll
+        for (int u = 0; u < SB; ++u) asm volatile("" ::"v"(sv[u].re), "v"(sv[u].im));
+        if (tid < nf / 2) tw[tid] = twv;
+#pragma unroll
+        for (int u = 0; u < GB; ++u) g_put(gl[u], gv[u]);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) s_store(u, sv[u]);
     }
-    const int64_t zstride = (int64_t)ncol;
-    // spectra of z < nz; the rest of the padded column is zero
-    for (int base = tid; base < P * nf * w; base += nthr * kLoadBatch) {
-        cplx<T> v[kLoadBatch];
+    // remaining batches (large meshes)
+    for (int base = tid + GB * nthr; base < gtotal; base += GB * nthr) {
+        float4 gv[GB];
+        int gl[GB];
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * nthr;
-            const int i = idx % w;
-            const int rest = idx / w;
-            const int zz = rest & (nf - 1);
-            const int b = rest >> logn;
-            const int col = col0 + i;
-            v[u] = {T(0), T(0)};
-            if (idx < P * nf * w && zz < nz && col < ncol)
-                v[u] = spec[((int64_t)b * nz + zz) * zstride + col];
-        }
+        for (int u = 0; u < GB; ++u) gv[u] = green4[g_at(base + u * nthr, gl[u])];
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * nthr;
-            if (idx >= P * nf * w) continue;
-            const int i = idx % w;
-            const int rest = idx / w;
-            const int zz = rest & (nf - 1);
-            const int b = rest >> logn;
-            buf[(b * w + i) * ls + zz] = v[u];
-        }
+        for (int u = 0; u < GB; ++u) asm volatile("" ::"v"(gv[u].x), "v"(gv[u].y), "v"(gv[u].z), "v"(gv[u].w));
+#pragma unroll
+        for (int u = 0; u < GB; ++u) g_put(gl[u], gv[u]);
+    }
+    for (int u0 = SB; s_b0 + u0 * s_db < P; u0 += SB) {
+        cplx<T> sv[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) sv[u] = s_load(u0 + u);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) asm volatile("" ::"v"(sv[u].re), "v"(sv[u].im));
+#pragma unroll
+        for (int u = 0; u < SB; ++u) s_store(u0 + u, sv[u]);
     }
     __syncthreads();
     fft_lines<T, false>(buf, logn, P * w, ls, 1, tw, tid, nthr);
@@ -483,8 +523,8 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
         const int ky = col / nh;
         const int kzr = kz <= nf / 2 ? kz : nf - kz;
         const int flip = (ky > nf / 2 ? 1 : 0) | (kz > nf / 2 ? 2 : 0);
-        const T *gp = gt + i * nhp + kzr;
-        const int gstride = w * nhp;
+        const T *gp = gt + i * slab + kzr;
+        const int gstride = nhp;
         const cplx<T> *mp = buf + i * ls + pos;
         cplx<T> *op = obuf + i * ls + pos;
         for (int ss = sub; ss < RS; ss += rs) {
@@ -498,13 +538,26 @@ __global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs,
     }
     __syncthreads();
     fft_lines<T, true>(obuf, logn, P * w, ls, 1, tw, tid, nthr);
-    for (int idx = tid; idx < P * nz * w; idx += nthr) {
-        const int ii = idx % w;
-        const int rest = idx / w;
-        const int zz = rest % nz;
-        const int a = rest / nz;
-        const int cc = col0 + ii;
-        if (cc < ncol) spec[((int64_t)a * nz + zz) * zstride + cc] = obuf[(a * w + ii) * ls + zz];
+    // local spectra of z < nz back to HBM, LDS reads in batches; a thread's
+    // elements share block column o_i and z, the component advances by o_da
+    const int lognz = __builtin_ctz(nz);
+    const int o_i = tid & (w - 1);
+    const int o_z = (tid >> logw) & (nz - 1);
+    const int o_a0 = tid >> (logw + lognz);
+    const int o_da = nthr >> (logw + lognz);
+    const bool o_live = col0 + o_i < ncol;
+    for (int u0 = 0; o_a0 + u0 * o_da < P; u0 += kLoadBatch) {
+        cplx<T> v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int a = o_a0 + (u0 + u) * o_da < P ? o_a0 + (u0 + u) * o_da : P - 1;
+            v[u] = obuf[(a * w + o_i) * ls + o_z];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int a = o_a0 + (u0 + u) * o_da;
+            if (a < P && o_live) spec[(a * nz + o_z) * ncol + col0 + o_i] = v[u];
+        }
     }
 }
 
@@ -533,6 +586,7 @@ static hipError_t column_launch(const FFTArgs &a, hipStream_t s) {
         lds = column_lds_w(PO, nf, sizeof(T), w, &rs);
         if (lds == 0) return hipErrorInvalidValue;
     }
+    if ((w & (w - 1)) != 0) return hipErrorInvalidValue;   // the kernel splits indices by shifts
     const int threads = rs * w * nf;
     const int ngroups = (ncol + w - 1) / w;
     const int grid = ((ngroups + 7) / 8) * 8;
@@ -555,7 +609,9 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     if (stage == 0) {
         e = ensure_lds(k_plane_fwd<T>, lds_plane);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, P, nsys), dim3(256), lds_plane, s, n, logn,
+        // periodic: one extra row of blocks (c == P) sums q|u|^2 per plane
+        const int rows = a.open ? P : P + 1;
+        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, rows, nsys), dim3(256), lds_plane, s, n, logn,
                            (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
                            a.open ? nullptr : a.qr2_partial);
         return hipGetLastError();

@@ -432,6 +432,7 @@ struct BinArgs {
     int periodic;
     int *cell_of, *slot, *count, *start, *scell, *perm, *flag;
     int *dense_cells, *dense_count;
+    int *tile_sums;    // [nsys][ceil(K / 4096)] scratch of the multi-block scan
     int dense_threshold;
     void *sorted;      // particle4<T>[n]
     // batch of nsys systems on this mesh (prange null: one system of n)
@@ -441,6 +442,8 @@ struct BinArgs {
 };
 template <typename T>
 hipError_t launch_bin(const BinArgs &a, hipStream_t s);
+// Tiles of the multi-block scan of the cell counts.
+inline int scan_tiles(int64_t K) { return (int)((K + 4095) / 4096); }
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path

@@ -55,10 +55,18 @@ __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ star
         T acc[P + 1];
 #pragma unroll
         for (int c = 0; c <= P; ++c) acc[c] = T(0);
-        for (int s = s0 + lane; s < s1; s += G) {
-            const particle4<T> r = sorted[s];
-            accumulate_regular<PO, T>(-r.ux, -r.uy, -r.uz, r.q, acc);  // q R(r_M - r_i)
-            acc[P] += r.q * (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
+        // two particles per lane and round, both loads in flight together; a
+        // clamped second particle past the cell's end enters with charge 0
+        // (same summation order as one particle per round)
+        for (int s = s0 + lane; s < s1; s += 2 * G) {
+            const bool two = s + G < s1;
+            const particle4<T> r0 = sorted[s];
+            const particle4<T> r1 = sorted[two ? s + G : s];
+            const T q1 = two ? r1.q : T(0);
+            accumulate_regular<PO, T>(-r0.ux, -r0.uy, -r0.uz, r0.q, acc);  // q R(r_M - r_i)
+            acc[P] += r0.q * (r0.ux * r0.ux + r0.uy * r0.uy + r0.uz * r0.uz);
+            accumulate_regular<PO, T>(-r1.ux, -r1.uy, -r1.uz, q1, acc);
+            acc[P] += q1 * (r1.ux * r1.ux + r1.uy * r1.uy + r1.uz * r1.uz);
         }
 #pragma unroll
         for (int off = G / 2; off >= 1; off >>= 1) {
