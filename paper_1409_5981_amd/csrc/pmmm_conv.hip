@@ -368,7 +368,7 @@ __device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
 // moment spectra buf[P][w][nf], local spectra obuf[P][w][nf] and the
 // block's transfer-kernel tile gt[w][Q][nhp] (kz' in [0, nf/2], padded).
 template <int PO, typename T>
-__global__ void __launch_bounds__(256) k_column(int nz, int logn, int w, int rs, int ncol,
+__global__ void __launch_bounds__(256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_column(int nz, int logn, int w, int rs, int ncol,
                                                 int ngroups,
                                                 const T *__restrict__ green,
                                                 cplx<T> *__restrict__ spec,

@@ -335,9 +335,11 @@ __device__ void fft_lines(cplx<T> *buf, int logn, int nlines, int lstride, int e
     }
 }
 
-// Line stride in LDS for lines of n complex values: one thread per line for
-// n <= 16, so pad by one element to spread the lines over the LDS banks.
-__host__ __device__ constexpr int lds_line(int n) { return n <= 16 ? n + 1 : n; }
+// Line stride in LDS for lines of n complex values, padded by one element:
+// the lanes of a wave work on different lines at the same offsets (one line
+// per lane for n <= 16, n / 16 lanes per line above), and an odd stride puts
+// those lines in different LDS banks.
+__host__ __device__ constexpr int lds_line(int n) { return n + 1; }
 
 // ------------------------------------------------- transfer-kernel terms
 // Value of Re S_n^k and Im S_n^k (any k) as sign * g[n + idx] where g holds
