@@ -216,7 +216,7 @@ __device__ __forceinline__ void mac(cplx<T> &acc, T c, cplx<T> m) {
 
 // Output orders are dealt to kRowSplit subsets at compile time, largest
 // first, each to the subset with the fewest rows so far (2l+1 rows per order).
-constexpr int kRowSplit = 4;
+constexpr int kRowSplit = kColumnRowSplit;
 
 __host__ __device__ constexpr int order_subset(int PO, int RS, int l) {
     int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -333,12 +333,29 @@ struct DCCorr {
     double l00, l10, l11re, l11im;
 };
 
-// Rows of subset S: M~ read from `mcol`, L~ = i^(l mod 2) acc (plus the
-// zero-frequency corrections) written to `ocol`.
+// Rows of subset S in increasing row index, and their count.
+__host__ __device__ constexpr int subset_rank(int PO, int RS, int S, int a) {
+    int r = 0;
+    for (int l = 0; l <= PO; ++l)
+        for (int m = -l; m <= l; ++m)
+            if (order_subset(PO, RS, l) == S && ridx(l, m) < a) ++r;
+    return r;
+}
+__host__ __device__ constexpr int subset_rows_max(int PO, int RS) {
+    int mx = 0;
+    for (int S = 0; S < RS; ++S) {
+        const int r = subset_rank(PO, RS, S, ridx(PO, PO) + 1);
+        mx = r > mx ? r : mx;
+    }
+    return mx;
+}
+
+// Rows of subset S: M~ read from `mcol`; res[rank] = L~ = i^(l mod 2) acc
+// plus the zero-frequency corrections.
 template <int PO, int RS, int S, typename T>
-__device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
-                                           const cplx<T> *mcol, cplx<T> *ocol, int stride,
-                                           DCCorr dc) {
+__device__ __forceinline__ void m2l_rows(const T *gcol, int gstride, int flip,
+                                         const cplx<T> *mcol, int stride, DCCorr dc,
+                                         cplx<T> *res) {
     constexpr int P = nreal(PO);
     cplx<T> acc[P];
     static_for<0, P>([&](auto ia) { acc[decltype(ia)::value] = {T(0), T(0)}; });
@@ -357,7 +374,21 @@ __device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
                     if constexpr (PO >= 1 && a == ridx(1, 1)) o.re += T(dc.l11re);
                     if constexpr (PO >= 1 && a == ridx(1, -1)) o.re += T(dc.l11im);
                 }
-                ocol[a * stride] = o;
+                res[subset_rank(PO, RS, S, a)] = o;
+            });
+        }
+    });
+}
+
+// res of subset S to its rows of `ocol`.
+template <int PO, int RS, int S, typename T>
+__device__ __forceinline__ void m2l_put(const cplx<T> *res, cplx<T> *ocol, int stride) {
+    static_for<0, PO + 1>([&](auto il) {
+        constexpr int l = decltype(il)::value;
+        if constexpr (order_subset(PO, RS, l) == S) {
+            static_for<-l, l + 1>([&](auto im) {
+                constexpr int a = ridx(l, decltype(im)::value);
+                ocol[a * stride] = res[subset_rank(PO, RS, S, a)];
             });
         }
     });
@@ -365,8 +396,10 @@ __device__ __forceinline__ void m2l_subset(const T *gcol, int gstride, int flip,
 
 // Block = rs row subsets x (w columns x nf frequencies) <= 256 threads; with
 // rs < kRowSplit each thread runs kRowSplit / rs of the subsets.  LDS:
-// moment spectra buf[P][w][nf], local spectra obuf[P][w][nf] and the
-// block's transfer-kernel tile gt[w][Q][nhp] (kz' in [0, nf/2], padded).
+// moment spectra buf[P][w][nf], local spectra obuf[P][w][nf] (buf itself
+// when rs = kRowSplit: the results wait in registers for a barrier after
+// the last read of buf) and the block's transfer-kernel tile gt[w][Q][nhp]
+// (kz' in [0, nf/2], padded).
 template <int PO, typename T>
 __global__ void __launch_bounds__(256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_column(int nz, int logn, int w, int rs, int ncol,
                                                 int ngroups,
@@ -382,9 +415,10 @@ __global__ void __launch_bounds__(256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_co
     const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ls = lds_line(nf);
     const int nfreq = w * nf;
     const int cstride = w * ls;                 // component stride in buf / obuf
+    const bool inplace = rs == RS;              // one row subset per thread
     cplx<T> *tw = (cplx<T> *)lds_raw;
     cplx<T> *buf = tw + nf / 2;
-    cplx<T> *obuf = buf + P * cstride;
+    cplx<T> *obuf = inplace ? buf : buf + P * cstride;
     T *gt = (T *)(obuf + P * cstride);
     // XCD-aware order: consecutive column groups stay on one XCD (blocks are
     // dealt round-robin over the 8 XCDs).
@@ -519,7 +553,8 @@ __global__ void __launch_bounds__(256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_co
         dcc.on = true;
         if (sub == 0) sums[0] = (double)m0[0].re;  // total charge
     }
-    if (col < ncol) {
+    {
+        const bool live = col < ncol;
         const int ky = col / nh;
         const int kzr = kz <= nf / 2 ? kz : nf - kz;
         const int flip = (ky > nf / 2 ? 1 : 0) | (kz > nf / 2 ? 2 : 0);
@@ -527,12 +562,25 @@ __global__ void __launch_bounds__(256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_co
         const int gstride = nhp;
         const cplx<T> *mp = buf + i * ls + pos;
         cplx<T> *op = obuf + i * ls + pos;
+        // rs divides RS: every thread runs RS / rs passes (one when in place)
         for (int ss = sub; ss < RS; ss += rs) {
-            switch (ss) {
-                case 0: m2l_subset<PO, RS, 0, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
-                case 1: m2l_subset<PO, RS, 1, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
-                case 2: m2l_subset<PO, RS, 2, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
-                default: m2l_subset<PO, RS, 3, T>(gp, gstride, flip, mp, op, cstride, dcc); break;
+            cplx<T> res[subset_rows_max(PO, RS)];
+            if (live) {
+                switch (ss) {
+                    case 0: m2l_rows<PO, RS, 0, T>(gp, gstride, flip, mp, cstride, dcc, res); break;
+                    case 1: m2l_rows<PO, RS, 1, T>(gp, gstride, flip, mp, cstride, dcc, res); break;
+                    case 2: m2l_rows<PO, RS, 2, T>(gp, gstride, flip, mp, cstride, dcc, res); break;
+                    default: m2l_rows<PO, RS, 3, T>(gp, gstride, flip, mp, cstride, dcc, res); break;
+                }
+            }
+            if (inplace) __syncthreads();       // every read of buf is done
+            if (live) {
+                switch (ss) {
+                    case 0: m2l_put<PO, RS, 0, T>(res, op, cstride); break;
+                    case 1: m2l_put<PO, RS, 1, T>(res, op, cstride); break;
+                    case 2: m2l_put<PO, RS, 2, T>(res, op, cstride); break;
+                    default: m2l_put<PO, RS, 3, T>(res, op, cstride); break;
+                }
             }
         }
     }

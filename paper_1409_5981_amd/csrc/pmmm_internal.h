@@ -377,38 +377,39 @@ __device__ __forceinline__ void sys_range(const int64_t *prange, int64_t n, int6
 // ------------------------------------------------------------ host side
 struct Plan;  // defined in pmmm_api.hip
 
-// Shape of the column kernel: w columns of nf frequencies per block and rs
-// row subsets (rs * w * nf <= 256 threads); LDS holds moment and local
-// spectra [P][w][nf] and the kernel tile [Q][w][nhp].  Returns the LDS
-// bytes, or 0 if no shape fits the 160 KB of one CU.
-// LDS bytes of the column kernel for w columns per block (0 if over 160 KB),
-// and its row subsets rs.
+// Row subsets of the column kernel's M2L (threads per frequency at most).
+constexpr int kColumnRowSplit = 4;
+
+// LDS bytes of the column kernel for w columns of nf frequencies per block
+// (0 if over 160 KB), and its row subsets rs (rs * w * nf <= 256 threads).
+// LDS holds the moment spectra [P][w][nf] (the local spectra overwrite them
+// when every thread runs one row subset, else they get a buffer of their
+// own), the kernel tile [w][Q][nhp] and the twiddles.
 inline size_t column_lds_w(int p, int nf, size_t tsize, int w, int *rs_out) {
+    if (w < 1 || (size_t)w * nf > 256) return 0;
     const size_t P = (size_t)(p + 1) * (p + 1), Q = (size_t)(2 * p + 1) * (2 * p + 1);
     const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
-    const size_t lds = 2 * P * w * (size_t)lds_line(nf) * 2 * tsize + Q * w * nhp * tsize +
+    const int rs = 256 / (w * nf) < kColumnRowSplit ? 256 / (w * nf) : kColumnRowSplit;
+    const size_t nbuf = rs == kColumnRowSplit ? 1 : 2;
+    const size_t lds = nbuf * P * w * (size_t)lds_line(nf) * 2 * tsize + Q * w * nhp * tsize +
                        (size_t)nf / 2 * 2 * tsize;
-    if (w < 1 || (size_t)w * nf > 256 || lds > 160 * 1024) return 0;
-    if (rs_out) *rs_out = 256 / (w * nf) < 4 ? 256 / (w * nf) : 4;
+    if (lds > 160 * 1024) return 0;
+    if (rs_out) *rs_out = rs;
     return lds;
 }
 
+// Widest shape that fits (w from 64 / nf down to 1).
 inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out) {
-    const size_t P = (size_t)(p + 1) * (p + 1), Q = (size_t)(2 * p + 1) * (2 * p + 1);
-    const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
-    int w = nf >= 64 ? 1 : 64 / nf;
-    for (;;) {
-        const size_t lds = 2 * P * w * (size_t)lds_line(nf) * 2 * tsize + Q * w * nhp * tsize +
-                           (size_t)nf / 2 * 2 * tsize;
-        if (lds <= 160 * 1024) {
-            const int rs = 256 / (w * nf) < 4 ? 256 / (w * nf) : 4;
+    for (int w = nf >= 64 ? 1 : 64 / nf; w >= 1; w >>= 1) {
+        int rs = 1;
+        const size_t lds = column_lds_w(p, nf, tsize, w, &rs);
+        if (lds > 0) {
             if (w_out) *w_out = w;
             if (rs_out) *rs_out = rs;
             return lds;
         }
-        if (w == 1) return 0;
-        w >>= 1;
     }
+    return 0;
 }
 
 // Raise a kernel's dynamic-LDS limit once (later calls with no larger size
