@@ -394,14 +394,14 @@ __device__ __forceinline__ void m2l_put(const cplx<T> *res, cplx<T> *ocol, int s
     });
 }
 
-// Block = rs row subsets x (w columns x nf frequencies) <= 256 threads; with
-// rs < kRowSplit each thread runs kRowSplit / rs of the subsets.  LDS:
-// moment spectra buf[P][w][nf], local spectra obuf[P][w][nf] (buf itself
-// when rs = kRowSplit: the results wait in registers for a barrier after
-// the last read of buf) and the block's transfer-kernel tile gt[w][Q][nhp]
-// (kz' in [0, nf/2], padded).
+// Block = rs row subsets x (w columns x nf frequencies) threads (at most
+// column_max_threads); with rs < kRowSplit each thread runs kRowSplit / rs
+// of the subsets.  LDS: moment spectra buf[P][w][nf], local spectra
+// obuf[P][w][nf] (buf itself when rs = kRowSplit: the results wait in
+// registers for a barrier after the last read of buf) and the block's
+// transfer-kernel tile gt[w][Q][nhp] (kz' in [0, nf/2], padded).
 template <int PO, typename T>
-__global__ void __launch_bounds__(256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_column(int nz, int logn, int w, int rs, int ncol,
+__global__ void __launch_bounds__(PO <= 6 ? 512 : 256, (PO == 7 && sizeof(T) == 4) ? 2 : 1) k_column(int nz, int logn, int w, int rs, int ncol,
                                                 int ngroups,
                                                 const T *__restrict__ green,
                                                 cplx<T> *__restrict__ spec,

@@ -380,8 +380,12 @@ struct Plan;  // defined in pmmm_api.hip
 // Row subsets of the column kernel's M2L (threads per frequency at most).
 constexpr int kColumnRowSplit = 4;
 
+// Threads per block of the column kernel: 512 up to order 6 (the 128-point
+// columns then still run one row subset per thread), else 256.
+inline int column_max_threads(int p) { return p <= 6 ? 512 : 256; }
+
 // LDS bytes of the column kernel for w columns of nf frequencies per block
-// (0 if over 160 KB), and its row subsets rs (rs * w * nf <= 256 threads).
+// (0 if over 160 KB), and its row subsets rs (rs * w * nf threads).
 // LDS holds the moment spectra [P][w][nf] (the local spectra overwrite them
 // when every thread runs one row subset, else they get a buffer of their
 // own), the kernel tile [w][Q][nhp] and the twiddles.
@@ -389,7 +393,8 @@ inline size_t column_lds_w(int p, int nf, size_t tsize, int w, int *rs_out) {
     if (w < 1 || (size_t)w * nf > 256) return 0;
     const size_t P = (size_t)(p + 1) * (p + 1), Q = (size_t)(2 * p + 1) * (2 * p + 1);
     const size_t nhp = ((size_t)nf / 2 + 1 + 3) & ~(size_t)3;
-    const int rs = 256 / (w * nf) < kColumnRowSplit ? 256 / (w * nf) : kColumnRowSplit;
+    const int fit = column_max_threads(p) / (w * nf);
+    const int rs = fit < kColumnRowSplit ? fit : kColumnRowSplit;
     const size_t nbuf = rs == kColumnRowSplit ? 1 : 2;
     const size_t lds = nbuf * P * w * (size_t)lds_line(nf) * 2 * tsize + Q * w * nhp * tsize +
                        (size_t)nf / 2 * 2 * tsize;
