@@ -186,14 +186,17 @@ int pmmm_near_f64(pmmm_plan plan, int64_t n, double *phi, double *gx, double *gy
                   int accumulate, void *stream);
 
 /* Launch-shape autotuner.  Runs the far field (pmmm_far_f32 or _f64 by the
- * plan's precision, same arguments and meaning) on the caller's particles for
- * each candidate shape -- columns per block of the FFT-z/M2L kernel (the
- * widest that fits LDS, half and a quarter of it) times lanes per cell in
- * P2M (4, 8, 16, 32) -- timing five calls of each with HIP events, and keeps
- * the fastest for later calls on this plan.  Synchronises the stream; the
- * outputs hold the result of the last trial.  Shapes change only the order
- * of floating-point sums.  pmmm_plan_get_tuning reports the kept shape (0:
- * the untuned default). */
+ * plan's precision, same arguments and meaning) on the caller's particles,
+ * timing with HIP events the P2M stage for each number of lanes per cell
+ * (4, 8, 16, 32), then the column stage (FFT along z, M2L) for each number of
+ * columns per block (the widest that fits LDS, half and a quarter of it);
+ * every candidate runs in three interleaved rounds of five calls and its
+ * shortest stage time counts.  The fastest of each is kept for later calls on
+ * this plan.  Synchronises the stream; the outputs hold the result of the
+ * last trial; stage profiling enabled by the caller is suspended meanwhile
+ * (its accumulated times are kept).  Shapes change only the order of
+ * floating-point sums.  pmmm_plan_get_tuning reports the kept shape (0: the
+ * untuned default). */
 int pmmm_plan_autotune(pmmm_plan plan, int64_t n, const void *x, const void *y, const void *z,
                        const void *q, void *phi, void *gx, void *gy, void *gz, void *stream);
 int pmmm_plan_get_tuning(pmmm_plan plan, int *column_width, int *p2m_lanes);

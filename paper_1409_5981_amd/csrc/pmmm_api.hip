@@ -592,9 +592,35 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
     return PMMM_OK;
 }
 
-// Autotuner: times the far-field call on the caller's particles for each
-// candidate launch shape (column-kernel width w from the widest that fits
-// down to a quarter of it; P2M lanes per cell 4..32) and keeps the fastest.
+// Shortest event time (ms) of one stage over `reps` far-field calls with the
+// plan's current launch shapes (after one untimed call).
+template <typename T>
+static int time_stage(pmmm_plan_s *pl, int stage, int reps, int64_t n, const T *x, const T *y,
+                      const T *z, const T *q, T *phi, T *gx, T *gy, T *gz, hipStream_t s,
+                      float *best_ms) {
+    int rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
+    pl->prof_mask = 1u << stage;
+    for (int it = 0; it < reps && rc == PMMM_OK; ++it)
+        rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
+    pl->prof_mask = 0;
+    float mn = 1e30f;
+    for (auto &pr : pl->ev_pending[stage]) {
+        float t = 1e30f;
+        if (hipEventSynchronize(pr.second) == hipSuccess &&
+            hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess)
+            mn = t < mn ? t : mn;
+        pl->ev_pool.push_back(pr.first);
+        pl->ev_pool.push_back(pr.second);
+    }
+    pl->ev_pending[stage].clear();
+    *best_ms = mn;
+    return rc;
+}
+
+// Autotuner: on the caller's particles, times the P2M stage for each number
+// of lanes per cell (4..32) and then the column stage for each column-kernel
+// width w (the widest that fits down to a quarter of it), each candidate in
+// three interleaved rounds, and keeps the fastest of each.
 template <typename T>
 static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T *z,
                          const T *q, T *phi, T *gx, T *gy, T *gz, hipStream_t s) {
@@ -604,42 +630,40 @@ static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, con
     if (wmax >= 2) ws.push_back(wmax / 2);
     if (wmax >= 4) ws.push_back(wmax / 4);
     const int gs[4] = {4, 8, 16, 32};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    PMMM_HIP(hipEventCreate(&e0));
-    PMMM_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    int bw = 0, bg = 0, rc = PMMM_OK;
-    for (int w : ws) {
-        for (int g : gs) {
-            pl->tune_col_w = w;
-            pl->tune_group = g;
-            for (int it = 0; it < 2 && rc == PMMM_OK; ++it)
-                rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
-            if (rc != PMMM_OK) break;
-            hipEventRecord(e0, s);
-            constexpr int kReps = 5;
-            for (int it = 0; it < kReps && rc == PMMM_OK; ++it)
-                rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
-            hipEventRecord(e1, s);
-            if (rc != PMMM_OK) break;
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                rc = PMMM_EHIP;
-                break;
-            }
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) {
-                best = ms;
-                bw = w;
-                bg = g;
-            }
+    constexpr int kRounds = 3, kReps = 5;
+    // the caller's own stage profiling (if any) is set aside meanwhile
+    int rc = pmmm_plan_read_profile(pl, nullptr, nullptr, 0);
+    if (rc != PMMM_OK) return rc;
+    const unsigned mask = pl->prof_mask;
+    float tg[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+    std::vector<float> tw(ws.size(), 1e30f);
+    pl->tune_col_w = wmax;
+    for (int r = 0; r < kRounds && rc == PMMM_OK; ++r) {
+        for (int k = 0; k < 4 && rc == PMMM_OK; ++k) {
+            pl->tune_group = gs[k];
+            float t = 0.f;
+            rc = time_stage<T>(pl, PMMM_STAGE_P2M, kReps, n, x, y, z, q, phi, gx, gy, gz, s, &t);
+            tg[k] = t < tg[k] ? t : tg[k];
         }
-        if (rc != PMMM_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    pl->tune_col_w = rc == PMMM_OK ? bw : 0;
-    pl->tune_group = rc == PMMM_OK ? bg : 0;
+    int bg = 0;
+    for (int k = 1; k < 4; ++k)
+        if (tg[k] < tg[bg]) bg = k;
+    pl->tune_group = gs[bg];
+    for (int r = 0; r < kRounds && rc == PMMM_OK; ++r) {
+        for (size_t k = 0; k < ws.size() && rc == PMMM_OK; ++k) {
+            pl->tune_col_w = ws[k];
+            float t = 0.f;
+            rc = time_stage<T>(pl, PMMM_STAGE_COLUMN, kReps, n, x, y, z, q, phi, gx, gy, gz, s, &t);
+            tw[k] = t < tw[k] ? t : tw[k];
+        }
+    }
+    size_t bw = 0;
+    for (size_t k = 1; k < ws.size(); ++k)
+        if (tw[k] < tw[bw]) bw = k;
+    pl->prof_mask = mask;
+    pl->tune_col_w = rc == PMMM_OK ? ws[bw] : 0;
+    pl->tune_group = rc == PMMM_OK ? gs[bg] : 0;
     return rc;
 }
 
