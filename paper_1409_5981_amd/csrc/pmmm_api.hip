@@ -47,7 +47,7 @@ struct Plan {
     // plan-lifetime buffers
     void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
     int *count = nullptr, *start = nullptr, *dense_cells = nullptr, *small = nullptr;
-    int *tile_sums = nullptr;
+    int *tile_sums = nullptr, *sstart = nullptr;
     double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
     int64_t cap = 0, last_n = -1;
@@ -258,6 +258,7 @@ static void destroy(Plan *pl) {
     hipFree(pl->start);
     hipFree(pl->dense_cells);
     hipFree(pl->tile_sums);
+    hipFree(pl->sstart);
     hipFree(pl->small);
     hipFree(pl->sums);
     hipFree(pl->qr2_partial);
@@ -292,14 +293,16 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->M, (size_t)(pl->P + 1) * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
     PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
-    PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * pl->K));
+    const int64_t KS = pl->K * count_shards(pl->K);   // binning sub-counters
+    PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * KS));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
     PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
-    PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * scan_tiles(pl->K)));
+    PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * scan_tiles(KS)));
+    if (KS > pl->K) PMMM_HIP(hipMalloc(&pl->sstart, sizeof(int) * (KS + 1)));
     PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] scan counter
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
     PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
-    PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * pl->K, s));
+    PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * KS, s));
     PMMM_HIP(hipMemsetAsync(pl->small, 0, sizeof(int) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->sums, 0, sizeof(double) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->M, 0, (size_t)(pl->P + 1) * pl->K * t, s));
@@ -367,6 +370,7 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
         b.tile_sums = pl->tile_sums;
+        b.sstart = pl->sstart;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         PMMM_HIP(launch_bin<T>(b, s));
@@ -551,6 +555,7 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
         b.tile_sums = pl->tile_sums;
+        b.sstart = pl->sstart;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         PMMM_HIP(launch_bin<float>(b, s));
@@ -676,7 +681,7 @@ struct BatchClass {
     pmmm_plan_s *plan = nullptr;    // transfer kernel, twiddles, constants
     std::vector<int> members;       // system indices in the caller's order
     int *count = nullptr, *start = nullptr, *dense = nullptr, *small = nullptr;
-    int *tile_sums = nullptr;
+    int *tile_sums = nullptr, *sstart = nullptr;
     void *M = nullptr, *spec = nullptr, *L = nullptr;
     double *qr2 = nullptr, *sums = nullptr;
     int64_t *d_prange = nullptr;    // [2 members]
@@ -726,6 +731,7 @@ static void batch_destroy(pmmm_batch_s *b) {
         hipFree(c.start);
         hipFree(c.dense);
         hipFree(c.tile_sums);
+        hipFree(c.sstart);
         hipFree(c.small);
         hipFree(c.M);
         hipFree(c.spec);
@@ -748,10 +754,12 @@ static void batch_destroy(pmmm_batch_s *b) {
 static int batch_alloc_class(BatchClass &c, hipStream_t s) {
     const Plan *pl = c.plan;
     const size_t ns = c.members.size(), K = pl->K, P = pl->P, t = pl->tsize;
-    PMMM_HIP(hipMalloc(&c.count, sizeof(int) * K * ns));
+    const size_t KS = K * (size_t)count_shards((int64_t)K);   // binning sub-counters
+    PMMM_HIP(hipMalloc(&c.count, sizeof(int) * KS * ns));
     PMMM_HIP(hipMalloc(&c.start, sizeof(int) * (K + 1) * ns));
     PMMM_HIP(hipMalloc(&c.dense, sizeof(int) * K * ns));
-    PMMM_HIP(hipMalloc(&c.tile_sums, sizeof(int) * scan_tiles(K) * ns));
+    PMMM_HIP(hipMalloc(&c.tile_sums, sizeof(int) * scan_tiles((int64_t)KS) * ns));
+    if (KS > K) PMMM_HIP(hipMalloc(&c.sstart, sizeof(int) * (KS + 1) * ns));
     PMMM_HIP(hipMalloc(&c.small, sizeof(int) * 8 * ns));
     PMMM_HIP(hipMalloc(&c.M, t * (P + 1) * K * ns));
     PMMM_HIP(hipMalloc(&c.spec, 2 * t * P * pl->n * pl->ncol * ns));
@@ -759,7 +767,7 @@ static int batch_alloc_class(BatchClass &c, hipStream_t s) {
     PMMM_HIP(hipMalloc(&c.qr2, sizeof(double) * pl->n * ns));
     PMMM_HIP(hipMalloc(&c.sums, sizeof(double) * 8 * ns));
     PMMM_HIP(hipMalloc(&c.d_prange, sizeof(int64_t) * 2 * ns));
-    PMMM_HIP(hipMemsetAsync(c.count, 0, sizeof(int) * K * ns, s));
+    PMMM_HIP(hipMemsetAsync(c.count, 0, sizeof(int) * KS * ns, s));
     PMMM_HIP(hipMemsetAsync(c.small, 0, sizeof(int) * 8 * ns, s));
     PMMM_HIP(hipMemsetAsync(c.M, 0, t * (P + 1) * K * ns, s));
     return PMMM_OK;
@@ -814,6 +822,7 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         bn.dense_cells = c.dense;
         bn.dense_count = c.small;
         bn.tile_sums = c.tile_sums;
+        bn.sstart = c.sstart;
         bn.dense_threshold = kDenseThreshold;
         bn.sorted = b->sorted;
         bn.prange = c.d_prange;

@@ -1,7 +1,10 @@
 // Cell binning (Sec. 2.1: "for each cell, the set of particles inside is
 // known ... achieved in an O(N) procedure"): a counting sort by cell.
 //   k_bin_count   cell of each particle, per-cell counts (int atomics) and the
-//                 particle's slot inside its cell
+//                 particle's slot inside its cell; meshes above 16^3 count
+//                 in S sub-counters per cell (particle i in sub-counter
+//                 i mod S), so that a cell holding a large share of the
+//                 particles does not serialise all of them on one address
 //   k_bin_tile_sums, k_bin_scan_tiles
 //                 exclusive scan of the counts -> cell_start in tiles of 4096
 //                 cells, resets the counts for the next call, lists cells above
@@ -43,14 +46,14 @@ __global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ p
                                                    const T *__restrict__ z, T inv_h, int nc,
                                                    int periodic, int *__restrict__ cell_of,
                                                    int *__restrict__ slot,
-                                                   int *__restrict__ count,
+                                                   int *__restrict__ count, int logS,
                                                    int *__restrict__ flag) {
     int64_t p0, np;
     sys_range(prange, n, p0, np);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= np) return;
     const int64_t i = p0 + j;
-    count += (int64_t)blockIdx.y * nc * nc * nc;
+    count += ((int64_t)blockIdx.y * nc * nc * nc) << logS;
     // the three loads are issued together, ahead of the branches below
     const T xv = x[i], yv = y[i], zv = z[i];
     asm volatile("" ::"v"(xv), "v"(yv), "v"(zv));
@@ -62,7 +65,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ p
     if (out) *flag = 1;
     const int c = (iz * nc + iy) * nc + ix;
     cell_of[i] = c;
-    slot[i] = atomicAdd(&count[c], 1);
+    slot[i] = atomicAdd(&count[(c << logS) + (int)(j & ((1 << logS) - 1))], 1);
 }
 
 // Exclusive scan of the counts in tiles of kScanTile, one 1024-thread block
@@ -72,22 +75,22 @@ __global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ p
 // particular order: each dense cell is reduced by one block in a fixed order).
 constexpr int kScanTile = 4096;
 
-__global__ void __launch_bounds__(1024) k_bin_tile_sums(int K, const int *__restrict__ count,
+__global__ void __launch_bounds__(1024) k_bin_tile_sums(int L, const int *__restrict__ count,
                                                         int *__restrict__ tile_sums,
                                                         int *__restrict__ dense_count) {
     const int ntiles = gridDim.x;
     {
         const int64_t sy = blockIdx.y;
-        count += sy * K;
+        count += sy * L;
         tile_sums += sy * ntiles;
         dense_count += sy * 8;
     }
     __shared__ int wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    // K = n^3 with n >= 4 is a multiple of 64: four counts per thread, 16-byte aligned
+    // L = S n^3 with n >= 4 is a multiple of 64: four counts per thread, 16-byte aligned
     const int idx = blockIdx.x * kScanTile + tid * 4;
     int v = 0;
-    if (idx < K) {
+    if (idx < L) {
         const int4 c4 = *(const int4 *)(count + idx);
         v = (c4.x + c4.y) + (c4.z + c4.w);
     }
@@ -103,17 +106,23 @@ __global__ void __launch_bounds__(1024) k_bin_tile_sums(int K, const int *__rest
     }
 }
 
-__global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int *__restrict__ count,
+// L = S K counters (S = 1 or kCountShards); with S > 1 sstart receives the start
+// of every sub-counter and start that of every cell (its first sub-counter),
+// and a cell's two halves sit in the two lanes of an even-odd pair.
+__global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *__restrict__ count,
                                                          const int *__restrict__ tile_sums,
-                                                         int *__restrict__ start, int dense_thr,
+                                                         int *__restrict__ start,
+                                                         int *__restrict__ sstart, int dense_thr,
                                                          int *__restrict__ dense_cells,
                                                          int *__restrict__ dense_count) {
     const int ntiles = gridDim.x, t = blockIdx.x;
+    const int L = K << logS;
     {
         const int64_t sy = blockIdx.y;
-        count += sy * K;
+        count += sy * L;
         tile_sums += sy * ntiles;
         start += sy * (K + 1);
+        sstart += sy * (L + 1);
         dense_cells += sy * K;
         dense_count += sy * 8;
     }
@@ -122,7 +131,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int *__restrict_
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int idx = t * kScanTile + tid * 4;
     int v[4] = {0, 0, 0, 0};
-    if (idx < K) {
+    if (idx < L) {
         const int4 c4 = *(const int4 *)(count + idx);
         v[0] = c4.x;
         v[1] = c4.y;
@@ -154,16 +163,35 @@ __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int *__restrict_
     __syncthreads();
     int run = pre_s + inc - tot;
     for (int w = 0; w < wid; ++w) run += wtot[w];
+    if (logS == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (idx + j < K) {
-            start[idx + j] = run;
-            if (v[j] > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = idx + j;
+        for (int j = 0; j < 4; ++j) {
+            if (idx + j < L) {
+                start[idx + j] = run;
+                if (v[j] > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = idx + j;
+            }
+            run += v[j];
         }
-        run += v[j];
+    } else {
+        // kCountShards = 8 sub-counters per cell: lanes 2m and 2m + 1 hold one cell
+        static_assert(kCountShards == 8, "a cell's sub-counters span one lane pair");
+        const int cell_tot = tot + __shfl_xor(tot, 1, 64);
+        if (idx < L && (tid & 1) == 0) {
+            const int cell = idx >> logS;
+            start[cell] = run;
+            if (cell_tot > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = cell;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (idx + j < L) sstart[idx + j] = run;
+            run += v[j];
+        }
     }
-    if (idx < K) *(int4 *)(count + idx) = make_int4(0, 0, 0, 0);
-    if (t == ntiles - 1 && tid == 1023) start[K] = run;
+    if (idx < L) *(int4 *)(count + idx) = make_int4(0, 0, 0, 0);
+    if (t == ntiles - 1 && tid == 1023) {
+        start[K] = run;
+        sstart[L] = run;
+    }
 }
 
 // Exclusive scan of K <= kInBlockScanMax counts by one 256-thread block into
@@ -225,15 +253,17 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     const int64_t *__restrict__ prange, int64_t n, const T *__restrict__ x,
     const T *__restrict__ y, const T *__restrict__ z, const T *__restrict__ q, T inv_h, int nc,
     int periodic, const int *__restrict__ cell_of, const int *__restrict__ slot,
-    int *__restrict__ start, int *__restrict__ perm, int *__restrict__ scell,
-    particle4<T> *__restrict__ sorted, int inblock, const int *__restrict__ count,
-    int dense_thr, int *__restrict__ dense_cells, int *__restrict__ dense_count) {
+    int *__restrict__ start, const int *__restrict__ sstart, int logS, int *__restrict__ perm,
+    int *__restrict__ scell, particle4<T> *__restrict__ sorted, int inblock,
+    const int *__restrict__ count, int dense_thr, int *__restrict__ dense_cells,
+    int *__restrict__ dense_count) {
     __shared__ int s_start[kInBlockScanMax + 1];
     const int K = nc * nc * nc;
     {
         const int64_t sy = blockIdx.y;
         count += sy * K;
         start += sy * (K + 1);
+        sstart += sy * (((int64_t)K << logS) + 1);
         dense_cells += sy * K;
         dense_count += sy * 8;
     }
@@ -265,7 +295,9 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     cell_coord(yv, inv_h, nc, periodic, iy, r.uy, out);
     cell_coord(zv, inv_h, nc, periodic, iz, r.uz, out);
     r.q = q != nullptr ? qv : T(0);
-    const int s = (inblock ? s_start[c] : start[c]) + sl;
+    // sub-counter of the particle as in k_bin_count (sstart is start when S = 1)
+    const int s =
+        (inblock ? s_start[c] : sstart[(c << logS) + (int)(j & ((1 << logS) - 1))]) + sl;
     if (s < 0 || (int64_t)s >= np) return;  // only reachable with inconsistent counts
     const int64_t g = p0 + s;
     perm[g] = (int)i;
@@ -281,24 +313,27 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
     const int64_t maxn = a.prange ? a.max_np : a.n;
     const int blocks = (int)((maxn + 255) / 256);
     const int inblock = K <= kInBlockScanMax ? 1 : 0;
+    const int logS = ilog2_shards(count_shards(K));
+    int *sstart = logS ? a.sstart : a.start;
+    if (logS && sstart == nullptr) return hipErrorInvalidValue;
     if (maxn > 0) {
         hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
-                           a.periodic, a.cell_of, a.slot, a.count, a.flag);
+                           a.periodic, a.cell_of, a.slot, a.count, logS, a.flag);
     }
     if (!inblock || maxn == 0) {
-        const int ntiles = (K + kScanTile - 1) / kScanTile;
-        hipLaunchKernelGGL(k_bin_tile_sums, dim3(ntiles, nsys), dim3(1024), 0, s, K, a.count,
-                           a.tile_sums, a.dense_count);
-        hipLaunchKernelGGL(k_bin_scan_tiles, dim3(ntiles, nsys), dim3(1024), 0, s, K, a.count,
-                           a.tile_sums, a.start, a.dense_threshold, a.dense_cells,
-                           a.dense_count);
+        const int ntiles = scan_tiles((int64_t)K << logS);
+        hipLaunchKernelGGL(k_bin_tile_sums, dim3(ntiles, nsys), dim3(1024), 0, s, K << logS,
+                           a.count, a.tile_sums, a.dense_count);
+        hipLaunchKernelGGL(k_bin_scan_tiles, dim3(ntiles, nsys), dim3(1024), 0, s, K, logS,
+                           a.count, a.tile_sums, a.start, sstart, a.dense_threshold,
+                           a.dense_cells, a.dense_count);
     }
     if (maxn > 0) {
         hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, (const T *)a.q,
-                           inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, a.perm,
-                           a.scell, (particle4<T> *)a.sorted, inblock, a.count,
+                           inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, sstart, logS,
+                           a.perm, a.scell, (particle4<T> *)a.sorted, inblock, a.count,
                            a.dense_threshold, a.dense_cells, a.dense_count);
     }
     return hipGetLastError();

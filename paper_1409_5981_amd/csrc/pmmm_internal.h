@@ -440,7 +440,8 @@ struct BinArgs {
     int periodic;
     int *cell_of, *slot, *count, *start, *scell, *perm, *flag;
     int *dense_cells, *dense_count;
-    int *tile_sums;    // [nsys][ceil(K / 4096)] scratch of the multi-block scan
+    int *tile_sums;    // [nsys][scan_tiles(S K)] scratch of the multi-block scan
+    int *sstart;       // [nsys][S K + 1] sub-counter starts (S = count_shards(K) > 1)
     int dense_threshold;
     void *sorted;      // particle4<T>[n]
     // batch of nsys systems on this mesh (prange null: one system of n)
@@ -451,7 +452,16 @@ struct BinArgs {
 template <typename T>
 hipError_t launch_bin(const BinArgs &a, hipStream_t s);
 // Tiles of the multi-block scan of the cell counts.
-inline int scan_tiles(int64_t K) { return (int)((K + 4095) / 4096); }
+inline int scan_tiles(int64_t L) { return (int)((L + 4095) / 4096); }
+// Sub-counters per cell of the binning counts: meshes up to 16^3 count in one
+// (their scan runs inside the scatter blocks), larger ones in 8.
+constexpr int kCountShards = 8;
+inline int count_shards(int64_t K) { return K <= 4096 ? 1 : kCountShards; }
+inline int ilog2_shards(int S) {
+    int l = 0;
+    while ((1 << l) < S) ++l;
+    return l;
+}
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path
