@@ -3,8 +3,9 @@
 //   k_bin_count   cell of each particle, per-cell counts (int atomics) and the
 //                 particle's slot inside its cell; meshes above 16^3 count
 //                 in S sub-counters per cell (particle i in sub-counter
-//                 i mod S), so that a cell holding a large share of the
-//                 particles does not serialise all of them on one address
+//                 i mod S), stored sub-counter-major ([S][K], each in its own
+//                 cache line), so that a cell holding a large share of the
+//                 particles does not serialise all of them on one line
 //   k_bin_tile_sums, k_bin_scan_tiles
 //                 exclusive scan of the counts -> cell_start in tiles of 4096
 //                 cells, resets the counts for the next call, lists cells above
@@ -65,7 +66,29 @@ __global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ p
     if (out) *flag = 1;
     const int c = (iz * nc + iy) * nc + ix;
     cell_of[i] = c;
-    slot[i] = atomicAdd(&count[(c << logS) + (int)(j & ((1 << logS) - 1))], 1);
+    slot[i] = atomicAdd(&count[(int)(j & ((1 << logS) - 1)) * (nc * nc * nc) + c], 1);
+}
+
+// Four consecutive counters e .. e + 3 of the scan order (cell-major: cell
+// e >> logS, sub-counter e mod S) from their sub-counter-major storage; with
+// S = 1 an aligned int4.  e is a multiple of 4 and the four share one cell
+// when S > 1.
+__device__ __forceinline__ int4 load_counts4(const int *count, int e, int logS, int K) {
+    if (logS == 0) return *(const int4 *)(count + e);
+    const int c = e >> logS, sh = e & ((1 << logS) - 1);
+    const int *p = count + (int64_t)sh * K + c;
+    return make_int4(p[0], p[K], p[2 * K], p[3 * K]);
+}
+__device__ __forceinline__ void zero_counts4(int *count, int e, int logS, int K) {
+    if (logS == 0) {
+        *(int4 *)(count + e) = make_int4(0, 0, 0, 0);
+        return;
+    }
+    int *p = count + (int64_t)(e & ((1 << logS) - 1)) * K + (e >> logS);
+    p[0] = 0;
+    p[K] = 0;
+    p[2 * K] = 0;
+    p[3 * K] = 0;
 }
 
 // Exclusive scan of the counts in tiles of kScanTile, one 1024-thread block
@@ -75,10 +98,11 @@ __global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ p
 // particular order: each dense cell is reduced by one block in a fixed order).
 constexpr int kScanTile = 4096;
 
-__global__ void __launch_bounds__(1024) k_bin_tile_sums(int L, const int *__restrict__ count,
+__global__ void __launch_bounds__(1024) k_bin_tile_sums(int K, int logS,
+                                                        const int *__restrict__ count,
                                                         int *__restrict__ tile_sums,
                                                         int *__restrict__ dense_count) {
-    const int ntiles = gridDim.x;
+    const int ntiles = gridDim.x, L = K << logS;
     {
         const int64_t sy = blockIdx.y;
         count += sy * L;
@@ -87,11 +111,11 @@ __global__ void __launch_bounds__(1024) k_bin_tile_sums(int L, const int *__rest
     }
     __shared__ int wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    // L = S n^3 with n >= 4 is a multiple of 64: four counts per thread, 16-byte aligned
+    // L = S n^3 with n >= 4 is a multiple of 64: four counters per thread
     const int idx = blockIdx.x * kScanTile + tid * 4;
     int v = 0;
     if (idx < L) {
-        const int4 c4 = *(const int4 *)(count + idx);
+        const int4 c4 = load_counts4(count, idx, logS, K);
         v = (c4.x + c4.y) + (c4.z + c4.w);
     }
 #pragma unroll
@@ -106,9 +130,10 @@ __global__ void __launch_bounds__(1024) k_bin_tile_sums(int L, const int *__rest
     }
 }
 
-// L = S K counters (S = 1 or kCountShards); with S > 1 sstart receives the start
-// of every sub-counter and start that of every cell (its first sub-counter),
-// and a cell's two halves sit in the two lanes of an even-odd pair.
+// L = S K counters (S = 1 or kCountShards) scanned in cell-major order; with
+// S > 1 sstart receives the start of every sub-counter (in that order) and
+// start that of every cell (its first sub-counter), and a cell's two halves
+// sit in the two lanes of an even-odd pair.
 __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *__restrict__ count,
                                                          const int *__restrict__ tile_sums,
                                                          int *__restrict__ start,
@@ -132,7 +157,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *_
     const int idx = t * kScanTile + tid * 4;
     int v[4] = {0, 0, 0, 0};
     if (idx < L) {
-        const int4 c4 = *(const int4 *)(count + idx);
+        const int4 c4 = load_counts4(count, idx, logS, K);
         v[0] = c4.x;
         v[1] = c4.y;
         v[2] = c4.z;
@@ -187,7 +212,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *_
             run += v[j];
         }
     }
-    if (idx < L) *(int4 *)(count + idx) = make_int4(0, 0, 0, 0);
+    if (idx < L) zero_counts4(count, idx, logS, K);
     if (t == ntiles - 1 && tid == 1023) {
         start[K] = run;
         sstart[L] = run;
@@ -323,7 +348,7 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
     }
     if (!inblock || maxn == 0) {
         const int ntiles = scan_tiles((int64_t)K << logS);
-        hipLaunchKernelGGL(k_bin_tile_sums, dim3(ntiles, nsys), dim3(1024), 0, s, K << logS,
+        hipLaunchKernelGGL(k_bin_tile_sums, dim3(ntiles, nsys), dim3(1024), 0, s, K, logS,
                            a.count, a.tile_sums, a.dense_count);
         hipLaunchKernelGGL(k_bin_scan_tiles, dim3(ntiles, nsys), dim3(1024), 0, s, K, logS,
                            a.count, a.tile_sums, a.start, sstart, a.dense_threshold,
