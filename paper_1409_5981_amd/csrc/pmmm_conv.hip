@@ -25,7 +25,7 @@ constexpr int kLoadBatch = 8;
 
 // ------------------------------------------------------------------ planes
 template <typename T>
-__global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
+__global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
                                                    const T *__restrict__ M,
                                                    cplx<T> *__restrict__ spec,
                                                    const cplx<T> *__restrict__ tw_g,
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
     if (c == P) {
         // blocks of the extra component row: sum over plane z of the per-cell
         // q|u|^2 (component P of M), fixed-order reduction
-        __shared__ double red[4];
+        __shared__ double red[8];
         const T *pl = M + ((int64_t)P * nin + z) * nin * nin;
         double acc = 0.0;
         for (int idx = tid; idx < nin * nin; idx += nthr) acc += (double)pl[idx];
@@ -55,7 +55,11 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if ((tid & 63) == 0) red[tid >> 6] = acc;
         __syncthreads();
-        if (tid == 0) qr2_partial[z] = ((red[0] + red[1]) + red[2]) + red[3];
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < (nthr >> 6); ++w) t += red[w];
+            qr2_partial[z] = t;
+        }
         return;
     }
     // twiddle load in flight together with the plane's loads (nf/2 <= blockDim.x)
@@ -109,7 +113,7 @@ __global__ void __launch_bounds__(256) k_plane_fwd(int nin, int logn,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_plane_inv(int nout, int logn,
+__global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
                                                    const cplx<T> *__restrict__ spec,
                                                    T *__restrict__ L,
                                                    const cplx<T> *__restrict__ tw_g, T scale) {
@@ -193,6 +197,10 @@ static hipError_t ensure_lds(Kern k, size_t bytes) {
 template <int PO, typename T>
 hipError_t column_launch(const FFTArgs &a, hipStream_t s);
 
+// Threads of a plane block: the 128-point planes need 100 KB of LDS, so one
+// block holds a CU; it gets 512 threads, the smaller planes 256.
+static int plane_threads(int nf) { return nf >= 128 ? 512 : 256; }
+
 template <typename T>
 hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const int P = nreal(a.p);
@@ -206,7 +214,7 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
         if (e != hipSuccess) return e;
         // periodic: one extra row of blocks (c == P) sums q|u|^2 per plane
         const int rows = a.open ? P : P + 1;
-        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, rows, nsys), dim3(256), lds_plane, s, n, logn,
+        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, rows, nsys), dim3(plane_threads(nf)), lds_plane, s, n, logn,
                            (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
                            a.open ? nullptr : a.qr2_partial);
         return hipGetLastError();
@@ -228,7 +236,7 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     e = ensure_lds(k_plane_inv<T>, lds_plane);
     if (e != hipSuccess) return e;
     const T scale = T(1.0 / ((double)nf * nf * nf));
-    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P, nsys), dim3(256), lds_plane, s, n, logn,
+    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P, nsys), dim3(plane_threads(nf)), lds_plane, s, n, logn,
                        (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw, scale);
     return hipGetLastError();
 }
