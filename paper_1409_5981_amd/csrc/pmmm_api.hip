@@ -299,7 +299,7 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
     PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * scan_tiles(KS)));
     if (KS > pl->K) PMMM_HIP(hipMalloc(&pl->sstart, sizeof(int) * (KS + 1)));
-    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] scan counter
+    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
     PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
     PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * KS, s));

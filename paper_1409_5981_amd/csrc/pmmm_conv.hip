@@ -29,12 +29,13 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
                                                    const T *__restrict__ M,
                                                    cplx<T> *__restrict__ spec,
                                                    const cplx<T> *__restrict__ tw_g,
-                                                   int P, double *__restrict__ qr2_partial) {
+                                                   int P, double *__restrict__ qr2_partial,
+                                                   int cw, int cws) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nf = 1 << logn, nh = nf / 2 + 1, npair = nin / 2, ls = lds_line(nf);
     cplx<T> *tw = (cplx<T> *)lds_raw;
     cplx<T> *buf1 = tw + nf / 2;           // [npair][ls] row pairs
-    cplx<T> *buf2 = buf1 + npair * ls;     // [nf][nh]
+    cplx<T> *buf2 = buf1 + npair * ls;     // [nf][cws]: kx columns k0 .. k0 + cw - 1
     const int z = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     {
@@ -89,34 +90,43 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
     if (tid < nf / 2) tw[tid] = twv;
     __syncthreads();
     fft_lines<T, false>(buf1, logn, npair, ls, 1, tw, tid, nthr);
-    for (int idx = tid; idx < nf * nh; idx += nthr) {
-        const int y = idx / nh, k = idx - y * nh;
-        cplx<T> v = {T(0), T(0)};
-        if (y < nin) {
-            const cplx<T> *row = buf1 + (y >> 1) * ls;
-            const cplx<T> zk = row[k & (nf - 1)];
-            const cplx<T> zm = row[(nf - k) & (nf - 1)];
-            if ((y & 1) == 0) {
-                v.re = T(0.5) * (zk.re + zm.re);
-                v.im = T(0.5) * (zk.im - zm.im);
-            } else {
-                v.re = T(0.5) * (zk.im + zm.im);
-                v.im = T(-0.5) * (zk.re - zm.re);
-            }
-        }
-        buf2[idx] = v;
-    }
-    __syncthreads();
-    fft_lines<T, false>(buf2, logn, nh, 1, nh, tw, tid, nthr);
+    // y FFTs in chunks of cw kx columns (all nh at once unless LDS is short)
     cplx<T> *out = spec + ((int64_t)c * nin + z) * nf * nh;
-    for (int idx = tid; idx < nf * nh; idx += nthr) out[idx] = buf2[idx];
+    for (int k0 = 0; k0 < nh; k0 += cw) {
+        const int cn = nh - k0 < cw ? nh - k0 : cw;
+        for (int idx = tid; idx < nf * cn; idx += nthr) {
+            const int y = idx / cn, kk = idx - y * cn, k = k0 + kk;
+            cplx<T> v = {T(0), T(0)};
+            if (y < nin) {
+                const cplx<T> *row = buf1 + (y >> 1) * ls;
+                const cplx<T> zk = row[k & (nf - 1)];
+                const cplx<T> zm = row[(nf - k) & (nf - 1)];
+                if ((y & 1) == 0) {
+                    v.re = T(0.5) * (zk.re + zm.re);
+                    v.im = T(0.5) * (zk.im - zm.im);
+                } else {
+                    v.re = T(0.5) * (zk.im + zm.im);
+                    v.im = T(-0.5) * (zk.re - zm.re);
+                }
+            }
+            buf2[y * cws + kk] = v;
+        }
+        __syncthreads();
+        fft_lines<T, false>(buf2, logn, cn, 1, cws, tw, tid, nthr);
+        for (int idx = tid; idx < nf * cn; idx += nthr) {
+            const int y = idx / cn, kk = idx - y * cn;
+            out[y * nh + k0 + kk] = buf2[y * cws + kk];
+        }
+        __syncthreads();   // buf2 is refilled by the next chunk
+    }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
                                                    const cplx<T> *__restrict__ spec,
                                                    T *__restrict__ L,
-                                                   const cplx<T> *__restrict__ tw_g, T scale) {
+                                                   const cplx<T> *__restrict__ tw_g, T scale,
+                                                   int cw, int cws) {
     {
         // system blockIdx.z of a batch: meshes at fixed strides
         const int64_t sy = blockIdx.z, P = gridDim.y;
@@ -127,50 +137,51 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nf = 1 << logn, nh = nf / 2 + 1, npair = nout / 2, ls = lds_line(nf);
     cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *buf2 = tw + nf / 2;           // [nf][nh]
-    cplx<T> *buf1 = buf2 + nf * nh;        // [npair][ls]
+    cplx<T> *buf2 = tw + nf / 2;           // [nf][cws]: kx columns k0 .. k0 + cw - 1
+    cplx<T> *buf1 = buf2 + nf * cws;       // [npair][ls]
     const int z = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     // twiddle load in flight together with the spectrum's (nf/2 <= blockDim.x)
     const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];
     const cplx<T> *in = spec + ((int64_t)c * nout + z) * nf * nh;
-    for (int base = tid; base < nf * nh; base += nthr * kLoadBatch) {
-        cplx<T> v[kLoadBatch];
+    // y inverse FFTs in chunks of cw kx columns (all nh at once unless LDS is
+    // short), each chunk packed into the C2R rows of buf1 (the columns kx and
+    // nf - kx of a row pair come from column kx)
+    for (int k0 = 0; k0 < nh; k0 += cw) {
+        const int cn = nh - k0 < cw ? nh - k0 : cw;
+        for (int base = tid; base < nf * cn; base += nthr * kLoadBatch) {
+            cplx<T> v[kLoadBatch];
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) {
-            // clamped, unconditional loads: the whole batch is issued at once
-            const int idx = base + u * nthr;
-            v[u] = in[idx < nf * nh ? idx : nf * nh - 1];
+            for (int u = 0; u < kLoadBatch; ++u) {
+                // clamped, unconditional loads: the whole batch is issued at once
+                const int idx = base + u * nthr < nf * cn ? base + u * nthr : nf * cn - 1;
+                const int y = idx / cn, kk = idx - y * cn;
+                v[u] = in[y * nh + k0 + kk];
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) asm volatile("" ::"v"(v[u].re), "v"(v[u].im));
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int idx = base + u * nthr;
+                const int y = idx / cn, kk = idx - y * cn;
+                if (idx < nf * cn) buf2[y * cws + kk] = v[u];
+            }
         }
-#pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) asm volatile("" ::"v"(v[u].re), "v"(v[u].im));
-#pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * nthr;
-            if (idx < nf * nh) buf2[idx] = v[u];
+        if (k0 == 0) {
+            asm volatile("" ::"v"(twv.re), "v"(twv.im));
+            if (tid < nf / 2) tw[tid] = twv;
         }
+        __syncthreads();
+        fft_lines<T, true>(buf2, logn, cn, 1, cws, tw, tid, nthr);
+        for (int idx = tid; idx < npair * cn; idx += nthr) {
+            const int j = idx / cn, kk = idx - j * cn, k = k0 + kk;
+            const cplx<T> A = buf2[(2 * j) * cws + kk];
+            const cplx<T> B = buf2[(2 * j + 1) * cws + kk];
+            buf1[j * ls + k] = {A.re - B.im, A.im + B.re};
+            if (k >= 1 && k < nf / 2) buf1[j * ls + nf - k] = {A.re + B.im, B.re - A.im};
+        }
+        __syncthreads();   // buf2 is refilled by the next chunk
     }
-    asm volatile("" ::"v"(twv.re), "v"(twv.im));
-    if (tid < nf / 2) tw[tid] = twv;
-    __syncthreads();
-    fft_lines<T, true>(buf2, logn, nh, 1, nh, tw, tid, nthr);
-    for (int idx = tid; idx < npair * nf; idx += nthr) {
-        const int j = idx >> logn, k = idx & (nf - 1);
-        const cplx<T> *ra = buf2 + (2 * j) * nh;
-        const cplx<T> *rb = buf2 + (2 * j + 1) * nh;
-        cplx<T> A, B;
-        if (k <= nf / 2) {
-            A = ra[k];
-            B = rb[k];
-        } else {
-            A = ra[nf - k];
-            B = rb[nf - k];
-            A.im = -A.im;
-            B.im = -B.im;
-        }
-        buf1[j * ls + k] = {A.re - B.im, A.im + B.re};
-    }
-    __syncthreads();
     fft_lines<T, true>(buf1, logn, npair, ls, 1, tw, tid, nthr);
     T *plane = L + ((int64_t)c * nout + z) * nout * nout;
     for (int idx = tid; idx < nout * nout; idx += nthr) {
@@ -197,9 +208,22 @@ static hipError_t ensure_lds(Kern k, size_t bytes) {
 template <int PO, typename T>
 hipError_t column_launch(const FFTArgs &a, hipStream_t s);
 
-// Threads of a plane block: the 128-point planes need 100 KB of LDS, so one
-// block holds a CU; it gets 512 threads, the smaller planes 256.
-static int plane_threads(int nf) { return nf >= 128 ? 512 : 256; }
+// Shape of a plane block: 256 threads; the y pass of a 128-point plane runs
+// in chunks of 16 kx columns (row stride 17 against bank conflicts), so that
+// a block needs 50 KB of LDS instead of 100 KB and three share a CU.
+struct PlaneShape {
+    int threads, cw, cws;
+    size_t lds;
+};
+static PlaneShape plane_shape(int n, int nf, size_t csz) {
+    const int nh = nf / 2 + 1;
+    PlaneShape ps;
+    ps.threads = 256;
+    ps.cw = nf >= 128 ? 16 : nh;
+    ps.cws = ps.cw == nh ? nh : ps.cw + 1;
+    ps.lds = (size_t)(nf / 2 + (n / 2) * lds_line(nf) + nf * ps.cws) * csz;
+    return ps;
+}
 
 template <typename T>
 hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
@@ -207,16 +231,17 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, n = a.n;
     const int nsys = a.nsys > 0 ? a.nsys : 1;
     const size_t csz = sizeof(cplx<T>);
-    const size_t lds_plane = (size_t)(nf / 2 + (n / 2) * lds_line(nf) + nf * nh) * csz;
+    const PlaneShape ps = plane_shape(n, nf, csz);
+    const size_t lds_plane = ps.lds;
     hipError_t e = hipSuccess;
     if (stage == 0) {
         e = ensure_lds(k_plane_fwd<T>, lds_plane);
         if (e != hipSuccess) return e;
         // periodic: one extra row of blocks (c == P) sums q|u|^2 per plane
         const int rows = a.open ? P : P + 1;
-        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, rows, nsys), dim3(plane_threads(nf)), lds_plane, s, n, logn,
-                           (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
-                           a.open ? nullptr : a.qr2_partial);
+        hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, rows, nsys), dim3(ps.threads), lds_plane, s, n,
+                           logn, (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
+                           a.open ? nullptr : a.qr2_partial, ps.cw, ps.cws);
         return hipGetLastError();
     }
     if (stage == 1) {
@@ -236,8 +261,9 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     e = ensure_lds(k_plane_inv<T>, lds_plane);
     if (e != hipSuccess) return e;
     const T scale = T(1.0 / ((double)nf * nf * nf));
-    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P, nsys), dim3(plane_threads(nf)), lds_plane, s, n, logn,
-                       (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw, scale);
+    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P, nsys), dim3(ps.threads), lds_plane, s, n, logn,
+                       (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw, scale, ps.cw,
+                       ps.cws);
     return hipGetLastError();
 }
 
