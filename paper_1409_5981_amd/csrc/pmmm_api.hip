@@ -37,6 +37,15 @@ int hip_fail(hipError_t e, const char *what) {
 // Cells denser than this go to the one-workgroup-per-cell FP64 path of P2M.
 constexpr int kDenseThreshold = 256;
 
+// Workgroups of the P2M launch that reduce the dense cells (one cell at a
+// time each): none below the threshold, one per 8192 particles within
+// [32, 512] above it (a clustered system has thousands of dense cells).
+static int dense_blocks_for(int64_t n) {
+    if (n <= kDenseThreshold) return 0;
+    const int64_t b = n / 8192;
+    return (int)(b < 32 ? 32 : (b > 512 ? 512 : b));
+}
+
 struct Plan {
     pmmm_params prm;
     int n, nf, p, P, Q, open, prec, cutoff, images;
@@ -381,7 +390,7 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         m.p = pl->p;
         m.ncell = pl->n;
         m.group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
-        m.may_have_dense = n > kDenseThreshold;
+        m.dense_blocks = dense_blocks_for(n);
         // meshes scanned inside the scatter kernel reset their counts here
         m.zero_count = (n > 0 && pl->K <= 4096) ? pl->count : nullptr;
         m.start = pl->start;
@@ -833,7 +842,7 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         m.p = pl->p;
         m.ncell = pl->n;
         m.group = group_for((double)c.tot_np / ((double)pl->K * ns));
-        m.may_have_dense = c.max_np > kDenseThreshold;
+        m.dense_blocks = dense_blocks_for(c.max_np);
         m.zero_count = (c.max_np > 0 && pl->K <= 4096) ? c.count : nullptr;
         m.start = c.start;
         m.dense_cells = c.dense;

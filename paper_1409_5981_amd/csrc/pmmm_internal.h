@@ -465,7 +465,7 @@ inline int ilog2_shards(int S) {
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path
-    int may_have_dense;             // n exceeds the dense threshold: add the dense blocks
+    int dense_blocks;               // workgroups for the dense cells (0: n below the threshold)
     int *zero_count;                // counts to reset for the next binning (or null)
     const int *start, *dense_cells, *dense_count;
     int dense_threshold;

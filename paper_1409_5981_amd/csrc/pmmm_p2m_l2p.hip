@@ -15,10 +15,8 @@
 
 namespace pmmm {
 
-constexpr int kDenseBlocks = 128;
-
 // Blocks [0, nlight) run the light path (G lanes per cell); the remaining
-// kDenseBlocks handle the listed dense cells, one workgroup per cell with
+// dense_blocks handle the listed dense cells, one workgroup per cell with
 // FP64 accumulation and a fixed-order reduction.  zero_count (when not
 // null) is reset for the next binning.
 template <int PO, typename T, int G>
@@ -90,12 +88,22 @@ __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ star
         double acc[P + 1];
 #pragma unroll
         for (int c = 0; c <= P; ++c) acc[c] = 0.0;
-        for (int s = s0 + tid; s < s1; s += 256) {
-            const particle4<T> r = sorted[s];
-            accumulate_regular<PO, double>(-(double)r.ux, -(double)r.uy, -(double)r.uz,
-                                           (double)r.q, acc);
-            acc[P] += (double)r.q * ((double)r.ux * r.ux + (double)r.uy * r.uy +
-                                     (double)r.uz * r.uz);
+        // four particles per thread and round, loads issued together; the
+        // per-thread order of the sum is unchanged (clamped extras enter with
+        // charge 0)
+        constexpr int U = 4;
+        for (int s = s0 + tid; s < s1; s += 256 * U) {
+            particle4<T> r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = sorted[s + u * 256 < s1 ? s + u * 256 : s1 - 1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double q = s + u * 256 < s1 ? (double)r[u].q : 0.0;
+                accumulate_regular<PO, double>(-(double)r[u].ux, -(double)r[u].uy,
+                                               -(double)r[u].uz, q, acc);
+                acc[P] += q * ((double)r[u].ux * r[u].ux + (double)r[u].uy * r[u].uy +
+                               (double)r[u].uz * r[u].uz);
+            }
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -202,7 +210,7 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
     const int G = a.group;
     int nlight = (int)(((int64_t)K * G + 255) / 256);
     if (a.zero_count && nlight * 256 < K) nlight = (K + 255) / 256;
-    const int grid = nlight + (a.may_have_dense ? kDenseBlocks : 0);
+    const int grid = nlight + a.dense_blocks;
     const int nsys = a.nsys > 0 ? a.nsys : 1;
     const int *st = a.start;
     const particle4<T> *so = (const particle4<T> *)a.sorted;
