@@ -37,6 +37,11 @@ int hip_fail(hipError_t e, const char *what) {
 // Cells denser than this go to the one-workgroup-per-cell FP64 path of P2M.
 constexpr int kDenseThreshold = 256;
 
+// From this many particles on, L2P writes its results in sorted order and a
+// second kernel sends them back to the caller's order (fewer, wider random
+// accesses); below it the extra launch costs more than it saves.
+constexpr int64_t kStagedL2PMinN = int64_t(1) << 18;
+
 // Workgroups of the P2M launch that reduce the dense cells (one cell at a
 // time each): none below the threshold, one per 8192 particles within
 // [32, 512] above it (a clustered system has thousands of dense cells).
@@ -60,8 +65,8 @@ struct Plan {
     double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
     int64_t cap = 0, last_n = -1;
-    int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr;
-    void *sorted = nullptr;
+    int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr, *pos = nullptr;
+    void *sorted = nullptr, *staged = nullptr;   // staged: out4<T>[cap] sorted-order results
     hipStream_t last_stream = nullptr;
     // multi-charge workspace (chunks of up to kMultiMaxSets sets)
     int mcap_sets = 0;
@@ -223,7 +228,7 @@ static size_t plan_bytes(const Plan *pl) {
 }
 
 static size_t particle_bytes(const Plan *pl, int64_t n) {
-    return (size_t)n * (4 * sizeof(int) + 4 * pl->tsize);
+    return (size_t)n * (5 * sizeof(int) + 8 * pl->tsize);
 }
 
 static void free_particles(Plan *pl) {
@@ -232,8 +237,10 @@ static void free_particles(Plan *pl) {
     hipFree(pl->perm);
     hipFree(pl->scell);
     hipFree(pl->sorted);
-    pl->cell_of = pl->slot = pl->perm = pl->scell = nullptr;
-    pl->sorted = nullptr;
+    hipFree(pl->pos);
+    hipFree(pl->staged);
+    pl->cell_of = pl->slot = pl->perm = pl->scell = pl->pos = nullptr;
+    pl->sorted = pl->staged = nullptr;
     pl->cap = 0;
 }
 
@@ -250,6 +257,8 @@ static int ensure_capacity(Plan *pl, int64_t n) {
     PMMM_HIP(hipMalloc(&pl->perm, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&pl->scell, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&pl->sorted, 4 * pl->tsize * n));
+    PMMM_HIP(hipMalloc(&pl->pos, sizeof(int) * n));
+    PMMM_HIP(hipMalloc(&pl->staged, 4 * pl->tsize * n));
     pl->cap = n;
     return PMMM_OK;
 }
@@ -378,6 +387,7 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         b.flag = pl->small + 1;
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
+        b.pos = n >= kStagedL2PMinN ? pl->pos : nullptr;
         b.tile_sums = pl->tile_sums;
         b.sstart = pl->sstart;
         b.dense_threshold = kDenseThreshold;
@@ -435,6 +445,10 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         l.phi = phi;
         l.gx = gx;
         l.gy = gy;
+        if (n >= kStagedL2PMinN) {
+            l.staged = pl->staged;
+            l.pos = pl->pos;
+        }
         l.gz = gz;
         PMMM_HIP(launch_l2p<T>(l, s));
     }

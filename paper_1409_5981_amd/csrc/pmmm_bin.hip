@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     int *__restrict__ start, const int *__restrict__ sstart, int logS, int *__restrict__ perm,
     int *__restrict__ scell, particle4<T> *__restrict__ sorted, int inblock,
     const int *__restrict__ count, int dense_thr, int *__restrict__ dense_cells,
-    int *__restrict__ dense_count) {
+    int *__restrict__ dense_count, int *__restrict__ pos) {
     __shared__ int s_start[kInBlockScanMax + 1];
     const int K = nc * nc * nc;
     {
@@ -328,6 +328,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(
     perm[g] = (int)i;
     scell[g] = c;
     sorted[g] = r;
+    if (pos != nullptr) pos[i] = (int)g;
 }
 
 template <typename T>
@@ -359,7 +360,7 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, (const T *)a.q,
                            inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, sstart, logS,
                            a.perm, a.scell, (particle4<T> *)a.sorted, inblock, a.count,
-                           a.dense_threshold, a.dense_cells, a.dense_count);
+                           a.dense_threshold, a.dense_cells, a.dense_count, a.pos);
     }
     return hipGetLastError();
 }

@@ -33,6 +33,13 @@ struct alignas(4 * sizeof(T)) particle4 {
     T ux, uy, uz, q;
 };
 
+// Potential and gradient of one particle, in sorted order before they are
+// sent back to the caller's order.
+template <typename T>
+struct alignas(4 * sizeof(T)) out4 {
+    T phi, gx, gy, gz;
+};
+
 __host__ __device__ constexpr int nreal(int p) { return (p + 1) * (p + 1); }
 __host__ __device__ constexpr int ridx(int l, int m) { return l * (l + 1) + m; }
 
@@ -441,6 +448,7 @@ struct BinArgs {
     int *cell_of, *slot, *count, *start, *scell, *perm, *flag;
     int *dense_cells, *dense_count;
     int *tile_sums;    // [nsys][scan_tiles(S K)] scratch of the multi-block scan
+    int *pos;          // [n] sorted slot of each particle in the caller's order (or null)
     int *sstart;       // [nsys][S K + 1] sub-counter starts (S = count_shards(K) > 1)
     int dense_threshold;
     void *sorted;      // particle4<T>[n]
@@ -503,6 +511,8 @@ struct L2PArgs {
     double alpha_cell;              // alpha h
     double inv_h;                   // 1 / h in the caller's length unit
     void *phi, *gx, *gy, *gz;
+    void *staged;                   // out4<T>[n] in sorted order, or null: scatter directly
+    const int *pos;                 // [n] sorted slot per caller index (with staged)
     const int64_t *prange;          // batch (see BinArgs)
     int nsys;
     int64_t max_np;

@@ -10,7 +10,10 @@
 //              eq. phigrad for grad Phi; the per-particle terms of a charged
 //              periodic system (App. B, correction procedure; the uniform
 //              corrections are already in L); results rescaled to the
-//              caller's units and scattered to input order.
+//              caller's units and scattered to input order -- for large N
+//              written in sorted order instead (16-byte stores) and sent
+//              back by k_unpermute, one 16-byte gather per particle in place
+//              of four scattered 4-byte stores.
 #include "pmmm_internal.h"
 
 namespace pmmm {
@@ -131,6 +134,7 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
                                              T inv_h, T *__restrict__ phi_out,
                                              T *__restrict__ gx_out, T *__restrict__ gy_out,
                                              T *__restrict__ gz_out,
+                                             out4<T> *__restrict__ staged,
                                              const int64_t *__restrict__ prange) {
     constexpr int P = nreal(PO);
     int64_t p0, np;
@@ -195,12 +199,35 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
         gy += T(4) * qtot_term * r.uy;
         gz += T(4) * qtot_term * r.uz;
     }
-    const int i = perm[s];
     const T ih2 = inv_h * inv_h;
+    if (staged != nullptr) {
+        // sorted order, one 16-byte store; k_unpermute sends it back
+        staged[s] = out4<T>{ph * inv_h, gx * ih2, gy * ih2, gz * ih2};
+        return;
+    }
+    const int i = perm[s];
     phi_out[i] = ph * inv_h;
     gx_out[i] = gx * ih2;
     gy_out[i] = gy * ih2;
     gz_out[i] = gz * ih2;
+}
+
+// Results back to the caller's order: particle i reads its sorted slot's
+// record (one 16-byte gather) and writes the four outputs coalesced.
+template <typename T>
+__global__ void __launch_bounds__(256) k_unpermute(int64_t n, const int *__restrict__ pos,
+                                                   const out4<T> *__restrict__ staged,
+                                                   T *__restrict__ phi_out, T *__restrict__ gx_out,
+                                                   T *__restrict__ gy_out, T *__restrict__ gz_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int g = pos[i];
+    if (g < 0 || (int64_t)g >= n) return;  // only reachable with inconsistent counts
+    const out4<T> v = staged[g];
+    phi_out[i] = v.phi;
+    gx_out[i] = v.gx;
+    gy_out[i] = v.gy;
+    gz_out[i] = v.gz;
 }
 
 // ------------------------------------------------------------- launchers
@@ -259,7 +286,13 @@ static hipError_t l2p_launch(const L2PArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_l2p<PO, T>), dim3(blocks, nsys), dim3(256), 0, s, a.n, K, a.periodic,
                        (const particle4<T> *)a.sorted, a.scell, a.perm, (const T *)a.L,
                        a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
-                       (T *)a.gx, (T *)a.gy, (T *)a.gz, a.prange);
+                       (T *)a.gx, (T *)a.gy, (T *)a.gz, (out4<T> *)a.staged, a.prange);
+    if (a.staged != nullptr) {
+        if (a.prange != nullptr || a.pos == nullptr) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_unpermute<T>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s,
+                           a.n, a.pos, (const out4<T> *)a.staged, (T *)a.phi, (T *)a.gx,
+                           (T *)a.gy, (T *)a.gz);
+    }
     return hipGetLastError();
 }
 
