@@ -24,6 +24,27 @@ namespace pmmm {
 constexpr int kLoadBatch = 8;
 
 // ------------------------------------------------------------------ planes
+// Row y, column k of the x spectra from the packed FFT of the row pair
+// (y & ~1, y | 1) held as one complex row (zero rows y >= nin).
+template <typename T>
+__device__ __forceinline__ cplx<T> unpack_row_pair(const cplx<T> *buf1, int ls, int nf, int nin,
+                                                   int y, int k) {
+    cplx<T> v = {T(0), T(0)};
+    if (y < nin) {
+        const cplx<T> *row = buf1 + (y >> 1) * ls;
+        const cplx<T> zk = row[k & (nf - 1)];
+        const cplx<T> zm = row[(nf - k) & (nf - 1)];
+        if ((y & 1) == 0) {
+            v.re = T(0.5) * (zk.re + zm.re);
+            v.im = T(0.5) * (zk.im - zm.im);
+        } else {
+            v.re = T(0.5) * (zk.im + zm.im);
+            v.im = T(-0.5) * (zk.re - zm.re);
+        }
+    }
+    return v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
                                                    const T *__restrict__ M,
@@ -90,26 +111,23 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
     if (tid < nf / 2) tw[tid] = twv;
     __syncthreads();
     fft_lines<T, false>(buf1, logn, npair, ls, 1, tw, tid, nthr);
-    // y FFTs in chunks of cw kx columns (all nh at once unless LDS is short)
     cplx<T> *out = spec + ((int64_t)c * nin + z) * nf * nh;
+    // y FFTs: all nh kx columns at once, or in chunks of cw when LDS is short
+    if (cw >= nh) {
+        for (int idx = tid; idx < nf * nh; idx += nthr) {
+            const int y = idx / nh, k = idx - y * nh;
+            buf2[idx] = unpack_row_pair(buf1, ls, nf, nin, y, k);
+        }
+        __syncthreads();
+        fft_lines<T, false>(buf2, logn, nh, 1, nh, tw, tid, nthr);
+        for (int idx = tid; idx < nf * nh; idx += nthr) out[idx] = buf2[idx];
+        return;
+    }
     for (int k0 = 0; k0 < nh; k0 += cw) {
         const int cn = nh - k0 < cw ? nh - k0 : cw;
         for (int idx = tid; idx < nf * cn; idx += nthr) {
-            const int y = idx / cn, kk = idx - y * cn, k = k0 + kk;
-            cplx<T> v = {T(0), T(0)};
-            if (y < nin) {
-                const cplx<T> *row = buf1 + (y >> 1) * ls;
-                const cplx<T> zk = row[k & (nf - 1)];
-                const cplx<T> zm = row[(nf - k) & (nf - 1)];
-                if ((y & 1) == 0) {
-                    v.re = T(0.5) * (zk.re + zm.re);
-                    v.im = T(0.5) * (zk.im - zm.im);
-                } else {
-                    v.re = T(0.5) * (zk.im + zm.im);
-                    v.im = T(-0.5) * (zk.re - zm.re);
-                }
-            }
-            buf2[y * cws + kk] = v;
+            const int y = idx / cn, kk = idx - y * cn;
+            buf2[y * cws + kk] = unpack_row_pair(buf1, ls, nf, nin, y, k0 + kk);
         }
         __syncthreads();
         fft_lines<T, false>(buf2, logn, cn, 1, cws, tw, tid, nthr);
@@ -144,43 +162,59 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
     // twiddle load in flight together with the spectrum's (nf/2 <= blockDim.x)
     const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];
     const cplx<T> *in = spec + ((int64_t)c * nout + z) * nf * nh;
-    // y inverse FFTs in chunks of cw kx columns (all nh at once unless LDS is
-    // short), each chunk packed into the C2R rows of buf1 (the columns kx and
-    // nf - kx of a row pair come from column kx)
-    for (int k0 = 0; k0 < nh; k0 += cw) {
-        const int cn = nh - k0 < cw ? nh - k0 : cw;
+    // y inverse FFTs: all nh kx columns at once, or in chunks of cw when LDS
+    // is short; the results are packed into the C2R rows of buf1 (columns kx
+    // and nf - kx of a row pair come from column kx)
+    const int nchunk = cw >= nh ? 1 : (nh + cw - 1) / cw;
+    const int cwl = cw >= nh ? nh : cw;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int k0 = ch * cwl;
+        const int cn = nh - k0 < cwl ? nh - k0 : cwl;
+        const int ld = nchunk == 1 ? nh : cws;       // row stride of buf2
         for (int base = tid; base < nf * cn; base += nthr * kLoadBatch) {
             cplx<T> v[kLoadBatch];
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
                 // clamped, unconditional loads: the whole batch is issued at once
                 const int idx = base + u * nthr < nf * cn ? base + u * nthr : nf * cn - 1;
-                const int y = idx / cn, kk = idx - y * cn;
-                v[u] = in[y * nh + k0 + kk];
+                v[u] = in[nchunk == 1 ? idx : (idx / cn) * nh + k0 + idx % cn];
             }
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) asm volatile("" ::"v"(v[u].re), "v"(v[u].im));
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
                 const int idx = base + u * nthr;
-                const int y = idx / cn, kk = idx - y * cn;
-                if (idx < nf * cn) buf2[y * cws + kk] = v[u];
+                if (idx < nf * cn) buf2[nchunk == 1 ? idx : (idx / cn) * ld + idx % cn] = v[u];
             }
         }
-        if (k0 == 0) {
+        if (ch == 0) {
             asm volatile("" ::"v"(twv.re), "v"(twv.im));
             if (tid < nf / 2) tw[tid] = twv;
         }
         __syncthreads();
-        fft_lines<T, true>(buf2, logn, cn, 1, cws, tw, tid, nthr);
-        for (int idx = tid; idx < npair * cn; idx += nthr) {
-            const int j = idx / cn, kk = idx - j * cn, k = k0 + kk;
-            const cplx<T> A = buf2[(2 * j) * cws + kk];
-            const cplx<T> B = buf2[(2 * j + 1) * cws + kk];
-            buf1[j * ls + k] = {A.re - B.im, A.im + B.re};
-            if (k >= 1 && k < nf / 2) buf1[j * ls + nf - k] = {A.re + B.im, B.re - A.im};
+        fft_lines<T, true>(buf2, logn, cn, 1, ld, tw, tid, nthr);
+        if (nchunk == 1) {
+            for (int idx = tid; idx < npair * nf; idx += nthr) {
+                const int j = idx >> logn, k = idx & (nf - 1);
+                const int kk = k <= nf / 2 ? k : nf - k;
+                cplx<T> A = buf2[(2 * j) * nh + kk];
+                cplx<T> B = buf2[(2 * j + 1) * nh + kk];
+                if (k > nf / 2) {
+                    A.im = -A.im;
+                    B.im = -B.im;
+                }
+                buf1[j * ls + k] = {A.re - B.im, A.im + B.re};
+            }
+        } else {
+            for (int idx = tid; idx < npair * cn; idx += nthr) {
+                const int j = idx / cn, kk = idx - j * cn, k = k0 + kk;
+                const cplx<T> A = buf2[(2 * j) * ld + kk];
+                const cplx<T> B = buf2[(2 * j + 1) * ld + kk];
+                buf1[j * ls + k] = {A.re - B.im, A.im + B.re};
+                if (k >= 1 && k < nf / 2) buf1[j * ls + nf - k] = {A.re + B.im, B.re - A.im};
+            }
         }
-        __syncthreads();   // buf2 is refilled by the next chunk
+        __syncthreads();   // buf1 complete / buf2 refilled by the next chunk
     }
     fft_lines<T, true>(buf1, logn, npair, ls, 1, tw, tid, nthr);
     T *plane = L + ((int64_t)c * nout + z) * nout * nout;
