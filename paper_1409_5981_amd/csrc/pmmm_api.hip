@@ -223,7 +223,10 @@ static size_t plan_bytes(const Plan *pl) {
     b += (size_t)(pl->P + 1) * pl->K * t;                // M
     b += (size_t)pl->P * pl->n * pl->ncol * c;           // spectra
     b += (size_t)pl->P * pl->K * t;                      // L
-    b += (size_t)(3 * pl->K + 1 + 8) * sizeof(int) + 8 * sizeof(double);
+    const size_t KS = (size_t)pl->K * count_shards(pl->K);   // binning sub-counters
+    b += (KS + pl->K + 1 + pl->K + 8 + scan_tiles((int64_t)KS)) * sizeof(int);  // counts, starts, dense, small, tiles
+    if (KS > (size_t)pl->K) b += (KS + 1) * sizeof(int);                         // sub-counter starts
+    b += 8 * sizeof(double) + (size_t)pl->n * sizeof(double);                     // sums, plane sums
     return b;
 }
 

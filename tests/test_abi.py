@@ -52,7 +52,9 @@ def test_parameter_validation_on_host(lib):
 def test_workspace_grows_with_particles(lib):
     from paper_1409_5981_amd._lib import make_params, workspace_bytes
     prm = make_params(32, 7, "periodic")
-    assert workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0) == (1 << 20) * 32
+    # per particle: cell, slot, permutation, sorted cell and sorted slot (5 ints),
+    # the sorted record and the sorted-order results (2 x 4 floats)
+    assert workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0) == (1 << 20) * 52
 
 
 def test_error_strings(lib):
