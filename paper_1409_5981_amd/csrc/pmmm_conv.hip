@@ -51,14 +51,11 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
                                                    cplx<T> *__restrict__ spec,
                                                    const cplx<T> *__restrict__ tw_g,
                                                    int P, double *__restrict__ qr2_partial,
-                                                   int cw, int cws) {
+                                                   int cw, int cws, int cpb) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nf = 1 << logn, nh = nf / 2 + 1, npair = nin / 2, ls = lds_line(nf);
-    cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *buf1 = tw + nf / 2;           // [npair][ls] row pairs
-    cplx<T> *buf2 = buf1 + npair * ls;     // [nf][cws]: kx columns k0 .. k0 + cw - 1
-    const int z = blockIdx.x, c = blockIdx.y;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int z = blockIdx.x;
+    const int btid = threadIdx.x, bnthr = blockDim.x;
     {
         // system blockIdx.z of a batch: meshes at fixed strides
         const int64_t sy = blockIdx.z, K = (int64_t)nin * nin * nin;
@@ -66,24 +63,33 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
         spec += sy * P * nin * nf * nh;
         if (qr2_partial != nullptr) qr2_partial += sy * nin;
     }
-    if (c == P) {
-        // blocks of the extra component row: sum over plane z of the per-cell
-        // q|u|^2 (component P of M), fixed-order reduction
+    if ((int)blockIdx.y == (P + cpb - 1) / cpb) {
+        // blocks of the extra row: sum over plane z of the per-cell q|u|^2
+        // (component P of M), fixed-order reduction
         __shared__ double red[8];
         const T *pl = M + ((int64_t)P * nin + z) * nin * nin;
         double acc = 0.0;
-        for (int idx = tid; idx < nin * nin; idx += nthr) acc += (double)pl[idx];
+        for (int idx = btid; idx < nin * nin; idx += bnthr) acc += (double)pl[idx];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        if ((btid & 63) == 0) red[btid >> 6] = acc;
         __syncthreads();
-        if (tid == 0) {
+        if (btid == 0) {
             double t = 0.0;
-            for (int w = 0; w < (nthr >> 6); ++w) t += red[w];
+            for (int w = 0; w < (bnthr >> 6); ++w) t += red[w];
             qr2_partial[z] = t;
         }
         return;
     }
+    // cpb components per block, one group of blockDim.x / cpb threads each
+    // with its own LDS lines (a group past the last component repeats it and
+    // stores nothing); tid, nthr below are the group's
+    const int nthr = bnthr / cpb, grp = btid / nthr, tid = btid - grp * nthr;
+    const bool live = (int)blockIdx.y * cpb + grp < P;
+    const int c = live ? (int)blockIdx.y * cpb + grp : P - 1;
+    cplx<T> *tw = (cplx<T> *)lds_raw;      // shared by the groups (each writes all of it)
+    cplx<T> *buf1 = tw + nf / 2 + grp * (npair * ls + nf * cws);   // [npair][ls] row pairs
+    cplx<T> *buf2 = buf1 + npair * ls;     // [nf][cws]: kx columns k0 .. k0 + cw - 1
     // twiddle load in flight together with the plane's loads (nf/2 <= blockDim.x)
     const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];
     const T *plane = M + ((int64_t)c * nin + z) * nin * nin;
@@ -120,7 +126,8 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
         }
         __syncthreads();
         fft_lines<T, false>(buf2, logn, nh, 1, nh, tw, tid, nthr);
-        for (int idx = tid; idx < nf * nh; idx += nthr) out[idx] = buf2[idx];
+        if (live)
+            for (int idx = tid; idx < nf * nh; idx += nthr) out[idx] = buf2[idx];
         return;
     }
     for (int k0 = 0; k0 < nh; k0 += cw) {
@@ -131,7 +138,7 @@ __global__ void __launch_bounds__(512) k_plane_fwd(int nin, int logn,
         }
         __syncthreads();
         fft_lines<T, false>(buf2, logn, cn, 1, cws, tw, tid, nthr);
-        for (int idx = tid; idx < nf * cn; idx += nthr) {
+        for (int idx = tid; live && idx < nf * cn; idx += nthr) {
             const int y = idx / cn, kk = idx - y * cn;
             out[y * nh + k0 + kk] = buf2[y * cws + kk];
         }
@@ -144,21 +151,24 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
                                                    const cplx<T> *__restrict__ spec,
                                                    T *__restrict__ L,
                                                    const cplx<T> *__restrict__ tw_g, T scale,
-                                                   int cw, int cws) {
+                                                   int P, int cw, int cws, int cpb) {
     {
         // system blockIdx.z of a batch: meshes at fixed strides
-        const int64_t sy = blockIdx.z, P = gridDim.y;
+        const int64_t sy = blockIdx.z;
         const int nf_ = 1 << logn;
         spec += sy * P * nout * nf_ * (nf_ / 2 + 1);
         L += sy * P * nout * nout * nout;
     }
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nf = 1 << logn, nh = nf / 2 + 1, npair = nout / 2, ls = lds_line(nf);
-    cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *buf2 = tw + nf / 2;           // [nf][cws]: kx columns k0 .. k0 + cw - 1
+    const int z = blockIdx.x;
+    // cpb components per block as in k_plane_fwd; tid, nthr are the group's
+    const int nthr = blockDim.x / cpb, grp = threadIdx.x / nthr, tid = threadIdx.x - grp * nthr;
+    const bool live = (int)blockIdx.y * cpb + grp < P;
+    const int c = live ? (int)blockIdx.y * cpb + grp : P - 1;
+    cplx<T> *tw = (cplx<T> *)lds_raw;      // shared by the groups (each writes all of it)
+    cplx<T> *buf2 = tw + nf / 2 + grp * (nf * cws + npair * ls);   // [nf][cws]: kx columns k0 .. k0 + cw - 1
     cplx<T> *buf1 = buf2 + nf * cws;       // [npair][ls]
-    const int z = blockIdx.x, c = blockIdx.y;
-    const int tid = threadIdx.x, nthr = blockDim.x;
     // twiddle load in flight together with the spectrum's (nf/2 <= blockDim.x)
     const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];
     const cplx<T> *in = spec + ((int64_t)c * nout + z) * nf * nh;
@@ -218,7 +228,7 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
     }
     fft_lines<T, true>(buf1, logn, npair, ls, 1, tw, tid, nthr);
     T *plane = L + ((int64_t)c * nout + z) * nout * nout;
-    for (int idx = tid; idx < nout * nout; idx += nthr) {
+    for (int idx = tid; live && idx < nout * nout; idx += nthr) {
         const int y = idx / nout, x = idx - y * nout;
         const cplx<T> v = buf1[(y >> 1) * ls + x];
         plane[idx] = ((y & 1) ? v.im : v.re) * scale;
@@ -242,20 +252,27 @@ static hipError_t ensure_lds(Kern k, size_t bytes) {
 template <int PO, typename T>
 hipError_t column_launch(const FFTArgs &a, hipStream_t s);
 
-// Shape of a plane block: 256 threads; the y pass of a 128-point plane runs
-// in chunks of 16 kx columns (row stride 17 against bank conflicts), so that
-// a block needs 50 KB of LDS instead of 100 KB and three share a CU.
+// Shape of a plane block: 256 threads in cpb groups, one component each.
+// Small planes keep only a few lanes busy per FFT stage, so when there are
+// planes enough to fill the GPU (at least 1024 of them) a block takes 8
+// components up to 16 points, 4 at 32, 2 at 64; a launch with fewer planes is
+// latency-bound and keeps one component per block (shorter chains).  The y
+// pass of a 128-point plane runs in chunks of 16 kx columns (row stride 17
+// against bank conflicts), so that a block needs 50 KB of LDS instead of
+// 100 KB and three share a CU.
 struct PlaneShape {
-    int threads, cw, cws;
+    int threads, cw, cws, cpb;
     size_t lds;
 };
-static PlaneShape plane_shape(int n, int nf, size_t csz) {
+static PlaneShape plane_shape(int n, int nf, int P, int nsys, size_t csz) {
     const int nh = nf / 2 + 1;
     PlaneShape ps;
     ps.threads = 256;
+    ps.cpb = nf <= 16 ? 8 : (nf == 32 ? 4 : (nf == 64 ? 2 : 1));
+    if ((int64_t)n * P * nsys < 1024) ps.cpb = 1;
     ps.cw = nf >= 128 ? 16 : nh;
     ps.cws = ps.cw == nh ? nh : ps.cw + 1;
-    ps.lds = (size_t)(nf / 2 + (n / 2) * lds_line(nf) + nf * ps.cws) * csz;
+    ps.lds = (size_t)(nf / 2 + ps.cpb * ((n / 2) * lds_line(nf) + nf * ps.cws)) * csz;
     return ps;
 }
 
@@ -265,17 +282,18 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, n = a.n;
     const int nsys = a.nsys > 0 ? a.nsys : 1;
     const size_t csz = sizeof(cplx<T>);
-    const PlaneShape ps = plane_shape(n, nf, csz);
+    const PlaneShape ps = plane_shape(n, nf, P, nsys, csz);
     const size_t lds_plane = ps.lds;
     hipError_t e = hipSuccess;
     if (stage == 0) {
         e = ensure_lds(k_plane_fwd<T>, lds_plane);
         if (e != hipSuccess) return e;
-        // periodic: one extra row of blocks (c == P) sums q|u|^2 per plane
-        const int rows = a.open ? P : P + 1;
+        // periodic: one extra row of blocks sums q|u|^2 per plane
+        const int crows = (P + ps.cpb - 1) / ps.cpb;
+        const int rows = a.open ? crows : crows + 1;
         hipLaunchKernelGGL(k_plane_fwd<T>, dim3(n, rows, nsys), dim3(ps.threads), lds_plane, s, n,
                            logn, (const T *)a.M, (cplx<T> *)a.spec, (const cplx<T> *)a.tw, P,
-                           a.open ? nullptr : a.qr2_partial, ps.cw, ps.cws);
+                           a.open ? nullptr : a.qr2_partial, ps.cw, ps.cws, ps.cpb);
         return hipGetLastError();
     }
     if (stage == 1) {
@@ -295,9 +313,9 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     e = ensure_lds(k_plane_inv<T>, lds_plane);
     if (e != hipSuccess) return e;
     const T scale = T(1.0 / ((double)nf * nf * nf));
-    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, P, nsys), dim3(ps.threads), lds_plane, s, n, logn,
-                       (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw, scale, ps.cw,
-                       ps.cws);
+    hipLaunchKernelGGL(k_plane_inv<T>, dim3(n, (P + ps.cpb - 1) / ps.cpb, nsys), dim3(ps.threads),
+                       lds_plane, s, n, logn, (const cplx<T> *)a.spec, (T *)a.L,
+                       (const cplx<T> *)a.tw, scale, P, ps.cw, ps.cws, ps.cpb);
     return hipGetLastError();
 }
 
