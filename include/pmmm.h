@@ -67,7 +67,7 @@ typedef struct pmmm_plan_s *pmmm_plan;
 typedef struct pmmm_batch_s *pmmm_batch;
 
 /* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
- *   nx, ny, nz  cells per axis.  This build needs nx == ny == nz == n, a
+ *   nx, ny, nz  cells per axis.  The library needs nx == ny == nz == n, a
  *               power of two with n >= 4 and an FFT mesh nf (2n open, n
  *               periodic) of at most 128 (FP32) or 64 (FP64); other meshes
  *               return PMMM_EUNSUPPORTED.

@@ -171,13 +171,13 @@ static int validate(const pmmm_params *prm, std::string &why) {
         return PMMM_EINVAL;
     }
     if (prm->nx != prm->ny || prm->nx != prm->nz || !is_pow2(n) || n < 4) {
-        why = "this build needs a cubic power-of-two mesh with n >= 4";
+        why = "the library needs a cubic power-of-two mesh with n >= 4";
         return PMMM_EUNSUPPORTED;
     }
     const int nf = prm->boundary == PMMM_OPEN ? 2 * n : n;
     const int nfmax = prm->precision == PMMM_F64 ? 64 : 128;
     if (nf > nfmax) {
-        why = "FFT mesh too large for this build (FP32: nf <= 128, FP64: nf <= 64)";
+        why = "FFT mesh too large for the library (FP32: nf <= 128, FP64: nf <= 64)";
         return PMMM_EUNSUPPORTED;
     }
     // the column kernel keeps the spectra and kernel tile of at least one
