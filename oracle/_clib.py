@@ -23,6 +23,7 @@ def lib():
                                   ctypes.c_double, _D, _D]
         L.ora_green_periodic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_double, ctypes.c_int, _D]
+        L.ora_lower_gamma_half.argtypes = [ctypes.c_int, ctypes.c_double, _D]
         L.ora_direct.argtypes = [ctypes.c_int64, _D, _D, _D, _D]
         L.ora_ewald.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, _D]

@@ -103,6 +103,34 @@ static void inc_gamma_half(int lmax, double x, double *Qg) {
     }
 }
 
+/* Regularised lower incomplete gamma P(l + 1/2, x) = 1 - Q(l + 1/2, x) for
+ * l = 0..lmax.  Below x = a + 1 by its power series
+ *     P(a, x) = x^a e^{-x} sum_{k >= 0} x^k / Gamma(a + k + 1),
+ * which has no cancellation where P is small (near the origin and at high
+ * order); above it as 1 - Q from inc_gamma_half. */
+void ora_lower_gamma_half(int lmax, double x, double *P) {
+    double Qg[2 * ORA_LMAX + 2];
+    inc_gamma_half(lmax, x, Qg);
+    double gam1 = 0.5 * sqrt(M_PI);  /* Gamma(a + 1) for a = 1/2 */
+    double xa = sqrt(x);             /* x^a */
+    const double ex = exp(-x);
+    for (int l = 0; l <= lmax; ++l) {
+        const double a = l + 0.5;
+        if (x < a + 1.0) {
+            double term = xa * ex / gam1, sum = 0.0;
+            for (int k = 0; k < 400 && term > 1e-18 * sum; ++k) {
+                sum += term;
+                term *= x / (a + k + 1.0);
+            }
+            P[l] = sum;
+        } else {
+            P[l] = 1.0 - Qg[l];
+        }
+        xa *= x;
+        gam1 *= a + 1.0;
+    }
+}
+
 static inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
 
 /* Periodic transfer-kernel mesh on an n^3 cell mesh of a cubic box of edge
@@ -110,14 +138,16 @@ static inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
  * j < (lmax+1)^2, at the cell displacement delta = minimum image of
  * (ix, iy, iz), r = delta * h.
  *
- *   G(r) = sum_{|n| <= nimg} Q(l+1/2, a^2|r + b n|^2) S(r + b n)
+ *   G(r) = sum_{|r + b n| <= nimg b} Q(l+1/2, a^2|r + b n|^2) S(r + b n)
  *        + sum_{0 < |n| <= nimg} (-i pi)^l / sqrt(pi) exp(-(pi k/a)^2)
  *              / Gamma(l+1/2) k^{2l-1} / V S(k_n) exp(2 pi i k_n . r)
  *
  * with k_n = n / b.  At delta = 0 the singular n = 0 real-space term is
  * left out (its smooth part stays in the reciprocal sum; the l = 0 limit is
  * removed later by the self correction).  For 0 < max|delta| <= cutoff the
- * one image covered by the near field, S(r), is subtracted. */
+ * one image covered by the near field, S(r), is subtracted: its real-space
+ * term Q S(r) - S(r) is taken as -P(l+1/2, a^2 r^2) S(r), the same quantity
+ * without the cancellation of two nearly equal large values. */
 void ora_green_periodic(int n, double box, int lmax, int cutoff, double alpha, int nimg,
                         double *G) {
     init_fact();
@@ -182,15 +212,29 @@ void ora_green_periodic(int n, double box, int lmax, int cutoff, double alpha, i
         double sre[ORA_LMAX * (ORA_LMAX + 1)], sim[ORA_LMAX * (ORA_LMAX + 1)];
         double Qg[ORA_LMAX + 2];
         for (int u = 0; u < ntri; ++u) accre[u] = accim[u] = 0.0;
-        /* real-space images */
-        for (int a = -nimg; a <= nimg; ++a)
-            for (int b = -nimg; b <= nimg; ++b)
-                for (int c = -nimg; c <= nimg; ++c) {
-                    if (a * a + b * b + c * c > nimg * nimg) continue;
+        /* the near field covers the primary image of the near cells */
+        int cheb = abs(dx);
+        if (abs(dy) > cheb) cheb = abs(dy);
+        if (abs(dz) > cheb) cheb = abs(dz);
+        const int near = cheb > 0 && cheb <= cutoff;
+        /* real-space images: every r + n b within nimg b of the origin (a
+         * ball in distance, so the image sets of r and -r mirror each other
+         * and do not depend on which image of a half-box offset is r) */
+        const double rmax2 = (double)nimg * nimg * box * box;
+        for (int a = -nimg - 1; a <= nimg + 1; ++a)
+            for (int b = -nimg - 1; b <= nimg + 1; ++b)
+                for (int c = -nimg - 1; c <= nimg + 1; ++c) {
                     if (dx == 0 && dy == 0 && dz == 0 && a == 0 && b == 0 && c == 0) continue;
                     double vx = rx + a * box, vy = ry + b * box, vz = rz + c * box;
                     double r2 = vx * vx + vy * vy + vz * vz;
-                    inc_gamma_half(lmax, alpha * alpha * r2, Qg);
+                    if (r2 > rmax2) continue;
+                    if (near && a == 0 && b == 0 && c == 0) {
+                        /* Q S - S of the subtracted image = -P S */
+                        ora_lower_gamma_half(lmax, alpha * alpha * r2, Qg);
+                        for (int l = 0; l <= lmax; ++l) Qg[l] = -Qg[l];
+                    } else {
+                        inc_gamma_half(lmax, alpha * alpha * r2, Qg);
+                    }
                     ora_solid_S(lmax, vx, vy, vz, sre, sim);
                     for (int l = 0; l <= lmax; ++l)
                         for (int m = 0; m <= l; ++m) {
@@ -207,17 +251,6 @@ void ora_green_periodic(int n, double box, int lmax, int cutoff, double alpha, i
             for (int u = 0; u < ntri; ++u) {
                 accre[u] += kr[u] * c - ki[u] * s;
                 accim[u] += kr[u] * s + ki[u] * c;
-            }
-        }
-        /* the near field covers the primary image of the near cells */
-        int cheb = abs(dx);
-        if (abs(dy) > cheb) cheb = abs(dy);
-        if (abs(dz) > cheb) cheb = abs(dz);
-        if (cheb > 0 && cheb <= cutoff) {
-            ora_solid_S(lmax, rx, ry, rz, sre, sim);
-            for (int u = 0; u < ntri; ++u) {
-                accre[u] -= sre[u];
-                accim[u] -= sim[u];
             }
         }
         for (int l = 0; l <= lmax; ++l) {

@@ -42,7 +42,7 @@ class Config:
     box: float = 1.0       # box edge b
     cutoff: int = 2        # near cube half-width c (27 cells: 1, 125 cells: 2)
     alpha: float | None = None   # periodic splitting parameter (default 1.5/b)
-    images: int = 4        # periodic lattice-sum radius |n| <= images
+    images: int = 4        # lattice-sum radius: |r + n b| <= images b (real), |n| <= images (reciprocal)
 
     @property
     def h(self) -> float:
@@ -135,6 +135,14 @@ def green_periodic(cfg: Config):
     return G
 
 
+def lower_gamma_half(lmax: int, x: float):
+    """Regularised lower incomplete gamma P(l + 1/2, x) for l = 0..lmax (the
+    C series the periodic kernel uses for the subtracted near image)."""
+    out = np.zeros(lmax + 1)
+    _clib.lib().ora_lower_gamma_half(int(lmax), float(x), _clib.dptr(out))
+    return out
+
+
 def green(cfg: Config):
     return green_open(cfg) if cfg.boundary == "open" else green_periodic(cfg)
 
@@ -223,9 +231,11 @@ def periodic_corrections(L, M, qr2, cfg: Config):
     L = L.copy()
     V, a = cfg.V, cfg.a
     sM = M.reshape(M.shape[0], -1).sum(axis=1)
-    L[ridx(1, 0)] += 4 * pi / (3 * V) * sM[ridx(1, 0)]
-    L[ridx(1, 1)] += 8 * pi / (3 * V) * sM[ridx(1, 1)]
-    L[ridx(1, -1)] += -8 * pi / (3 * V) * sM[ridx(1, -1)]
+    if cfg.p >= 1:
+        # the dipole terms act on L_1^m, which a p = 0 expansion does not carry
+        L[ridx(1, 0)] += 4 * pi / (3 * V) * sM[ridx(1, 0)]
+        L[ridx(1, 1)] += 8 * pi / (3 * V) * sM[ridx(1, 1)]
+        L[ridx(1, -1)] += -8 * pi / (3 * V) * sM[ridx(1, -1)]
     L[ridx(0, 0)] += -(2 * a / sqrt(pi)) * M[ridx(0, 0)] + 2 * pi / (3 * V) * qr2.sum()
     return L, sM[ridx(0, 0)]
 

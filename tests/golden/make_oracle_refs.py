@@ -3,7 +3,9 @@ infrastructure).  Calls only the oracle and the seeded input generators.
 
 For each workload the oracle computes the moments from ALL particles and
 evaluates the far field on a seeded sample of 4096 particles; the sample
-indices and the values are stored in tests/golden/ref_<workload>.npz.
+indices and the values are stored in tests/golden/ref_<workload>.npz.  The
+ewald_* files hold the Ewald sum (exact periodic potential and gradient)
+of every particle of a workload on the same kind of sample.
 
     python tests/golden/make_oracle_refs.py [workload ...]
 """
@@ -24,6 +26,8 @@ from paper_1409_5981_amd import inputs  # noqa: E402
 
 SAMPLE = 4096
 JOBS = {
+    "periodic_n32768_m16_p5": inputs.periodic_pm1,
+    "open_n4096_m8_p4_f64": inputs.open_equal_mass,
     "periodic_n1048576_m32_p7": inputs.periodic_pm1_blocks,
     "open_plummer_n4194304_m64_p6": inputs.plummer_sphere,
 }
@@ -56,14 +60,38 @@ def make_multi(name: str) -> str:
     return path
 
 
+# Exact periodic references (Ewald, the oracle's O1) for the method error of
+# the total field: the 32768-particle workload and the first 32768-particle
+# block of the 2^20-particle workload taken as a system of its own.
+EWALD = {
+    "ewald_periodic_n32768": lambda: inputs.periodic_pm1(),
+    "ewald_periodic_slice_n32768": lambda: inputs.periodic_pm1_blocks().subset(np.arange(32768)),
+}
+
+
+def make_ewald(name: str) -> str:
+    from oracle import exact
+    t0 = time.time()
+    ps = EWALD[name]()
+    rng = np.random.Generator(np.random.PCG64(1234))
+    idx = np.sort(rng.choice(ps.n, size=SAMPLE, replace=False))
+    phi, grad = exact.ewald(ps.pos, ps.q.astype(np.float64), box=ps.box)
+    path = os.path.join(HERE, f"ref_{name}.npz")
+    np.savez_compressed(path, idx=idx, phi=phi[idx], grad=grad[idx], n=ps.n)
+    print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
+    return path
+
+
 def make(name: str) -> str:
     if name in MULTI:
         return make_multi(name)
+    if name in EWALD:
+        return make_ewald(name)
     t0 = time.time()
     ps = JOBS[name]()
     cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=2)
     rng = np.random.Generator(np.random.PCG64(1234))
-    idx = np.sort(rng.choice(ps.n, size=SAMPLE, replace=False))
+    idx = np.sort(rng.choice(ps.n, size=min(SAMPLE, ps.n), replace=False))
     res = opm.far_field(ps.pos, ps.q.astype(np.float64), cfg, eval_idx=idx)
     path = os.path.join(HERE, f"ref_{name}.npz")
     np.savez_compressed(path, idx=idx, phi=res.phi, grad=res.grad,
@@ -73,5 +101,5 @@ def make(name: str) -> str:
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or list(JOBS) + list(MULTI)):
+    for nm in (sys.argv[1:] or list(JOBS) + list(MULTI) + list(EWALD)):
         make(nm)

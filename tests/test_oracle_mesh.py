@@ -118,21 +118,25 @@ def test_open_cell_centres_exact(p):
     assert exact.rel_rms(far.grad, dg - ng) < 1e-13
 
 
-@pytest.mark.parametrize("boundary", ["open", "periodic"])
-def test_green_spectrum_parity(boundary):
-    """G(-d) = (-1)^k G(d) for order k, so the spectra of even orders are real
-    and those of odd orders imaginary (to rounding)."""
-    cfg = pmmm.Config(n=5 if boundary == "periodic" else 4, p=3, boundary=boundary,
-                      cutoff=2 if boundary == "periodic" else 1)
-    Gt = pmmm.spectra(pmmm.green(cfg))
+@pytest.mark.parametrize("boundary,n", [("open", 4), ("periodic", 5), ("periodic", 8)])
+def test_green_spectrum_parity(boundary, n):
+    """G(-d) = (-1)^k G(d) for order k on the whole mesh, the half-box
+    (Nyquist) offsets of an even periodic mesh included, so the spectra of
+    even orders are real and those of odd orders imaginary (to rounding)."""
+    cfg = pmmm.Config(n=n, p=3, boundary=boundary, cutoff=2 if boundary == "periodic" else 1)
+    G = pmmm.green(cfg)
+    nf = G.shape[1]
+    mirror = (-np.arange(nf)) % nf
+    Gt = pmmm.spectra(G)
     for k in range(2 * cfg.p + 1):
+        sl = slice(k * k, (k + 1) * (k + 1))
+        Gm = G[sl][:, mirror][:, :, mirror][:, :, :, mirror]
+        assert np.max(np.abs(Gm - (-1) ** k * G[sl])) <= 1e-14 * np.max(np.abs(G[sl])), k
         for j in range(-k, k + 1):
             c = Gt[ridx(k, j)]
             big = np.max(np.abs(c))
             bad = np.max(np.abs(c.imag)) if k % 2 == 0 else np.max(np.abs(c.real))
-            # periodic kernels subtract the large near image S(d h) from the
-            # lattice sum, so their rounding floor sits near 1e-12 of the max
-            assert bad <= (1e-13 if boundary == "open" else 1e-11) * big, (k, j)
+            assert bad <= 1e-14 * big, (k, j)
 
 
 def test_periodic_green_low_orders_match_ewald():
@@ -184,6 +188,42 @@ def test_periodic_green_high_orders_match_image_sum():
             for j in range(-k, k + 1):
                 scale = np.max(np.abs(G[ridx(k, -k):ridx(k, k) + 1, lin]))
                 assert abs(G[ridx(k, j), lin] - ref[ridx(k, j)]) < 1e-5 * scale, (lin, k, j)
+
+
+def test_lower_incomplete_gamma_matches_scipy():
+    """The series the periodic kernel uses for the subtracted near image,
+    P(l + 1/2, x) = 1 - Q(l + 1/2, x), against scipy's regularised lower
+    incomplete gamma over the orders and arguments the kernels reach (and
+    beyond), including x where P is far below the rounding of 1 - Q."""
+    from scipy.special import gammainc
+    for x in [1e-8, 1e-4, 0.01, 0.1, 0.42, 1.0, 1.7, 4.0, 9.0, 25.0, 60.0]:
+        P = pmmm.lower_gamma_half(20, x)
+        for l in range(21):
+            ref = gammainc(l + 0.5, x)
+            if ref < 1e-290:
+                assert P[l] < 1e-280
+                continue
+            assert abs(P[l] - ref) <= 1e-13 * ref, (x, l, P[l], ref)
+
+
+def test_periodic_green_near_image_term():
+    """Subtracting the near image (App. B): at an offset of Chebyshev
+    distance 2 the c = 2 kernel equals the c = 1 kernel, where that offset
+    is not near and nothing is subtracted, minus S(delta h).  The c = 2
+    kernel takes the primary image's real-space term as -P S; the reference
+    here subtracts S in full, so they agree to the rounding of S."""
+    c2 = pmmm.Config(n=8, p=5, boundary="periodic", cutoff=2)
+    c1 = pmmm.Config(n=8, p=5, boundary="periodic", cutoff=1)
+    G2 = pmmm.green_periodic(c2).reshape(nreal(10), -1)
+    G1 = pmmm.green_periodic(c1).reshape(nreal(10), -1)
+    n, h = c2.n, c2.h
+    for d in [(2, 0, 0), (2, 1, -1), (-2, 2, 2), (1, -2, 0)]:
+        ix, iy, iz = (v % n for v in d)
+        lin = (iz * n + iy) * n + ix
+        S = to_real(solid_S(10, np.array([d[0] * h]), np.array([d[1] * h]),
+                            np.array([d[2] * h]))[0], 10)
+        ref = G1[:, lin] - S
+        assert np.max(np.abs(G2[:, lin] - ref) / (np.abs(S) + np.abs(G1[:, lin]))) < 1e-14, d
 
 
 def test_periodic_green_alpha_and_images_independent():
