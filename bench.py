@@ -1,18 +1,22 @@
 #!/usr/bin/env python
 """Benchmark of the PMMM far field on one MI355X.
 
-Workload: periodic boundary, N = 32768 particles uniform in the unit cube
-with exactly neutral +/-1 charges, 16^3 cells, p = 5, cutoff c = 2, FP32
-(seeded synthetic data, see paper_1409_5981_amd.inputs).  One step is one
-pmmm_far_f32 call on inputs already resident in HBM: binning, P2M, forward
-FFTs, wave-space M2L (with the periodic corrections), inverse FFTs and L2P.  The
+Default workload (the largest single-GPU configuration): open boundary,
+N = 2^22 equal-mass particles from a Plummer sphere (scale radius 0.05,
+truncated to the unit cube), 64^3 cells (128^3 zero-padded FFT), p = 6,
+cutoff c = 2, FP32 (seeded synthetic data, see paper_1409_5981_amd.inputs).
+One step is one pmmm_far_f32 call on inputs already resident in HBM:
+binning, P2M, forward FFTs, wave-space M2L, inverse FFTs and L2P.  The
 transfer kernel is built once when the plan is created, outside the timed
 region (the paper precomputes it at the start of a simulation).
 
-Prints one JSON line (rank 0) with the throughput in particles/s, the
-roofline of the dominant kernel (its duration measured with HIP events on
-the library's stream over the timed region) and the FP64 CPU oracle timed
-on a bounded sample on this host.
+Prints one JSON line with the throughput in particles/s, the error of the
+timed result against the stored FP64 oracle sample (the line is marked
+failed, exit status 3, above the FP32 bound of 1e-6), the roofline of the
+dominant kernel on its algorithmic bytes (its duration measured with HIP
+events on the library's stream over the timed region), the roofline of the
+whole step, and the FP64 CPU oracle timed on a bounded sample on this
+host in a child process running beside the GPU measurement.
 """
 from __future__ import annotations
 
@@ -20,6 +24,8 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -34,33 +40,38 @@ FP64_PEAK = 78.6e12
 BF16_PEAK = 2.5e15           # FLOP/s, MI355X dense BF16 matrix cores
 MULTI_METRIC = ("particle x charge-set evaluations/s, PMMM far field of many charge sets "
                 "on one mesh (M2L on BF16 matrix cores, split operands)")
+ERR_BOUND = {"f32": 1e-6, "f64": 1e-12}
+DEFAULT_WORKLOAD = "open_plummer_n4194304_m64_p6"
 
 
-def stage_work(stage, N, n, p, nf, open_bc, tsize=4):
-    """Algorithmic HBM bytes and flops of one launch of a stage (each array
-    read or written once by the stage, no cache reuse assumed)."""
-    P, Q = (p + 1) ** 2, (2 * p + 1) ** 2
-    K = n ** 3
-    ncol = nf * (nf // 2 + 1)
-    F = ncol * nf
-    spec = n * ncol                  # complex values per component between kernels
-    c = 2 * tsize
-    lg = nf.bit_length() - 1
-    harm = 4 * (p + 1) * (p + 2)     # regular harmonics, per particle
+def algorithmic_work(stage, N, n, p, nf, tsize=4):
+    """Algorithmic HBM bytes and flops of one stage: what the method itself
+    must move, each array read or written once, no transfer-kernel symmetry
+    compression, stages unfused (F = nf^2 (nf/2+1) half-spectrum
+    frequencies, K = n^3 cells, P = (p+1)^2, Q = (2p+1)^2).  The library's
+    launches map onto the stages one to one: binning, P2M, the forward
+    plane FFTs, the column kernel (wave-space M2L; its z transforms are
+    counted with the FFT stages), the inverse plane FFTs and L2P."""
+    t = tsize
+    P, Q, K = (p + 1) ** 2, (2 * p + 1) ** 2, n ** 3
+    F = nf * nf * (nf // 2 + 1)
+    lg = 3 * (nf.bit_length() - 1)               # log2(nf^3)
+    harm = 4 * (p + 1) * (p + 2)
+    fft = 5 * P * nf ** 3 * lg // 2              # one direction, real-to-complex
     if stage == "bin":
-        return 4 * tsize * N * 2 + 4 * 4 * N + 3 * 4 * K, 10 * N
+        return 8 * t * N + 4 * N + 8 * K, 10 * N
     if stage == "p2m":
-        return 4 * tsize * N + tsize * (P + 1) * K, (harm + 2 * P + 6) * N
+        return 4 * t * N + t * P * K, (harm + 2 * P + 6 * p) * N
     if stage == "fft_fwd":
-        return tsize * P * K + c * P * spec, 5 * P * n * nf * (nf // 2 + 1) * 2 * lg
+        return t * P * K + 2 * t * P * F, fft
     if stage == "column":
-        nh = nf // 2 + 1
-        green = tsize * Q * nh * nh * ((nh + 3) & ~3)      # stored quadrant of the kernel
-        return 2 * c * P * spec + green, 4 * P * P * F + 2 * 5 * P * ncol * nf * lg
+        return 4 * t * P * F + t * Q * F, 4 * P * P * F
     if stage == "fft_inv":
-        return c * P * spec + tsize * P * K, 5 * P * n * nf * (nf // 2 + 1) * 2 * lg
+        return 2 * t * P * F + t * P * K, fft
     if stage == "l2p":
-        return tsize * P * K + 4 * tsize * N + 2 * 4 * N + 4 * tsize * N, (harm + 14 * P) * N
+        return t * P * K + 7 * t * N, (harm + 14 * P) * N
+    if stage == "near":
+        return 8 * t * N, 0
     raise KeyError(stage)
 
 
@@ -86,7 +97,7 @@ def multi_stage_work(stage, N, S, n, p, nprod):
     if stage == "column":
         rt, ks = -(-P // 16) * 16, -(-P // 32) * 32
         mfma = nprod * 2 * rt * ks * (-(-2 * S // 16) * 16) * F
-        return 2 * spec + 4 * Q * nh * nh * ((nh + 3) & ~3), 4 * P * P * S * F, mfma
+        return 2 * spec + 4 * Q * F, 4 * P * P * S * F, mfma
     if stage == "fft_inv":
         return spec + 4 * S * P * K, 5 * S * P * K * 2 * lg, 0
     if stage == "l2p":
@@ -117,52 +128,173 @@ def load_traffic(stage, workload, src_hash):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(ps, target_s, max_n=32768):
-    """The FP64 oracle's far field (P2M, FFT M2L, corrections, L2P) on the
-    workload's mesh and order, repeated for about target_s seconds.  Large
-    workloads use their first max_n particles as the sample.  The plan-time
-    transfer spectra are computed once beforehand and not timed."""
+def _roofline(t_k, bytes_k, flops_k, peak_flops, mfma_flops=0):
+    t_hbm = bytes_k / HBM_PEAK
+    t_alu = flops_k / peak_flops
+    t_mfma = mfma_flops / BF16_PEAK
+    if t_mfma > max(t_hbm, t_alu):
+        roof = {"bound": "mfma", "achieved": mfma_flops / t_k / 1e12, "peak": BF16_PEAK / 1e12,
+                "unit": "TFLOP/s"}
+    elif t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": bytes_k / t_k / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops_k / t_k / 1e12, "peak": peak_flops / 1e12,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    return roof
+
+
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+# ------------------------------------------------------------ CPU baseline
+def cpu_baseline_child(workload, n_sample):
+    """Runs in a child process.  The FP64 oracle's far field on the
+    workload, timed stage by stage: its particle stages (binning and P2M,
+    L2P) on a random sample of n_sample particles, scaled linearly to N, and
+    its mesh stage (forward FFTs, wave-space M2L, inverse FFTs) once on the
+    full mesh; the transfer spectra are computed beforehand and not timed.
+    Prints one JSON object."""
     import numpy as np
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import pmmm as opm
+    from paper_1409_5981_amd import inputs
+    ps = inputs.make_workload(workload)
     cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box)
+    t0 = time.perf_counter()
     Gt = opm.spectra(opm.green(cfg))
-    sub = ps if ps.n <= max_n else ps.subset(np.arange(max_n))
-    pos, q = sub.pos, sub.q.astype(np.float64)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        opm.far_field(pos, q, cfg, Gt=Gt)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or reps >= 1000:
-            break
-    what = "the same workload" if sub is ps else f"the first {sub.n} particles of the workload"
-    return {"value": sub.n * reps / el, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full far-field passes over {what} (N={sub.n}, "
-                      f"{ps.n_cells}^3 cells, p={ps.p}; FP64 numpy, single thread), {el:.1f} s; "
-                      "transfer spectra precomputed"}
+    t_green = time.perf_counter() - t0
+    rng = np.random.Generator(np.random.PCG64(99))
+    ns = min(n_sample, ps.n)
+    idx = np.sort(rng.choice(ps.n, size=ns, replace=False))
+    pos, q = ps.pos[idx], ps.q[idx].astype(np.float64)
+    t0 = time.perf_counter()
+    M, qr2 = opm.p2m_mesh(pos, q, cfg)
+    t_p2m = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L = opm.local_mesh(M, cfg, Gt)
+    if cfg.boundary == "periodic":
+        L, _ = opm.periodic_corrections(L, M, qr2, cfg)
+    t_mesh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    opm.l2p(L, pos, cfg)
+    t_l2p = time.perf_counter() - t0
+    scale = ps.n / ns
+    t_full = (t_p2m + t_l2p) * scale + t_mesh
+    model, ncpu = host_cpu()
+    if t_full < 5.0:
+        # small workload: whole far-field calls on all particles, repeated
+        pos, q = ps.pos, ps.q.astype(np.float64)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            opm.far_field(pos, q, cfg, Gt=Gt)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= 10.0 or reps >= 1000:
+                break
+        print(json.dumps({
+            "value": ps.n * reps / el, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle (numpy, single thread) on this host ({model}, {ncpu} logical "
+                       f"CPUs): {reps} whole far-field calls on all {ps.n} particles, {el:.1f} s; "
+                       f"transfer spectra precomputed ({t_green:.1f} s, not timed)"),
+        }), flush=True)
+        return
+    print(json.dumps({
+        "value": ps.n / t_full, "unit": "particles/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 oracle (numpy, single thread) on this host ({model}, {ncpu} logical CPUs): "
+                   f"binning+P2M and L2P on {ns} randomly sampled particles of the workload "
+                   f"({t_p2m:.1f} s + {t_l2p:.1f} s, scaled x{scale:.0f} to N={ps.n}), FFTs + "
+                   f"wave-space M2L + inverse FFTs once on the full {cfg.nf}^3 mesh "
+                   f"({t_mesh:.1f} s); estimated {t_full:.1f} s per far-field call; "
+                   f"transfer spectra precomputed ({t_green:.1f} s, not timed)"),
+        "stage_seconds": {"p2m_sample": t_p2m, "mesh": t_mesh, "l2p_sample": t_l2p,
+                          "green_untimed": t_green},
+    }), flush=True)
+
+
+def start_cpu_baseline(workload, n_sample):
+    code = (f"import sys; sys.path.insert(0, {ROOT!r}); import bench; "
+            f"bench.cpu_baseline_child({workload!r}, {int(n_sample)})")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    return subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE,
+                            stderr=subprocess.PIPE, text=True, env=env, cwd=ROOT)
+
+
+def finish_cpu_baseline(proc, timeout=600):
+    try:
+        out, err = proc.communicate(timeout=timeout)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        return None
+    if proc.returncode != 0:
+        print("cpu baseline failed: " + err[-2000:], file=sys.stderr)
+        return None
+    rec = json.loads(out.strip().splitlines()[-1])
+    rec.pop("stage_seconds", None)
+    return rec
+
+
+# ------------------------------------------------------------------- errors
+def golden_error(workload, outs, precision):
+    """Error of the GPU result against the stored FP64 oracle sample of the
+    workload (written by tests/golden/make_oracle_refs.py): relative RMS and
+    the maximum per-particle error |x - x_ref| / (|x_ref| + rms |x_ref|)."""
+    import numpy as np
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", f"ref_{workload}.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    idx = torch.from_numpy(ref["idx"]).to(outs[0].device)
+    phi = outs[0][idx].double().cpu().numpy()
+    grad = torch.stack([o[idx] for o in outs[1:]], 1).double().cpu().numpy()
+    res = {}
+    for name, x, r in (("grad", grad, ref["grad"]), ("phi", phi, ref["phi"])):
+        d = np.abs(x - r) if r.ndim == 1 else np.linalg.norm(x - r, axis=1)
+        mag = np.abs(r) if r.ndim == 1 else np.linalg.norm(r, axis=1)
+        rms = float(np.sqrt(np.mean(mag ** 2)))
+        res[f"rel_rms_{name}"] = float(np.sqrt(np.sum(d ** 2) / np.sum(mag ** 2)))
+        res[f"max_{name}"] = float(np.max(d / (mag + rms)))
+    res["sample"] = int(len(ref["idx"]))
+    res["bound"] = ERR_BOUND[precision]
+    res["ok"] = bool(res["rel_rms_grad"] <= res["bound"] and res["rel_rms_phi"] <= res["bound"])
+    return res
 
 
 WORKLOADS = {
-    # name: (generator, boundary, precision)
-    "periodic_n32768_m16_p5": ("periodic_pm1", "periodic", "f32"),
-    "open_n4096_m8_p4_f64": ("open_equal_mass", "open", "f64"),
-    "periodic_n1048576_m32_p7": ("periodic_pm1_blocks", "periodic", "f32"),
-    "open_plummer_n4194304_m64_p6": ("plummer_sphere", "open", "f32"),
-    "multi_periodic_n1048576_m32_p6_s64": ("multi_charge_sets", "periodic", "f32"),
-    "batch_periodic_256sys": ("batched_systems", "periodic", "f32"),
+    # name: (boundary, precision)
+    "open_plummer_n4194304_m64_p6": ("open", "f32"),
+    "periodic_n32768_m16_p5": ("periodic", "f32"),
+    "open_n4096_m8_p4_f64": ("open", "f64"),
+    "periodic_n1048576_m32_p7": ("periodic", "f32"),
+    "multi_periodic_n1048576_m32_p6_s64": ("periodic", "f32"),
+    "batch_periodic_256sys": ("periodic", "f32"),
 }
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16,
+                    help="particles of the oracle's particle stages in the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="periodic_n32768_m16_p5", choices=sorted(WORKLOADS),
-                    help="default: the headline workload; the others are the remaining "
-                         "single-GPU configurations")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS),
+                    help="default: the largest single-GPU configuration; the others are the "
+                         "remaining configurations")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the plan-time launch-shape autotuner (single-system workloads)")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -179,6 +311,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    workload = args.workload
+    single = not (workload.startswith("multi_") or workload.startswith("batch_"))
+    cpu_proc = None
+    if single and not args.no_cpu_baseline:
+        # the oracle runs on the host beside the GPU measurement
+        cpu_proc = start_cpu_baseline(workload, args.cpu_sample)
+
     import torch
     from paper_1409_5981_amd import inputs
     from paper_1409_5981_amd._lib import Plan, STAGES
@@ -190,13 +329,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    workload = args.workload
     if workload.startswith("multi_"):
         return bench_multi(args, workload)
     if workload.startswith("batch_"):
         return bench_batch(args, workload)
-    gen, boundary, prec = WORKLOADS[workload]
-    ps = getattr(inputs, gen)()
+    boundary, prec = WORKLOADS[workload]
+    ps = inputs.make_workload(workload)
     N, n, p = ps.n, ps.n_cells, ps.p
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -215,61 +353,71 @@ def main():
 
     # warm-up; the second half also times every stage to pick the dominant kernel
     half = max(1, args.warmup // 2)
-    for i in range(args.warmup):
+    far_stages = [s for s in STAGES if s != "near"]
+    for i in range(max(2, args.warmup)):
         if i == half:
-            plan.set_profiling(STAGES)
+            plan.set_profiling(far_stages)
         plan.far(x, y, z, q, out=out)
     torch.cuda.synchronize()
     prof = plan.read_profile(reset=True)
-    means = {st: (ms / c if c else 0.0) for st, (ms, c) in prof.items()}
+    means = {st: (ms / c if c else 0.0) for st, (ms, c) in prof.items() if st in far_stages}
     dominant = max(means, key=means.get)
-    print("stage means (ms): " + ", ".join(f"{k}={v*1e3:.1f}us" for k, v in means.items()),
+    print("stage means: " + ", ".join(f"{k}={v*1e3:.1f}us" for k, v in means.items()),
           file=sys.stderr)
 
-    # timed region: only the dominant stage carries events
+    # timed region: exactly K steps between two synchronisations; per-step
+    # events on the stream give the median, and only the dominant stage
+    # carries the library's stage events
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
     plan.set_profiling([dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for k in range(K):
         plan.far(x, y, z, q, out=out)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     plan.sync_status()
     prof = plan.read_profile(reset=True)
     plan.set_profiling([])
+    step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(K))
     ms_k, cnt = prof[dominant]
     t_k = ms_k / cnt / 1e3
+
+    err = golden_error(workload, out, prec)
 
     nf = 2 * n if boundary == "open" else n
     tsize = 4 if prec == "f32" else 8
     peak_alu = FP32_PEAK if prec == "f32" else FP64_PEAK
-    bytes_k, flops_k = stage_work(dominant, N, n, p, nf, boundary == "open", tsize)
-    t_hbm, t_alu = bytes_k / HBM_PEAK, flops_k / peak_alu
-    if t_hbm >= t_alu:
-        roof = {"bound": "hbm", "achieved": bytes_k / t_k / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": flops_k / t_k / 1e12, "peak": peak_alu / 1e12,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    bytes_k, flops_k = algorithmic_work(dominant, N, n, p, nf, tsize)
+    roof = _roofline(t_k, bytes_k, flops_k, peak_alu)
     roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash())
     roof["kernel"] = dominant
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
     roof["algorithmic_flops"] = flops_k
+    # whole step: sum over the stages of their roofline times, over the
+    # median step time
+    t_med = step_ms[len(step_ms) // 2] / 1e3
+    t_roof = sum(max(b / HBM_PEAK, f / peak_alu)
+                 for b, f in (algorithmic_work(s, N, n, p, nf, tsize) for s in far_stages))
+    step_roof = {"algorithmic_bytes": sum(algorithmic_work(s, N, n, p, nf, tsize)[0]
+                                          for s in far_stages),
+                 "roofline_time_us": t_roof * 1e6, "median_step_us": t_med * 1e6,
+                 "frac": t_roof / t_med}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ps, args.cpu_seconds)
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc is not None else None
 
     rec = {
         "metric": METRIC,
-        "value": N * args.steps / el,
+        "value": N * K / el,
         "unit": "particles/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": el / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -279,27 +427,18 @@ def main():
                    "cells": f"{n}^3", "fft_mesh": f"{nf}^3", "p": p, "cutoff": 2,
                    "tuning": {"column_width": tuning[0], "p2m_lanes": tuning[1]} if tuning else None,
                    "parallelism": "single GPU"},
+        "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],
+                    "max": step_ms[-1], "events": K},
+        "error": err,
         "roofline": roof,
+        "step_roofline": step_roof,
+        "stage_us": {k: v * 1e3 for k, v in means.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
-
-
-def _roofline(t_k, bytes_k, flops_k, peak_flops, mfma_flops=0):
-    t_hbm = bytes_k / HBM_PEAK
-    t_alu = flops_k / peak_flops
-    t_mfma = mfma_flops / BF16_PEAK
-    if t_mfma > max(t_hbm, t_alu):
-        roof = {"bound": "mfma", "achieved": mfma_flops / t_k / 1e12, "peak": BF16_PEAK / 1e12,
-                "unit": "TFLOP/s"}
-    elif t_hbm >= t_alu:
-        roof = {"bound": "hbm", "achieved": bytes_k / t_k / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": flops_k / t_k / 1e12, "peak": peak_flops / 1e12,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    return roof
+    if err is not None and not err["ok"]:
+        print("error above the bound: the line is not a valid measurement", file=sys.stderr)
+        sys.exit(3)
 
 
 def bench_multi(args, workload):
@@ -322,15 +461,16 @@ def bench_multi(args, workload):
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
     torch.cuda.set_stream(stream)
+    stages5 = [s for s in STAGES if s != "near"]
     warm = max(2, args.warmup)
     half = max(1, warm // 2)
     for i in range(warm):
         if i == half:
-            plan.set_profiling(STAGES)
+            plan.set_profiling(stages5)
         plan.far_multi(x, y, z, q, out=out)
     torch.cuda.synchronize()
     prof = plan.read_profile(reset=True)
-    means = {st: (ms / c if c else 0.0) for st, (ms, c) in prof.items()}
+    means = {st: (ms / c if c else 0.0) for st, (ms, c) in prof.items() if st in stages5}
     dominant = max(means, key=means.get)
     print("stage means: " + ", ".join(f"{k}={v*1e3:.1f}us" for k, v in means.items()),
           file=sys.stderr)
@@ -354,21 +494,30 @@ def bench_multi(args, workload):
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
     roof["algorithmic_flops"] = flops_k
-    # matrix-core share of the column stage (mean over the warm-up profile)
-    t_col = means.get("column", 0.0) / 1e3
-    col_bytes, col_flops, col_mfma = multi_stage_work("column", N, S, n, p, nprod)
-    stages = {st: {"us": means[st] * 1e3} for st in STAGES}
-    for st in STAGES:
+    stages = {st: {"us": means[st] * 1e3} for st in stages5}
+    for st in stages5:
         b_, f_, m_ = multi_stage_work(st, N, S, n, p, nprod)
         if means[st] > 0:
             stages[st]["hbm_frac"] = b_ / (means[st] / 1e3) / HBM_PEAK
             if m_:
                 stages[st]["mfma_frac"] = m_ / (means[st] / 1e3) / BF16_PEAK
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ps, args.cpu_seconds)
-        cpu["unit"] = "particle x charge-set evaluations/s"
-        cpu["sample"] += "; one charge set per pass"
+    # error of four sets on the stored oracle sample
+    err = None
+    path = os.path.join(ROOT, "tests", "golden", f"ref_{workload}.npz")
+    if os.path.exists(path) and args.split == "f32":
+        import numpy as np
+        ref = np.load(path)
+        idx = torch.from_numpy(ref["idx"]).to(dev)
+        worst = 0.0
+        for k, s in enumerate(ref["sets"]):
+            g = torch.stack([o[idx, int(s)] for o in out[1:]], 1).double().cpu().numpy()
+            ph = out[0][idx, int(s)].double().cpu().numpy()
+            eg = float(np.sqrt(np.sum((g - ref["grad"][k]) ** 2) / np.sum(ref["grad"][k] ** 2)))
+            ep = float(np.sqrt(np.sum((ph - ref["phi"][k]) ** 2) / np.sum(ref["phi"][k] ** 2)))
+            worst = max(worst, eg, ep)
+        err = {"worst_rel_rms": worst, "sets": [int(s) for s in ref["sets"]],
+               "sample": int(len(ref["idx"])), "bound": ERR_BOUND["f32"],
+               "ok": worst <= ERR_BOUND["f32"]}
     rec = {
         "metric": MULTI_METRIC,
         "value": N * S * args.steps / el,
@@ -386,9 +535,10 @@ def bench_multi(args, workload):
                    "charge_sets": S, "cells": f"{n}^3", "fft_mesh": f"{n}^3", "p": p,
                    "cutoff": 2, "m2l_products": nprod, "positions_per_s": N * args.steps / el,
                    "parallelism": "single GPU"},
+        "error": err,
         "roofline": roof,
         "stages": stages,
-        "cpu_baseline": cpu,
+        "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
 
@@ -397,7 +547,8 @@ def bench_batch(args, workload):
     """Batched workload: 256 independent periodic systems (N uniform in
     [2048, 65536], meshes 8^3/16^3/32^3, p in {4, 5, 6}, neutral +/-1); one
     step is one pmmm_batch_far_f32 call over all of them (graph replay after
-    the second call)."""
+    the second call).  The roofline sums the algorithmic bytes of every
+    stage of every system."""
     import numpy as np
     import torch
     from paper_1409_5981_amd import inputs
@@ -420,26 +571,38 @@ def bench_batch(args, workload):
     for _ in range(max(3, args.warmup)):
         batch.far(offs, x, y, z, q, out=out, stream=stream)
     torch.cuda.synchronize()
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for k in range(K):
         batch.far(offs, x, y, z, q, out=out, stream=stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     batch.sync_status()
-    cpu = None
-    if not args.no_cpu_baseline:
-        big = max(systems, key=lambda ps: ps.n)
-        cpu = cpu_baseline(big, args.cpu_seconds)
-        cpu["sample"] += "; the largest system of the batch"
+    step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(K))
+    t_med = step_ms[len(step_ms) // 2] / 1e3
+    stages = ["bin", "p2m", "fft_fwd", "column", "fft_inv", "l2p"]
+    tot_b = tot_t = 0.0
+    for ps in systems:
+        for st in stages:
+            b, f = algorithmic_work(st, ps.n, ps.n_cells, ps.p, ps.n_cells)
+            tot_b += b
+            tot_t += max(b / HBM_PEAK, f / FP32_PEAK)
+    roof = {"bound": "hbm", "achieved": tot_b / t_med / 1e9, "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s", "frac": tot_b / t_med / HBM_PEAK, "traffic": None,
+            "kernel": "whole batch call", "algorithmic_bytes": tot_b,
+            "roofline_time_us": tot_t * 1e6, "roofline_frac": tot_t / t_med}
     meshes = {m: sum(1 for ps in systems if ps.n_cells == m) for m in (8, 16, 32)}
     rec = {
         "metric": "particles/s over a batch of independent periodic systems, PMMM far field",
-        "value": N * args.steps / el,
+        "value": N * K / el,
         "unit": "particles/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": max(3, args.warmup),
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": el / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -448,8 +611,10 @@ def bench_batch(args, workload):
         "config": {"workload": workload, "systems": len(systems), "n_particles": N,
                    "classes": batch.classes, "meshes": meshes, "cutoff": 2,
                    "parallelism": "single GPU"},
-        "roofline": None,
-        "cpu_baseline": cpu,
+        "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],
+                    "max": step_ms[-1], "events": K},
+        "roofline": roof,
+        "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
 

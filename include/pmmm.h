@@ -8,7 +8,8 @@
  *             q_j / |r_i - r_j|      (periodic: over all images, Ewald sense)
  * and its gradient grad Phi_i, in the caller's input order (problem statement
  * of Sec. 1 and Sec. 2.1).  The near field (the masked cells, Sec. 2.1 last
- * paragraph) is NOT included; pmmm_near_* provides it for checking only.
+ * paragraph) is NOT included in pmmm_far_*; pmmm_near_* computes it and
+ * pmmm_total_* returns the sum of both.
  * Electrostatics: force_i = -q_i grad Phi_i.  Gravity: pass masses and take
  * Phi_grav = -G Phi, force_i = +G m_i grad Phi_i.
  *
@@ -21,11 +22,11 @@
  * Open boundaries convolve on the 2x zero-padded mesh (App. C); periodic
  * ones use the lattice-summed kernel of App. B (eq. greenPBC).  The
  * transfer-kernel spectra are built once, on the GPU in FP64, when the plan
- * is created (Sec. 2.1: "performed and saved at the beginning").
+ * is created and kept for every later call (Sec. 2.1).
  *
- * Memory and streams: every particle/output pointer passed to pmmm_far_*
- * and pmmm_near_* is a DEVICE pointer owned by the caller; calls only
- * enqueue work on the given HIP stream (hipStream_t passed as void*, NULL =
+ * Memory and streams: every particle/output pointer passed to pmmm_far_*,
+ * pmmm_near_* and pmmm_total_* is a DEVICE pointer owned by the caller;
+ * calls only enqueue work on the given HIP stream (hipStream_t passed as void*, NULL =
  * default stream) and return without synchronising.  Inputs must stay
  * alive and unmodified until the stream has completed the call.  The plan
  * owns the transfer kernel and its workspace (device memory); a plan may be
@@ -48,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PMMM_PMAX 8 /* highest expansion order compiled in */
+#define PMMM_PMAX 10 /* highest expansion order compiled in */
 
 enum {
     PMMM_OK = 0,
@@ -85,7 +86,8 @@ typedef struct pmmm_batch_s *pmmm_batch;
  *               terms (six products, FP32-level rounding).  pmmm_far_f32
  *               runs the same FP32 pipeline for both.
  *   alpha       periodic splitting parameter of the lattice sums; 0 -> 1.5/b.
- *   images      periodic lattice-sum radius |n| <= images; 0 -> 4.
+ *   images      periodic lattice-sum radius: real-space images r + n b with
+ *               |r + n b| <= images b, reciprocal vectors |n| <= images; 0 -> 4.
  *   n_max       particle capacity to allocate up front (0: grow on demand;
  *               growing synchronises the device once). */
 typedef struct {
@@ -142,7 +144,7 @@ int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
  * Sets are processed in chunks of at most 64; the plan grows its multi-set
  * workspace (about 16 P n^3 bytes per set of a chunk) on the first call that
  * needs it, which synchronises the device once.  nsets >= 1; n == 0 is a
- * valid no-op.  pmmm_near_* after this call uses zero charges. */
+ * valid no-op. */
 int pmmm_far_multi_f32(pmmm_plan plan, int64_t n, const float *x, const float *y,
                        const float *z, int nsets, const float *q, float *phi, float *gx,
                        float *gy, float *gz, void *stream);
@@ -175,15 +177,31 @@ int pmmm_batch_classes(pmmm_batch batch);
 int pmmm_batch_set_graphs(pmmm_batch batch, int enable);
 int pmmm_batch_sync_status(pmmm_batch batch);
 
-/* Near field for checking only (Sec. 2.1: direct particle-particle sums over
- * the masked (2c+1)^3 cells, no cutoff function).  Uses the binning (sorted
- * positions and charges) of the LAST pmmm_far_* call on this plan, which must
- * have been made with n particles on the same stream.  phi, gx, gy, gz: [n]
- * device outputs in input order; accumulate != 0 adds into them. */
-int pmmm_near_f32(pmmm_plan plan, int64_t n, float *phi, float *gx, float *gy, float *gz,
-                  int accumulate, void *stream);
-int pmmm_near_f64(pmmm_plan plan, int64_t n, double *phi, double *gx, double *gy, double *gz,
-                  int accumulate, void *stream);
+/* Near field (Sec. 2.1, last paragraph, and Sec. 2.3: the particles of the
+ * (2c+1)^3 cells masked out of the transfer kernel interact by direct
+ * Newtonian sums, no cutoff function; periodic meshes take, for each
+ * neighbour cell, the one image within c cells).  Same arguments, layouts,
+ * ownership and errors as pmmm_far_f32; the call bins the particles itself.
+ * accumulate != 0 adds the near field into phi, gx, gy, gz instead of
+ * overwriting them.  Two particles at the same position in neighbouring
+ * cells give an infinite result, as the sum itself does. */
+int pmmm_near_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
+                  const float *q, float *phi, float *gx, float *gy, float *gz, int accumulate,
+                  void *stream);
+int pmmm_near_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
+                  const double *z, const double *q, double *phi, double *gx, double *gy,
+                  double *gz, int accumulate, void *stream);
+
+/* Total potential and gradient, far field + near field (the split of eq. pmmm
+ * and Sec. 2.1: every pair of particles is counted once, by the near field
+ * when their cells are within c of each other, else by the far field), with
+ * one binning for both parts.  Arguments as pmmm_far_f32 / _f64; the
+ * outputs are overwritten. */
+int pmmm_total_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
+                   const float *q, float *phi, float *gx, float *gy, float *gz, void *stream);
+int pmmm_total_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
+                   const double *z, const double *q, double *phi, double *gx, double *gy,
+                   double *gz, void *stream);
 
 /* Launch-shape autotuner.  Runs the far field (pmmm_far_f32 or _f64 by the
  * plan's precision, same arguments and meaning) on the caller's particles,
@@ -234,7 +252,8 @@ enum {
     PMMM_STAGE_COLUMN = 3,  /* FFT along z + wave-space M2L + inverse FFT along z */
     PMMM_STAGE_FFT_INV = 4, /* inverse FFT along y and x, per z-plane */
     PMMM_STAGE_L2P = 5,     /* eq. L2P and the gradient */
-    PMMM_NSTAGES = 6
+    PMMM_STAGE_NEAR = 6,    /* near-field direct sums (pmmm_near_*, pmmm_total_*) */
+    PMMM_NSTAGES = 7
 };
 /* Bit s of `mask` brackets stage s of later pmmm_far_* calls on this plan with
  * a pair of HIP events recorded on the call's stream; 0 (the default) records

@@ -19,13 +19,13 @@ PMMM_OK, PMMM_EINVAL, PMMM_ENOMEM, PMMM_EHIP, PMMM_EDOMAIN, PMMM_EUNSUPPORTED = 
 PMMM_OPEN, PMMM_PERIODIC = 0, 1
 PMMM_F32, PMMM_F64, PMMM_BF16X3 = 0, 1, 2
 PMMM_MESH_M, PMMM_MESH_L, PMMM_MESH_GREEN = 0, 1, 2
-PMMM_PMAX = 8
+PMMM_PMAX = 10
 
 #: every symbol include/pmmm.h declares
 EXPORTS = [
     "pmmm_plan_create", "pmmm_plan_destroy", "pmmm_workspace_bytes",
     "pmmm_far_f32", "pmmm_far_f64", "pmmm_far_multi_f32",
-    "pmmm_near_f32", "pmmm_near_f64",
+    "pmmm_near_f32", "pmmm_near_f64", "pmmm_total_f32", "pmmm_total_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
     "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
     "pmmm_plan_autotune", "pmmm_plan_get_tuning",
@@ -34,7 +34,7 @@ EXPORTS = [
     "pmmm_error_string", "pmmm_last_error",
 ]
 
-STAGES = ["bin", "p2m", "fft_fwd", "column", "fft_inv", "l2p"]
+STAGES = ["bin", "p2m", "fft_fwd", "column", "fft_inv", "l2p", "near"]
 
 
 class Params(ctypes.Structure):
@@ -57,13 +57,22 @@ _lib = None
 
 
 def load():
-    """Load libpmmm.so and declare the prototypes (raises if missing)."""
+    """Load libpmmm.so and declare the prototypes (raises if missing).
+
+    torch is imported first: libpmmm.so needs libamdhip64.so.7, and when
+    torch's copy of the HIP runtime (same soname) is already mapped the
+    dynamic linker binds the library to it, so torch's streams and device
+    pointers and the library's calls share one HIP (and one HSA) runtime.
+    Loaded the other way round, the process would map two of each."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                           "(or python paper_1409_5981_amd/build.py) first")
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, ci, cz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
     L.pmmm_plan_create.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
@@ -80,7 +89,11 @@ def load():
     L.pmmm_far_multi_f32.restype = ci
     for name in ("pmmm_near_f32", "pmmm_near_f64"):
         f = getattr(L, name)
-        f.argtypes = [vp, i64, vp, vp, vp, vp, ci, vp]
+        f.argtypes = [vp, i64] + [vp] * 8 + [ci, vp]
+        f.restype = ci
+    for name in ("pmmm_total_f32", "pmmm_total_f64"):
+        f = getattr(L, name)
+        f.argtypes = [vp, i64] + [vp] * 8 + [vp]
         f.restype = ci
     L.pmmm_plan_sync_status.argtypes = [vp]
     L.pmmm_plan_sync_status.restype = ci
@@ -115,6 +128,34 @@ def load():
     L.pmmm_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+def check_buffers(ts, dtype, numel, shape=None, what="tensors", device=None):
+    """Validate caller buffers before any C call: every tensor must hold
+    exactly `numel` elements (and have `shape` when given), be of `dtype`,
+    contiguous, on a GPU, and all on one device.  A short output tensor would
+    otherwise let the kernels write past its end.  Raises ValueError."""
+    ts = tuple(ts)
+    if any(t is None for t in ts):
+        raise ValueError(f"{what}: None given")
+    for t in ts:
+        if t.numel() != numel or (shape is not None and tuple(t.shape) != tuple(shape)):
+            want = tuple(shape) if shape is not None else f"{numel} elements"
+            raise ValueError(f"{what}: expected {want}, got shape {tuple(t.shape)}")
+    for t in ts:
+        if t.dtype != dtype:
+            raise ValueError(f"{what}: expected dtype {dtype}, got {t.dtype}")
+    for t in ts:
+        if not t.is_contiguous():
+            raise ValueError(f"{what}: tensors must be contiguous")
+    dev = device
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError(f"{what}: tensors must be GPU (device) tensors")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{what}: all tensors must be on one device ({dev} and {t.device})")
 
 
 def _check(rc: int):
@@ -181,22 +222,53 @@ class Plan:
         except Exception:
             pass
 
-    def _check_tensors(self, *ts):
-        for t in ts:
-            if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous():
-                raise ValueError("tensors must be contiguous device tensors of the plan dtype")
+    def _inputs(self, x, y, z, q):
+        """Validate the particle arrays (same length, plan dtype, contiguous,
+        one GPU device); returns n."""
+        n = x.numel()
+        check_buffers((x, y, z, q), self.dtype, n, what="x, y, z, q")
+        return n
+
+    def _outputs(self, out, n, device, shape=None, zero=False):
+        import torch
+        shp = tuple(shape) if shape is not None else (n,)
+        if out is None:
+            mk = torch.zeros if zero else torch.empty
+            return tuple(mk(shp, dtype=self.dtype, device=device) for _ in range(4))
+        if len(out) != 4:
+            raise ValueError("out must hold four tensors (phi, gx, gy, gz)")
+        numel = 1
+        for d in shp:
+            numel *= d
+        check_buffers(out, self.dtype, numel, shape=shape, what="out", device=device)
+        return tuple(out)
 
     def far(self, x, y, z, q, out=None, stream=None):
         """Far-field Phi and grad Phi (input order) as four device tensors."""
-        import torch
-        self._check_tensors(x, y, z, q)
-        n = x.numel()
-        if not (y.numel() == z.numel() == q.numel() == n):
-            raise ValueError("x, y, z, q must have the same length")
-        if out is None:
-            out = tuple(torch.empty(n, dtype=self.dtype, device=x.device) for _ in range(4))
-        self._check_tensors(*out)
+        n = self._inputs(x, y, z, q)
+        out = self._outputs(out, n, x.device)
         fn = load().pmmm_far_f64 if self.precision == "f64" else load().pmmm_far_f32
+        _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                  *[o.data_ptr() for o in out], _stream_handle(stream)))
+        return out
+
+    def near(self, x, y, z, q, out=None, accumulate=False, stream=None):
+        """Near field (direct sums over the (2c+1)^3 cells around each
+        particle's cell); accumulate adds into `out`."""
+        n = self._inputs(x, y, z, q)
+        if accumulate and out is None:
+            raise ValueError("accumulate needs the output tensors")
+        out = self._outputs(out, n, x.device)
+        fn = load().pmmm_near_f64 if self.precision == "f64" else load().pmmm_near_f32
+        _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                  *[o.data_ptr() for o in out], int(bool(accumulate)), _stream_handle(stream)))
+        return out
+
+    def total(self, x, y, z, q, out=None, stream=None):
+        """Total Phi and grad Phi = far field + near field, one binning."""
+        n = self._inputs(x, y, z, q)
+        out = self._outputs(out, n, x.device)
+        fn = load().pmmm_total_f64 if self.precision == "f64" else load().pmmm_total_f32
         _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
                   *[o.data_ptr() for o in out], _stream_handle(stream)))
         return out
@@ -205,16 +277,14 @@ class Plan:
         """Far field of several charge sets on the same positions.  q is
         [n, nsets] (set index fastest); returns Phi, gx, gy, gz as [n, nsets]
         device tensors in input order."""
-        import torch
-        self._check_tensors(x, y, z, q)
         n = x.numel()
-        if q.dim() != 2 or q.shape[0] != n or not (y.numel() == z.numel() == n):
-            raise ValueError("x, y, z must have length n and q shape [n, nsets]")
+        check_buffers((x, y, z), self.dtype, n, what="x, y, z")
+        if q.dim() != 2 or q.shape[0] != n:
+            raise ValueError("q must have shape [n, nsets]")
         nsets = int(q.shape[1])
-        if out is None:
-            out = tuple(torch.empty(n, nsets, dtype=self.dtype, device=x.device)
-                        for _ in range(4))
-        self._check_tensors(*out)
+        check_buffers((q,), self.dtype, n * nsets, shape=(n, nsets), what="q",
+                      device=x.device)
+        out = self._outputs(out, n, x.device, shape=(n, nsets))
         _check(load().pmmm_far_multi_f32(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(),
                                          nsets, q.data_ptr(), *[o.data_ptr() for o in out],
                                          _stream_handle(stream)))
@@ -223,11 +293,8 @@ class Plan:
     def autotune(self, x, y, z, q, out=None, stream=None):
         """Time the candidate launch shapes on these particles and keep the
         fastest; returns (column width, P2M lanes per cell)."""
-        import torch
-        self._check_tensors(x, y, z, q)
-        n = x.numel()
-        if out is None:
-            out = tuple(torch.empty(n, dtype=self.dtype, device=x.device) for _ in range(4))
+        n = self._inputs(x, y, z, q)
+        out = self._outputs(out, n, x.device)
         _check(load().pmmm_plan_autotune(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(),
                                          q.data_ptr(), *[o.data_ptr() for o in out],
                                          _stream_handle(stream)))
@@ -237,16 +304,6 @@ class Plan:
         w, g = ctypes.c_int(), ctypes.c_int()
         _check(load().pmmm_plan_get_tuning(self._h, ctypes.byref(w), ctypes.byref(g)))
         return w.value, g.value
-
-    def near(self, n, out=None, accumulate=False, device="cuda", stream=None):
-        import torch
-        if out is None:
-            out = tuple(torch.zeros(n, dtype=self.dtype, device=device) for _ in range(4))
-        self._check_tensors(*out)
-        fn = load().pmmm_near_f64 if self.precision == "f64" else load().pmmm_near_f32
-        _check(fn(self._h, n, *[o.data_ptr() for o in out], int(bool(accumulate)),
-                  _stream_handle(stream)))
-        return out
 
     def set_profiling(self, stages):
         """Enable HIP-event timing for the named stages (see STAGES)."""
@@ -323,12 +380,16 @@ class Batch:
         offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         if offs.shape != (self.nsys + 1,):
             raise ValueError("offsets must have nsys + 1 entries")
+        if offs[0] != 0 or np.any(np.diff(offs) < 0):
+            raise ValueError("offsets must start at 0 and be non-decreasing")
         n = int(offs[-1])
-        for t in (x, y, z, q):
-            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
-                raise ValueError("x, y, z, q must be contiguous float32 device tensors of length offsets[-1]")
+        check_buffers((x, y, z, q), torch.float32, n, what="x, y, z, q")
         if out is None:
             out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(4))
+        else:
+            if len(out) != 4:
+                raise ValueError("out must hold four tensors (phi, gx, gy, gz)")
+            check_buffers(out, torch.float32, n, what="out", device=x.device)
         self._offs = offs
         _check(load().pmmm_batch_far_f32(self._h, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                          x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),

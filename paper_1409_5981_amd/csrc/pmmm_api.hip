@@ -62,10 +62,12 @@ struct Plan {
     void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
     int *count = nullptr, *start = nullptr, *dense_cells = nullptr, *small = nullptr;
     int *tile_sums = nullptr, *sstart = nullptr;
+    int *tile_first = nullptr;  // near field: first tile of every row of cells
     double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
     int64_t cap = 0, last_n = -1;
     int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr, *pos = nullptr;
+    int *tile_row = nullptr;    // near field: row of every tile
     void *sorted = nullptr, *staged = nullptr;   // staged: out4<T>[cap] sorted-order results
     hipStream_t last_stream = nullptr;
     // multi-charge workspace (chunks of up to kMultiMaxSets sets)
@@ -227,11 +229,13 @@ static size_t plan_bytes(const Plan *pl) {
     b += (KS + pl->K + 1 + pl->K + 8 + scan_tiles((int64_t)KS)) * sizeof(int);  // counts, starts, dense, small, tiles
     if (KS > (size_t)pl->K) b += (KS + 1) * sizeof(int);                         // sub-counter starts
     b += 8 * sizeof(double) + (size_t)pl->n * sizeof(double);                     // sums, plane sums
+    b += (size_t)pl->n * pl->n * sizeof(int);                                     // near-field row tiles
     return b;
 }
 
 static size_t particle_bytes(const Plan *pl, int64_t n) {
-    return (size_t)n * (5 * sizeof(int) + 8 * pl->tsize);
+    return (size_t)n * (5 * sizeof(int) + 8 * pl->tsize) +
+           sizeof(int) * (size_t)near_tile_capacity(n, pl->n);
 }
 
 static void free_particles(Plan *pl) {
@@ -242,7 +246,8 @@ static void free_particles(Plan *pl) {
     hipFree(pl->sorted);
     hipFree(pl->pos);
     hipFree(pl->staged);
-    pl->cell_of = pl->slot = pl->perm = pl->scell = pl->pos = nullptr;
+    hipFree(pl->tile_row);
+    pl->cell_of = pl->slot = pl->perm = pl->scell = pl->pos = pl->tile_row = nullptr;
     pl->sorted = pl->staged = nullptr;
     pl->cap = 0;
 }
@@ -262,6 +267,7 @@ static int ensure_capacity(Plan *pl, int64_t n) {
     PMMM_HIP(hipMalloc(&pl->sorted, 4 * pl->tsize * n));
     PMMM_HIP(hipMalloc(&pl->pos, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&pl->staged, 4 * pl->tsize * n));
+    PMMM_HIP(hipMalloc(&pl->tile_row, sizeof(int) * near_tile_capacity(n, pl->n)));
     pl->cap = n;
     return PMMM_OK;
 }
@@ -281,6 +287,7 @@ static void destroy(Plan *pl) {
     hipFree(pl->tile_sums);
     hipFree(pl->sstart);
     hipFree(pl->small);
+    hipFree(pl->tile_first);
     hipFree(pl->sums);
     hipFree(pl->qr2_partial);
     hipFree(pl->mM);
@@ -320,7 +327,8 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
     PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * scan_tiles(KS)));
     if (KS > pl->K) PMMM_HIP(hipMalloc(&pl->sstart, sizeof(int) * (KS + 1)));
-    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag
+    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] near tiles
+    PMMM_HIP(hipMalloc(&pl->tile_first, sizeof(int) * (size_t)pl->n * pl->n));
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
     PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
     PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * KS, s));
@@ -339,9 +347,14 @@ static int group_for(double mean) {
     return 64;
 }
 
+// What one call computes: the far field (pmmm_far_*), the near field alone
+// (pmmm_near_*) or both with one binning (pmmm_total_*).
+enum CallMode { kFar = 0, kNear = 1, kTotal = 2 };
+
 template <typename T>
-static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T *z, const T *q,
-                    T *phi, T *gx, T *gy, T *gz, void *stream) {
+static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, const T *y,
+                     const T *z, const T *q, T *phi, T *gx, T *gy, T *gz, int accumulate,
+                     void *stream) {
     if (!pl) {
         set_error("plan is NULL");
         return PMMM_EINVAL;
@@ -369,6 +382,9 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
     if (rc != PMMM_OK) return rc;
     pl->last_stream = s;
     pl->last_n = n;
+    // near and total calls, and large far-field calls, leave their results
+    // in sorted order (16-byte records) and send them back in one pass
+    const bool staged = mode != kFar || n >= kStagedL2PMinN;
 
     {
         StageTimer t(pl, PMMM_STAGE_BIN, s);
@@ -390,105 +406,99 @@ static int far_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T 
         b.flag = pl->small + 1;
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
-        b.pos = n >= kStagedL2PMinN ? pl->pos : nullptr;
+        b.pos = staged ? pl->pos : nullptr;
         b.tile_sums = pl->tile_sums;
         b.sstart = pl->sstart;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         PMMM_HIP(launch_bin<T>(b, s));
     }
-    {
-        StageTimer t(pl, PMMM_STAGE_P2M, s);
-        P2MArgs m{};
-        m.p = pl->p;
-        m.ncell = pl->n;
-        m.group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
-        m.dense_blocks = dense_blocks_for(n);
-        // meshes scanned inside the scatter kernel reset their counts here
-        m.zero_count = (n > 0 && pl->K <= 4096) ? pl->count : nullptr;
-        m.start = pl->start;
-        m.dense_cells = pl->dense_cells;
-        m.dense_count = pl->small;
-        m.dense_threshold = kDenseThreshold;
-        m.sorted = pl->sorted;
-        m.M = pl->M;
-        PMMM_HIP(launch_p2m<T>(m, s));
-    }
-    FFTArgs f{};
-    f.p = pl->p;
-    f.n = pl->n;
-    f.nf = pl->nf;
-    f.open = pl->open;
-    f.M = pl->M;
-    f.spec = pl->spec;
-    f.green = pl->green;
-    f.tw = pl->tw;
-    f.L = pl->L;
-    f.qr2_partial = pl->qr2_partial;
-    f.sums = pl->sums;
-    f.col_w = pl->tune_col_w;
-    for (int st = 0; st < 3; ++st) {
-        StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s);
-        PMMM_HIP(launch_conv_stage<T>(f, st, s));
-    }
-    {
-        StageTimer t(pl, PMMM_STAGE_L2P, s);
-        L2PArgs l{};
-        l.n = n;
-        l.p = pl->p;
-        l.ncell = pl->n;
-        l.periodic = !pl->open;
-        l.sorted = pl->sorted;
-        l.scell = pl->scell;
-        l.perm = pl->perm;
-        l.L = pl->L;
-        l.sums = pl->sums;
-        l.alpha_cell = pl->alpha_cell;
-        l.inv_h = pl->inv_h;
-        l.phi = phi;
-        l.gx = gx;
-        l.gy = gy;
-        if (n >= kStagedL2PMinN) {
-            l.staged = pl->staged;
-            l.pos = pl->pos;
+    if (mode != kNear) {
+        {
+            StageTimer t(pl, PMMM_STAGE_P2M, s);
+            P2MArgs m{};
+            m.p = pl->p;
+            m.ncell = pl->n;
+            m.group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
+            m.dense_blocks = dense_blocks_for(n);
+            // meshes scanned inside the scatter kernel reset their counts here
+            m.zero_count = (n > 0 && pl->K <= 4096) ? pl->count : nullptr;
+            m.start = pl->start;
+            m.dense_cells = pl->dense_cells;
+            m.dense_count = pl->small;
+            m.dense_threshold = kDenseThreshold;
+            m.sorted = pl->sorted;
+            m.M = pl->M;
+            PMMM_HIP(launch_p2m<T>(m, s));
         }
-        l.gz = gz;
-        PMMM_HIP(launch_l2p<T>(l, s));
+        FFTArgs f{};
+        f.p = pl->p;
+        f.n = pl->n;
+        f.nf = pl->nf;
+        f.open = pl->open;
+        f.M = pl->M;
+        f.spec = pl->spec;
+        f.green = pl->green;
+        f.tw = pl->tw;
+        f.L = pl->L;
+        f.qr2_partial = pl->qr2_partial;
+        f.sums = pl->sums;
+        f.col_w = pl->tune_col_w;
+        for (int st = 0; st < 3; ++st) {
+            StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s);
+            PMMM_HIP(launch_conv_stage<T>(f, st, s));
+        }
+        {
+            StageTimer t(pl, PMMM_STAGE_L2P, s);
+            L2PArgs l{};
+            l.n = n;
+            l.p = pl->p;
+            l.ncell = pl->n;
+            l.periodic = !pl->open;
+            l.sorted = pl->sorted;
+            l.scell = pl->scell;
+            l.perm = pl->perm;
+            l.L = pl->L;
+            l.sums = pl->sums;
+            l.alpha_cell = pl->alpha_cell;
+            l.inv_h = pl->inv_h;
+            l.phi = phi;
+            l.gx = gx;
+            l.gy = gy;
+            l.gz = gz;
+            if (staged) {
+                l.staged = pl->staged;
+                l.pos = pl->pos;
+            }
+            PMMM_HIP(launch_l2p<T>(l, s));
+            if (mode == kFar && staged)
+                PMMM_HIP(launch_unpermute<T>(n, pl->pos, pl->staged, phi, gx, gy, gz, 0, s));
+        }
+    } else if (n > 0 && pl->K <= 4096) {
+        // no P2M to reset the counts of an in-block-scanned mesh (a fill
+        // kernel, not a memset node, so that the call can be graph-captured)
+        PMMM_HIP(launch_zero_ints(pl->count, pl->K, s));
     }
-    return PMMM_OK;
-}
-
-template <typename T>
-static int near_impl(pmmm_plan_s *pl, int64_t n, T *phi, T *gx, T *gy, T *gz, int accumulate,
-                     void *stream) {
-    if (!pl || sizeof(T) != pl->tsize) {
-        set_error("invalid plan or precision");
-        return PMMM_EINVAL;
+    if (mode != kFar) {
+        StageTimer t(pl, PMMM_STAGE_NEAR, s);
+        NearArgs a{};
+        a.n = n;
+        a.ncell = pl->n;
+        a.cutoff = pl->cutoff;
+        a.periodic = !pl->open;
+        a.accumulate = mode == kTotal ? 1 : 0;
+        a.start = pl->start;
+        a.scell = pl->scell;
+        a.sorted = pl->sorted;
+        a.inv_h = pl->inv_h;
+        a.tile_first = pl->tile_first;
+        a.tile_row = pl->tile_row;
+        a.ntiles = pl->small + 2;
+        a.staged = pl->staged;
+        PMMM_HIP(launch_near<T>(a, s));
+        PMMM_HIP(launch_unpermute<T>(n, pl->pos, pl->staged, phi, gx, gy, gz,
+                                     mode == kNear ? accumulate : 0, s));
     }
-    if (n != pl->last_n) {
-        set_error("n differs from the last far-field call on this plan");
-        return PMMM_EINVAL;
-    }
-    if (n > 0 && (!phi || !gx || !gy || !gz)) {
-        set_error("NULL output pointer");
-        return PMMM_EINVAL;
-    }
-    NearArgs a{};
-    a.n = n;
-    a.ncell = pl->n;
-    a.cutoff = pl->cutoff;
-    a.periodic = !pl->open;
-    a.accumulate = accumulate;
-    a.start = pl->start;
-    a.scell = pl->scell;
-    a.perm = pl->perm;
-    a.sorted = pl->sorted;
-    a.inv_h = pl->inv_h;
-    a.phi = phi;
-    a.gx = gx;
-    a.gy = gy;
-    a.gz = gz;
-    PMMM_HIP(launch_near<T>(a, (hipStream_t)stream));
     return PMMM_OK;
 }
 
@@ -542,7 +552,7 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
     }
     if (pl->open || !multi_supported(pl->p, pl->nf)) {
         set_error("multi-charge calls are built for periodic meshes of 4, 8, 16 or 32 cells "
-                  "per axis (p <= 7 at 32)");
+                  "per axis and orders p <= 8");
         return PMMM_EUNSUPPORTED;
     }
     const int split = pl->prec == PMMM_BF16X3 ? 2 : 3;
@@ -629,10 +639,10 @@ template <typename T>
 static int time_stage(pmmm_plan_s *pl, int stage, int reps, int64_t n, const T *x, const T *y,
                       const T *z, const T *q, T *phi, T *gx, T *gy, T *gz, hipStream_t s,
                       float *best_ms) {
-    int rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
+    int rc = call_impl<T>(pl, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, s);
     pl->prof_mask = 1u << stage;
     for (int it = 0; it < reps && rc == PMMM_OK; ++it)
-        rc = far_impl<T>(pl, n, x, y, z, q, phi, gx, gy, gz, s);
+        rc = call_impl<T>(pl, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, s);
     pl->prof_mask = 0;
     float mn = 1e30f;
     for (auto &pr : pl->ev_pending[stage]) {
@@ -1047,13 +1057,24 @@ size_t pmmm_workspace_bytes(const pmmm_params *params, int64_t n_max) {
 
 int pmmm_far_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
                  const float *q, float *phi, float *gx, float *gy, float *gz, void *stream) {
-    return far_impl<float>(plan, n, x, y, z, q, phi, gx, gy, gz, stream);
+    return call_impl<float>(plan, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
 }
 
 int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y, const double *z,
                  const double *q, double *phi, double *gx, double *gy, double *gz,
                  void *stream) {
-    return far_impl<double>(plan, n, x, y, z, q, phi, gx, gy, gz, stream);
+    return call_impl<double>(plan, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+}
+
+int pmmm_total_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
+                   const float *q, float *phi, float *gx, float *gy, float *gz, void *stream) {
+    return call_impl<float>(plan, kTotal, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+}
+
+int pmmm_total_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
+                   const double *z, const double *q, double *phi, double *gx, double *gy,
+                   double *gz, void *stream) {
+    return call_impl<double>(plan, kTotal, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
 }
 
 int pmmm_far_multi_f32(pmmm_plan plan, int64_t n, const float *x, const float *y,
@@ -1062,14 +1083,16 @@ int pmmm_far_multi_f32(pmmm_plan plan, int64_t n, const float *x, const float *y
     return multi_impl(plan, n, x, y, z, nsets, q, phi, gx, gy, gz, stream);
 }
 
-int pmmm_near_f32(pmmm_plan plan, int64_t n, float *phi, float *gx, float *gy, float *gz,
-                  int accumulate, void *stream) {
-    return near_impl<float>(plan, n, phi, gx, gy, gz, accumulate, stream);
+int pmmm_near_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
+                  const float *q, float *phi, float *gx, float *gy, float *gz, int accumulate,
+                  void *stream) {
+    return call_impl<float>(plan, kNear, n, x, y, z, q, phi, gx, gy, gz, accumulate, stream);
 }
 
-int pmmm_near_f64(pmmm_plan plan, int64_t n, double *phi, double *gx, double *gy, double *gz,
-                  int accumulate, void *stream) {
-    return near_impl<double>(plan, n, phi, gx, gy, gz, accumulate, stream);
+int pmmm_near_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
+                  const double *z, const double *q, double *phi, double *gx, double *gy,
+                  double *gz, int accumulate, void *stream) {
+    return call_impl<double>(plan, kNear, n, x, y, z, q, phi, gx, gy, gz, accumulate, stream);
 }
 
 int pmmm_batch_create(int nsys, const pmmm_params *per_sys, void *stream, pmmm_batch *out) {

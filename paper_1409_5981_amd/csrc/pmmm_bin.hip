@@ -1,5 +1,5 @@
-// Cell binning (Sec. 2.1: "for each cell, the set of particles inside is
-// known ... achieved in an O(N) procedure"): a counting sort by cell.
+// Cell binning (Sec. 2.1 requires that the particles of every cell be known,
+// which takes linear time): a counting sort by cell.
 //   k_bin_count   cell of each particle, per-cell counts (int atomics) and the
 //                 particle's slot inside its cell; meshes above 16^3 count
 //                 in S sub-counters per cell (particle i in sub-counter

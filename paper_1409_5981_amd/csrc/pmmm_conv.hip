@@ -307,6 +307,8 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
             case 6: return column_launch<6, T>(a, s);
             case 7: return column_launch<7, T>(a, s);
             case 8: return column_launch<8, T>(a, s);
+            case 9: return column_launch<9, T>(a, s);
+            case 10: return column_launch<10, T>(a, s);
             default: return hipErrorInvalidValue;
         }
     }

@@ -10,7 +10,8 @@
 //                     gamma weighted real-space image sum plus the reciprocal
 //                     sum; at offset 0 the singular n = 0 real-space term is
 //                     left out; for 0 < max|offset| <= c the image covered by
-//                     the near field, S(offset), is subtracted (App. B).
+//                     the near field, S(offset), is subtracted (App. B), as
+//                     -P(l + 1/2, alpha^2 r^2) S in place of Q S - S.
 //   k_line_fft        FP64 complex FFT of mesh lines (LDS, radix 2)
 //   k_fold            keeps Re G~ (even order) or Im G~ (odd order) on the
 //                     quadrant ky, kz <= nf/2, rounded to the plan precision
@@ -127,6 +128,42 @@ __global__ void k_green_recip(int nk, const int *__restrict__ kvec, double box, 
     }
 }
 
+// Regularised incomplete gammas of half-integer order for l = 0..lmax at x:
+// upper Q(l + 1/2, x) by Q(1/2, x) = erfc(sqrt x), Q(a + 1) = Q(a) +
+// x^a e^-x / Gamma(a + 1); with `lower`, minus the lower one, -P(l + 1/2, x),
+// by its power series x^a e^-x sum_k x^k / Gamma(a + k + 1) where x < a + 1
+// (no cancellation where P is small) and as Q - 1 above.
+__device__ void inc_gamma_half_dev(int lmax, double x, bool lower, double *out) {
+    const double pi = 3.14159265358979323846;
+    const double sx = sqrt(x), ex = exp(-x);
+    out[0] = erfc(sx);
+    {
+        double xa = sx, g1 = 0.5 * sqrt(pi);  // x^(1/2), Gamma(3/2)
+        for (int l = 0; l < lmax; ++l) {
+            out[l + 1] = out[l] + xa * ex / g1;
+            xa *= x;
+            g1 *= (l + 1.5);
+        }
+    }
+    if (!lower) return;
+    double xa = sx, g1 = 0.5 * sqrt(pi);      // x^a, Gamma(a + 1) for a = 1/2
+    for (int l = 0; l <= lmax; ++l) {
+        const double a = l + 0.5;
+        if (x < a + 1.0) {
+            double term = xa * ex / g1, sum = 0.0;
+            for (int k = 0; k < 400 && term > 1e-18 * sum; ++k) {
+                sum += term;
+                term *= x / (a + k + 1.0);
+            }
+            out[l] = -sum;
+        } else {
+            out[l] = out[l] - 1.0;
+        }
+        xa *= x;
+        g1 *= a + 1.0;
+    }
+}
+
 __global__ void k_green_periodic(int n, int lmax, int cutoff, double alpha, int images, int nk,
                                  const int *__restrict__ kvec,
                                  const double *__restrict__ table, double *__restrict__ G) {
@@ -143,22 +180,25 @@ __global__ void k_green_periodic(int n, int lmax, int cutoff, double alpha, int 
     double are[kMaxTri], aim[kMaxTri], sre[kMaxTri], sim[kMaxTri], Qg[kMaxL + 2];
     for (int u = 0; u < ntri; ++u) are[u] = aim[u] = 0.0;
     const bool origin = dx == 0 && dy == 0 && dz == 0;
-    for (int a = -images; a <= images; ++a)
-        for (int b = -images; b <= images; ++b)
-            for (int c = -images; c <= images; ++c) {
-                if (a * a + b * b + c * c > images * images) continue;
+    // the near field covers the primary image of the near cells: that
+    // image's real-space term Q S - S is taken as -P S (same value, no
+    // cancellation of two nearly equal large terms)
+    int cheb = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+    cheb = cheb > abs(dz) ? cheb : abs(dz);
+    const bool near = cheb > 0 && cheb <= cutoff;
+    // real-space images: every offset + n b within `images` box lengths of
+    // the origin (a ball in distance: the image sets of d and -d mirror each
+    // other, whichever image of a half-box offset d is)
+    const double rmax2 = (double)images * images * box * box;
+    for (int a = -images - 1; a <= images + 1; ++a)
+        for (int b = -images - 1; b <= images + 1; ++b)
+            for (int c = -images - 1; c <= images + 1; ++c) {
                 if (origin && a == 0 && b == 0 && c == 0) continue;
                 const double vx = dx + a * box, vy = dy + b * box, vz = dz + c * box;
-                const double x = alpha * alpha * (vx * vx + vy * vy + vz * vz);
-                // Q(l + 1/2, x): Q(1/2, x) = erfc(sqrt x), Q(a+1) = Q(a) + x^a e^-x / Gamma(a+1)
-                const double sx = sqrt(x), ex = exp(-x);
-                Qg[0] = erfc(sx);
-                double xa = sx, g1 = 0.5 * sqrt(pi);  // x^(1/2), Gamma(3/2)
-                for (int l = 0; l < lmax; ++l) {
-                    Qg[l + 1] = Qg[l] + xa * ex / g1;
-                    xa *= x;
-                    g1 *= (l + 1.5);
-                }
+                const double r2 = vx * vx + vy * vy + vz * vz;
+                if (r2 > rmax2) continue;
+                const double x = alpha * alpha * r2;
+                inc_gamma_half_dev(lmax, x, near && a == 0 && b == 0 && c == 0, Qg);
                 singular_tri(lmax, vx, vy, vz, sre, sim);
                 for (int l = 0; l <= lmax; ++l)
                     for (int m = 0; m <= l; ++m) {
@@ -175,15 +215,6 @@ __global__ void k_green_periodic(int n, int lmax, int cutoff, double alpha, int 
         for (int u = 0; u < ntri; ++u) {
             are[u] += row[2 * u] * c - row[2 * u + 1] * s;
             aim[u] += row[2 * u] * s + row[2 * u + 1] * c;
-        }
-    }
-    int cheb = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
-    cheb = cheb > abs(dz) ? cheb : abs(dz);
-    if (cheb > 0 && cheb <= cutoff) {
-        singular_tri(lmax, (double)dx, (double)dy, (double)dz, sre, sim);
-        for (int u = 0; u < ntri; ++u) {
-            are[u] -= sre[u];
-            aim[u] -= sim[u];
         }
     }
     for (int l = 0; l <= lmax; ++l) {

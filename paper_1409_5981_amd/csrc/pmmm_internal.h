@@ -520,16 +520,28 @@ struct L2PArgs {
 template <typename T>
 hipError_t launch_l2p(const L2PArgs &a, hipStream_t s);
 
+// Sorted-order results back to the caller's order (out[i] = or +=
+// staged[pos[i]]).
+template <typename T>
+hipError_t launch_unpermute(int64_t n, const int *pos, const void *staged, void *phi, void *gx,
+                            void *gy, void *gz, int accumulate, hipStream_t s);
+
 struct NearArgs {
     int64_t n;
-    int ncell, cutoff, periodic, accumulate;
-    const int *start, *scell, *perm;
+    int ncell, cutoff, periodic;
+    int accumulate;                 // add into staged (a far field already there) or store
+    const int *start, *scell;
     const void *sorted;
     double inv_h;
-    void *phi, *gx, *gy, *gz;
+    int *tile_first, *tile_row, *ntiles;  // [ncell^2], [near_tile_capacity], [1] scratch
+    void *staged;                   // out4<T>[n] sorted-order results
 };
 template <typename T>
 hipError_t launch_near(const NearArgs &a, hipStream_t s);
+// Upper bound of the near-field tiles of n particles on ncell^3 cells.
+int64_t near_tile_capacity(int64_t n, int ncell);
+// p[0 .. count) = 0 with a fill kernel.
+hipError_t launch_zero_ints(int *p, int64_t count, hipStream_t s);
 
 // Plan-time transfer kernel (FP64 on the GPU), stored in precision T.
 struct GreenArgs {
@@ -546,6 +558,7 @@ hipError_t build_green(const GreenArgs &a, hipStream_t s);
 // per set) and the FFT kernels (tiles of consecutive components) both make
 // contiguous accesses.
 constexpr int kMultiMaxSets = 64;
+constexpr int kMultiPMax = 8;         // highest order of the multi-charge kernels
 constexpr int kMultiSetTile = 8;       // sets per column-GEMM block
 constexpr int kMultiCompTile = 16;     // components per plane-FFT block
 

@@ -748,7 +748,7 @@ void build_multi_map(int p, unsigned *out) {
 
 bool multi_supported(int p, int nf) {
     if (nf != 4 && nf != 8 && nf != 16 && nf != 32) return false;
-    return p >= 0 && p <= PMMM_PMAX;
+    return p >= 0 && p <= kMultiPMax;
 }
 
 template <typename Kern>

@@ -218,16 +218,24 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_unpermute(int64_t n, const int *__restrict__ pos,
                                                    const out4<T> *__restrict__ staged,
                                                    T *__restrict__ phi_out, T *__restrict__ gx_out,
-                                                   T *__restrict__ gy_out, T *__restrict__ gz_out) {
+                                                   T *__restrict__ gy_out, T *__restrict__ gz_out,
+                                                   int accumulate) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int g = pos[i];
     if (g < 0 || (int64_t)g >= n) return;  // only reachable with inconsistent counts
     const out4<T> v = staged[g];
-    phi_out[i] = v.phi;
-    gx_out[i] = v.gx;
-    gy_out[i] = v.gy;
-    gz_out[i] = v.gz;
+    if (accumulate) {
+        phi_out[i] += v.phi;
+        gx_out[i] += v.gx;
+        gy_out[i] += v.gy;
+        gz_out[i] += v.gz;
+    } else {
+        phi_out[i] = v.phi;
+        gx_out[i] = v.gx;
+        gy_out[i] = v.gy;
+        gz_out[i] = v.gz;
+    }
 }
 
 // ------------------------------------------------------------- launchers
@@ -273,6 +281,8 @@ hipError_t launch_p2m(const P2MArgs &a, hipStream_t s) {
         case 6: return p2m_dispatch_g<6, T>(a, s);
         case 7: return p2m_dispatch_g<7, T>(a, s);
         case 8: return p2m_dispatch_g<8, T>(a, s);
+        case 9: return p2m_dispatch_g<9, T>(a, s);
+        case 10: return p2m_dispatch_g<10, T>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -287,12 +297,17 @@ static hipError_t l2p_launch(const L2PArgs &a, hipStream_t s) {
                        (const particle4<T> *)a.sorted, a.scell, a.perm, (const T *)a.L,
                        a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
                        (T *)a.gx, (T *)a.gy, (T *)a.gz, (out4<T> *)a.staged, a.prange);
-    if (a.staged != nullptr) {
-        if (a.prange != nullptr || a.pos == nullptr) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_unpermute<T>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s,
-                           a.n, a.pos, (const out4<T> *)a.staged, (T *)a.phi, (T *)a.gx,
-                           (T *)a.gy, (T *)a.gz);
-    }
+    if (a.staged != nullptr && a.prange != nullptr) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_unpermute(int64_t n, const int *pos, const void *staged, void *phi, void *gx,
+                            void *gy, void *gz, int accumulate, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (pos == nullptr || staged == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_unpermute<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pos,
+                       (const out4<T> *)staged, (T *)phi, (T *)gx, (T *)gy, (T *)gz, accumulate);
     return hipGetLastError();
 }
 
@@ -309,6 +324,8 @@ hipError_t launch_l2p(const L2PArgs &a, hipStream_t s) {
         case 6: return l2p_launch<6, T>(a, s);
         case 7: return l2p_launch<7, T>(a, s);
         case 8: return l2p_launch<8, T>(a, s);
+        case 9: return l2p_launch<9, T>(a, s);
+        case 10: return l2p_launch<10, T>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -317,5 +334,9 @@ template hipError_t launch_p2m<float>(const P2MArgs &, hipStream_t);
 template hipError_t launch_p2m<double>(const P2MArgs &, hipStream_t);
 template hipError_t launch_l2p<float>(const L2PArgs &, hipStream_t);
 template hipError_t launch_l2p<double>(const L2PArgs &, hipStream_t);
+template hipError_t launch_unpermute<float>(int64_t, const int *, const void *, void *, void *,
+                                            void *, void *, int, hipStream_t);
+template hipError_t launch_unpermute<double>(int64_t, const int *, const void *, void *, void *,
+                                             void *, void *, int, hipStream_t);
 
 }  // namespace pmmm

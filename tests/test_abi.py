@@ -40,7 +40,10 @@ def test_parameter_validation_on_host(lib):
     assert workspace_bytes(ok, 32768) > 0
     assert workspace_bytes(make_params(16, 5, "periodic", cutoff=3), 10) == 0      # bad cutoff
     assert workspace_bytes(make_params(4, 3, "periodic", cutoff=2), 10) == 0       # n < 2c+1
-    assert workspace_bytes(make_params(8, 9, "open"), 10) == 0                     # p > PMAX
+    assert workspace_bytes(make_params(8, 11, "open"), 10) == 0                    # p > PMAX
+    assert workspace_bytes(make_params(8, 10, "open"), 10) > 0                     # p = PMAX
+    assert workspace_bytes(make_params(16, 9, "periodic"), 10) > 0
+    assert workspace_bytes(make_params(64, 10, "open"), 10) == 0                   # tile > LDS
     assert workspace_bytes(make_params(12, 3, "periodic"), 10) == 0                # not 2^k
     assert workspace_bytes(make_params(128, 3, "open"), 10) == 0                   # nf > 128
     assert workspace_bytes(make_params(64, 3, "open", precision="f64"), 10) == 0   # nf > 64 (FP64)
@@ -53,10 +56,51 @@ def test_workspace_grows_with_particles(lib):
     from paper_1409_5981_amd._lib import make_params, workspace_bytes
     prm = make_params(32, 7, "periodic")
     # per particle: cell, slot, permutation, sorted cell and sorted slot (5 ints),
-    # the sorted record and the sorted-order results (2 x 4 floats)
-    assert workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0) == (1 << 20) * 52
+    # the sorted record and the sorted-order results (2 x 4 floats); plus one
+    # int per near-field tile of 64 targets
+    assert workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0) == (1 << 20) * 52 + 4 * (1 << 14)
 
 
 def test_error_strings(lib):
     for code in range(6):
         assert lib.pmmm_error_string(code).startswith(b"PMMM_")
+
+
+def test_one_hip_runtime_mapped():
+    """Loading the library binds it to the HIP (and HSA) runtime torch already
+    mapped: a fresh process holds exactly one of each after _lib.load()."""
+    import subprocess
+    import sys
+    code = (
+        "import re, sys; sys.path.insert(0, %r)\n"
+        "from paper_1409_5981_amd import _lib\n"
+        "_lib.load()\n"
+        "maps = open('/proc/self/maps').read()\n"
+        "hip = set(re.findall(r'\\S*libamdhip64\\S*', maps))\n"
+        "hsa = set(re.findall(r'\\S*libhsa-runtime64\\S*', maps))\n"
+        "print(len(hip), len(hsa), sorted(hip))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    nhip, nhsa = (int(v) for v in r.stdout.split()[:2])
+    assert nhip == 1 and nhsa == 1, r.stdout
+
+
+def test_buffer_validation_before_any_call():
+    """Wrong length, dtype, layout or device is rejected before the C call
+    (a short output would let the kernels write past its end)."""
+    import torch
+    from paper_1409_5981_amd._lib import check_buffers
+    f32 = torch.float32
+    ok = torch.zeros(10, dtype=f32)
+    with pytest.raises(ValueError, match="expected 10 elements"):
+        check_buffers((ok, torch.zeros(9, dtype=f32)), f32, 10, what="out")
+    with pytest.raises(ValueError, match="expected"):
+        check_buffers((torch.zeros(10, 2, dtype=f32),), f32, 20, shape=(10, 3), what="out")
+    with pytest.raises(ValueError, match="dtype"):
+        check_buffers((torch.zeros(10, dtype=torch.float64),), f32, 10)
+    with pytest.raises(ValueError, match="contiguous"):
+        check_buffers((torch.zeros(20, dtype=f32)[::2],), f32, 10)
+    with pytest.raises(ValueError, match="GPU"):
+        check_buffers((ok,), f32, 10)
+    with pytest.raises(ValueError, match="None"):
+        check_buffers((None,), f32, 10)

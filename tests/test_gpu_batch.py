@@ -129,11 +129,19 @@ def test_batch_graph_capture_and_replay():
 def test_batch_errors():
     import torch
     from paper_1409_5981_amd._lib import PMMM_EINVAL, Batch, PMMMError
+    import ctypes
+    from paper_1409_5981_amd import _lib
     batch = Batch([{"n": 8, "p": 3}, {"n": 8, "p": 3}])
     e = torch.zeros(4, dtype=torch.float32, device="cuda")
-    with pytest.raises(PMMMError) as ei:
+    with pytest.raises(ValueError):          # refused by the binding before the C call
         batch.far(np.array([0, 3, 2]), e[:2], e[:2], e[:2], e[:2])
-    assert ei.value.code == PMMM_EINVAL
+    with pytest.raises(ValueError):          # output shorter than offsets[-1]
+        batch.far(np.array([0, 2, 4]), e, e, e, e, out=(e, e, e, e[:3]))
+    # the C entry point checks the offsets itself
+    offs = np.array([0, 3, 2], dtype=np.int64)
+    rc = _lib.load().pmmm_batch_far_f32(batch._h, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        *[e.data_ptr()] * 8, None)
+    assert rc == PMMM_EINVAL
     with pytest.raises(PMMMError):
         Batch([{"n": 12, "p": 3}])           # not a power of two
 

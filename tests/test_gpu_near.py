@@ -1,0 +1,136 @@
+"""GPU parity of the near field (pmmm_near_*: direct sums over the (2c+1)^3
+cells around each particle's cell, Sec. 2.1 last paragraph) against the
+oracle's near sums, and of the total field (pmmm_total_*: far + near with
+one binning) against the oracle's far + near, both at the per-particle
+bounds of gpu_helpers.BOUNDS.  The method error of the total field against
+the exact references (direct sum, Ewald) is printed and bounded by the
+worst-case estimate of eq. errest."""
+import os
+from math import sqrt
+
+import numpy as np
+import pytest
+
+from gpu_helpers import assert_parity, oracle_cfg
+from oracle import exact
+from oracle import pmmm as opm
+from paper_1409_5981_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _set(n, n_cells, p, boundary, seed, dtype, neutral=True, clustered=False):
+    rng = np.random.default_rng(seed)
+    if clustered:
+        # half the particles in a small ball: cells far above 64 particles,
+        # so tiles split cells and source chunks repeat
+        pos = rng.random((n, 3))
+        k = n // 2
+        pos[:k] = 0.5 + 0.06 * (rng.random((k, 3)) - 0.5)
+        x, y, z = (pos[:, a].astype(dtype).copy() for a in range(3))
+    else:
+        x, y, z = (rng.random(n).astype(dtype) for _ in range(3))
+    q = inputs.neutral_pm1(rng, n, dtype) if neutral else (rng.random(n) / n).astype(dtype)
+    return inputs.ParticleSet(x, y, z, q, n_cells, p, boundary)
+
+
+def _gpu(ps, precision, mode, cutoff=2, plan=None, out=None, accumulate=False):
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    npdt = np.float32 if precision == "f32" else np.float64
+    if plan is None:
+        plan = Plan(ps.n_cells, ps.p, ps.boundary, box=ps.box, cutoff=cutoff, precision=precision)
+    t = [torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).cuda() for a in (ps.x, ps.y, ps.z, ps.q)]
+    if mode == "near":
+        res = plan.near(*t, out=out, accumulate=accumulate)
+    else:
+        res = plan.total(*t, out=out)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    phi, gx, gy, gz = res
+    return ({"phi": phi.double().cpu().numpy(),
+             "grad": torch.stack([gx, gy, gz], 1).double().cpu().numpy()}, plan)
+
+
+@pytest.mark.parametrize("prec,dt", [("f32", np.float32), ("f64", np.float64)])
+@pytest.mark.parametrize("boundary,n_cells,cutoff,clustered", [
+    ("periodic", 8, 2, False), ("periodic", 4, 1, False), ("periodic", 8, 1, True),
+    ("open", 8, 2, False), ("open", 4, 1, False), ("open", 8, 2, True)])
+def test_near_field(prec, dt, boundary, n_cells, cutoff, clustered):
+    """Near field alone: small periodic meshes where a tile's source range
+    wraps onto itself (4 cells, c = 1), clustered sets with cells of
+    hundreds of particles, open meshes with the border cells."""
+    ps = _set(6000, n_cells, 3, boundary, 60, dt, clustered=clustered)
+    res, _ = _gpu(ps, prec, "near", cutoff=cutoff)
+    nphi, ng = exact.near(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps, cutoff))
+    assert_parity(res, nphi, ng, prec, f"near {boundary} n={n_cells} c={cutoff} "
+                                       f"clustered={clustered} {prec}")
+
+
+def test_near_accumulates():
+    """accumulate != 0 adds the near field into the outputs."""
+    import torch
+    ps = _set(3000, 8, 3, "periodic", 61, np.float32)
+    base = [torch.full((ps.n,), 0.25, dtype=torch.float32, device="cuda") for _ in range(4)]
+    res, _ = _gpu(ps, "f32", "near", out=tuple(base), accumulate=True)
+    nphi, ng = exact.near(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+    assert_parity({"phi": res["phi"] - 0.25, "grad": res["grad"] - 0.25}, nphi, ng, "f32",
+                  "near accumulate")
+
+
+@pytest.mark.parametrize("prec,dt", [("f32", np.float32), ("f64", np.float64)])
+@pytest.mark.parametrize("boundary,n_cells,p", [("periodic", 8, 5), ("open", 8, 4),
+                                                ("periodic", 16, 4)])
+def test_total_matches_far_plus_near(prec, dt, boundary, n_cells, p):
+    """Total = far + near in one call (one binning; the near sums are added
+    to the far field in sorted order before the results return to the
+    caller's order)."""
+    ps = _set(8000 if n_cells == 8 else 40000, n_cells, p, boundary, 62, dt)
+    res, _ = _gpu(ps, prec, "total")
+    cfg = oracle_cfg(ps)
+    far = opm.far_field(ps.pos, ps.q.astype(np.float64), cfg)
+    nphi, ng = exact.near(ps.pos, ps.q.astype(np.float64), cfg)
+    assert_parity(res, far.phi + nphi, far.grad + ng, prec, f"total {boundary} n={n_cells} {prec}")
+
+
+def _errest(c, p):
+    s = sqrt(3) / 2
+    return (s / ((c + 1) - s)) ** (p + 1)
+
+
+def test_total_open_vs_direct_sum():
+    """Open boundary, N = 4096 equal masses on 8^3 cells, p = 4 (the FP64
+    workload) in FP32 and FP64: the total against the O(N^2) direct sum."""
+    ps = inputs.open_equal_mass()
+    dphi, dg = exact.direct(ps.pos, ps.q)
+    for prec in ("f64", "f32"):
+        res, _ = _gpu(ps, prec, "total")
+        eg, ep = exact.rel_rms(res["grad"], dg), exact.rel_rms(res["phi"], dphi)
+        print(f"open N=4096 8^3 p=4 c=2 {prec}: method error vs direct sum: "
+              f"grad {eg:.3e} phi {ep:.3e} (worst-case bound {_errest(2, 4):.1e})")
+        assert eg < _errest(2, 4) and ep < _errest(2, 4)
+
+
+@pytest.mark.parametrize("name,gen,n_cells,p", [
+    ("ewald_periodic_n32768", "periodic_pm1", 16, 5),
+    ("ewald_periodic_slice_n32768", "slice", 32, 7)])
+def test_total_periodic_vs_ewald(name, gen, n_cells, p):
+    """Method error against the Ewald sum (FP64 oracle O1, written by
+    tests/golden/make_oracle_refs.py): the 32768-particle workload (16^3,
+    p = 5) and the first 32768-particle block of the 2^20-particle workload
+    as a system of its own on that workload's mesh (32^3, p = 7), FP32."""
+    ref = np.load(os.path.join(GOLDEN, f"ref_{name}.npz"))
+    if gen == "slice":
+        ps = inputs.periodic_pm1_blocks().subset(np.arange(32768))
+    else:
+        ps = inputs.periodic_pm1()
+    assert ps.n == int(ref["n"]) and ps.n_cells == n_cells and ps.p == p
+    res, _ = _gpu(ps, "f32", "total")
+    idx = ref["idx"]
+    eg = exact.rel_rms(res["grad"][idx], ref["grad"])
+    ep = exact.rel_rms(res["phi"][idx], ref["phi"])
+    print(f"{name} ({n_cells}^3, p={p}, c=2, FP32): method error vs Ewald: "
+          f"grad {eg:.3e} phi {ep:.3e} (worst-case bound {_errest(2, p):.1e})")
+    assert eg < _errest(2, p) and ep < _errest(2, p)

@@ -1,24 +1,19 @@
 """GPU parity of the HIP far-field path (through the C ABI) against the FP64
-oracle, on seeded inputs.  Tolerances: FP64 plans 1e-12 relative RMS, FP32
-plans 1e-6 relative RMS of grad Phi (the stated accuracy target) and of Phi.
-Stage meshes (moments, transfer spectra, local expansions) are compared too
-so that a failure names its stage."""
+oracle, on seeded inputs.  Every comparison bounds the relative RMS, the
+99th percentile and the maximum of the per-particle error of Phi and of
+grad Phi (gpu_helpers.BOUNDS): FP32 plans 1e-6 / 3e-6 / 2e-5, FP64 plans
+1e-12 / 3e-12 / 2e-11.  Stage meshes (moments, transfer spectra, local
+expansions) are compared too so that a failure names its stage."""
 import numpy as np
 import pytest
 
-from gpu_helpers import cell_unit_mesh, folded_green, gpu_far, oracle_cfg
+from gpu_helpers import (BOUNDS, assert_parity, cell_unit_mesh, err_stats, folded_green,
+                         gpu_far, oracle_cfg)
 from oracle import exact
 from oracle import pmmm as opm
 from paper_1409_5981_amd import inputs
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"f32": 1e-6, "f64": 1e-12}
-# Periodic FP64 kernels are lattice sums from which the near image S(d) is
-# subtracted (App. B); the cancellation leaves a rounding floor near 1e-12 of
-# the largest kernel value that depends on summation order, so GPU and oracle
-# agree to about 1e-12 relative, not better.
-TOL_F64_PERIODIC = 1e-11
 
 
 def _small(n, n_cells, p, boundary, seed, dtype, neutral=True):
@@ -31,18 +26,12 @@ def _small(n, n_cells, p, boundary, seed, dtype, neutral=True):
     return inputs.ParticleSet(x, y, z, q, n_cells, p, boundary)
 
 
-def _compare(ps, precision, cutoff=2, tol=None):
-    if tol is None:
-        tol = TOL_F64_PERIODIC if (precision == "f64" and ps.boundary == "periodic") else TOL[precision]
+def _compare(ps, precision, cutoff=2, bounds=None):
     res, plan = gpu_far(ps, precision, cutoff=cutoff)
     cfg = oracle_cfg(ps, cutoff)
     ref = opm.far_field(ps.pos, ps.q.astype(np.float64), cfg)
-    eg = exact.rel_rms(res["grad"], ref.grad)
-    ep = exact.rel_rms(res["phi"], ref.phi)
-    print(f"{ps.boundary} n={ps.n_cells} p={ps.p} N={ps.n} {precision}: "
-          f"rel-RMS grad {eg:.3e} phi {ep:.3e}", flush=True)
-    assert eg <= tol, eg
-    assert ep <= tol, ep
+    what = f"{ps.boundary} n={ps.n_cells} p={ps.p} c={cutoff} N={ps.n} {precision}"
+    assert_parity(res, ref.phi, ref.grad, precision, what, bounds=bounds)
     return res, ref, plan, cfg
 
 
@@ -59,6 +48,78 @@ def test_small_f64(boundary, n_cells, p):
 def test_small_f32(boundary, n_cells, p, cutoff):
     ps = _small(6000, n_cells, p, boundary, 12, np.float32)
     _compare(ps, "f32", cutoff=cutoff)
+
+
+@pytest.mark.parametrize("p", [1, 2, 8, 9, 10])
+@pytest.mark.parametrize("boundary", ["open", "periodic"])
+def test_every_order_f32(boundary, p):
+    """Orders the library compiles beyond the workloads' 4..7, up to
+    PMMM_PMAX = 10 (the paper notes that p >= 10 is needed at c = 2 for
+    errors below 1e-4, Sec. 3.2)."""
+    n_cells = 8 if boundary == "open" else 16
+    ps = _small(5000, n_cells, p, boundary, 40 + p, np.float32)
+    _compare(ps, "f32")
+
+
+@pytest.mark.parametrize("boundary", ["open", "periodic"])
+def test_order_zero(boundary):
+    """p = 0: Phi is the monopole far field and grad Phi is identically zero
+    (no order-one local coefficient exists)."""
+    for prec, dt in (("f32", np.float32), ("f64", np.float64)):
+        ps = _small(3000, 8, 0, boundary, 50, dt)
+        res, plan = gpu_far(ps, prec)
+        ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+        assert np.all(res["grad"] == 0.0)
+        st = err_stats(res["phi"], ref.phi)
+        print(f"p=0 {boundary} {prec}: phi rel-RMS {st[0]:.2e} p99 {st[1]:.2e} max {st[2]:.2e}")
+        b = BOUNDS[prec]
+        assert st[0] <= b[0] and st[1] <= b[1] and st[2] <= b[2], st
+
+
+@pytest.mark.parametrize("prec,dt", [("f32", np.float32), ("f64", np.float64)])
+def test_charged_periodic_system(prec, dt):
+    """Non-neutral periodic system (all charges positive): the per-particle
+    terms of the correction procedure for Q_tot != 0 (App. B) on Phi and
+    grad Phi, at the full parity bound."""
+    ps = _small(4000, 8, 5, "periodic", 51, dt, neutral=False)
+    assert float(np.sum(ps.q)) > 0.5
+    _compare(ps, prec)
+
+
+def test_fp64_fft_mesh_64():
+    """FP64 plans at their largest FFT mesh, 64 points per axis: open 32^3
+    cells (64^3 padded) and periodic 64^3 cells."""
+    ps = _small(20000, 32, 3, "open", 52, np.float64)
+    _compare(ps, "f64")
+    ps = _small(30000, 64, 2, "periodic", 53, np.float64)
+    _compare(ps, "f64")
+
+
+@pytest.mark.parametrize("boundary", ["open", "periodic"])
+def test_particles_on_cell_faces(boundary):
+    """Particles exactly on cell faces and edges (k/n, exact in FP32), at 0,
+    at the last float below the box edge and (periodic) at or beyond the
+    box edge and below zero, which wrap: the cell assignment (floor, clamp,
+    wrap first) matches the oracle's."""
+    n_cells, p = 8, 4
+    rng = np.random.default_rng(54)
+    k = rng.integers(0, n_cells, size=(3000, 3)).astype(np.float64) / n_cells
+    pos = k.copy()
+    pos[:1000, 1] = rng.random(1000)               # faces, not edges
+    pos[1000:1500, 2] = rng.random(500)
+    pos[1500] = [0.0, 0.0, 0.0]
+    top = np.nextafter(np.float32(1.0), np.float32(0.0))
+    pos[1501] = [top, top, top]
+    pos[1502] = [top, 0.0, 0.5]
+    if boundary == "periodic":
+        pos[1503] = [1.0, 0.25, 0.5]
+        pos[1504] = [-0.25, 1.75, 0.125]
+        pos[1505] = [2.0, -1.0, 0.0]
+    pos = pos.astype(np.float32)
+    q = inputs.neutral_pm1(rng, len(pos), np.float32)
+    ps = inputs.ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, n_cells, p,
+                            boundary)
+    _compare(ps, "f32")
 
 
 def test_stage_meshes_f32():
@@ -79,16 +140,39 @@ def test_stage_meshes_f32():
     assert exact.rel_rms(Lg, cell_unit_mesh(L, cfg, "L")) < 2e-6
 
 
-def test_stage_meshes_open_f64():
-    ps = _small(3000, 4, 3, "open", 14, np.float64)
-    res, plan = gpu_far(ps, "f64", cutoff=1)
+@pytest.mark.parametrize("boundary,cutoff", [("open", 1), ("periodic", 2)])
+def test_stage_meshes_f64(boundary, cutoff):
+    n_cells = 4 if boundary == "open" else 8
+    ps = _small(3000, n_cells, 3, boundary, 14, np.float64)
+    res, plan = gpu_far(ps, "f64", cutoff=cutoff)
     from paper_1409_5981_amd._lib import PMMM_MESH_GREEN, PMMM_MESH_L, PMMM_MESH_M
-    cfg = oracle_cfg(ps, cutoff=1)
-    M, _ = opm.p2m_mesh(ps.pos, ps.q, cfg)
+    cfg = oracle_cfg(ps, cutoff=cutoff)
+    M, qr2 = opm.p2m_mesh(ps.pos, ps.q, cfg)
     L = opm.local_mesh(M, cfg)
+    if boundary == "periodic":
+        L, _ = opm.periodic_corrections(L, M, qr2, cfg)
     assert exact.rel_rms(plan.mesh(PMMM_MESH_M), cell_unit_mesh(M, cfg, "M")) < 1e-13
-    assert exact.rel_rms(plan.mesh(PMMM_MESH_GREEN), folded_green(cfg)) < 1e-13
-    assert exact.rel_rms(plan.mesh(PMMM_MESH_L), cell_unit_mesh(L, cfg, "L")) < 1e-12
+    Gg, Gref = plan.mesh(PMMM_MESH_GREEN), folded_green(cfg)
+    eg = np.max(np.abs(Gg - Gref)) / np.max(np.abs(Gref))
+    print(f"{boundary} FP64 transfer spectra: max abs diff / max {eg:.2e}")
+    for k in range(2 * ps.p + 1):
+        sl = slice(k * k, (k + 1) * (k + 1))
+        print(f"  order {k}: max |dG| / max |G| {np.max(np.abs(Gg[:, :, sl] - Gref[:, :, sl])) / np.max(np.abs(Gref[:, :, sl])):.2e}"
+              f" (max |G| {np.max(np.abs(Gref[:, :, sl])):.2e}); at k = 0: "
+              f"{np.max(np.abs(Gg[0, 0, sl, 0] - Gref[0, 0, sl, 0])):.2e}")
+    assert eg < 1e-13
+    Lg, Lref = plan.mesh(PMMM_MESH_L), cell_unit_mesh(L, cfg, "L")
+    Mg, Mref = plan.mesh(PMMM_MESH_M), cell_unit_mesh(M, cfg, "M")
+    for a in range(min(9, Lg.shape[0])):
+        D = np.fft.fftn(Lg[a] - Lref[a])          # [kz, ky, kx]
+        e2 = np.abs(D) ** 2
+        h = Lg.shape[1] // 2
+        nyq = e2[h].sum() + e2[:, h].sum() + e2[:, :, h].sum()
+        print(f"  L component {a}: rel-RMS {exact.rel_rms(Lg[a], Lref[a]):.2e}; "
+              f"M rel-RMS {exact.rel_rms(Mg[a], Mref[a]):.2e}; diff energy: k=0 "
+              f"{e2[0, 0, 0] / e2.sum():.2f}, Nyquist planes {nyq / e2.sum():.2f}, "
+              f"kz=0 plane {e2[0].sum() / e2.sum():.2f}")
+    assert exact.rel_rms(Lg, Lref) < 1e-12
 
 
 def test_open_equal_mass_n4096_f64():
@@ -109,21 +193,14 @@ def test_periodic_pm1_n32768_f32():
     _compare(ps, "f32")
 
 
-def test_near_field_matches_oracle():
-    ps = _small(4000, 8, 3, "periodic", 15, np.float32)
-    res, plan = gpu_far(ps, "f32", near=True)
-    cfg = oracle_cfg(ps)
-    nphi, ng = exact.near(ps.pos, ps.q.astype(np.float64), cfg)
-    assert exact.rel_rms(res["near_grad"], ng) < 1e-5
-    assert exact.rel_rms(res["near_phi"], nphi) < 1e-5
-
-
 def test_zero_and_single_particle():
     import torch
     from paper_1409_5981_amd._lib import Plan
     plan = Plan(8, 3, "periodic")
     e = torch.empty(0, dtype=torch.float32, device="cuda")
     out = plan.far(e, e, e, e)
+    assert all(o.numel() == 0 for o in out)
+    out = plan.total(e, e, e, e)
     assert all(o.numel() == 0 for o in out)
     one = torch.tensor([0.3], dtype=torch.float32, device="cuda")
     phi, gx, gy, gz = plan.far(one, one, one, torch.tensor([1.0], device="cuda"))
@@ -132,20 +209,21 @@ def test_zero_and_single_particle():
                             np.array([0.3], np.float32), np.array([1.0], np.float32), 8, 3,
                             "periodic")
     ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
-    assert abs(phi.item() - ref.phi[0]) < 1e-5 * abs(ref.phi[0])
+    assert abs(phi.item() - ref.phi[0]) < 1e-6 * abs(ref.phi[0])
+    g = np.array([gx.item(), gy.item(), gz.item()])
+    assert np.linalg.norm(g - ref.grad[0]) < 1e-6 * max(np.linalg.norm(ref.grad[0]), 1.0)
 
 
-def test_two_calls_in_a_row_and_determinism():
-    """A second call with a smaller input reuses the plan correctly, and
-    repeated calls give identical results to rounding."""
-    import torch
+def test_two_calls_in_a_row():
+    """A second call with a smaller input reuses the plan correctly and a
+    third call repeats the first to rounding."""
     ps = _small(8000, 8, 4, "open", 16, np.float32, neutral=False)
     res1, plan = gpu_far(ps, "f32")
     small = ps.subset(np.arange(3000))
     res2, _ = gpu_far(small, "f32", plan=plan)
     cfg = oracle_cfg(ps)
     ref2 = opm.far_field(small.pos, small.q.astype(np.float64), cfg)
-    assert exact.rel_rms(res2["grad"], ref2.grad) < 1e-6
+    assert_parity(res2, ref2.phi, ref2.grad, "f32", "second, smaller call")
     res3, _ = gpu_far(ps, "f32", plan=plan)
     assert exact.rel_rms(res3["grad"], res1["grad"]) < 1e-6
 
@@ -163,6 +241,25 @@ def test_open_domain_flag():
     plan.sync_status()   # flag cleared
 
 
+def test_binding_rejects_bad_outputs_on_device():
+    """Short, mistyped or non-contiguous output tensors are refused before
+    any kernel runs."""
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    plan = Plan(8, 3, "periodic")
+    x = torch.rand(100, device="cuda")
+    good = tuple(torch.empty(100, device="cuda") for _ in range(4))
+    for bad in (torch.empty(99, device="cuda"), torch.empty(100, device="cuda", dtype=torch.float64),
+                torch.empty(200, device="cuda")[::2], torch.empty(100)):
+        out = (good[0], good[1], bad, good[3])
+        with pytest.raises(ValueError):
+            plan.far(x, x, x, x, out=out)
+        with pytest.raises(ValueError):
+            plan.total(x, x, x, x, out=out)
+    with pytest.raises(ValueError):
+        plan.far(x, x, x[:50], x)
+
+
 @pytest.mark.parametrize("name,gen", [("periodic_n1048576_m32_p7", "periodic_pm1_blocks"),
                                       ("open_plummer_n4194304_m64_p6", "plummer_sphere")])
 def test_full_size_sampled(name, gen):
@@ -175,12 +272,7 @@ def test_full_size_sampled(name, gen):
     ps = getattr(inputs, gen)()
     assert ps.n == int(ref["n"]) and ps.n_cells == int(ref["n_cells"]) and ps.p == int(ref["p"])
     res, plan = gpu_far(ps, "f32")
-    idx = ref["idx"]
-    eg = exact.rel_rms(res["grad"][idx], ref["grad"])
-    ep = exact.rel_rms(res["phi"][idx], ref["phi"])
-    print(f"{name}: sampled rel-RMS grad {eg:.3e} phi {ep:.3e}", flush=True)
-    assert eg <= TOL["f32"], eg
-    assert ep <= TOL["f32"], ep
+    assert_parity(res, ref["phi"], ref["grad"], "f32", name, idx=ref["idx"])
 
 
 def test_autotune_keeps_parity():
@@ -196,5 +288,4 @@ def test_autotune_keeps_parity():
     print(f"autotune: column width {w}, P2M lanes {g}")
     res, _ = gpu_far(ps, "f32", plan=plan)
     ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
-    assert exact.rel_rms(res["grad"], ref.grad) <= TOL["f32"]
-    assert exact.rel_rms(res["phi"], ref.phi) <= TOL["f32"]
+    assert_parity(res, ref.phi, ref.grad, "f32", "autotuned")
