@@ -123,6 +123,25 @@ size_t pmmm_workspace_bytes(const pmmm_params *params, int64_t n_max);
 int pmmm_far_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
                  const float *q, float *phi, float *gx, float *gy, float *gz, void *stream);
 
+/* Allocation-free variant of pmmm_far_f32, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation after set-up).  Same arguments, result and errors
+ * as pmmm_far_f32 for an FP32 (or BF16X3) plan, but the per-particle work
+ * space (cell indices, permutation, sorted records, sorted-order results)
+ * lives in a static device array of the library sized for
+ * PMMM_NOALLOC_MAX_N particles (52 bytes each, 13 MiB; each GPU the library
+ * runs on holds its own copy until the process ends), so the call makes no
+ * allocation and records no events (stage profiling does not apply).  The
+ * array's device address is looked up when a plan is created on a device.
+ * n above PMMM_NOALLOC_MAX_N returns PMMM_EINVAL before anything is
+ * enqueued.  All calls on one GPU share that GPU's array: calls whose
+ * execution overlaps on one GPU (other streams, other plans, other threads)
+ * race and give undefined results. */
+#define PMMM_NOALLOC_MAX_N (1 << 18)
+int pmmm_far_f32_noalloc(pmmm_plan plan, int64_t n, const float *x, const float *y,
+                         const float *z, const float *q, float *phi, float *gx, float *gy,
+                         float *gz, void *stream);
+
 /* Same as pmmm_far_f32 for an FP64 plan. */
 int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
                  const double *z, const double *q, double *phi, double *gx, double *gy,

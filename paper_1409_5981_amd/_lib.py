@@ -20,11 +20,12 @@ PMMM_OPEN, PMMM_PERIODIC = 0, 1
 PMMM_F32, PMMM_F64, PMMM_BF16X3 = 0, 1, 2
 PMMM_MESH_M, PMMM_MESH_L, PMMM_MESH_GREEN = 0, 1, 2
 PMMM_PMAX = 10
+PMMM_NOALLOC_MAX_N = 1 << 18
 
 #: every symbol include/pmmm.h declares
 EXPORTS = [
     "pmmm_plan_create", "pmmm_plan_destroy", "pmmm_workspace_bytes",
-    "pmmm_far_f32", "pmmm_far_f64", "pmmm_far_multi_f32",
+    "pmmm_far_f32", "pmmm_far_f64", "pmmm_far_multi_f32", "pmmm_far_f32_noalloc",
     "pmmm_near_f32", "pmmm_near_f64", "pmmm_total_f32", "pmmm_total_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
     "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
@@ -81,7 +82,7 @@ def load():
     L.pmmm_plan_destroy.restype = None
     L.pmmm_workspace_bytes.argtypes = [ctypes.POINTER(Params), i64]
     L.pmmm_workspace_bytes.restype = cz
-    for name in ("pmmm_far_f32", "pmmm_far_f64"):
+    for name in ("pmmm_far_f32", "pmmm_far_f64", "pmmm_far_f32_noalloc"):
         f = getattr(L, name)
         f.argtypes = [vp, i64] + [vp] * 8 + [vp]
         f.restype = ci
@@ -250,6 +251,16 @@ class Plan:
         fn = load().pmmm_far_f64 if self.precision == "f64" else load().pmmm_far_f32
         _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
                   *[o.data_ptr() for o in out], _stream_handle(stream)))
+        return out
+
+    def far_noalloc(self, x, y, z, q, out, stream=None):
+        """pmmm_far_f32_noalloc: the FP32 far field with the library's static
+        per-particle scratch (n <= PMMM_NOALLOC_MAX_N; outputs required)."""
+        n = self._inputs(x, y, z, q)
+        out = self._outputs(out, n, x.device)
+        _check(load().pmmm_far_f32_noalloc(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                                           q.data_ptr(), *[o.data_ptr() for o in out],
+                                           _stream_handle(stream)))
         return out
 
     def near(self, x, y, z, q, out=None, accumulate=False, stream=None):

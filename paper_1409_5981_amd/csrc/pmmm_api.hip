@@ -92,8 +92,9 @@ struct StageTimer {
     int stage;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    StageTimer(Plan *pl_, int st, hipStream_t s_) : pl(pl_), stage(st), s(s_) {
-        if (!(pl->prof_mask & (1u << stage))) return;
+    StageTimer(Plan *pl_, int st, hipStream_t s_, bool enabled = true)
+        : pl(pl_), stage(st), s(s_) {
+        if (!enabled || !(pl->prof_mask & (1u << stage))) return;
         a = take();
         b = take();
         if (a) hipEventRecord(a, s);
@@ -351,10 +352,25 @@ static int group_for(double mean) {
 // (pmmm_near_*) or both with one binning (pmmm_total_*).
 enum CallMode { kFar = 0, kNear = 1, kTotal = 2 };
 
+// Per-particle device buffers of one call: the plan's own (grown on demand)
+// or, for the allocation-free entry point, slices of the static scratch.
+struct PBuf {
+    int *cell_of, *slot, *perm, *scell, *pos, *tile_row;
+    void *sorted, *staged;
+};
+
+static PBuf plan_pbuf(const Plan *pl) {
+    return PBuf{pl->cell_of, pl->slot,   pl->perm,   pl->scell,
+                pl->pos,     pl->tile_row, pl->sorted, pl->staged};
+}
+
+// ext == nullptr: the plan's particle buffers, grown to n if needed (which
+// allocates) and stage timing as configured; otherwise the caller's buffers
+// (capacity checked by the caller), no allocation and no events.
 template <typename T>
 static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, const T *y,
                      const T *z, const T *q, T *phi, T *gx, T *gy, T *gz, int accumulate,
-                     void *stream) {
+                     void *stream, const PBuf *ext = nullptr) {
     if (!pl) {
         set_error("plan is NULL");
         return PMMM_EINVAL;
@@ -378,8 +394,12 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         set_error("current device differs from the plan's device");
         return PMMM_EINVAL;
     }
-    int rc = ensure_capacity(pl, n > 0 ? n : 1);
-    if (rc != PMMM_OK) return rc;
+    if (ext == nullptr) {
+        const int rc = ensure_capacity(pl, n > 0 ? n : 1);
+        if (rc != PMMM_OK) return rc;
+    }
+    const PBuf pb = ext != nullptr ? *ext : plan_pbuf(pl);
+    const bool timed = ext == nullptr;
     pl->last_stream = s;
     pl->last_n = n;
     // near and total calls, and large far-field calls, leave their results
@@ -387,7 +407,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
     const bool staged = mode != kFar || n >= kStagedL2PMinN;
 
     {
-        StageTimer t(pl, PMMM_STAGE_BIN, s);
+        StageTimer t(pl, PMMM_STAGE_BIN, s, timed);
         BinArgs b{};
         b.n = n;
         b.x = x;
@@ -397,25 +417,25 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.ncell = pl->n;
         b.inv_h = pl->inv_h;
         b.periodic = !pl->open;
-        b.cell_of = pl->cell_of;
-        b.slot = pl->slot;
+        b.cell_of = pb.cell_of;
+        b.slot = pb.slot;
         b.count = pl->count;
         b.start = pl->start;
-        b.scell = pl->scell;
-        b.perm = pl->perm;
+        b.scell = pb.scell;
+        b.perm = pb.perm;
         b.flag = pl->small + 1;
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
-        b.pos = staged ? pl->pos : nullptr;
+        b.pos = staged ? pb.pos : nullptr;
         b.tile_sums = pl->tile_sums;
         b.sstart = pl->sstart;
         b.dense_threshold = kDenseThreshold;
-        b.sorted = pl->sorted;
+        b.sorted = pb.sorted;
         PMMM_HIP(launch_bin<T>(b, s));
     }
     if (mode != kNear) {
         {
-            StageTimer t(pl, PMMM_STAGE_P2M, s);
+            StageTimer t(pl, PMMM_STAGE_P2M, s, timed);
             P2MArgs m{};
             m.p = pl->p;
             m.ncell = pl->n;
@@ -427,7 +447,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
             m.dense_cells = pl->dense_cells;
             m.dense_count = pl->small;
             m.dense_threshold = kDenseThreshold;
-            m.sorted = pl->sorted;
+            m.sorted = pb.sorted;
             m.M = pl->M;
             PMMM_HIP(launch_p2m<T>(m, s));
         }
@@ -445,19 +465,19 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         f.sums = pl->sums;
         f.col_w = pl->tune_col_w;
         for (int st = 0; st < 3; ++st) {
-            StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s);
+            StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s, timed);
             PMMM_HIP(launch_conv_stage<T>(f, st, s));
         }
         {
-            StageTimer t(pl, PMMM_STAGE_L2P, s);
+            StageTimer t(pl, PMMM_STAGE_L2P, s, timed);
             L2PArgs l{};
             l.n = n;
             l.p = pl->p;
             l.ncell = pl->n;
             l.periodic = !pl->open;
-            l.sorted = pl->sorted;
-            l.scell = pl->scell;
-            l.perm = pl->perm;
+            l.sorted = pb.sorted;
+            l.scell = pb.scell;
+            l.perm = pb.perm;
             l.L = pl->L;
             l.sums = pl->sums;
             l.alpha_cell = pl->alpha_cell;
@@ -467,12 +487,12 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
             l.gy = gy;
             l.gz = gz;
             if (staged) {
-                l.staged = pl->staged;
-                l.pos = pl->pos;
+                l.staged = pb.staged;
+                l.pos = pb.pos;
             }
             PMMM_HIP(launch_l2p<T>(l, s));
             if (mode == kFar && staged)
-                PMMM_HIP(launch_unpermute<T>(n, pl->pos, pl->staged, phi, gx, gy, gz, 0, s));
+                PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz, 0, s));
         }
     } else if (n > 0 && pl->K <= 4096) {
         // no P2M to reset the counts of an in-block-scanned mesh (a fill
@@ -480,7 +500,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         PMMM_HIP(launch_zero_ints(pl->count, pl->K, s));
     }
     if (mode != kFar) {
-        StageTimer t(pl, PMMM_STAGE_NEAR, s);
+        StageTimer t(pl, PMMM_STAGE_NEAR, s, timed);
         NearArgs a{};
         a.n = n;
         a.ncell = pl->n;
@@ -488,18 +508,89 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         a.periodic = !pl->open;
         a.accumulate = mode == kTotal ? 1 : 0;
         a.start = pl->start;
-        a.scell = pl->scell;
-        a.sorted = pl->sorted;
+        a.scell = pb.scell;
+        a.sorted = pb.sorted;
         a.inv_h = pl->inv_h;
         a.tile_first = pl->tile_first;
-        a.tile_row = pl->tile_row;
+        a.tile_row = pb.tile_row;
         a.ntiles = pl->small + 2;
-        a.staged = pl->staged;
+        a.staged = pb.staged;
         PMMM_HIP(launch_near<T>(a, s));
-        PMMM_HIP(launch_unpermute<T>(n, pl->pos, pl->staged, phi, gx, gy, gz,
+        PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz,
                                      mode == kNear ? accumulate : 0, s));
     }
     return PMMM_OK;
+}
+
+// ------------------------------------------- allocation-free far field
+// Per-particle scratch of pmmm_far_f32_noalloc in one file-scope device
+// array: cell, slot, permutation, sorted cell and sorted-slot arrays (5 ints
+// per particle) and the sorted records and sorted-order results (two
+// 16-byte records per particle), each region 256-byte aligned.  Every region
+// is written before it is read within a call, so nothing needs clearing.
+constexpr int64_t kNoAllocMaxN = PMMM_NOALLOC_MAX_N;
+constexpr size_t kNoAllocInts = (size_t)kNoAllocMaxN * sizeof(int);
+constexpr size_t kNoAllocRecs = (size_t)kNoAllocMaxN * sizeof(particle4<float>);
+constexpr size_t kNoAllocBytes = 5 * kNoAllocInts + 2 * kNoAllocRecs;
+static_assert(kNoAllocInts % 256 == 0 && kNoAllocRecs % 256 == 0, "256-byte aligned regions");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of each GPU's copy of `scratch`, looked up once per device
+// (with that device current); host code uses these, never the array's name.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {nullptr};
+
+static int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("device index beyond the library's table of devices");
+        return PMMM_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device] != nullptr) return PMMM_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = ptr;
+    return PMMM_OK;
+}
+
+static int far_noalloc(pmmm_plan_s *pl, int64_t n, const float *x, const float *y,
+                       const float *z, const float *q, float *phi, float *gx, float *gy,
+                       float *gz, void *stream) {
+    if (!pl) {
+        set_error("plan is NULL");
+        return PMMM_EINVAL;
+    }
+    if (pl->tsize != sizeof(float)) {
+        set_error("pmmm_far_f32_noalloc needs a PMMM_F32 or PMMM_BF16X3 plan");
+        return PMMM_EINVAL;
+    }
+    if (n < 0 || n > kNoAllocMaxN) {
+        set_error("n outside 0..PMMM_NOALLOC_MAX_N, the capacity of the static scratch");
+        return PMMM_EINVAL;
+    }
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (pl->device >= 0 && pl->device < kMaxDevices) base = g_scratch_dev[pl->device];
+    }
+    if (base == nullptr) {
+        set_error("static scratch of the plan's device not set up");
+        return PMMM_EHIP;
+    }
+    unsigned char *b = (unsigned char *)base;
+    PBuf pb{};
+    pb.cell_of = (int *)(b);
+    pb.slot = (int *)(b + kNoAllocInts);
+    pb.perm = (int *)(b + 2 * kNoAllocInts);
+    pb.scell = (int *)(b + 3 * kNoAllocInts);
+    pb.pos = (int *)(b + 4 * kNoAllocInts);
+    pb.sorted = b + 5 * kNoAllocInts;
+    pb.staged = b + 5 * kNoAllocInts + kNoAllocRecs;
+    pb.tile_row = nullptr;  // far field only
+    return call_impl<float>(pl, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream, &pb);
 }
 
 static int ensure_multi(Plan *pl, int sets, hipStream_t s) {
@@ -1023,6 +1114,7 @@ int pmmm_plan_create(const pmmm_params *params, void *stream, pmmm_plan *out) {
         return rc;
     }
     rc = alloc_plan(pl, s);
+    if (rc == PMMM_OK) rc = scratch_setup(pl->device);
     if (rc == PMMM_OK && params->n_max > 0) rc = ensure_capacity(pl, params->n_max);
     if (rc == PMMM_OK) {
         GreenArgs g{};
@@ -1064,6 +1156,12 @@ int pmmm_far_f64(pmmm_plan plan, int64_t n, const double *x, const double *y, co
                  const double *q, double *phi, double *gx, double *gy, double *gz,
                  void *stream) {
     return call_impl<double>(plan, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+}
+
+int pmmm_far_f32_noalloc(pmmm_plan plan, int64_t n, const float *x, const float *y,
+                         const float *z, const float *q, float *phi, float *gx, float *gy,
+                         float *gz, void *stream) {
+    return far_noalloc(plan, n, x, y, z, q, phi, gx, gy, gz, stream);
 }
 
 int pmmm_total_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, const float *z,
