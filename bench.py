@@ -297,6 +297,9 @@ def main():
                          "remaining configurations")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the plan-time launch-shape autotuner (single-system workloads)")
+    ap.add_argument("--column-kernel", default=None,
+                    choices=["tile", "stream1", "stream2", "stream4"],
+                    help="fix the column-kernel form instead of tuning it")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "benchmark (calibration of the HBM traffic counters)")
@@ -347,7 +350,10 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.set_stream(stream)
     tuning = None
-    if not args.no_autotune:
+    if args.column_kernel is not None:
+        plan.set_tuning(column_kernel=args.column_kernel)
+        tuning = plan.tuning()
+    elif not args.no_autotune:
         # plan-time choice of launch shapes on this workload (not timed)
         tuning = plan.autotune(x, y, z, q, out=out)
 
@@ -425,7 +431,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "boundary": boundary, "n_particles": N,
                    "cells": f"{n}^3", "fft_mesh": f"{nf}^3", "p": p, "cutoff": 2,
-                   "tuning": {"column_width": tuning[0], "p2m_lanes": tuning[1]} if tuning else None,
+                   "tuning": tuning,
                    "parallelism": "single GPU"},
         "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],
                     "max": step_ms[-1], "events": K},

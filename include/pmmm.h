@@ -225,18 +225,43 @@ int pmmm_total_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
 /* Launch-shape autotuner.  Runs the far field (pmmm_far_f32 or _f64 by the
  * plan's precision, same arguments and meaning) on the caller's particles,
  * timing with HIP events the P2M stage for each number of lanes per cell
- * (4, 8, 16, 32), then the column stage (FFT along z, M2L) for each number of
- * columns per block (the widest that fits LDS, half and a quarter of it);
+ * (4, 8, 16, 32), then the column stage (FFT along z, M2L) for each kernel
+ * form and, for the staged tile, each number of columns per block (the
+ * widest that fits LDS, half and a quarter of it);
  * every candidate runs in three interleaved rounds of five calls and its
  * shortest stage time counts.  The fastest of each is kept for later calls on
  * this plan.  Synchronises the stream; the outputs hold the result of the
  * last trial; stage profiling enabled by the caller is suspended meanwhile
  * (its accumulated times are kept).  Shapes change only the order of
- * floating-point sums.  pmmm_plan_get_tuning reports the kept shape (0: the
- * untuned default). */
+ * floating-point sums.  The column stage is timed for every kernel form that
+ * fits the plan (PMMM_COLUMN_*, below; the tile form at each width).
+ * pmmm_plan_get_tuning reports the kept shapes. */
 int pmmm_plan_autotune(pmmm_plan plan, int64_t n, const void *x, const void *y, const void *z,
                        const void *q, void *phi, void *gx, void *gy, void *gz, void *stream);
-int pmmm_plan_get_tuning(pmmm_plan plan, int *column_width, int *p2m_lanes);
+
+/* Forms of the column kernel (FFT along z, wave-space M2L, inverse FFT):
+ * the transfer-kernel tile of w columns staged in LDS, or the kernel values
+ * streamed from memory at each thread's frequency with one column per block
+ * and each thread running 1, 2 or 4 of the four row subsets of the M2L
+ * (less LDS per block, so several blocks share a compute unit). */
+enum {
+    PMMM_COLUMN_DEFAULT = 0,
+    PMMM_COLUMN_TILE = 1,
+    PMMM_COLUMN_STREAM_1 = 2,
+    PMMM_COLUMN_STREAM_2 = 3,
+    PMMM_COLUMN_STREAM_4 = 4
+};
+/* Launch shapes of a plan; 0 in any field means the library's default. */
+typedef struct {
+    int column_kernel; /* PMMM_COLUMN_* */
+    int column_width;  /* columns per block of PMMM_COLUMN_TILE (power of two) */
+    int p2m_lanes;     /* lanes per cell of the light P2M path: 4, 8, 16, 32 or 64 */
+} pmmm_tuning;
+/* The kept shapes (zeros until set or tuned). */
+int pmmm_plan_get_tuning(pmmm_plan plan, pmmm_tuning *out);
+/* Set shapes, e.g. ones saved from an earlier pmmm_plan_autotune: PMMM_EINVAL
+ * for a form or width that does not fit this plan, or lanes outside the list. */
+int pmmm_plan_set_tuning(pmmm_plan plan, const pmmm_tuning *in);
 
 /* Synchronise the plan's last stream and report a device-side condition
  * (PMMM_EDOMAIN for an out-of-box open-boundary particle) since the last call

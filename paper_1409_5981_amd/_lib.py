@@ -29,7 +29,7 @@ EXPORTS = [
     "pmmm_near_f32", "pmmm_near_f64", "pmmm_total_f32", "pmmm_total_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
     "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
-    "pmmm_plan_autotune", "pmmm_plan_get_tuning",
+    "pmmm_plan_autotune", "pmmm_plan_get_tuning", "pmmm_plan_set_tuning",
     "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
     "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
     "pmmm_error_string", "pmmm_last_error",
@@ -46,6 +46,14 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("images", ctypes.c_int),
         ("n_max", ctypes.c_int64),
     ]
+
+
+COLUMN_KERNELS = {"default": 0, "tile": 1, "stream1": 2, "stream2": 3, "stream4": 4}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("column_kernel", ctypes.c_int), ("column_width", ctypes.c_int),
+                ("p2m_lanes", ctypes.c_int)]
 
 
 class PMMMError(RuntimeError):
@@ -109,8 +117,10 @@ def load():
     L.pmmm_plan_read_profile.restype = ci
     L.pmmm_plan_autotune.argtypes = [vp, i64] + [vp] * 8 + [vp]
     L.pmmm_plan_autotune.restype = ci
-    L.pmmm_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.pmmm_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.pmmm_plan_get_tuning.restype = ci
+    L.pmmm_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.pmmm_plan_set_tuning.restype = ci
     L.pmmm_batch_create.argtypes = [ci, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     L.pmmm_batch_create.restype = ci
     L.pmmm_batch_destroy.argtypes = [vp]
@@ -303,7 +313,7 @@ class Plan:
 
     def autotune(self, x, y, z, q, out=None, stream=None):
         """Time the candidate launch shapes on these particles and keep the
-        fastest; returns (column width, P2M lanes per cell)."""
+        fastest; returns the kept shapes as a dict (see tuning())."""
         n = self._inputs(x, y, z, q)
         out = self._outputs(out, n, x.device)
         _check(load().pmmm_plan_autotune(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(),
@@ -312,9 +322,17 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        w, g = ctypes.c_int(), ctypes.c_int()
-        _check(load().pmmm_plan_get_tuning(self._h, ctypes.byref(w), ctypes.byref(g)))
-        return w.value, g.value
+        """{"column_kernel": name, "column_width": w, "p2m_lanes": g} (0 / "default":
+        the library's choice)."""
+        t = Tuning()
+        _check(load().pmmm_plan_get_tuning(self._h, ctypes.byref(t)))
+        names = {v: k for k, v in COLUMN_KERNELS.items()}
+        return {"column_kernel": names.get(t.column_kernel, str(t.column_kernel)),
+                "column_width": t.column_width, "p2m_lanes": t.p2m_lanes}
+
+    def set_tuning(self, column_kernel="default", column_width=0, p2m_lanes=0):
+        t = Tuning(COLUMN_KERNELS[column_kernel], int(column_width), int(p2m_lanes))
+        _check(load().pmmm_plan_set_tuning(self._h, ctypes.byref(t)))
 
     def set_profiling(self, stages):
         """Enable HIP-event timing for the named stages (see STAGES)."""

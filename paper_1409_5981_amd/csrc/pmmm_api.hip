@@ -77,7 +77,7 @@ struct Plan {
     unsigned *mtmap = nullptr;    // t-matrix map in MFMA fragment order
     double *mqr2 = nullptr, *mqtot = nullptr;
     // tuned launch shapes (0: defaults)
-    int tune_col_w = 0, tune_group = 0;
+    int tune_col_w = 0, tune_group = 0, tune_col_kernel = 0;
     // stage timing
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -183,11 +183,9 @@ static int validate(const pmmm_params *prm, std::string &why) {
         why = "FFT mesh too large for the library (FP32: nf <= 128, FP64: nf <= 64)";
         return PMMM_EUNSUPPORTED;
     }
-    // the column kernel keeps the spectra and kernel tile of at least one
-    // column in LDS (160 KB per CU)
-    const size_t lds = column_shape(prm->p, nf, prm->precision == PMMM_F64 ? 8 : 4, nullptr, nullptr);
-    if (lds == 0) {
-        why = "order too high for this FFT mesh: the column kernel's tile exceeds 160 KB of LDS";
+    // the column kernel keeps at least one column's spectra in LDS (160 KB per CU)
+    if (column_default_kernel(prm->p, nf, prm->precision == PMMM_F64 ? 8 : 4) == 0) {
+        why = "order too high for this FFT mesh: one column's spectra exceed 160 KB of LDS";
         return PMMM_EUNSUPPORTED;
     }
     return PMMM_OK;
@@ -464,6 +462,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         f.qr2_partial = pl->qr2_partial;
         f.sums = pl->sums;
         f.col_w = pl->tune_col_w;
+        f.col_kernel = pl->tune_col_kernel;
         for (int st = 0; st < 3; ++st) {
             StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s, timed);
             PMMM_HIP(launch_conv_stage<T>(f, st, s));
@@ -756,11 +755,19 @@ static int time_stage(pmmm_plan_s *pl, int stage, int reps, int64_t n, const T *
 template <typename T>
 static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, const T *z,
                          const T *q, T *phi, T *gx, T *gy, T *gz, hipStream_t s) {
-    int wmax = 1, rs = 1;
-    if (column_shape(pl->p, pl->nf, pl->tsize, &wmax, &rs) == 0) return PMMM_EUNSUPPORTED;
-    std::vector<int> ws = {wmax};
-    if (wmax >= 2) ws.push_back(wmax / 2);
-    if (wmax >= 4) ws.push_back(wmax / 4);
+    // column candidates: (form, width)
+    std::vector<std::pair<int, int>> cand;
+    {
+        int wmax = 1, rs = 1;
+        if (column_shape(pl->p, pl->nf, pl->tsize, &wmax, &rs) > 0) {
+            cand.push_back({PMMM_COLUMN_TILE, wmax});
+            if (wmax >= 2) cand.push_back({PMMM_COLUMN_TILE, wmax / 2});
+            if (wmax >= 4) cand.push_back({PMMM_COLUMN_TILE, wmax / 4});
+        }
+        for (int kind : {PMMM_COLUMN_STREAM_1, PMMM_COLUMN_STREAM_2, PMMM_COLUMN_STREAM_4})
+            if (column_kernel_fits(kind, pl->p, pl->nf, pl->tsize)) cand.push_back({kind, 0});
+    }
+    if (cand.empty()) return PMMM_EUNSUPPORTED;
     const int gs[4] = {4, 8, 16, 32};
     constexpr int kRounds = 3, kReps = 5;
     // the caller's own stage profiling (if any) is set aside meanwhile
@@ -768,8 +775,9 @@ static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, con
     if (rc != PMMM_OK) return rc;
     const unsigned mask = pl->prof_mask;
     float tg[4] = {1e30f, 1e30f, 1e30f, 1e30f};
-    std::vector<float> tw(ws.size(), 1e30f);
-    pl->tune_col_w = wmax;
+    std::vector<float> tw(cand.size(), 1e30f);
+    pl->tune_col_kernel = 0;
+    pl->tune_col_w = 0;
     for (int r = 0; r < kRounds && rc == PMMM_OK; ++r) {
         for (int k = 0; k < 4 && rc == PMMM_OK; ++k) {
             pl->tune_group = gs[k];
@@ -783,18 +791,20 @@ static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, con
         if (tg[k] < tg[bg]) bg = k;
     pl->tune_group = gs[bg];
     for (int r = 0; r < kRounds && rc == PMMM_OK; ++r) {
-        for (size_t k = 0; k < ws.size() && rc == PMMM_OK; ++k) {
-            pl->tune_col_w = ws[k];
+        for (size_t k = 0; k < cand.size() && rc == PMMM_OK; ++k) {
+            pl->tune_col_kernel = cand[k].first;
+            pl->tune_col_w = cand[k].second;
             float t = 0.f;
             rc = time_stage<T>(pl, PMMM_STAGE_COLUMN, kReps, n, x, y, z, q, phi, gx, gy, gz, s, &t);
             tw[k] = t < tw[k] ? t : tw[k];
         }
     }
     size_t bw = 0;
-    for (size_t k = 1; k < ws.size(); ++k)
+    for (size_t k = 1; k < cand.size(); ++k)
         if (tw[k] < tw[bw]) bw = k;
     pl->prof_mask = mask;
-    pl->tune_col_w = rc == PMMM_OK ? ws[bw] : 0;
+    pl->tune_col_kernel = rc == PMMM_OK ? cand[bw].first : 0;
+    pl->tune_col_w = rc == PMMM_OK ? cand[bw].second : 0;
     pl->tune_group = rc == PMMM_OK ? gs[bg] : 0;
     return rc;
 }
@@ -1308,13 +1318,44 @@ int pmmm_plan_autotune(pmmm_plan plan, int64_t n, const void *x, const void *y, 
                                 (float *)gz, s);
 }
 
-int pmmm_plan_get_tuning(pmmm_plan plan, int *column_width, int *p2m_lanes) {
-    if (!plan) {
-        set_error("plan is NULL");
+int pmmm_plan_get_tuning(pmmm_plan plan, pmmm_tuning *out) {
+    if (!plan || !out) {
+        set_error("plan or out is NULL");
         return PMMM_EINVAL;
     }
-    if (column_width) *column_width = plan->tune_col_w;
-    if (p2m_lanes) *p2m_lanes = plan->tune_group;
+    out->column_kernel = plan->tune_col_kernel;
+    out->column_width = plan->tune_col_w;
+    out->p2m_lanes = plan->tune_group;
+    return PMMM_OK;
+}
+
+int pmmm_plan_set_tuning(pmmm_plan plan, const pmmm_tuning *in) {
+    if (!plan || !in) {
+        set_error("plan or in is NULL");
+        return PMMM_EINVAL;
+    }
+    const int kind = in->column_kernel;
+    if (kind != 0 && !column_kernel_fits(kind, plan->p, plan->nf, plan->tsize)) {
+        set_error("column kernel form unknown or not fitting this plan");
+        return PMMM_EINVAL;
+    }
+    if (in->column_width != 0) {
+        int wmax = 0, rs = 0;
+        const int w = in->column_width;
+        if (kind != PMMM_COLUMN_TILE || w < 0 || (w & (w - 1)) != 0 ||
+            column_shape(plan->p, plan->nf, plan->tsize, &wmax, &rs) == 0 || w > wmax) {
+            set_error("column width needs the tile form and a power of two that fits LDS");
+            return PMMM_EINVAL;
+        }
+    }
+    const int g = in->p2m_lanes;
+    if (g != 0 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64) {
+        set_error("p2m_lanes must be 0, 4, 8, 16, 32 or 64");
+        return PMMM_EINVAL;
+    }
+    plan->tune_col_kernel = kind;
+    plan->tune_col_w = in->column_width;
+    plan->tune_group = g;
     return PMMM_OK;
 }
 

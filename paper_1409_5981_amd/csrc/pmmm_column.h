@@ -444,6 +444,211 @@ __global__ void __launch_bounds__(PO <= 6 ? 512 : 256, (PO == 7 && sizeof(T) == 
     }
 }
 
+// ------------------------------------------- streamed-kernel column variant
+// For large FFT meshes the block's transfer-kernel tile (Q x (nf/2+1) values
+// per column) would fill most of the LDS, leaving room for one block per CU.
+// This variant reads the kernel values straight from the stored quadrant at
+// the thread's frequency (lanes at consecutive kz read consecutive addresses
+// of a column's [Q][nhp] slab), one order ahead of their use, so LDS holds
+// only the twiddles and one column's spectra and several blocks share a CU.
+// Each thread runs RSP of the kRowSplit row subsets one after another and
+// keeps their results in registers until every read of the moment spectra
+// is done; they then overwrite the spectra in place.
+
+// Next order >= from whose kernel values subset S needs (2 PO + 1: none).
+__host__ __device__ constexpr int next_order(int PO, int RS, int S, int from) {
+    for (int NN = from; NN <= 2 * PO; ++NN)
+        if (subset_needs(PO, RS, S, NN)) return NN;
+    return 2 * PO + 1;
+}
+
+// Stored kernel values of order NN (component j = NN^2 + k at gp[j * gstride]).
+template <int NN, typename T>
+__device__ __forceinline__ void load_order(const T *__restrict__ gp, int gstride, T *raw) {
+    static_for<0, 2 * NN + 1>([&](auto ik) {
+        constexpr int k = decltype(ik)::value;
+        raw[k] = gp[(NN * NN + k) * gstride];
+    });
+}
+
+// Orders NN, next_order(NN + 1), ... of subset S: the values of the next
+// needed order are loaded before this order's products are issued.
+template <int PO, int NN, int RS, int S, typename T>
+struct M2LOrdersG {
+    __device__ static __forceinline__ void run(const T *__restrict__ gp, int gstride, int flip,
+                                               const cplx<T> *mcol, int mstride, cplx<T> *acc,
+                                               const T *raw) {
+        constexpr int NX = next_order(PO, RS, S, NN + 1);
+        constexpr int NXL = NX <= 2 * PO ? 2 * NX + 1 : 1;
+        T nxt[NXL];
+        if constexpr (NX <= 2 * PO) load_order<NX, T>(gp, gstride, nxt);
+        T g[2 * NN + 1];
+        static_for<0, 2 * NN + 1>([&](auto ik) {
+            constexpr int k = decltype(ik)::value;
+            constexpr int kk = k - NN;
+            constexpr int odd_z = (NN + (kk < 0 ? -kk : kk)) & 1;
+            const int neg = ((flip & 1) && kk < 0) ^ ((flip & 2) && odd_z);
+            g[k] = neg ? -raw[k] : raw[k];
+        });
+        m2l_order<PO, NN, RS, S, T>(g, mcol, mstride, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (NX <= 2 * PO)
+            M2LOrdersG<PO, NX, RS, S, T>::run(gp, gstride, flip, mcol, mstride, acc, nxt);
+    }
+};
+
+// As m2l_rows, with the kernel values streamed from global memory.
+template <int PO, int RS, int S, typename T>
+__device__ __forceinline__ void m2l_rows_g(const T *__restrict__ gp, int gstride, int flip,
+                                           const cplx<T> *mcol, int stride, DCCorr dc,
+                                           cplx<T> *res) {
+    constexpr int P = nreal(PO);
+    constexpr int N0 = next_order(PO, RS, S, 0);
+    cplx<T> acc[P];
+    static_for<0, P>([&](auto ia) { acc[decltype(ia)::value] = {T(0), T(0)}; });
+    if constexpr (N0 <= 2 * PO) {
+        T raw[2 * N0 + 1];
+        load_order<N0, T>(gp, gstride, raw);
+        M2LOrdersG<PO, N0, RS, S, T>::run(gp, gstride, flip, mcol, stride, acc, raw);
+    }
+    static_for<0, PO + 1>([&](auto il) {
+        constexpr int l = decltype(il)::value;
+        if constexpr (order_subset(PO, RS, l) == S) {
+            static_for<-l, l + 1>([&](auto im) {
+                constexpr int m = decltype(im)::value;
+                constexpr int a = ridx(l, m);
+                const cplx<T> v = acc[a];
+                cplx<T> o = (l & 1) ? cplx<T>{-v.im, v.re} : v;
+                if (dc.on) {
+                    if constexpr (a == 0) o.re += T(dc.l00);
+                    if constexpr (PO >= 1 && a == ridx(1, 0)) o.re += T(dc.l10);
+                    if constexpr (PO >= 1 && a == ridx(1, 1)) o.re += T(dc.l11re);
+                    if constexpr (PO >= 1 && a == ridx(1, -1)) o.re += T(dc.l11im);
+                }
+                res[subset_rank(PO, RS, S, a)] = o;
+            });
+        }
+    });
+}
+
+// One block per column; NSUB = kRowSplit / RSP threads per frequency, so
+// NSUB * nf threads.  LDS: twiddles and the column's spectra buf[P][nf+1].
+template <int PO, typename T, int RSP>
+__global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP >= 2 ? 2 : 1)
+    k_column_g(int nz, int logn, int ncol, int ngroups, const T *__restrict__ green,
+               cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw_g, int periodic,
+               const double *__restrict__ qr2_partial, double *__restrict__ sums) {
+    constexpr int P = nreal(PO);
+    constexpr int Q = nreal(2 * PO);
+    constexpr int RS = kRowSplit;
+    constexpr int NSUB = RS / RSP;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ls = lds_line(nf);
+    cplx<T> *tw = (cplx<T> *)lds_raw;
+    cplx<T> *buf = tw + nf / 2;
+    // XCD-aware order: consecutive columns stay on one XCD (blocks are dealt
+    // round-robin over the 8 XCDs)
+    const int per_xcd = (ngroups + 7) / 8;
+    const int col = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (col >= ngroups) return;
+    {
+        const int64_t sy = blockIdx.y;
+        spec += sy * P * nz * ncol;
+        qr2_partial += sy * nz;
+        sums += sy * 8;
+    }
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    // spectra of z < nz: thread element u is component s_b0 + u * s_db at z = s_z
+    const int s_z = tid & (nf - 1);
+    const int s_b0 = tid >> logn;
+    const int s_db = nthr >> logn;
+    const bool s_live = s_z < nz;
+    const int s_g = (s_z < nz ? s_z : nz - 1) * ncol + col;
+    auto s_comp = [&](int u) { return s_b0 + u * s_db < P ? s_b0 + u * s_db : P - 1; };
+    constexpr int SB = 2 * kColumnLoadBatch;
+    {
+        const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];   // nf/2 <= blockDim.x
+        for (int u0 = 0; s_b0 + u0 * s_db < P; u0 += SB) {
+            cplx<T> sv[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) sv[u] = spec[s_comp(u0 + u) * nz * ncol + s_g];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) asm volatile("" ::"v"(sv[u].re), "v"(sv[u].im));
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                buf[s_comp(u0 + u) * ls + s_z] =
+                    cplx<T>{s_live ? sv[u].re : T(0), s_live ? sv[u].im : T(0)};
+        }
+        if (tid < nf / 2) tw[tid] = twv;
+    }
+    __syncthreads();
+    fft_lines<T, false>(buf, logn, P, ls, 1, tw, tid, nthr);
+    // M2L: thread = (row-subset group sub, frequency kz)
+    const int sub = tid >> logn, kz = tid & (nf - 1);
+    DCCorr dcc = {false, 0.0, 0.0, 0.0, 0.0};
+    if (periodic && col == 0 && kz == 0) {
+        // zero frequency: M~_c(0) = sum over cells of M_c (real)
+        const cplx<T> *m0 = buf;
+        const double V = (double)nf * nf * nf;  // box volume in cell units (nf = n)
+        const double pi = 3.14159265358979323846;
+        double qr2 = 0.0;
+        for (int z = 0; z < nz; ++z) qr2 += qr2_partial[z];
+        const double m10 = PO >= 1 ? (double)m0[ridx(1, 0) * ls].re : 0.0;
+        const double m11 = PO >= 1 ? (double)m0[ridx(1, 1) * ls].re : 0.0;
+        const double m1m1 = PO >= 1 ? (double)m0[ridx(1, -1) * ls].re : 0.0;
+        dcc.l00 = 2.0 * pi / (3.0 * V) * qr2 * V;
+        dcc.l10 = 4.0 * pi / (3.0 * V) * m10 * V;
+        dcc.l11re = 8.0 * pi / (3.0 * V) * m11 * V;
+        dcc.l11im = -8.0 * pi / (3.0 * V) * m1m1 * V;
+        dcc.on = true;
+        if (sub == 0) sums[0] = (double)m0[0].re;  // total charge
+    }
+    {
+        const int ky = small_div(col, 1.0f / (float)nh), kx = col - ky * nh;
+        const int kyr = ky <= nf / 2 ? ky : nf - ky;
+        const int kzr = kz <= nf / 2 ? kz : nf - kz;
+        const int flip = (ky > nf / 2 ? 1 : 0) | (kz > nf / 2 ? 2 : 0);
+        const T *gp = green + (int64_t)(kyr * nh + kx) * Q * nhp + kzr;
+        const cplx<T> *mp = buf + kz;
+        cplx<T> res[RSP][subset_rows_max(PO, RS)];
+        static_for<0, RSP>([&](auto ik) {
+            constexpr int k = decltype(ik)::value;
+            static_for<0, NSUB>([&](auto is) {
+                constexpr int s = decltype(is)::value;
+                if (sub == s) m2l_rows_g<PO, RS, k * NSUB + s, T>(gp, nhp, flip, mp, ls, dcc, res[k]);
+            });
+        });
+        __syncthreads();  // every read of the moment spectra is done
+        static_for<0, RSP>([&](auto ik) {
+            constexpr int k = decltype(ik)::value;
+            static_for<0, NSUB>([&](auto is) {
+                constexpr int s = decltype(is)::value;
+                if (sub == s) m2l_put<PO, RS, k * NSUB + s, T>(res[k], buf + kz, ls);
+            });
+        });
+    }
+    __syncthreads();
+    fft_lines<T, true>(buf, logn, P, ls, 1, tw, tid, nthr);
+    // local spectra of z < nz back to HBM, LDS reads in batches
+    const int lognz = __builtin_ctz(nz);
+    const int o_z = tid & (nz - 1);
+    const int o_a0 = tid >> lognz;
+    const int o_da = nthr >> lognz;
+    for (int u0 = 0; o_a0 + u0 * o_da < P; u0 += kColumnLoadBatch) {
+        cplx<T> v[kColumnLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kColumnLoadBatch; ++u) {
+            const int a = o_a0 + (u0 + u) * o_da < P ? o_a0 + (u0 + u) * o_da : P - 1;
+            v[u] = buf[a * ls + o_z];
+        }
+#pragma unroll
+        for (int u = 0; u < kColumnLoadBatch; ++u) {
+            const int a = o_a0 + (u0 + u) * o_da;
+            if (a < P) spec[(a * nz + o_z) * ncol + col] = v[u];
+        }
+    }
+}
+
 // --------------------------------------------------------------- launcher
 inline int column_ilog2(int v) {
     int l = 0;
@@ -451,8 +656,32 @@ inline int column_ilog2(int v) {
     return l;
 }
 
+template <int PO, typename T, int RSP>
+hipError_t column_launch_g(const FFTArgs &a, hipStream_t s) {
+    const int nf = a.nf, logn = column_ilog2(nf), nh = nf / 2 + 1, ncol = nf * nh;
+    const size_t lds = column_g_lds(PO, nf, sizeof(T));
+    if (lds == 0 || nf < 16 || nf > 128) return hipErrorInvalidValue;
+    const int threads = (kRowSplit / RSP) * nf;
+    if (threads < 64 || threads > (kRowSplit / RSP) * 128) return hipErrorInvalidValue;
+    const int grid = ((ncol + 7) / 8) * 8;
+    hipError_t e = lds <= 65536 ? hipSuccess : set_max_lds((const void *)k_column_g<PO, T, RSP>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_column_g<PO, T, RSP>), dim3(grid, a.nsys > 0 ? a.nsys : 1), dim3(threads),
+                       lds, s, a.n, logn, ncol, ncol, (const T *)a.green, (cplx<T> *)a.spec,
+                       (const cplx<T> *)a.tw, a.open ? 0 : 1, a.qr2_partial, a.sums);
+    return hipGetLastError();
+}
+
 template <int PO, typename T>
 hipError_t column_launch(const FFTArgs &a, hipStream_t s) {
+    const int kind = a.col_kernel > 0 ? a.col_kernel : column_default_kernel(PO, a.nf, sizeof(T));
+    switch (kind) {
+        case PMMM_COLUMN_STREAM_1: return column_launch_g<PO, T, 1>(a, s);
+        case PMMM_COLUMN_STREAM_2: return column_launch_g<PO, T, 2>(a, s);
+        case PMMM_COLUMN_STREAM_4: return column_launch_g<PO, T, 4>(a, s);
+        case PMMM_COLUMN_TILE: break;
+        default: return hipErrorInvalidValue;
+    }
     const int nf = a.nf, logn = column_ilog2(nf), nh = nf / 2 + 1, ncol = nf * nh;
     int w = 1, rs = 1;
     size_t lds = column_shape(PO, nf, sizeof(T), &w, &rs);

@@ -410,6 +410,23 @@ inline size_t column_lds_w(int p, int nf, size_t tsize, int w, int *rs_out) {
     return lds;
 }
 
+// LDS bytes of the streamed-kernel column variant (twiddles and one column's
+// spectra; 0 if over 160 KB).
+inline size_t column_g_lds(int p, int nf, size_t tsize) {
+    const size_t P = (size_t)(p + 1) * (p + 1);
+    const size_t lds = P * (size_t)lds_line(nf) * 2 * tsize + (size_t)nf / 2 * 2 * tsize;
+    return lds > 160 * 1024 ? 0 : lds;
+}
+
+// Column kernel forms (PMMM_COLUMN_* in pmmm.h): the kernel tile staged in
+// LDS for w columns per block, or streamed from memory with each thread
+// running 1, 2 or 4 row subsets.
+inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize);
+// Default form: the streamed kernel with two subsets per thread for FFT
+// meshes of 64 points and more (or wherever the staged tile does not fit),
+// else the staged tile.
+inline int column_default_kernel(int p, int nf, size_t tsize);
+
 // Widest shape that fits (w from 64 / nf down to 1).
 inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out) {
     for (int w = nf >= 64 ? 1 : 64 / nf; w >= 1; w >>= 1) {
@@ -421,6 +438,26 @@ inline size_t column_shape(int p, int nf, size_t tsize, int *w_out, int *rs_out)
             return lds;
         }
     }
+    return 0;
+}
+
+inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize) {
+    switch (kind) {
+        case PMMM_COLUMN_TILE: return column_shape(p, nf, tsize, nullptr, nullptr) > 0;
+        case PMMM_COLUMN_STREAM_1:
+        case PMMM_COLUMN_STREAM_2:
+        case PMMM_COLUMN_STREAM_4:
+            return nf >= 16 && column_g_lds(p, nf, tsize) > 0 &&
+                   (kColumnRowSplit >> (kind - PMMM_COLUMN_STREAM_1)) * nf >= 64;
+        default: return false;
+    }
+}
+
+inline int column_default_kernel(int p, int nf, size_t tsize) {
+    if (nf >= 64 && column_kernel_fits(PMMM_COLUMN_STREAM_2, p, nf, tsize))
+        return PMMM_COLUMN_STREAM_2;
+    if (column_kernel_fits(PMMM_COLUMN_TILE, p, nf, tsize)) return PMMM_COLUMN_TILE;
+    if (column_kernel_fits(PMMM_COLUMN_STREAM_2, p, nf, tsize)) return PMMM_COLUMN_STREAM_2;
     return 0;
 }
 
@@ -496,6 +533,7 @@ struct FFTArgs {
     void *L;                        // [P][n^3]
     int nsys;                       // batch of systems at fixed strides (1: one)
     int col_w;                      // columns per column-kernel block (0: largest that fits)
+    int col_kernel;                 // PMMM_COLUMN_* form (0: column_default_kernel)
 };
 // stage 0: forward plane FFTs, 1: column FFT + M2L + inverse, 2: inverse planes
 template <typename T>

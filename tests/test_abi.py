@@ -43,7 +43,7 @@ def test_parameter_validation_on_host(lib):
     assert workspace_bytes(make_params(8, 11, "open"), 10) == 0                    # p > PMAX
     assert workspace_bytes(make_params(8, 10, "open"), 10) > 0                     # p = PMAX
     assert workspace_bytes(make_params(16, 9, "periodic"), 10) > 0
-    assert workspace_bytes(make_params(64, 10, "open"), 10) == 0                   # tile > LDS
+    assert workspace_bytes(make_params(64, 10, "open"), 10) > 0                    # streamed column kernel
     assert workspace_bytes(make_params(12, 3, "periodic"), 10) == 0                # not 2^k
     assert workspace_bytes(make_params(128, 3, "open"), 10) == 0                   # nf > 128
     assert workspace_bytes(make_params(64, 3, "open", precision="f64"), 10) == 0   # nf > 64 (FP64)

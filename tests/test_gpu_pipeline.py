@@ -276,16 +276,51 @@ def test_full_size_sampled(name, gen):
 
 
 def test_autotune_keeps_parity():
-    """The launch-shape autotuner picks a column width and P2M lane count; the
-    far field computed with the kept shape still matches the oracle."""
+    """The launch-shape autotuner picks a column-kernel form (and width) and
+    a P2M lane count; the far field computed with the kept shape still
+    matches the oracle."""
     import torch
     from paper_1409_5981_amd._lib import Plan
     ps = _small(20000, 16, 5, "periodic", 17, np.float32)
     plan = Plan(16, 5, "periodic")
     t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (ps.x, ps.y, ps.z, ps.q)]
-    w, g = plan.autotune(*t)
-    assert w in (1, 2, 4) and g in (4, 8, 16, 32), (w, g)
-    print(f"autotune: column width {w}, P2M lanes {g}")
+    tu = plan.autotune(*t)
+    assert tu["p2m_lanes"] in (4, 8, 16, 32), tu
+    assert tu["column_kernel"] in ("tile", "stream1", "stream2", "stream4"), tu
+    print(f"autotune: {tu}")
     res, _ = gpu_far(ps, "f32", plan=plan)
     ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
     assert_parity(res, ref.phi, ref.grad, "f32", "autotuned")
+
+
+@pytest.mark.parametrize("form", ["tile", "stream1", "stream2", "stream4"])
+@pytest.mark.parametrize("boundary,n_cells,p", [("open", 32, 5), ("periodic", 64, 3),
+                                                ("open", 16, 7), ("periodic", 32, 6)])
+def test_column_kernel_forms(form, boundary, n_cells, p):
+    """Every column-kernel form that fits a plan gives the oracle's far field
+    (the staged tile and the streamed kernel with 1, 2 or 4 row subsets per
+    thread); forms that do not fit are refused by pmmm_plan_set_tuning."""
+    import torch
+    from paper_1409_5981_amd._lib import PMMM_EINVAL, Plan, PMMMError
+    ps = _small(30000, n_cells, p, boundary, 18, np.float32)
+    plan = Plan(n_cells, p, boundary)
+    try:
+        plan.set_tuning(column_kernel=form)
+    except PMMMError as e:
+        assert e.code == PMMM_EINVAL
+        pytest.skip(f"{form} does not fit {boundary} {n_cells}^3 p={p}")
+    res, _ = gpu_far(ps, "f32", plan=plan)
+    ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+    assert_parity(res, ref.phi, ref.grad, "f32", f"column form {form} {boundary} n={n_cells} p={p}")
+
+
+@pytest.mark.parametrize("p", [7, 8, 10])
+def test_open_64_high_orders(p):
+    """Open 64^3 cells (128^3 FFT) at orders whose transfer-kernel tile does
+    not fit LDS: the streamed column kernel makes them possible (moments of
+    a seeded sample of 4096 particles checked against the oracle)."""
+    ps = _small(200000, 64, p, "open", 19, np.float32)
+    res, _ = gpu_far(ps, "f32")
+    idx = np.sort(np.random.default_rng(19).choice(ps.n, 4096, replace=False))
+    ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps), eval_idx=idx)
+    assert_parity(res, ref.phi, ref.grad, "f32", f"open 64^3 p={p}", idx=idx)
