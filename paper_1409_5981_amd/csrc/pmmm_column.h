@@ -534,7 +534,7 @@ __device__ __forceinline__ void m2l_rows_g(const T *__restrict__ gp, int gstride
 // One block per column; NSUB = kRowSplit / RSP threads per frequency, so
 // NSUB * nf threads.  LDS: twiddles and the column's spectra buf[P][nf+1].
 template <int PO, typename T, int RSP>
-__global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP >= 2 ? 2 : 1)
+__global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T) == 4 ? 3 : 2) : (RSP == 4 ? 2 : 1))
     k_column_g(int nz, int logn, int ncol, int ngroups, const T *__restrict__ green,
                cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw_g, int periodic,
                const double *__restrict__ qr2_partial, double *__restrict__ sums) {

@@ -308,13 +308,19 @@ def test_column_kernel_forms(form, boundary, n_cells, p):
         plan.set_tuning(column_kernel=form)
     except PMMMError as e:
         assert e.code == PMMM_EINVAL
-        pytest.skip(f"{form} does not fit {boundary} {n_cells}^3 p={p}")
+        pytest.skip(f"the {form} form does not fit {boundary} {n_cells}^3 p={p} (refused as it should)")
     res, _ = gpu_far(ps, "f32", plan=plan)
-    ref = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+    key = (boundary, n_cells, p)
+    if key not in _FORM_REFS:
+        _FORM_REFS[key] = opm.far_field(ps.pos, ps.q.astype(np.float64), oracle_cfg(ps))
+    ref = _FORM_REFS[key]
     assert_parity(res, ref.phi, ref.grad, "f32", f"column form {form} {boundary} n={n_cells} p={p}")
 
 
-@pytest.mark.parametrize("p", [7, 8, 10])
+_FORM_REFS = {}
+
+
+@pytest.mark.parametrize("p", [7, 10])
 def test_open_64_high_orders(p):
     """Open 64^3 cells (128^3 FFT) at orders whose transfer-kernel tile does
     not fit LDS: the streamed column kernel makes them possible (moments of
