@@ -60,14 +60,14 @@ struct Plan {
     size_t tsize;
     // plan-lifetime buffers
     void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
-    int *count = nullptr, *start = nullptr, *dense_cells = nullptr, *small = nullptr;
-    int *tile_sums = nullptr, *sstart = nullptr;
+    int *start = nullptr, *dense_cells = nullptr, *small = nullptr;
     int *tile_first = nullptr;  // near field: first tile of every row of cells
     double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
     int64_t cap = 0, last_n = -1;
     int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr, *pos = nullptr;
     int *tile_row = nullptr;    // near field: row of every tile
+    int *count = nullptr, *tile_sums = nullptr;  // radix-sort histograms and scan scratch
     void *sorted = nullptr, *staged = nullptr;   // staged: out4<T>[cap] sorted-order results
     hipStream_t last_stream = nullptr;
     // multi-charge workspace (chunks of up to kMultiMaxSets sets)
@@ -224,9 +224,7 @@ static size_t plan_bytes(const Plan *pl) {
     b += (size_t)(pl->P + 1) * pl->K * t;                // M
     b += (size_t)pl->P * pl->n * pl->ncol * c;           // spectra
     b += (size_t)pl->P * pl->K * t;                      // L
-    const size_t KS = (size_t)pl->K * count_shards(pl->K);   // binning sub-counters
-    b += (KS + pl->K + 1 + pl->K + 8 + scan_tiles((int64_t)KS)) * sizeof(int);  // counts, starts, dense, small, tiles
-    if (KS > (size_t)pl->K) b += (KS + 1) * sizeof(int);                         // sub-counter starts
+    b += ((size_t)pl->K + 1 + pl->K + 8) * sizeof(int);                           // starts, dense list, small
     b += 8 * sizeof(double) + (size_t)pl->n * sizeof(double);                     // sums, plane sums
     b += (size_t)pl->n * pl->n * sizeof(int);                                     // near-field row tiles
     return b;
@@ -234,7 +232,8 @@ static size_t plan_bytes(const Plan *pl) {
 
 static size_t particle_bytes(const Plan *pl, int64_t n) {
     return (size_t)n * (5 * sizeof(int) + 8 * pl->tsize) +
-           sizeof(int) * (size_t)near_tile_capacity(n, pl->n);
+           sizeof(int) * (size_t)(near_tile_capacity(n, pl->n) + bin_hist_ints(n) +
+                                  bin_scan_tiles(n));
 }
 
 static void free_particles(Plan *pl) {
@@ -246,7 +245,10 @@ static void free_particles(Plan *pl) {
     hipFree(pl->pos);
     hipFree(pl->staged);
     hipFree(pl->tile_row);
+    hipFree(pl->count);
+    hipFree(pl->tile_sums);
     pl->cell_of = pl->slot = pl->perm = pl->scell = pl->pos = pl->tile_row = nullptr;
+    pl->count = pl->tile_sums = nullptr;
     pl->sorted = pl->staged = nullptr;
     pl->cap = 0;
 }
@@ -267,6 +269,8 @@ static int ensure_capacity(Plan *pl, int64_t n) {
     PMMM_HIP(hipMalloc(&pl->pos, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&pl->staged, 4 * pl->tsize * n));
     PMMM_HIP(hipMalloc(&pl->tile_row, sizeof(int) * near_tile_capacity(n, pl->n)));
+    PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * bin_hist_ints(n)));
+    PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * bin_scan_tiles(n)));
     pl->cap = n;
     return PMMM_OK;
 }
@@ -280,11 +284,8 @@ static void destroy(Plan *pl) {
     hipFree(pl->M);
     hipFree(pl->spec);
     hipFree(pl->L);
-    hipFree(pl->count);
     hipFree(pl->start);
     hipFree(pl->dense_cells);
-    hipFree(pl->tile_sums);
-    hipFree(pl->sstart);
     hipFree(pl->small);
     hipFree(pl->tile_first);
     hipFree(pl->sums);
@@ -320,17 +321,12 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->M, (size_t)(pl->P + 1) * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
     PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
-    const int64_t KS = pl->K * count_shards(pl->K);   // binning sub-counters
-    PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * KS));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
     PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
-    PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * scan_tiles(KS)));
-    if (KS > pl->K) PMMM_HIP(hipMalloc(&pl->sstart, sizeof(int) * (KS + 1)));
     PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] near tiles
     PMMM_HIP(hipMalloc(&pl->tile_first, sizeof(int) * (size_t)pl->n * pl->n));
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
     PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
-    PMMM_HIP(hipMemsetAsync(pl->count, 0, sizeof(int) * KS, s));
     PMMM_HIP(hipMemsetAsync(pl->small, 0, sizeof(int) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->sums, 0, sizeof(double) * 8, s));
     PMMM_HIP(hipMemsetAsync(pl->M, 0, (size_t)(pl->P + 1) * pl->K * t, s));
@@ -353,13 +349,13 @@ enum CallMode { kFar = 0, kNear = 1, kTotal = 2 };
 // Per-particle device buffers of one call: the plan's own (grown on demand)
 // or, for the allocation-free entry point, slices of the static scratch.
 struct PBuf {
-    int *cell_of, *slot, *perm, *scell, *pos, *tile_row;
+    int *cell_of, *slot, *perm, *scell, *pos, *tile_row, *count, *tile_sums;
     void *sorted, *staged;
 };
 
 static PBuf plan_pbuf(const Plan *pl) {
-    return PBuf{pl->cell_of, pl->slot,   pl->perm,   pl->scell,
-                pl->pos,     pl->tile_row, pl->sorted, pl->staged};
+    return PBuf{pl->cell_of,  pl->slot,  pl->perm,      pl->scell,  pl->pos,
+                pl->tile_row, pl->count, pl->tile_sums, pl->sorted, pl->staged};
 }
 
 // ext == nullptr: the plan's particle buffers, grown to n if needed (which
@@ -417,7 +413,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.periodic = !pl->open;
         b.cell_of = pb.cell_of;
         b.slot = pb.slot;
-        b.count = pl->count;
+        b.count = pb.count;
         b.start = pl->start;
         b.scell = pb.scell;
         b.perm = pb.perm;
@@ -425,8 +421,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
         b.pos = staged ? pb.pos : nullptr;
-        b.tile_sums = pl->tile_sums;
-        b.sstart = pl->sstart;
+        b.tile_sums = pb.tile_sums;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pb.sorted;
         PMMM_HIP(launch_bin<T>(b, s));
@@ -439,8 +434,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
             m.ncell = pl->n;
             m.group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
             m.dense_blocks = dense_blocks_for(n);
-            // meshes scanned inside the scatter kernel reset their counts here
-            m.zero_count = (n > 0 && pl->K <= 4096) ? pl->count : nullptr;
+            m.zero_count = nullptr;
             m.start = pl->start;
             m.dense_cells = pl->dense_cells;
             m.dense_count = pl->small;
@@ -493,10 +487,6 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
             if (mode == kFar && staged)
                 PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz, 0, s));
         }
-    } else if (n > 0 && pl->K <= 4096) {
-        // no P2M to reset the counts of an in-block-scanned mesh (a fill
-        // kernel, not a memset node, so that the call can be graph-captured)
-        PMMM_HIP(launch_zero_ints(pl->count, pl->K, s));
     }
     if (mode != kFar) {
         StageTimer t(pl, PMMM_STAGE_NEAR, s, timed);
@@ -530,8 +520,12 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
 constexpr int64_t kNoAllocMaxN = PMMM_NOALLOC_MAX_N;
 constexpr size_t kNoAllocInts = (size_t)kNoAllocMaxN * sizeof(int);
 constexpr size_t kNoAllocRecs = (size_t)kNoAllocMaxN * sizeof(particle4<float>);
-constexpr size_t kNoAllocBytes = 5 * kNoAllocInts + 2 * kNoAllocRecs;
-static_assert(kNoAllocInts % 256 == 0 && kNoAllocRecs % 256 == 0, "256-byte aligned regions");
+// radix-sort histograms (512 buckets x 64 tiles) and their scan scratch
+constexpr size_t kNoAllocHist = 512 * ((kNoAllocMaxN + 4095) / 4096) * sizeof(int);
+constexpr size_t kNoAllocSums = 256;
+constexpr size_t kNoAllocBytes = 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist + kNoAllocSums;
+static_assert(kNoAllocInts % 256 == 0 && kNoAllocRecs % 256 == 0 && kNoAllocHist % 256 == 0,
+              "256-byte aligned regions");
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
@@ -588,7 +582,14 @@ static int far_noalloc(pmmm_plan_s *pl, int64_t n, const float *x, const float *
     pb.pos = (int *)(b + 4 * kNoAllocInts);
     pb.sorted = b + 5 * kNoAllocInts;
     pb.staged = b + 5 * kNoAllocInts + kNoAllocRecs;
+    pb.count = (int *)(b + 5 * kNoAllocInts + 2 * kNoAllocRecs);
+    pb.tile_sums = (int *)(b + 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist);
     pb.tile_row = nullptr;  // far field only
+    if ((size_t)bin_hist_ints(n) * sizeof(int) > kNoAllocHist ||
+        (size_t)bin_scan_tiles(n) * sizeof(int) > kNoAllocSums) {
+        set_error("radix-sort scratch exceeds the static array");
+        return PMMM_EINVAL;
+    }
     return call_impl<float>(pl, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream, &pb);
 }
 
@@ -681,7 +682,6 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         b.dense_cells = pl->dense_cells;
         b.dense_count = pl->small;
         b.tile_sums = pl->tile_sums;
-        b.sstart = pl->sstart;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         PMMM_HIP(launch_bin<float>(b, s));
@@ -697,7 +697,7 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         a.ld = nsets;
         a.start = pl->start;
         a.perm = pl->perm;
-        a.zero_count = (s0 == 0 && n > 0 && pl->K <= 4096) ? pl->count : nullptr;
+        a.zero_count = nullptr;
         a.sorted = pl->sorted;
         a.q = q + s0;
         a.M = pl->mM;
@@ -817,8 +817,9 @@ static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, con
 struct BatchClass {
     pmmm_plan_s *plan = nullptr;    // transfer kernel, twiddles, constants
     std::vector<int> members;       // system indices in the caller's order
-    int *count = nullptr, *start = nullptr, *dense = nullptr, *small = nullptr;
-    int *tile_sums = nullptr, *sstart = nullptr;
+    int *start = nullptr, *dense = nullptr, *small = nullptr;
+    int *count = nullptr, *tile_sums = nullptr;   // radix-sort scratch, sized by max_np
+    int64_t hist_cap = -1;          // max_np the radix scratch holds
     void *M = nullptr, *spec = nullptr, *L = nullptr;
     double *qr2 = nullptr, *sums = nullptr;
     int64_t *d_prange = nullptr;    // [2 members]
@@ -868,7 +869,6 @@ static void batch_destroy(pmmm_batch_s *b) {
         hipFree(c.start);
         hipFree(c.dense);
         hipFree(c.tile_sums);
-        hipFree(c.sstart);
         hipFree(c.small);
         hipFree(c.M);
         hipFree(c.spec);
@@ -891,12 +891,8 @@ static void batch_destroy(pmmm_batch_s *b) {
 static int batch_alloc_class(BatchClass &c, hipStream_t s) {
     const Plan *pl = c.plan;
     const size_t ns = c.members.size(), K = pl->K, P = pl->P, t = pl->tsize;
-    const size_t KS = K * (size_t)count_shards((int64_t)K);   // binning sub-counters
-    PMMM_HIP(hipMalloc(&c.count, sizeof(int) * KS * ns));
     PMMM_HIP(hipMalloc(&c.start, sizeof(int) * (K + 1) * ns));
     PMMM_HIP(hipMalloc(&c.dense, sizeof(int) * K * ns));
-    PMMM_HIP(hipMalloc(&c.tile_sums, sizeof(int) * scan_tiles((int64_t)KS) * ns));
-    if (KS > K) PMMM_HIP(hipMalloc(&c.sstart, sizeof(int) * (KS + 1) * ns));
     PMMM_HIP(hipMalloc(&c.small, sizeof(int) * 8 * ns));
     PMMM_HIP(hipMalloc(&c.M, t * (P + 1) * K * ns));
     PMMM_HIP(hipMalloc(&c.spec, 2 * t * P * pl->n * pl->ncol * ns));
@@ -904,7 +900,6 @@ static int batch_alloc_class(BatchClass &c, hipStream_t s) {
     PMMM_HIP(hipMalloc(&c.qr2, sizeof(double) * pl->n * ns));
     PMMM_HIP(hipMalloc(&c.sums, sizeof(double) * 8 * ns));
     PMMM_HIP(hipMalloc(&c.d_prange, sizeof(int64_t) * 2 * ns));
-    PMMM_HIP(hipMemsetAsync(c.count, 0, sizeof(int) * KS * ns, s));
     PMMM_HIP(hipMemsetAsync(c.small, 0, sizeof(int) * 8 * ns, s));
     PMMM_HIP(hipMemsetAsync(c.M, 0, t * (P + 1) * K * ns, s));
     return PMMM_OK;
@@ -959,7 +954,6 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         bn.dense_cells = c.dense;
         bn.dense_count = c.small;
         bn.tile_sums = c.tile_sums;
-        bn.sstart = c.sstart;
         bn.dense_threshold = kDenseThreshold;
         bn.sorted = b->sorted;
         bn.prange = c.d_prange;
@@ -971,7 +965,7 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         m.ncell = pl->n;
         m.group = group_for((double)c.tot_np / ((double)pl->K * ns));
         m.dense_blocks = dense_blocks_for(c.max_np);
-        m.zero_count = (c.max_np > 0 && pl->K <= 4096) ? c.count : nullptr;
+        m.zero_count = nullptr;
         m.start = c.start;
         m.dense_cells = c.dense;
         m.dense_count = c.small;
@@ -1072,6 +1066,17 @@ static int batch_far(pmmm_batch_s *b, const int64_t *offsets, const float *x, co
             PMMM_HIP(hipMemcpyAsync(c.d_prange, h, sizeof(int64_t) * 2 * c.members.size(),
                                     hipMemcpyHostToDevice, s));
             PMMM_HIP(hipStreamSynchronize(s));
+            if (c.count == nullptr || bin_hist_ints(c.max_np) > bin_hist_ints(c.hist_cap)) {
+                // radix-sort scratch for the largest system of the class
+                const size_t ns = c.members.size();
+                hipFree(c.count);
+                hipFree(c.tile_sums);
+                c.count = c.tile_sums = nullptr;
+                c.hist_cap = -1;
+                PMMM_HIP(hipMalloc(&c.count, sizeof(int) * bin_hist_ints(c.max_np) * ns));
+                PMMM_HIP(hipMalloc(&c.tile_sums, sizeof(int) * bin_scan_tiles(c.max_np) * ns));
+                c.hist_cap = c.max_np;
+            }
         }
         b->offsets.assign(offsets, offsets + b->nsys + 1);
     }

@@ -1,29 +1,38 @@
 // Cell binning (Sec. 2.1 requires that the particles of every cell be known,
-// which takes linear time): a counting sort by cell.
-//   k_bin_count   cell of each particle, per-cell counts (int atomics) and the
-//                 particle's slot inside its cell; meshes above 16^3 count
-//                 in S sub-counters per cell (particle i in sub-counter
-//                 i mod S), stored sub-counter-major ([S][K], each in its own
-//                 cache line), so that a cell holding a large share of the
-//                 particles does not serialise all of them on one line
-//   k_bin_tile_sums, k_bin_scan_tiles
-//                 exclusive scan of the counts -> cell_start in tiles of 4096
-//                 cells, resets the counts for the next call, lists cells above
-//                 the dense threshold (meshes up to 16^3 skip it: each scatter
-//                 block scans the counts itself and the P2M kernel resets them)
-//   k_bin_scatter sorted structure-of-arrays record (offset from the cell
-//                 centre in cell units, charge), permutation and cell of each
-//                 sorted slot
+// which takes linear time): a stable sort of the particles by cell index, as
+// a least-significant-digit radix sort with digits of at most 9 bits, so the
+// particles of a cell keep the caller's order and every result is bitwise
+// reproducible (no atomics decide an order).
+//   k_rb_keys     cell of each particle (keys) and its index (values) in
+//                 tiles of 4096, and the tile histogram of the first digit
+//   k_rb_hist     tile histogram of a later digit
+//   k_rb_scan_sums, k_rb_scan
+//                 exclusive scan of the histograms in bucket-major order (so
+//                 tile t's bucket-d elements start after every smaller digit
+//                 and after bucket d of the tiles before t)
+//   k_rb_scatter  stable scatter of one digit: in rounds of 1024 elements,
+//                 ranks among equal digits from wave ballots plus the counts
+//                 of the earlier waves and rounds of the tile; the last
+//                 digit's pass writes the sorted cell, the permutation, the
+//                 sorted record (offset from the cell centre in cell units,
+//                 charge) and, on request, each particle's sorted slot
+//   k_rb_bounds   start of every cell by binary search in the sorted cells,
+//                 and the list of cells above the dense threshold
 // Cell index: I = floor(r n / b) per axis, clamped to [0, n-1]; periodic
 // positions are first wrapped into the box (in cell units).
 //
 // Batches: blockIdx.y selects one of several independent systems on meshes of
 // the same size; prange[2s], prange[2s+1] bound system s's particles in the
-// caller's arrays (null: one system, particles [0, n)), and its cell arrays
-// sit at fixed strides (count K, start K + 1, dense list K, small 8).
+// caller's arrays (null: one system, particles [0, n)), and its per-system
+// arrays sit at fixed strides (start K + 1, dense list K, small 8,
+// histograms bin_hist_ints(max_np), scan sums bin_scan_tiles(max_np)).
 #include "pmmm_internal.h"
 
 namespace pmmm {
+
+constexpr int kRadixTile = 4096;   // elements per tile (1024 threads x 4 rounds)
+constexpr int kRadixMaxBits = 9;   // bucket count per pass at most 512
+constexpr int kRadixBuckets = 1 << kRadixMaxBits;
 
 template <typename T>
 __device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, int &ic, T &u,
@@ -40,132 +49,133 @@ __device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, in
     u = s - T(i) - T(0.5);
 }
 
+__device__ __forceinline__ void sys_offsets(int64_t hist_ints, int64_t &hoff) {
+    hoff = (int64_t)blockIdx.y * hist_ints;
+}
+
+__global__ void k_rb_reset_dense(int nsys, int *__restrict__ dense_count) {
+    for (int sy = threadIdx.x; sy < nsys; sy += blockDim.x) dense_count[(int64_t)sy * 8] = 0;
+}
+
+// Tile histogram of digit (key >> shift) & (2^bits - 1) into LDS, written to
+// hist[d * tiles + t] (every block writes all 2^bits of its entries).
+__device__ __forceinline__ void write_tile_hist(int *s_hist, int nb, int *__restrict__ hist,
+                                                int tiles, int t) {
+    __syncthreads();
+    for (int d = threadIdx.x; d < nb; d += blockDim.x) hist[(int64_t)d * tiles + t] = s_hist[d];
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_bin_count(const int64_t *__restrict__ prange, int64_t n,
-                                                   const T *__restrict__ x,
-                                                   const T *__restrict__ y,
-                                                   const T *__restrict__ z, T inv_h, int nc,
-                                                   int periodic, int *__restrict__ cell_of,
-                                                   int *__restrict__ slot,
-                                                   int *__restrict__ count, int logS,
-                                                   int *__restrict__ flag) {
+__global__ void __launch_bounds__(1024) k_rb_keys(const int64_t *__restrict__ prange, int64_t n,
+                                                  const T *__restrict__ x, const T *__restrict__ y,
+                                                  const T *__restrict__ z, T inv_h, int nc,
+                                                  int periodic, int *__restrict__ keys,
+                                                  int *__restrict__ vals, int *__restrict__ hist,
+                                                  int64_t hist_ints, int tiles, int bits,
+                                                  int *__restrict__ flag,
+                                                  int *__restrict__ dense_count) {
+    __shared__ int s_hist[kRadixBuckets];
     int64_t p0, np;
     sys_range(prange, n, p0, np);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= np) return;
-    const int64_t i = p0 + j;
-    count += ((int64_t)blockIdx.y * nc * nc * nc) << logS;
-    // the three loads are issued together, ahead of the branches below
-    const T xv = x[i], yv = y[i], zv = z[i];
-    asm volatile("" ::"v"(xv), "v"(yv), "v"(zv));
-    int ix, iy, iz, out = 0;
-    T ux, uy, uz;
-    cell_coord(xv, inv_h, nc, periodic, ix, ux, out);
-    cell_coord(yv, inv_h, nc, periodic, iy, uy, out);
-    cell_coord(zv, inv_h, nc, periodic, iz, uz, out);
+    const int nb = 1 << bits, t = blockIdx.x;
+    for (int d = threadIdx.x; d < nb; d += blockDim.x) s_hist[d] = 0;
+    if (t == 0 && threadIdx.x == 0) dense_count[(int64_t)blockIdx.y * 8] = 0;
+    __syncthreads();
+    // the loads of the four rounds are issued together
+    T xv[4], yv[4], zv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + threadIdx.x;
+        const int64_t i = p0 + (j < np ? j : (np > 0 ? np - 1 : 0));
+        xv[r] = np > 0 ? x[i] : T(0);
+        yv[r] = np > 0 ? y[i] : T(0);
+        zv[r] = np > 0 ? z[i] : T(0);
+    }
+    int out = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + threadIdx.x;
+        if (j >= np) continue;
+        int ix, iy, iz;
+        T ux, uy, uz;
+        cell_coord(xv[r], inv_h, nc, periodic, ix, ux, out);
+        cell_coord(yv[r], inv_h, nc, periodic, iy, uy, out);
+        cell_coord(zv[r], inv_h, nc, periodic, iz, uz, out);
+        const int c = (iz * nc + iy) * nc + ix;
+        keys[p0 + j] = c;
+        vals[p0 + j] = (int)(p0 + j);
+        atomicAdd(&s_hist[c & (nb - 1)], 1);
+    }
     if (out) *flag = 1;
-    const int c = (iz * nc + iy) * nc + ix;
-    cell_of[i] = c;
-    slot[i] = atomicAdd(&count[(int)(j & ((1 << logS) - 1)) * (nc * nc * nc) + c], 1);
+    int64_t hoff;
+    sys_offsets(hist_ints, hoff);
+    write_tile_hist(s_hist, nb, hist + hoff, tiles, t);
 }
 
-// Four consecutive counters e .. e + 3 of the scan order (cell-major: cell
-// e >> logS, sub-counter e mod S) from their sub-counter-major storage; with
-// S = 1 an aligned int4.  e is a multiple of 4 and the four share one cell
-// when S > 1.
-__device__ __forceinline__ int4 load_counts4(const int *count, int e, int logS, int K) {
-    if (logS == 0) return *(const int4 *)(count + e);
-    const int c = e >> logS, sh = e & ((1 << logS) - 1);
-    const int *p = count + (int64_t)sh * K + c;
-    return make_int4(p[0], p[K], p[2 * K], p[3 * K]);
-}
-__device__ __forceinline__ void zero_counts4(int *count, int e, int logS, int K) {
-    if (logS == 0) {
-        *(int4 *)(count + e) = make_int4(0, 0, 0, 0);
-        return;
+__global__ void __launch_bounds__(1024) k_rb_hist(const int64_t *__restrict__ prange, int64_t n,
+                                                  const int *__restrict__ keys,
+                                                  int *__restrict__ hist, int64_t hist_ints,
+                                                  int tiles, int shift, int bits) {
+    __shared__ int s_hist[kRadixBuckets];
+    int64_t p0, np;
+    sys_range(prange, n, p0, np);
+    const int nb = 1 << bits, t = blockIdx.x;
+    for (int d = threadIdx.x; d < nb; d += blockDim.x) s_hist[d] = 0;
+    __syncthreads();
+    int kv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + threadIdx.x;
+        kv[r] = j < np ? keys[p0 + j] : -1;
     }
-    int *p = count + (int64_t)(e & ((1 << logS) - 1)) * K + (e >> logS);
-    p[0] = 0;
-    p[K] = 0;
-    p[2 * K] = 0;
-    p[3 * K] = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (kv[r] >= 0) atomicAdd(&s_hist[(kv[r] >> shift) & (nb - 1)], 1);
+    int64_t hoff;
+    sys_offsets(hist_ints, hoff);
+    write_tile_hist(s_hist, nb, hist + hoff, tiles, t);
 }
 
-// Exclusive scan of the counts in tiles of kScanTile, one 1024-thread block
-// per tile: k_bin_tile_sums adds up every tile, then k_bin_scan_tiles scans
-// its tile starting from the sum of the tiles before it, resets the counts
-// for the next call and lists the cells above the dense threshold (in no
-// particular order: each dense cell is reduced by one block in a fixed order).
-constexpr int kScanTile = 4096;
-
-__global__ void __launch_bounds__(1024) k_bin_tile_sums(int K, int logS,
-                                                        const int *__restrict__ count,
-                                                        int *__restrict__ tile_sums,
-                                                        int *__restrict__ dense_count) {
-    const int ntiles = gridDim.x, L = K << logS;
-    {
-        const int64_t sy = blockIdx.y;
-        count += sy * L;
-        tile_sums += sy * ntiles;
-        dense_count += sy * 8;
-    }
+// Exclusive scan of the L = buckets x tiles histogram entries of every
+// system, in place, in scan tiles of 4096: per-tile sums, then each tile
+// scanned from the sum of the tiles before it.
+__global__ void __launch_bounds__(1024) k_rb_scan_sums(int64_t L, int64_t hist_ints,
+                                                       const int *__restrict__ hist,
+                                                       int *__restrict__ sums) {
     __shared__ int wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    // L = S n^3 with n >= 4 is a multiple of 64: four counters per thread
-    const int idx = blockIdx.x * kScanTile + tid * 4;
+    hist += (int64_t)blockIdx.y * hist_ints;
+    sums += (int64_t)blockIdx.y * gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * 4096 + tid * 4;
     int v = 0;
-    if (idx < L) {
-        const int4 c4 = load_counts4(count, idx, logS, K);
-        v = (c4.x + c4.y) + (c4.z + c4.w);
-    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < L) v += hist[base + k];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) wsum[wid] = v;
     __syncthreads();
     if (tid == 0) {
-        int t = 0;
-        for (int w = 0; w < 16; ++w) t += wsum[w];
-        tile_sums[blockIdx.x] = t;
-        if (blockIdx.x == 0) *dense_count = 0;
+        int a = 0;
+        for (int w = 0; w < 16; ++w) a += wsum[w];
+        sums[blockIdx.x] = a;
     }
 }
 
-// L = S K counters (S = 1 or kCountShards) scanned in cell-major order; with
-// S > 1 sstart receives the start of every sub-counter (in that order) and
-// start that of every cell (its first sub-counter), and a cell's two halves
-// sit in the two lanes of an even-odd pair.
-__global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *__restrict__ count,
-                                                         const int *__restrict__ tile_sums,
-                                                         int *__restrict__ start,
-                                                         int *__restrict__ sstart, int dense_thr,
-                                                         int *__restrict__ dense_cells,
-                                                         int *__restrict__ dense_count) {
-    const int ntiles = gridDim.x, t = blockIdx.x;
-    const int L = K << logS;
-    {
-        const int64_t sy = blockIdx.y;
-        count += sy * L;
-        tile_sums += sy * ntiles;
-        start += sy * (K + 1);
-        sstart += sy * (L + 1);
-        dense_cells += sy * K;
-        dense_count += sy * 8;
-    }
+__global__ void __launch_bounds__(1024) k_rb_scan(int64_t L, int64_t hist_ints,
+                                                  int *__restrict__ hist,
+                                                  const int *__restrict__ sums) {
     __shared__ int wtot[16];
     __shared__ int pre_s;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int idx = t * kScanTile + tid * 4;
-    int v[4] = {0, 0, 0, 0};
-    if (idx < L) {
-        const int4 c4 = load_counts4(count, idx, logS, K);
-        v[0] = c4.x;
-        v[1] = c4.y;
-        v[2] = c4.z;
-        v[3] = c4.w;
-    }
-    // sum of the tiles before this one
+    hist += (int64_t)blockIdx.y * hist_ints;
+    sums += (int64_t)blockIdx.y * gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * 4096 + tid * 4;
+    int v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = base + k < L ? hist[base + k] : 0;
     int pre = 0;
-    for (int k = tid; k < t; k += 1024) pre += tile_sums[k];
+    for (int k = tid; k < (int)blockIdx.x; k += 1024) pre += sums[k];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) pre += __shfl_xor(pre, off, 64);
     if (lane == 0) wtot[wid] = pre;
@@ -176,7 +186,6 @@ __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *_
         pre_s = a;
     }
     __syncthreads();
-    // in-tile exclusive scan: wave scan of the thread totals, then the waves
     const int tot = (v[0] + v[1]) + (v[2] + v[3]);
     int inc = tot;
 #pragma unroll
@@ -188,147 +197,146 @@ __global__ void __launch_bounds__(1024) k_bin_scan_tiles(int K, int logS, int *_
     __syncthreads();
     int run = pre_s + inc - tot;
     for (int w = 0; w < wid; ++w) run += wtot[w];
-    if (logS == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (idx + j < L) {
-                start[idx + j] = run;
-                if (v[j] > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = idx + j;
-            }
-            run += v[j];
-        }
-    } else {
-        // kCountShards = 8 sub-counters per cell: lanes 2m and 2m + 1 hold one cell
-        static_assert(kCountShards == 8, "a cell's sub-counters span one lane pair");
-        const int cell_tot = tot + __shfl_xor(tot, 1, 64);
-        if (idx < L && (tid & 1) == 0) {
-            const int cell = idx >> logS;
-            start[cell] = run;
-            if (cell_tot > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = cell;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (idx + j < L) sstart[idx + j] = run;
-            run += v[j];
-        }
-    }
-    if (idx < L) zero_counts4(count, idx, logS, K);
-    if (t == ntiles - 1 && tid == 1023) {
-        start[K] = run;
-        sstart[L] = run;
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < L) hist[base + k] = run;
+        run += v[k];
     }
 }
 
-// Exclusive scan of K <= kInBlockScanMax counts by one 256-thread block into
-// LDS (s_start[0..K]); block 0 also publishes start[] and the dense list.
-constexpr int kInBlockScanMax = 4096;
-
-__device__ void block_scan_small(int K, const int *__restrict__ count, int *s_start,
-                                 int publish, int *__restrict__ start, int dense_thr,
-                                 int *__restrict__ dense_cells, int *__restrict__ dense_count) {
-    __shared__ int wtot[4];
-    __shared__ int ndense;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    constexpr int PER = kInBlockScanMax / 256;  // 16 counts per thread
-    int v[PER], tot = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int idx = tid * PER + j;
-        v[j] = idx < K ? count[idx] : 0;
-        tot += v[j];
-    }
-    int inc = tot;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) wtot[wid] = inc;
-    if (tid == 0) ndense = 0;
-    __syncthreads();
-    int run = inc - tot;
-    for (int w = 0; w < wid; ++w) run += wtot[w];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int idx = tid * PER + j;
-        if (idx < K) {
-            s_start[idx] = run;
-            if (publish) {
-                start[idx] = run;
-                if (v[j] > dense_thr) dense_cells[atomicAdd(&ndense, 1)] = idx;
-            }
-        }
-        run += v[j];
-    }
-    if (tid == 255) {
-        s_start[K] = run;
-        if (publish) start[K] = run;
-    }
-    __syncthreads();
-    if (publish && tid == 0) *dense_count = ndense;
-}
-
-// Scatter into the sorted structure-of-arrays record.  With inblock, every
-// block scans the counts itself (small meshes), else start[] comes from the
-// scan kernel.
-// Sorted slot g of system s is p0 + start[c] + slot: perm[g] holds the
-// particle's index in the caller's arrays, scell[g] its cell.
+// Stable scatter of one digit.  LDS: per-wave digit counts and their
+// exclusive prefixes over the waves of a round, and the tile's running count
+// per digit.  With `last`, the outputs are the sorted cell (keys_out), the
+// permutation (vals_out), the sorted records and, if pos is not null, each
+// particle's sorted slot.
 template <typename T>
-__global__ void __launch_bounds__(256) k_bin_scatter(
-    const int64_t *__restrict__ prange, int64_t n, const T *__restrict__ x,
-    const T *__restrict__ y, const T *__restrict__ z, const T *__restrict__ q, T inv_h, int nc,
-    int periodic, const int *__restrict__ cell_of, const int *__restrict__ slot,
-    int *__restrict__ start, const int *__restrict__ sstart, int logS, int *__restrict__ perm,
-    int *__restrict__ scell, particle4<T> *__restrict__ sorted, int inblock,
-    const int *__restrict__ count, int dense_thr, int *__restrict__ dense_cells,
-    int *__restrict__ dense_count, int *__restrict__ pos) {
-    __shared__ int s_start[kInBlockScanMax + 1];
-    const int K = nc * nc * nc;
-    {
-        const int64_t sy = blockIdx.y;
-        count += sy * K;
-        start += sy * (K + 1);
-        sstart += sy * (((int64_t)K << logS) + 1);
-        dense_cells += sy * K;
-        dense_count += sy * 8;
-    }
+__global__ void __launch_bounds__(1024) k_rb_scatter(
+    const int64_t *__restrict__ prange, int64_t n, const int *__restrict__ keys_in,
+    const int *__restrict__ vals_in, int *__restrict__ keys_out, int *__restrict__ vals_out,
+    const int *__restrict__ offs, int64_t hist_ints, int tiles, int shift, int bits, int last,
+    const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
+    const T *__restrict__ q, T inv_h, int nc, int periodic, particle4<T> *__restrict__ sorted,
+    int *__restrict__ pos) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int nb = 1 << bits;
+    int *cnt = (int *)lds_raw;        // [16][nb] counts of the round
+    int *pre = cnt + 16 * nb;         // [16][nb] exclusive prefixes over waves
+    int *run = pre + 16 * nb;         // [nb] tile running count
     int64_t p0, np;
     sys_range(prange, n, p0, np);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // The particle's inputs are read first (clamped index, so unconditional):
-    // their loads overlap those of the in-block scan.
-    const int64_t i = p0 + (j < np ? j : np - 1);
-    T xv = T(0), yv = T(0), zv = T(0), qv = T(0);
-    int c = 0, sl = 0;
-    if (np > 0) {
-        const T *qp = q != nullptr ? q : x;
-        xv = x[i];
-        yv = y[i];
-        zv = z[i];
-        qv = qp[i];
-        c = cell_of[i];
-        sl = slot[i];
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    offs += (int64_t)blockIdx.y * hist_ints;
+    for (int e = tid; e < 16 * nb; e += 1024) cnt[e] = 0;
+    for (int d = tid; d < nb; d += 1024) run[d] = 0;
+    int kv[4], vv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + tid;
+        const bool act = j < np;
+        kv[r] = act ? keys_in[p0 + j] : 0;
+        vv[r] = act ? vals_in[p0 + j] : 0;
     }
-    if (inblock)
-        block_scan_small(K, count, s_start, blockIdx.x == 0, start, dense_thr, dense_cells,
-                         dense_count);
-    if (j >= np) return;
-    asm volatile("" ::"v"(xv), "v"(yv), "v"(zv), "v"(qv), "v"(c), "v"(sl));
-    int ix, iy, iz, out = 0;
-    particle4<T> r;
-    cell_coord(xv, inv_h, nc, periodic, ix, r.ux, out);
-    cell_coord(yv, inv_h, nc, periodic, iy, r.uy, out);
-    cell_coord(zv, inv_h, nc, periodic, iz, r.uz, out);
-    r.q = q != nullptr ? qv : T(0);
-    // sub-counter of the particle as in k_bin_count (sstart is start when S = 1)
-    const int s =
-        (inblock ? s_start[c] : sstart[(c << logS) + (int)(j & ((1 << logS) - 1))]) + sl;
-    if (s < 0 || (int64_t)s >= np) return;  // only reachable with inconsistent counts
-    const int64_t g = p0 + s;
-    perm[g] = (int)i;
-    scell[g] = c;
-    sorted[g] = r;
-    if (pos != nullptr) pos[i] = (int)g;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + tid;
+        const bool act = j < np;
+        const int d = (kv[r] >> shift) & (nb - 1);
+        // lanes of this wave holding the same digit (active lanes only)
+        uint64_t peers = __ballot(act);
+        for (int b = 0; b < bits; ++b) {
+            const uint64_t m = __ballot(act && ((d >> b) & 1));
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        const int rw = __popcll(peers & lt);
+        if (act && rw == 0) cnt[wid * nb + d] = __popcll(peers);
+        __syncthreads();
+        for (int dd = tid; dd < nb; dd += 1024) {
+            int s = run[dd];
+#pragma unroll
+            for (int w = 0; w < 16; ++w) {
+                const int c = cnt[w * nb + dd];
+                pre[w * nb + dd] = s;
+                cnt[w * nb + dd] = 0;
+                s += c;
+            }
+            run[dd] = s;
+        }
+        __syncthreads();
+        if (act) {
+            const int dest = offs[(int64_t)d * tiles + t] + pre[wid * nb + d] + rw;
+            const int64_t g = p0 + dest;
+            if (!last) {
+                keys_out[g] = kv[r];
+                vals_out[g] = vv[r];
+            } else {
+                const int i = vv[r];
+                int ix, iy, iz, out = 0;
+                particle4<T> rec;
+                cell_coord(x[i], inv_h, nc, periodic, ix, rec.ux, out);
+                cell_coord(y[i], inv_h, nc, periodic, iy, rec.uy, out);
+                cell_coord(z[i], inv_h, nc, periodic, iz, rec.uz, out);
+                rec.q = q != nullptr ? q[i] : T(0);
+                keys_out[g] = kv[r];
+                vals_out[g] = i;
+                sorted[g] = rec;
+                if (pos != nullptr) pos[i] = (int)g;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// start[c] = first sorted slot of the system with cell >= c (relative to the
+// system's first particle), c = 0..K; cells above the dense threshold are
+// listed (in no particular order: each dense cell is reduced by one block in
+// a fixed order).
+__global__ void __launch_bounds__(256) k_rb_bounds(const int64_t *__restrict__ prange, int64_t n,
+                                                   int K, const int *__restrict__ skeys,
+                                                   int *__restrict__ start, int dense_thr,
+                                                   int *__restrict__ dense_cells,
+                                                   int *__restrict__ dense_count) {
+    int64_t p0, np;
+    sys_range(prange, n, p0, np);
+    start += (int64_t)blockIdx.y * (K + 1);
+    dense_cells += (int64_t)blockIdx.y * K;
+    dense_count += (int64_t)blockIdx.y * 8;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > K) return;
+    const int *k = skeys + p0;
+    auto lower = [&](int v) {
+        int lo = 0, hi = (int)np;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (k[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int s0 = lower(c);
+    start[c] = s0;
+    if (c < K) {
+        const int s1 = lower(c + 1);
+        if (s1 - s0 > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = c;
+    }
+}
+
+int64_t bin_hist_ints(int64_t max_np) {
+    const int64_t tiles = max_np > 0 ? (max_np + kRadixTile - 1) / kRadixTile : 1;
+    return (int64_t)kRadixBuckets * tiles;
+}
+int64_t bin_scan_tiles(int64_t max_np) { return (bin_hist_ints(max_np) + 4095) / 4096; }
+
+// Digit widths of the passes for keys below K (at most kRadixMaxBits each,
+// as even as possible).
+static int radix_passes(int K, int widths[8]) {
+    int bits = 0;
+    while ((1 << bits) < K) ++bits;
+    if (bits == 0) bits = 1;
+    const int np = (bits + kRadixMaxBits - 1) / kRadixMaxBits;
+    for (int i = 0; i < np; ++i) widths[i] = bits / np + (i < bits % np ? 1 : 0);
+    return np;
 }
 
 template <typename T>
@@ -337,31 +345,53 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
     const T inv_h = T(a.inv_h);
     const int nsys = a.nsys > 0 ? a.nsys : 1;
     const int64_t maxn = a.prange ? a.max_np : a.n;
-    const int blocks = (int)((maxn + 255) / 256);
-    const int inblock = K <= kInBlockScanMax ? 1 : 0;
-    const int logS = ilog2_shards(count_shards(K));
-    int *sstart = logS ? a.sstart : a.start;
-    if (logS && sstart == nullptr) return hipErrorInvalidValue;
+    const int tiles = (int)(maxn > 0 ? (maxn + kRadixTile - 1) / kRadixTile : 1);
+    const int64_t hist_ints = bin_hist_ints(maxn);
+    int widths[8];
+    const int passes = radix_passes(K, widths);
+    // ping-pong so that the last pass lands in (scell, perm)
+    int *kA = a.cell_of, *vA = a.slot, *kB = a.scell, *vB = a.perm;
+    int *kin = (passes & 1) ? kA : kB, *vin = (passes & 1) ? vA : vB;
     if (maxn > 0) {
-        hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,
+        hipLaunchKernelGGL(k_rb_keys<T>, dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
                            (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
-                           a.periodic, a.cell_of, a.slot, a.count, logS, a.flag);
+                           a.periodic, kin, vin, a.count, hist_ints, tiles, widths[0], a.flag,
+                           a.dense_count);
+        int shift = 0;
+        for (int ps = 0; ps < passes; ++ps) {
+            const int bits = widths[ps];
+            if (ps > 0)
+                hipLaunchKernelGGL(k_rb_hist, dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
+                                   kin, a.count, hist_ints, tiles, shift, bits);
+            const int64_t L = (int64_t)(1 << bits) * tiles;
+            const int st = (int)((L + 4095) / 4096);
+            hipLaunchKernelGGL(k_rb_scan_sums, dim3(st, nsys), dim3(1024), 0, s, L, hist_ints,
+                               a.count, a.tile_sums);
+            hipLaunchKernelGGL(k_rb_scan, dim3(st, nsys), dim3(1024), 0, s, L, hist_ints, a.count,
+                               a.tile_sums);
+            const int last = ps == passes - 1;
+            int *kout = kin == kA ? kB : kA, *vout = vin == vA ? vB : vA;
+            const size_t lds = (size_t)(33 << bits) * sizeof(int);
+            if (lds > 65536) {
+                const hipError_t e = set_max_lds((const void *)k_rb_scatter<T>, lds);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(k_rb_scatter<T>, dim3(tiles, nsys), dim3(1024), lds, s, a.prange,
+                               a.n, kin, vin, kout, vout, a.count, hist_ints, tiles, shift, bits,
+                               last, (const T *)a.x, (const T *)a.y, (const T *)a.z,
+                               (const T *)a.q, inv_h, a.ncell, a.periodic,
+                               (particle4<T> *)a.sorted, a.pos);
+            kin = kout;
+            vin = vout;
+            shift += bits;
+        }
     }
-    if (!inblock || maxn == 0) {
-        const int ntiles = scan_tiles((int64_t)K << logS);
-        hipLaunchKernelGGL(k_bin_tile_sums, dim3(ntiles, nsys), dim3(1024), 0, s, K, logS,
-                           a.count, a.tile_sums, a.dense_count);
-        hipLaunchKernelGGL(k_bin_scan_tiles, dim3(ntiles, nsys), dim3(1024), 0, s, K, logS,
-                           a.count, a.tile_sums, a.start, sstart, a.dense_threshold,
-                           a.dense_cells, a.dense_count);
-    }
-    if (maxn > 0) {
-        hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks, nsys), dim3(256), 0, s, a.prange, a.n,
-                           (const T *)a.x, (const T *)a.y, (const T *)a.z, (const T *)a.q,
-                           inv_h, a.ncell, a.periodic, a.cell_of, a.slot, a.start, sstart, logS,
-                           a.perm, a.scell, (particle4<T> *)a.sorted, inblock, a.count,
-                           a.dense_threshold, a.dense_cells, a.dense_count, a.pos);
-    }
+    // a system with no particles still gets its zero starts; the dense count
+    // of an empty call is reset here
+    if (maxn == 0)
+        hipLaunchKernelGGL(k_rb_reset_dense, dim3(1), dim3(64), 0, s, nsys, a.dense_count);
+    hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s, a.prange,
+                       a.n, K, a.scell, a.start, a.dense_threshold, a.dense_cells, a.dense_count);
     return hipGetLastError();
 }
 

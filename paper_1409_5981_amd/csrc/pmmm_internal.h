@@ -482,11 +482,15 @@ struct BinArgs {
     int ncell;         // cells per axis
     double inv_h;      // n / b
     int periodic;
-    int *cell_of, *slot, *count, *start, *scell, *perm, *flag;
+    // [n] key/value ping-pong arrays of the radix sort; the sorted cell and
+    // the permutation (caller index of every sorted slot) end in scell, perm
+    int *cell_of, *slot, *scell, *perm;
+    int *start;        // [nsys][K + 1] first sorted slot of every cell (system-relative)
+    int *flag;         // set when an open-boundary particle lies outside the box
     int *dense_cells, *dense_count;
-    int *tile_sums;    // [nsys][scan_tiles(S K)] scratch of the multi-block scan
+    int *count;        // [nsys][bin_hist_ints(max_np)] radix histograms / offsets
+    int *tile_sums;    // [nsys][bin_scan_tiles(max_np)] scan scratch
     int *pos;          // [n] sorted slot of each particle in the caller's order (or null)
-    int *sstart;       // [nsys][S K + 1] sub-counter starts (S = count_shards(K) > 1)
     int dense_threshold;
     void *sorted;      // particle4<T>[n]
     // batch of nsys systems on this mesh (prange null: one system of n)
@@ -496,17 +500,9 @@ struct BinArgs {
 };
 template <typename T>
 hipError_t launch_bin(const BinArgs &a, hipStream_t s);
-// Tiles of the multi-block scan of the cell counts.
-inline int scan_tiles(int64_t L) { return (int)((L + 4095) / 4096); }
-// Sub-counters per cell of the binning counts: meshes up to 16^3 count in one
-// (their scan runs inside the scatter blocks), larger ones in 8.
-constexpr int kCountShards = 8;
-inline int count_shards(int64_t K) { return K <= 4096 ? 1 : kCountShards; }
-inline int ilog2_shards(int S) {
-    int l = 0;
-    while ((1 << l) < S) ++l;
-    return l;
-}
+// Radix-sort scratch per system for up to max_np particles.
+int64_t bin_hist_ints(int64_t max_np);
+int64_t bin_scan_tiles(int64_t max_np);
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path

@@ -95,8 +95,8 @@ def test_batch_matches_single_system_path():
 
 def test_batch_graph_capture_and_replay():
     """Eager call, captured call, two replays (with eager work and
-    synchronisations in between), then new offsets: every result against
-    the oracle's."""
+    synchronisations in between), all bitwise equal, then new offsets:
+    every result against the oracle's."""
     import torch
     systems = _mixed(33)
     batch = _batch(systems)
@@ -116,9 +116,10 @@ def test_batch_graph_capture_and_replay():
             _ = (t[0] * 2).sum().item()        # unrelated eager work between replays
     _check(systems, offs, *results[0])
     for phi, grad in results[1:]:
-        assert np.all(np.isfinite(phi))
-        assert exact.rel_rms(grad, results[0][1]) < 1e-6
-        assert exact.rel_rms(phi, results[0][0]) < 1e-6
+        # the binning is a stable sort: the eager call, the captured call and
+        # the replays are bitwise equal
+        assert np.array_equal(phi, results[0][0])
+        assert np.array_equal(grad, results[0][1])
     # new offsets: drop the first 100 particles of system 0
     sub = list(systems)
     sub[0] = systems[0].subset(np.arange(100, systems[0].n))
