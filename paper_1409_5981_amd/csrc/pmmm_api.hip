@@ -424,6 +424,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.tile_sums = pb.tile_sums;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pb.sorted;
+        b.recs = pb.staged;   // free until L2P
         PMMM_HIP(launch_bin<T>(b, s));
     }
     if (mode != kNear) {
@@ -520,9 +521,9 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
 constexpr int64_t kNoAllocMaxN = PMMM_NOALLOC_MAX_N;
 constexpr size_t kNoAllocInts = (size_t)kNoAllocMaxN * sizeof(int);
 constexpr size_t kNoAllocRecs = (size_t)kNoAllocMaxN * sizeof(particle4<float>);
-// radix-sort histograms (512 buckets x 64 tiles) and their scan scratch
-constexpr size_t kNoAllocHist = 512 * ((kNoAllocMaxN + 4095) / 4096) * sizeof(int);
-constexpr size_t kNoAllocSums = 256;
+// radix-sort histograms (512 buckets per tile) and their scan scratch
+constexpr size_t kNoAllocHist = (size_t)bin_hist_ints(kNoAllocMaxN) * sizeof(int);
+constexpr size_t kNoAllocSums = ((size_t)bin_scan_tiles(kNoAllocMaxN) * sizeof(int) + 255) / 256 * 256;
 constexpr size_t kNoAllocBytes = 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist + kNoAllocSums;
 static_assert(kNoAllocInts % 256 == 0 && kNoAllocRecs % 256 == 0 && kNoAllocHist % 256 == 0,
               "256-byte aligned regions");
@@ -684,6 +685,7 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         b.tile_sums = pl->tile_sums;
         b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
+        b.recs = pl->staged;
         PMMM_HIP(launch_bin<float>(b, s));
     }
     for (int s0 = 0; s0 < nsets; s0 += kMultiMaxSets) {
@@ -831,7 +833,7 @@ struct pmmm_batch_s {
     std::vector<BatchClass> cls;
     int64_t cap = 0;
     int *cell_of = nullptr, *slot = nullptr, *perm = nullptr, *scell = nullptr;
-    void *sorted = nullptr;
+    void *sorted = nullptr, *recs = nullptr;
     int *flag = nullptr;
     int64_t *h_prange = nullptr;    // pinned staging [2 nsys]
     std::vector<int64_t> offsets;   // of the last call
@@ -883,6 +885,7 @@ static void batch_destroy(pmmm_batch_s *b) {
     hipFree(b->perm);
     hipFree(b->scell);
     hipFree(b->sorted);
+    hipFree(b->recs);
     hipFree(b->flag);
     if (b->h_prange) hipHostFree(b->h_prange);
     delete b;
@@ -918,12 +921,15 @@ static int batch_capacity(pmmm_batch_s *b, int64_t n) {
     hipFree(b->perm);
     hipFree(b->scell);
     hipFree(b->sorted);
+    hipFree(b->recs);
+    b->sorted = b->recs = nullptr;
     b->cap = 0;
     PMMM_HIP(hipMalloc(&b->cell_of, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&b->slot, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&b->perm, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&b->scell, sizeof(int) * n));
     PMMM_HIP(hipMalloc(&b->sorted, sizeof(float) * 4 * n));
+    PMMM_HIP(hipMalloc(&b->recs, sizeof(float) * 4 * n));
     b->cap = n;
     return PMMM_OK;
 }
@@ -956,6 +962,7 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         bn.tile_sums = c.tile_sums;
         bn.dense_threshold = kDenseThreshold;
         bn.sorted = b->sorted;
+        bn.recs = b->recs;
         bn.prange = c.d_prange;
         bn.nsys = ns;
         bn.max_np = c.max_np;

@@ -2,22 +2,26 @@
 // which takes linear time): a stable sort of the particles by cell index, as
 // a least-significant-digit radix sort with digits of at most 9 bits, so the
 // particles of a cell keep the caller's order and every result is bitwise
-// reproducible (no atomics decide an order).
-//   k_rb_keys     cell of each particle (keys) and its index (values) in
-//                 tiles of 4096, and the tile histogram of the first digit
-//   k_rb_hist     tile histogram of a later digit
-//   k_rb_scan_sums, k_rb_scan
+// reproducible (no atomics decide an order).  Each pass carries the key (cell),
+// the value (caller index) and the particle record, so no pass gathers.
+//   k_rb_hist     tile histogram of one digit; the first pass computes the
+//                 cells from the positions (and flags open-boundary particles
+//                 outside the box)
+//   k_rb_scan1 or k_rb_scan_sums + k_rb_scan
 //                 exclusive scan of the histograms in bucket-major order (so
 //                 tile t's bucket-d elements start after every smaller digit
 //                 and after bucket d of the tiles before t)
-//   k_rb_scatter  stable scatter of one digit: in rounds of 1024 elements,
-//                 ranks among equal digits from wave ballots plus the counts
-//                 of the earlier waves and rounds of the tile; the last
-//                 digit's pass writes the sorted cell, the permutation, the
-//                 sorted record (offset from the cell centre in cell units,
-//                 charge) and, on request, each particle's sorted slot
-//   k_rb_bounds   start of every cell by binary search in the sorted cells,
-//                 and the list of cells above the dense threshold
+//   k_rb_scatter  stable scatter of one digit: each wave ranks a contiguous
+//                 chunk of the tile (wave ballots for equal digits plus the
+//                 wave's running count per digit), one prefix over the waves
+//                 per tile, then the tile is put in digit order in LDS and
+//                 written out in runs; the first pass builds the keys and
+//                 records from the positions, the last writes the sorted cell,
+//                 the permutation, the sorted records and, on request, each
+//                 particle's sorted slot
+//   k_rb_bounds   start of every cell by binary search among the sorted slots
+//                 of its last digit, and the list of cells above the dense
+//                 threshold
 // Cell index: I = floor(r n / b) per axis, clamped to [0, n-1]; periodic
 // positions are first wrapped into the box (in cell units).
 //
@@ -30,9 +34,8 @@
 
 namespace pmmm {
 
-constexpr int kRadixTile = 4096;   // elements per tile (1024 threads x 4 rounds)
-constexpr int kRadixMaxBits = 9;   // bucket count per pass at most 512
 constexpr int kRadixBuckets = 1 << kRadixMaxBits;
+constexpr int kScanOneBlock = 16384;   // histograms up to this size: one-block scan
 
 template <typename T>
 __device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, int &ic, T &u,
@@ -49,96 +52,123 @@ __device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, in
     u = s - T(i) - T(0.5);
 }
 
-__device__ __forceinline__ void sys_offsets(int64_t hist_ints, int64_t &hoff) {
-    hoff = (int64_t)blockIdx.y * hist_ints;
+// Tile handled by block b of G: blocks are dealt to the 8 XCDs in turn, and
+// this mapping gives each XCD a contiguous range of tiles, so the runs that
+// neighbouring tiles write side by side meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int q = G >> 3, r = G & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// LDS of the scatter: the per-wave counts [16][nb], later reused as the
+// staging area of one tile, then ls[nb], goff[nb], wtot[16].
+template <typename T, int R>
+__host__ __device__ constexpr size_t scatter_region(int bits) {
+    return (size_t)16 * ((size_t)1 << bits) * sizeof(int) >
+                   (size_t)1024 * R * sizeof(particle4<T>)
+               ? (size_t)16 * ((size_t)1 << bits) * sizeof(int)
+               : (size_t)1024 * R * sizeof(particle4<T>);
+}
+template <typename T, int R>
+constexpr size_t scatter_lds(int bits) {
+    return scatter_region<T, R>(bits) + (size_t)(2 * (1 << bits) + 16) * sizeof(int);
 }
 
 __global__ void k_rb_reset_dense(int nsys, int *__restrict__ dense_count) {
     for (int sy = threadIdx.x; sy < nsys; sy += blockDim.x) dense_count[(int64_t)sy * 8] = 0;
 }
 
-// Tile histogram of digit (key >> shift) & (2^bits - 1) into LDS, written to
+// Tile histogram of digit (key >> shift) & (2^bits - 1), written to
 // hist[d * tiles + t] (every block writes all 2^bits of its entries).
-__device__ __forceinline__ void write_tile_hist(int *s_hist, int nb, int *__restrict__ hist,
-                                                int tiles, int t) {
-    __syncthreads();
-    for (int d = threadIdx.x; d < nb; d += blockDim.x) hist[(int64_t)d * tiles + t] = s_hist[d];
-}
-
-template <typename T>
-__global__ void __launch_bounds__(1024) k_rb_keys(const int64_t *__restrict__ prange, int64_t n,
-                                                  const T *__restrict__ x, const T *__restrict__ y,
-                                                  const T *__restrict__ z, T inv_h, int nc,
-                                                  int periodic, int *__restrict__ keys,
-                                                  int *__restrict__ vals, int *__restrict__ hist,
-                                                  int64_t hist_ints, int tiles, int bits,
-                                                  int *__restrict__ flag,
-                                                  int *__restrict__ dense_count) {
+template <typename T, int R>
+__global__ void __launch_bounds__(1024) k_rb_hist(
+    const int64_t *__restrict__ prange, int64_t n, int first, const T *__restrict__ x,
+    const T *__restrict__ y, const T *__restrict__ z, T inv_h, int nc, int periodic,
+    const int *__restrict__ keys, int *__restrict__ hist, int64_t hist_ints, int tiles,
+    int shift, int bits, int *__restrict__ flag, int *__restrict__ dense_count) {
     __shared__ int s_hist[kRadixBuckets];
     int64_t p0, np;
     sys_range(prange, n, p0, np);
     const int nb = 1 << bits, t = blockIdx.x;
     for (int d = threadIdx.x; d < nb; d += blockDim.x) s_hist[d] = 0;
-    if (t == 0 && threadIdx.x == 0) dense_count[(int64_t)blockIdx.y * 8] = 0;
+    if (first && t == 0 && threadIdx.x == 0) dense_count[(int64_t)blockIdx.y * 8] = 0;
     __syncthreads();
-    // the loads of the four rounds are issued together
-    T xv[4], yv[4], zv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + threadIdx.x;
-        const int64_t i = p0 + (j < np ? j : (np > 0 ? np - 1 : 0));
-        xv[r] = np > 0 ? x[i] : T(0);
-        yv[r] = np > 0 ? y[i] : T(0);
-        zv[r] = np > 0 ? z[i] : T(0);
-    }
+    int kv[R];
     int out = 0;
+    if (first) {
+        T xv[R], yv[R], zv[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + threadIdx.x;
-        if (j >= np) continue;
-        int ix, iy, iz;
-        T ux, uy, uz;
-        cell_coord(xv[r], inv_h, nc, periodic, ix, ux, out);
-        cell_coord(yv[r], inv_h, nc, periodic, iy, uy, out);
-        cell_coord(zv[r], inv_h, nc, periodic, iz, uz, out);
-        const int c = (iz * nc + iy) * nc + ix;
-        keys[p0 + j] = c;
-        vals[p0 + j] = (int)(p0 + j);
-        atomicAdd(&s_hist[c & (nb - 1)], 1);
-    }
-    if (out) *flag = 1;
-    int64_t hoff;
-    sys_offsets(hist_ints, hoff);
-    write_tile_hist(s_hist, nb, hist + hoff, tiles, t);
-}
-
-__global__ void __launch_bounds__(1024) k_rb_hist(const int64_t *__restrict__ prange, int64_t n,
-                                                  const int *__restrict__ keys,
-                                                  int *__restrict__ hist, int64_t hist_ints,
-                                                  int tiles, int shift, int bits) {
-    __shared__ int s_hist[kRadixBuckets];
-    int64_t p0, np;
-    sys_range(prange, n, p0, np);
-    const int nb = 1 << bits, t = blockIdx.x;
-    for (int d = threadIdx.x; d < nb; d += blockDim.x) s_hist[d] = 0;
-    __syncthreads();
-    int kv[4];
+        for (int r = 0; r < R; ++r) {
+            const int64_t j = (int64_t)t * (1024 * R) + r * 1024 + threadIdx.x;
+            const int64_t i = p0 + (j < np ? j : 0);
+            const bool act = j < np;
+            xv[r] = act ? x[i] : T(0);
+            yv[r] = act ? y[i] : T(0);
+            zv[r] = act ? z[i] : T(0);
+        }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + threadIdx.x;
-        kv[r] = j < np ? keys[p0 + j] : -1;
+        for (int r = 0; r < R; ++r) {
+            const int64_t j = (int64_t)t * (1024 * R) + r * 1024 + threadIdx.x;
+            int ix, iy, iz;
+            T u;
+            cell_coord(xv[r], inv_h, nc, periodic, ix, u, out);
+            cell_coord(yv[r], inv_h, nc, periodic, iy, u, out);
+            cell_coord(zv[r], inv_h, nc, periodic, iz, u, out);
+            kv[r] = j < np ? (iz * nc + iy) * nc + ix : -1;
+        }
+        if (out && np > 0) {
+            // only lanes with particles can be outside (inactive lanes read 0)
+            *flag = 1;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t j = (int64_t)t * (1024 * R) + r * 1024 + threadIdx.x;
+            kv[r] = j < np ? keys[p0 + j] : -1;
+        }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < R; ++r)
         if (kv[r] >= 0) atomicAdd(&s_hist[(kv[r] >> shift) & (nb - 1)], 1);
-    int64_t hoff;
-    sys_offsets(hist_ints, hoff);
-    write_tile_hist(s_hist, nb, hist + hoff, tiles, t);
+    __syncthreads();
+    int *h = hist + (int64_t)blockIdx.y * hist_ints;
+    for (int d = threadIdx.x; d < nb; d += blockDim.x) h[(int64_t)d * tiles + t] = s_hist[d];
 }
 
-// Exclusive scan of the L = buckets x tiles histogram entries of every
-// system, in place, in scan tiles of 4096: per-tile sums, then each tile
-// scanned from the sum of the tiles before it.
+// Exclusive scan of the L (<= kScanOneBlock) histogram entries of every
+// system in one block: 16 consecutive entries per thread.
+__global__ void __launch_bounds__(1024) k_rb_scan1(int64_t L, int64_t hist_ints,
+                                                   int *__restrict__ hist) {
+    __shared__ int wtot[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    hist += (int64_t)blockIdx.y * hist_ints;
+    const int64_t base = (int64_t)tid * 16;
+    int v[16];
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = base + k < L ? hist[base + k] : 0;
+        tot += v[k];
+    }
+    int inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += u;
+    }
+    if (lane == 63) wtot[wid] = inc;
+    __syncthreads();
+    int run = inc - tot;
+    for (int w = 0; w < wid; ++w) run += wtot[w];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (base + k < L) hist[base + k] = run;
+        run += v[k];
+    }
+}
+
+// The same for larger histograms, in scan tiles of 4096: per-tile sums, then
+// each tile scanned from the sum of the tiles before it.
 __global__ void __launch_bounds__(1024) k_rb_scan_sums(int64_t L, int64_t hist_ints,
                                                        const int *__restrict__ hist,
                                                        int *__restrict__ sums) {
@@ -204,109 +234,190 @@ __global__ void __launch_bounds__(1024) k_rb_scan(int64_t L, int64_t hist_ints,
     }
 }
 
-// Stable scatter of one digit.  LDS: per-wave digit counts and their
-// exclusive prefixes over the waves of a round, and the tile's running count
-// per digit.  With `last`, the outputs are the sorted cell (keys_out), the
-// permutation (vals_out), the sorted records and, if pos is not null, each
-// particle's sorted slot.
-template <typename T>
+// Stable scatter of one digit over tiles of 1024 R elements; wave w ranks
+// elements [64 R w, 64 R (w + 1)) of its tile, 64 at a time.
+template <typename T, int R>
 __global__ void __launch_bounds__(1024) k_rb_scatter(
-    const int64_t *__restrict__ prange, int64_t n, const int *__restrict__ keys_in,
-    const int *__restrict__ vals_in, int *__restrict__ keys_out, int *__restrict__ vals_out,
-    const int *__restrict__ offs, int64_t hist_ints, int tiles, int shift, int bits, int last,
-    const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
-    const T *__restrict__ q, T inv_h, int nc, int periodic, particle4<T> *__restrict__ sorted,
-    int *__restrict__ pos) {
+    const int64_t *__restrict__ prange, int64_t n, int first, int last, const T *__restrict__ x,
+    const T *__restrict__ y, const T *__restrict__ z, const T *__restrict__ q, T inv_h, int nc,
+    int periodic, const int *__restrict__ keys_in, const int *__restrict__ vals_in,
+    const particle4<T> *__restrict__ recs_in, int *__restrict__ keys_out,
+    int *__restrict__ vals_out, particle4<T> *__restrict__ recs_out, int *__restrict__ pos,
+    const int *__restrict__ offs, int64_t hist_ints, int tiles, int shift, int bits) {
+    constexpr int TILE = 1024 * R;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int nb = 1 << bits;
-    int *cnt = (int *)lds_raw;        // [16][nb] counts of the round
-    int *pre = cnt + 16 * nb;         // [16][nb] exclusive prefixes over waves
-    int *run = pre + 16 * nb;         // [nb] tile running count
+    int *wcnt = (int *)lds_raw;                      // [16][nb] while ranking
+    int *sint = (int *)lds_raw;                      // staging: TILE ints
+    particle4<T> *srec = (particle4<T> *)lds_raw;    // staging: TILE records
+    int *ls = (int *)(lds_raw + scatter_region<T, R>(bits));  // [nb] tile-local digit start
+    int *goff = ls + nb;                             // [nb] global slot - local slot
+    int *wtot = goff + nb;                           // [16]
     int64_t p0, np;
     sys_range(prange, n, p0, np);
-    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     offs += (int64_t)blockIdx.y * hist_ints;
-    for (int e = tid; e < 16 * nb; e += 1024) cnt[e] = 0;
-    for (int d = tid; d < nb; d += 1024) run[d] = 0;
-    int kv[4], vv[4];
+    const int64_t t0 = (int64_t)t * TILE;
+    const int na = (int)(np - t0 <= 0 ? 0 : (np - t0 > TILE ? TILE : np - t0));
+    for (int e = tid; e < 16 * nb; e += 1024) wcnt[e] = 0;
+
+    int key[R], val[R], dig[R];
+    particle4<T> rec[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + tid;
-        const bool act = j < np;
-        kv[r] = act ? keys_in[p0 + j] : 0;
-        vv[r] = act ? vals_in[p0 + j] : 0;
+    for (int r = 0; r < R; ++r) {
+        const int e = wid * 64 * R + r * 64 + lane;
+        const int64_t i = p0 + t0 + (e < na ? e : 0);
+        if (e < na) {
+            if (first) {
+                int ix, iy, iz, out = 0;
+                cell_coord(x[i], inv_h, nc, periodic, ix, rec[r].ux, out);
+                cell_coord(y[i], inv_h, nc, periodic, iy, rec[r].uy, out);
+                cell_coord(z[i], inv_h, nc, periodic, iz, rec[r].uz, out);
+                rec[r].q = q != nullptr ? q[i] : T(0);
+                key[r] = (iz * nc + iy) * nc + ix;
+                val[r] = (int)i;
+            } else {
+                key[r] = keys_in[i];
+                val[r] = vals_in[i];
+                rec[r] = recs_in[i];
+            }
+        } else {
+            key[r] = 0;
+            val[r] = 0;
+            rec[r] = particle4<T>{T(0), T(0), T(0), T(0)};
+        }
+        dig[r] = (key[r] >> shift) & (nb - 1);
     }
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll 1
-    for (int r = 0; r < 4; ++r) {
-        const int64_t j = (int64_t)t * kRadixTile + r * 1024 + tid;
-        const bool act = j < np;
-        const int d = (kv[r] >> shift) & (nb - 1);
-        // lanes of this wave holding the same digit (active lanes only)
+
+    // rank among the wave's earlier elements of the same digit: the running
+    // count of the digit before this group of 64, plus the lower lanes that
+    // hold it; one lane per digit group then advances the count (the wave's
+    // LDS reads precede its writes, and only this wave touches its counts)
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = wid * 64 * R + r * 64 + lane;
+        const bool act = e < na;
+        const int d = dig[r];
         uint64_t peers = __ballot(act);
         for (int b = 0; b < bits; ++b) {
             const uint64_t m = __ballot(act && ((d >> b) & 1));
             peers &= ((d >> b) & 1) ? m : ~m;
         }
-        const int rw = __popcll(peers & lt);
-        if (act && rw == 0) cnt[wid * nb + d] = __popcll(peers);
-        __syncthreads();
-        for (int dd = tid; dd < nb; dd += 1024) {
-            int s = run[dd];
+        const int before = __popcll(peers & lt);
+        const int base = act ? wcnt[wid * nb + d] : 0;
+        __builtin_amdgcn_wave_barrier();
+        rank[r] = base + before;
+        if (act && before == 0) wcnt[wid * nb + d] = base + __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // per digit: exclusive prefix over the waves (in place) and the tile count
+    int tot = 0;
+    if (tid < nb) {
 #pragma unroll
-            for (int w = 0; w < 16; ++w) {
-                const int c = cnt[w * nb + dd];
-                pre[w * nb + dd] = s;
-                cnt[w * nb + dd] = 0;
-                s += c;
-            }
-            run[dd] = s;
+        for (int w = 0; w < 16; ++w) {
+            const int c = wcnt[w * nb + tid];
+            wcnt[w * nb + tid] = tot;
+            tot += c;
         }
-        __syncthreads();
-        if (act) {
-            const int dest = offs[(int64_t)d * tiles + t] + pre[wid * nb + d] + rw;
-            const int64_t g = p0 + dest;
-            if (!last) {
-                keys_out[g] = kv[r];
-                vals_out[g] = vv[r];
-            } else {
-                const int i = vv[r];
-                int ix, iy, iz, out = 0;
-                particle4<T> rec;
-                cell_coord(x[i], inv_h, nc, periodic, ix, rec.ux, out);
-                cell_coord(y[i], inv_h, nc, periodic, iy, rec.uy, out);
-                cell_coord(z[i], inv_h, nc, periodic, iz, rec.uz, out);
-                rec.q = q != nullptr ? q[i] : T(0);
-                keys_out[g] = kv[r];
-                vals_out[g] = i;
-                sorted[g] = rec;
-                if (pos != nullptr) pos[i] = (int)g;
-            }
+    }
+    // exclusive scan of the tile counts over the digits
+    int inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += u;
+    }
+    if (lane == 63) wtot[wid] = inc;
+    __syncthreads();
+    if (tid < nb) {
+        int pre = 0;
+        for (int w = 0; w < wid; ++w) pre += wtot[w];
+        const int l = pre + inc - tot;
+        ls[tid] = l;
+        goff[tid] = offs[(int64_t)tid * tiles + t] - l;
+    }
+    __syncthreads();
+    int lidx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = wid * 64 * R + r * 64 + lane;
+        lidx[r] = e < na ? ls[dig[r]] + wcnt[wid * nb + dig[r]] + rank[r] : 0;
+    }
+    __syncthreads();  // the counts' region becomes the staging area
+
+    // the tile in digit order: slot jj of the tile goes to goff[digit] + jj
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (wid * 64 * R + r * 64 + lane < na) sint[lidx[r]] = key[r];
+    __syncthreads();
+    int dst[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int jj = r * 1024 + tid;
+        dst[r] = 0;
+        if (jj < na) {
+            const int k = sint[jj];
+            dst[r] = goff[(k >> shift) & (nb - 1)] + jj;
+            keys_out[p0 + dst[r]] = k;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (wid * 64 * R + r * 64 + lane < na) sint[lidx[r]] = val[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int jj = r * 1024 + tid;
+        if (jj < na) {
+            const int v = sint[jj];
+            vals_out[p0 + dst[r]] = v;
+            if (last && pos != nullptr) pos[v] = (int)(p0 + dst[r]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (wid * 64 * R + r * 64 + lane < na) srec[lidx[r]] = rec[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int jj = r * 1024 + tid;
+        if (jj < na) recs_out[p0 + dst[r]] = srec[jj];
     }
 }
 
 // start[c] = first sorted slot of the system with cell >= c (relative to the
-// system's first particle), c = 0..K; cells above the dense threshold are
-// listed (in no particular order: each dense cell is reduced by one block in
-// a fixed order).
-__global__ void __launch_bounds__(256) k_rb_bounds(const int64_t *__restrict__ prange, int64_t n,
-                                                   int K, const int *__restrict__ skeys,
-                                                   int *__restrict__ start, int dense_thr,
-                                                   int *__restrict__ dense_cells,
-                                                   int *__restrict__ dense_count) {
+// system's first particle), c = 0..K, searched among the slots whose last
+// digit equals c's (their range comes from the last pass's scanned
+// histogram); cells above the dense threshold are listed (in no particular
+// order: each dense cell is reduced by one block in a fixed order).
+__global__ void __launch_bounds__(256) k_rb_bounds(
+    const int64_t *__restrict__ prange, int64_t n, int K, const int *__restrict__ skeys,
+    int *__restrict__ start, int dense_thr, int *__restrict__ dense_cells,
+    int *__restrict__ dense_count, const int *__restrict__ offs, int64_t hist_ints, int tiles,
+    int shift, int bits) {
     int64_t p0, np;
     sys_range(prange, n, p0, np);
     start += (int64_t)blockIdx.y * (K + 1);
     dense_cells += (int64_t)blockIdx.y * K;
     dense_count += (int64_t)blockIdx.y * 8;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > K) return;
+    offs += (int64_t)blockIdx.y * hist_ints;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
+    const int nb = 1 << bits;
     const int *k = skeys + p0;
     auto lower = [&](int v) {
-        int lo = 0, hi = (int)np;
+        if (np == 0) return 0;
+        const int dh = v >> shift;
+        if (dh >= nb) return (int)np;
+        int lo = offs[(int64_t)dh * tiles];
+        int hi = dh + 1 < nb ? offs[(int64_t)(dh + 1) * tiles] : (int)np;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (k[mid] < v) lo = mid + 1;
@@ -314,19 +425,12 @@ __global__ void __launch_bounds__(256) k_rb_bounds(const int64_t *__restrict__ p
         }
         return lo;
     };
-    const int s0 = lower(c);
-    start[c] = s0;
-    if (c < K) {
-        const int s1 = lower(c + 1);
-        if (s1 - s0 > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = c;
-    }
+    const int s0 = lower(c < K ? c : K);
+    int s1 = __shfl_down(s0, 1, 64);
+    if (lane == 63 && c < K) s1 = lower(c + 1);
+    if (c <= K) start[c] = s0;
+    if (c < K && s1 - s0 > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = c;
 }
-
-int64_t bin_hist_ints(int64_t max_np) {
-    const int64_t tiles = max_np > 0 ? (max_np + kRadixTile - 1) / kRadixTile : 1;
-    return (int64_t)kRadixBuckets * tiles;
-}
-int64_t bin_scan_tiles(int64_t max_np) { return (bin_hist_ints(max_np) + 4095) / 4096; }
 
 // Digit widths of the passes for keys below K (at most kRadixMaxBits each,
 // as even as possible).
@@ -339,60 +443,77 @@ static int radix_passes(int K, int widths[8]) {
     return np;
 }
 
-template <typename T>
-hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
-    const int K = a.ncell * a.ncell * a.ncell;
+template <typename T, int R>
+static hipError_t radix_bin(const BinArgs &a, int K, int64_t maxn, hipStream_t s) {
     const T inv_h = T(a.inv_h);
     const int nsys = a.nsys > 0 ? a.nsys : 1;
-    const int64_t maxn = a.prange ? a.max_np : a.n;
-    const int tiles = (int)(maxn > 0 ? (maxn + kRadixTile - 1) / kRadixTile : 1);
+    const int tiles = (int)bin_tiles(maxn);
     const int64_t hist_ints = bin_hist_ints(maxn);
     int widths[8];
     const int passes = radix_passes(K, widths);
-    // ping-pong so that the last pass lands in (scell, perm)
-    int *kA = a.cell_of, *vA = a.slot, *kB = a.scell, *vB = a.perm;
-    int *kin = (passes & 1) ? kA : kB, *vin = (passes & 1) ? vA : vB;
-    if (maxn > 0) {
-        hipLaunchKernelGGL(k_rb_keys<T>, dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
-                           (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
-                           a.periodic, kin, vin, a.count, hist_ints, tiles, widths[0], a.flag,
+    int *kA = a.cell_of, *vA = a.slot, *kF = a.scell, *vF = a.perm;
+    particle4<T> *rA = (particle4<T> *)a.recs, *rF = (particle4<T> *)a.sorted;
+    const int *kin = nullptr, *vin = nullptr;
+    const particle4<T> *rin = nullptr;
+    int shift = 0;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int bits = widths[ps], first = ps == 0, last = ps == passes - 1;
+        // alternate so that the last pass lands in (scell, perm, sorted)
+        const bool to_final = ((passes - 1 - ps) & 1) == 0;
+        int *ko = to_final ? kF : kA, *vo = to_final ? vF : vA;
+        particle4<T> *ro = to_final ? rF : rA;
+        hipLaunchKernelGGL((k_rb_hist<T, R>), dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
+                           first, (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
+                           a.periodic, kin, a.count, hist_ints, tiles, shift, bits, a.flag,
                            a.dense_count);
-        int shift = 0;
-        for (int ps = 0; ps < passes; ++ps) {
-            const int bits = widths[ps];
-            if (ps > 0)
-                hipLaunchKernelGGL(k_rb_hist, dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
-                                   kin, a.count, hist_ints, tiles, shift, bits);
-            const int64_t L = (int64_t)(1 << bits) * tiles;
+        const int64_t L = (int64_t)(1 << bits) * tiles;
+        if (L <= kScanOneBlock) {
+            hipLaunchKernelGGL(k_rb_scan1, dim3(1, nsys), dim3(1024), 0, s, L, hist_ints, a.count);
+        } else {
             const int st = (int)((L + 4095) / 4096);
             hipLaunchKernelGGL(k_rb_scan_sums, dim3(st, nsys), dim3(1024), 0, s, L, hist_ints,
                                a.count, a.tile_sums);
-            hipLaunchKernelGGL(k_rb_scan, dim3(st, nsys), dim3(1024), 0, s, L, hist_ints, a.count,
-                               a.tile_sums);
-            const int last = ps == passes - 1;
-            int *kout = kin == kA ? kB : kA, *vout = vin == vA ? vB : vA;
-            const size_t lds = (size_t)(33 << bits) * sizeof(int);
-            if (lds > 65536) {
-                const hipError_t e = set_max_lds((const void *)k_rb_scatter<T>, lds);
-                if (e != hipSuccess) return e;
-            }
-            hipLaunchKernelGGL(k_rb_scatter<T>, dim3(tiles, nsys), dim3(1024), lds, s, a.prange,
-                               a.n, kin, vin, kout, vout, a.count, hist_ints, tiles, shift, bits,
-                               last, (const T *)a.x, (const T *)a.y, (const T *)a.z,
-                               (const T *)a.q, inv_h, a.ncell, a.periodic,
-                               (particle4<T> *)a.sorted, a.pos);
-            kin = kout;
-            vin = vout;
-            shift += bits;
+            hipLaunchKernelGGL(k_rb_scan, dim3(st, nsys), dim3(1024), 0, s, L, hist_ints,
+                               a.count, a.tile_sums);
         }
+        const size_t lds = scatter_lds<T, R>(bits);
+        if (lds > 65536) {
+            const hipError_t e = set_max_lds((const void *)k_rb_scatter<T, R>, lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((k_rb_scatter<T, R>), dim3(tiles, nsys), dim3(1024), lds, s, a.prange,
+                           a.n, first, last, (const T *)a.x, (const T *)a.y, (const T *)a.z,
+                           (const T *)a.q, inv_h, a.ncell, a.periodic, kin, vin, rin, ko, vo, ro,
+                           a.pos, a.count, hist_ints, tiles, shift, bits);
+        kin = ko;
+        vin = vo;
+        rin = ro;
+        if (!last) shift += bits;
     }
-    // a system with no particles still gets its zero starts; the dense count
-    // of an empty call is reset here
-    if (maxn == 0)
-        hipLaunchKernelGGL(k_rb_reset_dense, dim3(1), dim3(64), 0, s, nsys, a.dense_count);
     hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s, a.prange,
-                       a.n, K, a.scell, a.start, a.dense_threshold, a.dense_cells, a.dense_count);
+                       a.n, K, a.scell, a.start, a.dense_threshold, a.dense_cells, a.dense_count,
+                       a.count, hist_ints, tiles, shift, widths[passes - 1]);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
+    const int K = a.ncell * a.ncell * a.ncell;
+    const int64_t maxn = a.prange ? a.max_np : a.n;
+    if (maxn == 0) {
+        // every system is empty: zero starts, and the dense count reset here
+        const int nsys = a.nsys > 0 ? a.nsys : 1;
+        hipLaunchKernelGGL(k_rb_reset_dense, dim3(1), dim3(64), 0, s, nsys, a.dense_count);
+        hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s,
+                           a.prange, a.n, K, a.scell, a.start, a.dense_threshold, a.dense_cells,
+                           a.dense_count, a.count, (int64_t)0, 1, 0, 1);
+        return hipGetLastError();
+    }
+    switch (bin_tile_items(maxn)) {
+    case 4: return radix_bin<T, 4>(a, K, maxn, s);
+    case 2: return radix_bin<T, 2>(a, K, maxn, s);
+    default: return radix_bin<T, 1>(a, K, maxn, s);
+    }
 }
 
 template hipError_t launch_bin<float>(const BinArgs &, hipStream_t);

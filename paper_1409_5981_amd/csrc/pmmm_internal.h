@@ -482,9 +482,11 @@ struct BinArgs {
     int ncell;         // cells per axis
     double inv_h;      // n / b
     int periodic;
-    // [n] key/value ping-pong arrays of the radix sort; the sorted cell and
-    // the permutation (caller index of every sorted slot) end in scell, perm
+    // [n] key/value/record ping-pong arrays of the radix sort; the sorted
+    // cell, the permutation (caller index of every sorted slot) and the
+    // sorted records end in scell, perm, sorted
     int *cell_of, *slot, *scell, *perm;
+    void *recs;        // particle4<T>[n] records between passes
     int *start;        // [nsys][K + 1] first sorted slot of every cell (system-relative)
     int *flag;         // set when an open-boundary particle lies outside the box
     int *dense_cells, *dense_count;
@@ -500,9 +502,28 @@ struct BinArgs {
 };
 template <typename T>
 hipError_t launch_bin(const BinArgs &a, hipStream_t s);
-// Radix-sort scratch per system for up to max_np particles.
-int64_t bin_hist_ints(int64_t max_np);
-int64_t bin_scan_tiles(int64_t max_np);
+// Radix-sort tiles: 1024 R elements, R = 1, 2 or 4 growing with the
+// particle count, and at most 2^9 buckets per digit.
+constexpr int kRadixMaxBits = 9;
+constexpr int bin_tile_items(int64_t max_np) {
+    return max_np >= (int64_t(1) << 21) ? 4 : (max_np >= (int64_t(1) << 20) ? 2 : 1);
+}
+constexpr int64_t bin_tiles(int64_t max_np) {
+    return max_np > 0 ? (max_np + 1024 * bin_tile_items(max_np) - 1) /
+                            (1024 * bin_tile_items(max_np))
+                      : 1;
+}
+constexpr int64_t bin_max64(int64_t a, int64_t b) { return a > b ? a : b; }
+constexpr int64_t bin_min64(int64_t a, int64_t b) { return a < b ? a : b; }
+// Histogram ints per system for every particle count up to max_np (the tile
+// count is not monotonic where R steps up, hence the maximum).
+constexpr int64_t bin_hist_ints(int64_t max_np) {
+    return (int64_t(1) << kRadixMaxBits) *
+           bin_max64(bin_tiles(max_np),
+                     bin_max64(bin_tiles(bin_min64(max_np, (int64_t(1) << 21) - 1)),
+                               bin_tiles(bin_min64(max_np, (int64_t(1) << 20) - 1))));
+}
+constexpr int64_t bin_scan_tiles(int64_t max_np) { return (bin_hist_ints(max_np) + 4095) / 4096; }
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path

@@ -57,8 +57,13 @@ def test_workspace_grows_with_particles(lib):
     prm = make_params(32, 7, "periodic")
     # per particle: cell, slot, permutation, sorted cell and sorted slot (5 ints),
     # the sorted record and the sorted-order results (2 x 4 floats); plus one
-    # int per near-field tile of 64 targets
-    assert workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0) == (1 << 20) * 52 + 4 * (1 << 14)
+    # int per near-field tile of 64 targets, and the radix-sort histograms:
+    # 512 ints per tile, sized for the most tiles any count up to 2^20 uses
+    # (2^20 - 1 particles in 1024 tiles of 1024), with one scan sum per 4096
+    hist = 512 * 1024 - 512
+    sums = 512 * 1024 // 4096 - 1
+    assert (workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0)
+            == (1 << 20) * 52 + 4 * (1 << 14) + 4 * (hist + sums))
 
 
 def test_error_strings(lib):
