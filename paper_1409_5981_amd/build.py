@@ -34,12 +34,37 @@ def _newest_header() -> float:
     return max(os.path.getmtime(h) for h in hdrs)
 
 
-def _compile(src: str, incremental: bool = False) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+# The column-stage unit is compiled once per (order, precision): the orders
+# are the slowest part of the build, and apart they compile in parallel.
+COLUMN_UNIT = "pmmm_column_inst.hip"
+PMAX = 10
+
+
+def _units() -> list[tuple[str, str, list[str]]]:
+    """(source, object name, extra flags) of every compile job, longest first."""
+    units = []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        base = os.path.basename(src).replace(".hip", "")
+        if os.path.basename(src) == COLUMN_UNIT:
+            for p in range(PMAX, -1, -1):
+                for t in ("float", "double"):
+                    units.append((src, f"{base}_p{p}_{t}",
+                                  [f"-DPMMM_COLUMN_ORDER={p}", f"-DPMMM_COLUMN_T={t}"]))
+        else:
+            units.append((src, base, []))
+    # high orders first, then the largest other units
+    units.sort(key=lambda u: (-int(u[1].split("_p")[1].split("_")[0]) - 100
+                              if u[0].endswith(COLUMN_UNIT) else -os.path.getsize(u[0]) / 1e6))
+    return units
+
+
+def _compile(unit: tuple[str, str, list[str]], incremental: bool = False) -> str:
+    src, name, extra = unit
+    obj = os.path.join(BUILD, name + ".o")
     if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(
             os.path.getmtime(src), _newest_header()):
         return obj
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -50,12 +75,10 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     """Compile every unit (incremental: only units older than their source or
     any header) and link libpmmm.so."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    # longest units first so that the parallel build ends sooner
-    srcs.sort(key=lambda f: -os.path.getsize(f) - (10 ** 6 if "column_p" in f else 0))
+    units = _units()
     jobs = jobs or min(8, os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
+        objs = list(ex.map(lambda u: _compile(u, incremental), units))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -75,12 +75,12 @@ __host__ __device__ constexpr bool subset_needs(int PO, int RS, int S, int NN) {
 
 // acc[a] += sum_b t_ab(g of order NN) * M~_b over the output orders l of
 // subset S with lam = NN - l; M~ of order lam is read from LDS (column
-// `mcol`, row stride `mstride`) and pre-multiplied by i^(lam mod 2).  Every
-// index is a compile-time constant (static_for), so acc, Mh and g stay in
-// registers.
+// `mcol`, row stride `mstride`, plus `odd` for odd rows b when the rows are
+// swizzled) and pre-multiplied by i^(lam mod 2).  Every index is a
+// compile-time constant (static_for), so acc, Mh and g stay in registers.
 template <int PO, int NN, int RS, int S, typename T>
 __device__ __forceinline__ void m2l_order(const T *g, const cplx<T> *mcol, int mstride,
-                                          cplx<T> *acc) {
+                                          cplx<T> *acc, int odd = 0) {
     constexpr int lo = NN - PO > 0 ? NN - PO : 0;
     constexpr int hi = NN < PO ? NN : PO;
     static_for<lo, hi + 1>([&](auto il) {
@@ -92,7 +92,7 @@ __device__ __forceinline__ void m2l_order(const T *g, const cplx<T> *mcol, int m
             static_for<0, 2 * lam + 1>([&](auto ik) {
                 constexpr int k = decltype(ik)::value;
                 constexpr int mu = k - lam;
-                const cplx<T> v = mcol[ridx(lam, mu) * mstride];
+                const cplx<T> v = mcol[ridx(lam, mu) * mstride + ((ridx(lam, mu) & 1) ? odd : 0)];
                 Mh[k] = (lam & 1) ? cplx<T>{-v.im, v.re} : v;
             });
             static_for<0, l + 1>([&](auto im) {
@@ -217,13 +217,14 @@ __device__ __forceinline__ void m2l_rows(const T *gcol, int gstride, int flip,
 
 // res of subset S to its rows of `ocol`.
 template <int PO, int RS, int S, typename T>
-__device__ __forceinline__ void m2l_put(const cplx<T> *res, cplx<T> *ocol, int stride) {
+__device__ __forceinline__ void m2l_put(const cplx<T> *res, cplx<T> *ocol, int stride,
+                                        int odd = 0) {
     static_for<0, PO + 1>([&](auto il) {
         constexpr int l = decltype(il)::value;
         if constexpr (order_subset(PO, RS, l) == S) {
             static_for<-l, l + 1>([&](auto im) {
                 constexpr int a = ridx(l, decltype(im)::value);
-                ocol[a * stride] = res[subset_rank(PO, RS, S, a)];
+                ocol[a * stride + ((a & 1) ? odd : 0)] = res[subset_rank(PO, RS, S, a)];
             });
         }
     });
@@ -454,6 +455,82 @@ __global__ void __launch_bounds__(PO <= 6 ? 512 : 256, (PO == 7 && sizeof(T) == 
 // Each thread runs RSP of the kRowSplit row subsets one after another and
 // keeps their results in registers until every read of the moment spectra
 // is done; they then overwrite the spectra in place.
+//
+// LDS layout of the spectra: element e of row b at b * nf + cpos(b, e), the
+// low three bits of e flipped by bits 4..6 of e and bit 3 by the row's
+// parity.  For 128-point rows every access of the kernel -- 16 consecutive
+// elements of a row, or the FFT's (row, e) patterns of 16 lanes -- then
+// falls on 16 distinct 8-byte bank pairs, with no padding, so three blocks
+// share a CU (64- and 32-point rows keep some two- and four-way conflicts
+// in the first FFT pass).
+__device__ __forceinline__ constexpr int cpos(int row, int e) {
+    return e ^ (((e >> 4) & 7) | ((row & 1) << 3));
+}
+
+// In-place FFTs of nlines rows of N = 16 N2 points (N = 32, 64, 128) in the
+// layout above: 16-point register FFTs over n1 of x[n1 N2 + t2], twiddles
+// W_N^(t2 k1), then N2-point FFTs over t2.  The lanes of one row's items sit
+// in one wave, so each in-place pass needs no barrier between its reads and
+// writes (a wave's LDS operations complete in order; the asm statement keeps
+// the compiler from moving the writes up).  HALF: only the first N/2 inputs
+// are non-zero (forward) or only the first N/2 outputs are kept (inverse).
+template <typename T, bool INV, int N, bool HALF>
+__device__ __forceinline__ void fft_col(cplx<T> *buf, int nlines, const cplx<T> *tw, int tid,
+                                        int nthr) {
+    constexpr int N2 = N / 16, L2 = ilog2c(N2);
+    const int items = nlines * N2;
+    for (int it = tid; it < items; it += nthr) {
+        const int line = it >> L2, t2 = it & (N2 - 1);
+        cplx<T> *b = buf + line * N;
+        cplx<T> v[16];
+        static_for<0, 16>([&](auto in) {
+            constexpr int n1 = decltype(in)::value;
+            if constexpr (!INV && HALF && n1 >= 8) v[n1] = {T(0), T(0)};
+            else v[n1] = b[cpos(line, n1 * N2 + t2)];
+        });
+        fft_reg<16, INV, T>(v);
+        static_for<1, 16>([&](auto ik) {
+            constexpr int k1 = decltype(ik)::value;
+            const int e = t2 * k1;  // < N
+            cplx<T> w = e < N / 2 ? tw[e] : tw[e - N / 2];
+            if (e >= N / 2) {
+                w.re = -w.re;
+                w.im = -w.im;
+            }
+            if (INV) w.im = -w.im;
+            v[k1] = cmul(v[k1], w);
+        });
+        asm volatile("" ::: "memory");
+        static_for<0, 16>([&](auto ik) {
+            constexpr int k1 = decltype(ik)::value;
+            b[cpos(line, t2 * 16 + k1)] = v[k1];
+        });
+    }
+    __syncthreads();
+    for (int it = tid; it < nlines * 16; it += nthr) {
+        const int line = it >> 4, k1 = it & 15;
+        cplx<T> *b = buf + line * N;
+        cplx<T> u[N2];
+        static_for<0, N2>([&](auto it2) {
+            constexpr int t2 = decltype(it2)::value;
+            u[t2] = b[cpos(line, t2 * 16 + k1)];
+        });
+        fft_reg<N2, INV, T>(u);
+        asm volatile("" ::: "memory");
+        static_for<0, N2>([&](auto ik2) {
+            constexpr int k2 = decltype(ik2)::value;
+            if constexpr (!(INV && HALF && k2 >= N2 / 2)) b[cpos(line, k2 * 16 + k1)] = u[k2];
+        });
+    }
+    __syncthreads();
+}
+
+template <typename T, bool INV, int N>
+__device__ __forceinline__ void fft_col_rt(cplx<T> *buf, bool half, int nlines,
+                                           const cplx<T> *tw, int tid, int nthr) {
+    if (half) fft_col<T, INV, N, true>(buf, nlines, tw, tid, nthr);
+    else fft_col<T, INV, N, false>(buf, nlines, tw, tid, nthr);
+}
 
 // Next order >= from whose kernel values subset S needs (2 PO + 1: none).
 __host__ __device__ constexpr int next_order(int PO, int RS, int S, int from) {
@@ -462,12 +539,38 @@ __host__ __device__ constexpr int next_order(int PO, int RS, int S, int from) {
     return 2 * PO + 1;
 }
 
-// Stored kernel values of order NN (component j = NN^2 + k at gp[j * gstride]).
+// The stored kernel values of one column: a buffer resource over the
+// column's [Q][nhp] slab (block-uniform, so it lives in scalar registers),
+// the byte offset of the thread's frequency, and the bytes between
+// components -- every load then takes its address from one vector register
+// plus a scalar offset, with no per-load address arithmetic.
+struct GSlab {
+    __amdgpu_buffer_rsrc_t rsrc;
+    int voff, sstride;
+};
+template <typename T>
+__device__ __forceinline__ GSlab make_gslab(const T *slab, int nvals, int kzr, int gstride) {
+    // word 3: 32-bit data format, as raw (untyped) buffer loads require
+    return GSlab{__builtin_amdgcn_make_buffer_rsrc((void *)slab, 0, nvals * (int)sizeof(T),
+                                                   0x00020000),
+                 kzr * (int)sizeof(T), gstride * (int)sizeof(T)};
+}
+template <typename T>
+__device__ __forceinline__ T gslab_load(const GSlab &g, int j) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(g.rsrc, g.voff,
+                                                                          j * g.sstride, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(g.rsrc, g.voff,
+                                                                          j * g.sstride, 0));
+}
+
+// Stored kernel values of order NN (component j = NN^2 + k).
 template <int NN, typename T>
-__device__ __forceinline__ void load_order(const T *__restrict__ gp, int gstride, T *raw) {
+__device__ __forceinline__ void load_order(const GSlab &gs, T *raw) {
     static_for<0, 2 * NN + 1>([&](auto ik) {
         constexpr int k = decltype(ik)::value;
-        raw[k] = gp[(NN * NN + k) * gstride];
+        raw[k] = gslab_load<T>(gs, NN * NN + k);
     });
 }
 
@@ -475,13 +578,13 @@ __device__ __forceinline__ void load_order(const T *__restrict__ gp, int gstride
 // needed order are loaded before this order's products are issued.
 template <int PO, int NN, int RS, int S, typename T>
 struct M2LOrdersG {
-    __device__ static __forceinline__ void run(const T *__restrict__ gp, int gstride, int flip,
+    __device__ static __forceinline__ void run(const GSlab &gs, int flip,
                                                const cplx<T> *mcol, int mstride, cplx<T> *acc,
-                                               const T *raw) {
+                                               const T *raw, int odd) {
         constexpr int NX = next_order(PO, RS, S, NN + 1);
         constexpr int NXL = NX <= 2 * PO ? 2 * NX + 1 : 1;
         T nxt[NXL];
-        if constexpr (NX <= 2 * PO) load_order<NX, T>(gp, gstride, nxt);
+        if constexpr (NX <= 2 * PO) load_order<NX, T>(gs, nxt);
         T g[2 * NN + 1];
         static_for<0, 2 * NN + 1>([&](auto ik) {
             constexpr int k = decltype(ik)::value;
@@ -490,26 +593,26 @@ struct M2LOrdersG {
             const int neg = ((flip & 1) && kk < 0) ^ ((flip & 2) && odd_z);
             g[k] = neg ? -raw[k] : raw[k];
         });
-        m2l_order<PO, NN, RS, S, T>(g, mcol, mstride, acc);
+        m2l_order<PO, NN, RS, S, T>(g, mcol, mstride, acc, odd);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (NX <= 2 * PO)
-            M2LOrdersG<PO, NX, RS, S, T>::run(gp, gstride, flip, mcol, mstride, acc, nxt);
+            M2LOrdersG<PO, NX, RS, S, T>::run(gs, flip, mcol, mstride, acc, nxt, odd);
     }
 };
 
 // As m2l_rows, with the kernel values streamed from global memory.
 template <int PO, int RS, int S, typename T>
-__device__ __forceinline__ void m2l_rows_g(const T *__restrict__ gp, int gstride, int flip,
+__device__ __forceinline__ void m2l_rows_g(const GSlab &gs, int flip,
                                            const cplx<T> *mcol, int stride, DCCorr dc,
-                                           cplx<T> *res) {
+                                           cplx<T> *res, int odd) {
     constexpr int P = nreal(PO);
     constexpr int N0 = next_order(PO, RS, S, 0);
     cplx<T> acc[P];
     static_for<0, P>([&](auto ia) { acc[decltype(ia)::value] = {T(0), T(0)}; });
     if constexpr (N0 <= 2 * PO) {
         T raw[2 * N0 + 1];
-        load_order<N0, T>(gp, gstride, raw);
-        M2LOrdersG<PO, N0, RS, S, T>::run(gp, gstride, flip, mcol, stride, acc, raw);
+        load_order<N0, T>(gs, raw);
+        M2LOrdersG<PO, N0, RS, S, T>::run(gs, flip, mcol, stride, acc, raw, odd);
     }
     static_for<0, PO + 1>([&](auto il) {
         constexpr int l = decltype(il)::value;
@@ -532,10 +635,14 @@ __device__ __forceinline__ void m2l_rows_g(const T *__restrict__ gp, int gstride
 }
 
 // One block per column; NSUB = kRowSplit / RSP threads per frequency, so
-// NSUB * nf threads.  LDS: twiddles and the column's spectra buf[P][nf+1].
-template <int PO, typename T, int RSP>
+// NSUB * nf threads (nf = 2^LOGN = 64 or 128, a compile-time size: the
+// index arithmetic folds and the kernel needs fewer registers).  LDS:
+// twiddles and the column's spectra buf[P][nf] in the swizzled layout.  Open
+// boundaries (nz = nf / 2) skip the zero half of the forward transforms and
+// the discarded half of the inverse ones.
+template <int PO, typename T, int RSP, int LOGN>
 __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T) == 4 ? 3 : 2) : (RSP == 4 ? 2 : 1))
-    k_column_g(int nz, int logn, int ncol, int ngroups, const T *__restrict__ green,
+    k_column_g(int nz, int ncol, int ngroups, const T *__restrict__ green,
                cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ tw_g, int periodic,
                const double *__restrict__ qr2_partial, double *__restrict__ sums) {
     constexpr int P = nreal(PO);
@@ -543,7 +650,8 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
     constexpr int RS = kRowSplit;
     constexpr int NSUB = RS / RSP;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int nf = 1 << logn, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ls = lds_line(nf);
+    constexpr int logn = LOGN, nf = 1 << LOGN, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ls = nf;
+    const bool half = 2 * nz == nf;
     cplx<T> *tw = (cplx<T> *)lds_raw;
     cplx<T> *buf = tw + nf / 2;
     // XCD-aware order: consecutive columns stay on one XCD (blocks are dealt
@@ -557,65 +665,74 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
         qr2_partial += sy * nz;
         sums += sy * 8;
     }
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    constexpr int nthr = NSUB * nf;
     // spectra of z < nz: thread element u is component s_b0 + u * s_db at z = s_z
     const int s_z = tid & (nf - 1);
     const int s_b0 = tid >> logn;
-    const int s_db = nthr >> logn;
+    constexpr int s_db = nthr >> logn;
     const bool s_live = s_z < nz;
     const int s_g = (s_z < nz ? s_z : nz - 1) * ncol + col;
     auto s_comp = [&](int u) { return s_b0 + u * s_db < P ? s_b0 + u * s_db : P - 1; };
     constexpr int SB = 2 * kColumnLoadBatch;
     {
         const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];   // nf/2 <= blockDim.x
-        for (int u0 = 0; s_b0 + u0 * s_db < P; u0 += SB) {
-            cplx<T> sv[SB];
+        // the zero half of an open column is never read (pruned transform)
+        if (s_live) {
+            for (int u0 = 0; s_b0 + u0 * s_db < P; u0 += SB) {
+                cplx<T> sv[SB];
 #pragma unroll
-            for (int u = 0; u < SB; ++u) sv[u] = spec[s_comp(u0 + u) * nz * ncol + s_g];
+                for (int u = 0; u < SB; ++u) sv[u] = spec[s_comp(u0 + u) * nz * ncol + s_g];
 #pragma unroll
-            for (int u = 0; u < SB; ++u) asm volatile("" ::"v"(sv[u].re), "v"(sv[u].im));
+                for (int u = 0; u < SB; ++u) asm volatile("" ::"v"(sv[u].re), "v"(sv[u].im));
 #pragma unroll
-            for (int u = 0; u < SB; ++u)
-                buf[s_comp(u0 + u) * ls + s_z] =
-                    cplx<T>{s_live ? sv[u].re : T(0), s_live ? sv[u].im : T(0)};
+                for (int u = 0; u < SB; ++u) {
+                    const int c = s_comp(u0 + u);
+                    buf[c * ls + cpos(c, s_z)] = sv[u];
+                }
+            }
         }
         if (tid < nf / 2) tw[tid] = twv;
     }
     __syncthreads();
-    fft_lines<T, false>(buf, logn, P, ls, 1, tw, tid, nthr);
+    fft_col_rt<T, false, nf>(buf, half, P, tw, tid, nthr);
     // M2L: thread = (row-subset group sub, frequency kz)
     const int sub = tid >> logn, kz = tid & (nf - 1);
     DCCorr dcc = {false, 0.0, 0.0, 0.0, 0.0};
     if (periodic && col == 0 && kz == 0) {
         // zero frequency: M~_c(0) = sum over cells of M_c (real)
-        const cplx<T> *m0 = buf;
+        auto m0 = [&](int c) { return (double)buf[c * ls + cpos(c, 0)].re; };
         const double V = (double)nf * nf * nf;  // box volume in cell units (nf = n)
         const double pi = 3.14159265358979323846;
         double qr2 = 0.0;
         for (int z = 0; z < nz; ++z) qr2 += qr2_partial[z];
-        const double m10 = PO >= 1 ? (double)m0[ridx(1, 0) * ls].re : 0.0;
-        const double m11 = PO >= 1 ? (double)m0[ridx(1, 1) * ls].re : 0.0;
-        const double m1m1 = PO >= 1 ? (double)m0[ridx(1, -1) * ls].re : 0.0;
+        const double m10 = PO >= 1 ? m0(ridx(1, 0)) : 0.0;
+        const double m11 = PO >= 1 ? m0(ridx(1, 1)) : 0.0;
+        const double m1m1 = PO >= 1 ? m0(ridx(1, -1)) : 0.0;
         dcc.l00 = 2.0 * pi / (3.0 * V) * qr2 * V;
         dcc.l10 = 4.0 * pi / (3.0 * V) * m10 * V;
         dcc.l11re = 8.0 * pi / (3.0 * V) * m11 * V;
         dcc.l11im = -8.0 * pi / (3.0 * V) * m1m1 * V;
         dcc.on = true;
-        if (sub == 0) sums[0] = (double)m0[0].re;  // total charge
+        if (sub == 0) sums[0] = m0(0);  // total charge
     }
     {
         const int ky = small_div(col, 1.0f / (float)nh), kx = col - ky * nh;
         const int kyr = ky <= nf / 2 ? ky : nf - ky;
         const int kzr = kz <= nf / 2 ? kz : nf - kz;
         const int flip = (ky > nf / 2 ? 1 : 0) | (kz > nf / 2 ? 2 : 0);
-        const T *gp = green + (int64_t)(kyr * nh + kx) * Q * nhp + kzr;
-        const cplx<T> *mp = buf + kz;
+        const GSlab gs = make_gslab<T>(green + (int64_t)(kyr * nh + kx) * Q * nhp, Q * nhp, kzr, nhp);
+        // row b of the thread's frequency sits at buf + b * ls + kpos (+ odd
+        // for odd b)
+        const int kpos = cpos(0, kz), odd = cpos(1, kz) - kpos;
+        const cplx<T> *mp = buf + kpos;
         cplx<T> res[RSP][subset_rows_max(PO, RS)];
         static_for<0, RSP>([&](auto ik) {
             constexpr int k = decltype(ik)::value;
             static_for<0, NSUB>([&](auto is) {
                 constexpr int s = decltype(is)::value;
-                if (sub == s) m2l_rows_g<PO, RS, k * NSUB + s, T>(gp, nhp, flip, mp, ls, dcc, res[k]);
+                if (sub == s)
+                    m2l_rows_g<PO, RS, k * NSUB + s, T>(gs, flip, mp, ls, dcc, res[k], odd);
             });
         });
         __syncthreads();  // every read of the moment spectra is done
@@ -623,12 +740,12 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
             constexpr int k = decltype(ik)::value;
             static_for<0, NSUB>([&](auto is) {
                 constexpr int s = decltype(is)::value;
-                if (sub == s) m2l_put<PO, RS, k * NSUB + s, T>(res[k], buf + kz, ls);
+                if (sub == s) m2l_put<PO, RS, k * NSUB + s, T>(res[k], buf + kpos, ls, odd);
             });
         });
     }
     __syncthreads();
-    fft_lines<T, true>(buf, logn, P, ls, 1, tw, tid, nthr);
+    fft_col_rt<T, true, nf>(buf, half, P, tw, tid, nthr);
     // local spectra of z < nz back to HBM, LDS reads in batches
     const int lognz = __builtin_ctz(nz);
     const int o_z = tid & (nz - 1);
@@ -639,7 +756,7 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
 #pragma unroll
         for (int u = 0; u < kColumnLoadBatch; ++u) {
             const int a = o_a0 + (u0 + u) * o_da < P ? o_a0 + (u0 + u) * o_da : P - 1;
-            v[u] = buf[a * ls + o_z];
+            v[u] = buf[a * ls + cpos(a, o_z)];
         }
 #pragma unroll
         for (int u = 0; u < kColumnLoadBatch; ++u) {
@@ -656,20 +773,30 @@ inline int column_ilog2(int v) {
     return l;
 }
 
+template <int PO, typename T, int RSP, int LOGN>
+hipError_t column_launch_g(const FFTArgs &a, hipStream_t s) {
+    constexpr int nf = 1 << LOGN, nh = nf / 2 + 1, ncol = nf * nh;
+    const size_t lds = column_g_lds(PO, nf, sizeof(T));
+    if (lds == 0 || a.nf != nf || (a.n != nf && 2 * a.n != nf)) return hipErrorInvalidValue;
+    const int threads = (kRowSplit / RSP) * nf;
+    if (threads < 64) return hipErrorInvalidValue;
+    const int grid = ((ncol + 7) / 8) * 8;
+    hipError_t e =
+        lds <= 65536 ? hipSuccess : set_max_lds((const void *)k_column_g<PO, T, RSP, LOGN>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_column_g<PO, T, RSP, LOGN>), dim3(grid, a.nsys > 0 ? a.nsys : 1),
+                       dim3(threads), lds, s, a.n, ncol, ncol, (const T *)a.green,
+                       (cplx<T> *)a.spec, (const cplx<T> *)a.tw, a.open ? 0 : 1, a.qr2_partial,
+                       a.sums);
+    return hipGetLastError();
+}
+
+// The streamed form at the plan's FFT size (64 or 128 points).
 template <int PO, typename T, int RSP>
 hipError_t column_launch_g(const FFTArgs &a, hipStream_t s) {
-    const int nf = a.nf, logn = column_ilog2(nf), nh = nf / 2 + 1, ncol = nf * nh;
-    const size_t lds = column_g_lds(PO, nf, sizeof(T));
-    if (lds == 0 || nf < 16 || nf > 128) return hipErrorInvalidValue;
-    const int threads = (kRowSplit / RSP) * nf;
-    if (threads < 64 || threads > (kRowSplit / RSP) * 128) return hipErrorInvalidValue;
-    const int grid = ((ncol + 7) / 8) * 8;
-    hipError_t e = lds <= 65536 ? hipSuccess : set_max_lds((const void *)k_column_g<PO, T, RSP>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_column_g<PO, T, RSP>), dim3(grid, a.nsys > 0 ? a.nsys : 1), dim3(threads),
-                       lds, s, a.n, logn, ncol, ncol, (const T *)a.green, (cplx<T> *)a.spec,
-                       (const cplx<T> *)a.tw, a.open ? 0 : 1, a.qr2_partial, a.sums);
-    return hipGetLastError();
+    if (a.nf == 128) return column_launch_g<PO, T, RSP, 7>(a, s);
+    if (a.nf == 64) return column_launch_g<PO, T, RSP, 6>(a, s);
+    return hipErrorInvalidValue;
 }
 
 template <int PO, typename T>

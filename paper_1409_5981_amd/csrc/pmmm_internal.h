@@ -411,16 +411,16 @@ inline size_t column_lds_w(int p, int nf, size_t tsize, int w, int *rs_out) {
 }
 
 // LDS bytes of the streamed-kernel column variant (twiddles and one column's
-// spectra; 0 if over 160 KB).
+// spectra, rows of nf without padding; 0 if over 160 KB).
 inline size_t column_g_lds(int p, int nf, size_t tsize) {
     const size_t P = (size_t)(p + 1) * (p + 1);
-    const size_t lds = P * (size_t)lds_line(nf) * 2 * tsize + (size_t)nf / 2 * 2 * tsize;
+    const size_t lds = P * (size_t)nf * 2 * tsize + (size_t)nf / 2 * 2 * tsize;
     return lds > 160 * 1024 ? 0 : lds;
 }
 
 // Column kernel forms (PMMM_COLUMN_* in pmmm.h): the kernel tile staged in
 // LDS for w columns per block, or streamed from memory with each thread
-// running 1, 2 or 4 row subsets.
+// running 1, 2 or 4 row subsets (FFT meshes of 64 and 128 points).
 inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize);
 // Default form: the streamed kernel with two subsets per thread for FFT
 // meshes of 64 points and more (or wherever the staged tile does not fit),
@@ -447,8 +447,7 @@ inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize) {
         case PMMM_COLUMN_STREAM_1:
         case PMMM_COLUMN_STREAM_2:
         case PMMM_COLUMN_STREAM_4:
-            return nf >= 16 && column_g_lds(p, nf, tsize) > 0 &&
-                   (kColumnRowSplit >> (kind - PMMM_COLUMN_STREAM_1)) * nf >= 64;
+            return (nf == 64 || nf == 128) && column_g_lds(p, nf, tsize) > 0;
         default: return false;
     }
 }
