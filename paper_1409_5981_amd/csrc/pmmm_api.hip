@@ -34,22 +34,15 @@ int hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? PMMM_ENOMEM : PMMM_EHIP;
 }
 
-// Cells denser than this go to the one-workgroup-per-cell FP64 path of P2M.
-constexpr int kDenseThreshold = 256;
+// P2M: a cell of more than 16 G particles (G lanes per light cell, so at
+// most 16 particles per lane there) is cut into dense items of kDenseItem
+// particles, one wave each.
+static int dense_threshold_for(int group) { return 16 * group; }
 
 // From this many particles on, L2P writes its results in sorted order and a
 // second kernel sends them back to the caller's order (fewer, wider random
 // accesses); below it the extra launch costs more than it saves.
 constexpr int64_t kStagedL2PMinN = int64_t(1) << 18;
-
-// Workgroups of the P2M launch that reduce the dense cells (one cell at a
-// time each): none below the threshold, one per 8192 particles within
-// [32, 512] above it (a clustered system has thousands of dense cells).
-static int dense_blocks_for(int64_t n) {
-    if (n <= kDenseThreshold) return 0;
-    const int64_t b = n / 8192;
-    return (int)(b < 32 ? 32 : (b > 512 ? 512 : b));
-}
 
 struct Plan {
     pmmm_params prm;
@@ -60,7 +53,7 @@ struct Plan {
     size_t tsize;
     // plan-lifetime buffers
     void *green = nullptr, *tw = nullptr, *M = nullptr, *spec = nullptr, *L = nullptr;
-    int *start = nullptr, *dense_cells = nullptr, *small = nullptr;
+    int *start = nullptr, *small = nullptr;
     int *tile_first = nullptr;  // near field: first tile of every row of cells
     double *sums = nullptr, *qr2_partial = nullptr;
     // particle buffers
@@ -69,6 +62,8 @@ struct Plan {
     int *tile_row = nullptr;    // near field: row of every tile
     int *count = nullptr, *tile_sums = nullptr;  // radix-sort histograms and scan scratch
     void *sorted = nullptr, *staged = nullptr;   // staged: out4<T>[cap] sorted-order results
+    int4 *items = nullptr;                       // dense P2M items [dense_items_cap(cap, K)]
+    float *partial = nullptr;                    // [dense_slots_cap(cap)][P + 1]
     hipStream_t last_stream = nullptr;
     // multi-charge workspace (chunks of up to kMultiMaxSets sets)
     int mcap_sets = 0;
@@ -224,7 +219,7 @@ static size_t plan_bytes(const Plan *pl) {
     b += (size_t)(pl->P + 1) * pl->K * t;                // M
     b += (size_t)pl->P * pl->n * pl->ncol * c;           // spectra
     b += (size_t)pl->P * pl->K * t;                      // L
-    b += ((size_t)pl->K + 1 + pl->K + 8) * sizeof(int);                           // starts, dense list, small
+    b += ((size_t)pl->K + 1 + 8) * sizeof(int);                                   // starts, small
     b += 8 * sizeof(double) + (size_t)pl->n * sizeof(double);                     // sums, plane sums
     b += (size_t)pl->n * pl->n * sizeof(int);                                     // near-field row tiles
     return b;
@@ -233,7 +228,9 @@ static size_t plan_bytes(const Plan *pl) {
 static size_t particle_bytes(const Plan *pl, int64_t n) {
     return (size_t)n * (5 * sizeof(int) + 8 * pl->tsize) +
            sizeof(int) * (size_t)(near_tile_capacity(n, pl->n) + bin_hist_ints(n) +
-                                  bin_scan_tiles(n));
+                                  bin_scan_tiles(n)) +
+           sizeof(int4) * (size_t)dense_items_cap(n, pl->K) +
+           sizeof(float) * (size_t)dense_slots_cap(n) * (pl->P + 1);
 }
 
 static void free_particles(Plan *pl) {
@@ -247,9 +244,13 @@ static void free_particles(Plan *pl) {
     hipFree(pl->tile_row);
     hipFree(pl->count);
     hipFree(pl->tile_sums);
+    hipFree(pl->items);
+    hipFree(pl->partial);
     pl->cell_of = pl->slot = pl->perm = pl->scell = pl->pos = pl->tile_row = nullptr;
     pl->count = pl->tile_sums = nullptr;
     pl->sorted = pl->staged = nullptr;
+    pl->items = nullptr;
+    pl->partial = nullptr;
     pl->cap = 0;
 }
 
@@ -271,6 +272,8 @@ static int ensure_capacity(Plan *pl, int64_t n) {
     PMMM_HIP(hipMalloc(&pl->tile_row, sizeof(int) * near_tile_capacity(n, pl->n)));
     PMMM_HIP(hipMalloc(&pl->count, sizeof(int) * bin_hist_ints(n)));
     PMMM_HIP(hipMalloc(&pl->tile_sums, sizeof(int) * bin_scan_tiles(n)));
+    PMMM_HIP(hipMalloc(&pl->items, sizeof(int4) * dense_items_cap(n, pl->K)));
+    PMMM_HIP(hipMalloc(&pl->partial, sizeof(float) * dense_slots_cap(n) * (pl->P + 1)));
     pl->cap = n;
     return PMMM_OK;
 }
@@ -285,7 +288,6 @@ static void destroy(Plan *pl) {
     hipFree(pl->spec);
     hipFree(pl->L);
     hipFree(pl->start);
-    hipFree(pl->dense_cells);
     hipFree(pl->small);
     hipFree(pl->tile_first);
     hipFree(pl->sums);
@@ -322,8 +324,8 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
     PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
-    PMMM_HIP(hipMalloc(&pl->dense_cells, sizeof(int) * pl->K));
-    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));  // [0] dense count, [1] domain flag, [2] near tiles
+    // [0] dense items, [1] domain flag, [2] near tiles, [3] partial slots
+    PMMM_HIP(hipMalloc(&pl->small, sizeof(int) * 8));
     PMMM_HIP(hipMalloc(&pl->tile_first, sizeof(int) * (size_t)pl->n * pl->n));
     PMMM_HIP(hipMalloc(&pl->sums, sizeof(double) * 8));
     PMMM_HIP(hipMalloc(&pl->qr2_partial, sizeof(double) * pl->n));
@@ -351,11 +353,16 @@ enum CallMode { kFar = 0, kNear = 1, kTotal = 2 };
 struct PBuf {
     int *cell_of, *slot, *perm, *scell, *pos, *tile_row, *count, *tile_sums;
     void *sorted, *staged;
+    int4 *items;
+    float *partial;
+    int64_t items_cap, slots_cap;
 };
 
 static PBuf plan_pbuf(const Plan *pl) {
-    return PBuf{pl->cell_of,  pl->slot,  pl->perm,      pl->scell,  pl->pos,
-                pl->tile_row, pl->count, pl->tile_sums, pl->sorted, pl->staged};
+    return PBuf{pl->cell_of,    pl->slot,   pl->perm,   pl->scell,
+                pl->pos,        pl->tile_row, pl->count, pl->tile_sums,
+                pl->sorted,     pl->staged, pl->items,  pl->partial,
+                dense_items_cap(pl->cap, pl->K), dense_slots_cap(pl->cap)};
 }
 
 // ext == nullptr: the plan's particle buffers, grown to n if needed (which
@@ -399,6 +406,8 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
     // near and total calls, and large far-field calls, leave their results
     // in sorted order (16-byte records) and send them back in one pass
     const bool staged = mode != kFar || n >= kStagedL2PMinN;
+    const int group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
+    const int dense_thr = dense_threshold_for(group);
 
     {
         StageTimer t(pl, PMMM_STAGE_BIN, s, timed);
@@ -418,11 +427,12 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.scell = pb.scell;
         b.perm = pb.perm;
         b.flag = pl->small + 1;
-        b.dense_cells = pl->dense_cells;
-        b.dense_count = pl->small;
+        b.items = mode != kNear ? pb.items : nullptr;
+        b.items_cap = pb.items_cap;
+        b.small = pl->small;
         b.pos = staged ? pb.pos : nullptr;
         b.tile_sums = pb.tile_sums;
-        b.dense_threshold = kDenseThreshold;
+        b.dense_threshold = dense_thr;
         b.sorted = pb.sorted;
         b.recs = pb.staged;   // free until L2P
         PMMM_HIP(launch_bin<T>(b, s));
@@ -433,13 +443,14 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
             P2MArgs m{};
             m.p = pl->p;
             m.ncell = pl->n;
-            m.group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
-            m.dense_blocks = dense_blocks_for(n);
-            m.zero_count = nullptr;
+            m.group = group;
             m.start = pl->start;
-            m.dense_cells = pl->dense_cells;
-            m.dense_count = pl->small;
-            m.dense_threshold = kDenseThreshold;
+            m.dense_threshold = dense_thr;
+            m.items = pb.items;
+            m.items_cap = pb.items_cap;
+            m.small = pl->small;
+            m.partial = pb.partial;
+            m.slots_cap = pb.slots_cap;
             m.sorted = pb.sorted;
             m.M = pl->M;
             PMMM_HIP(launch_p2m<T>(m, s));
@@ -515,16 +526,26 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
 // ------------------------------------------- allocation-free far field
 // Per-particle scratch of pmmm_far_f32_noalloc in one file-scope device
 // array: cell, slot, permutation, sorted cell and sorted-slot arrays (5 ints
-// per particle) and the sorted records and sorted-order results (two
-// 16-byte records per particle), each region 256-byte aligned.  Every region
-// is written before it is read within a call, so nothing needs clearing.
+// per particle), the sorted records and sorted-order results (two 16-byte
+// records per particle), the radix-sort histograms, and the dense P2M items
+// and partial sums (for orders up to PMMM_PMAX), each region 256-byte
+// aligned.  Every region is written before it is read within a call (the
+// item counts are reset by the binning), so nothing needs clearing.
 constexpr int64_t kNoAllocMaxN = PMMM_NOALLOC_MAX_N;
 constexpr size_t kNoAllocInts = (size_t)kNoAllocMaxN * sizeof(int);
 constexpr size_t kNoAllocRecs = (size_t)kNoAllocMaxN * sizeof(particle4<float>);
 // radix-sort histograms (512 buckets per tile) and their scan scratch
 constexpr size_t kNoAllocHist = (size_t)bin_hist_ints(kNoAllocMaxN) * sizeof(int);
 constexpr size_t kNoAllocSums = ((size_t)bin_scan_tiles(kNoAllocMaxN) * sizeof(int) + 255) / 256 * 256;
-constexpr size_t kNoAllocBytes = 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist + kNoAllocSums;
+// dense items: at most max_n / (threshold + 1) dense cells whatever the mesh
+constexpr int64_t kNoAllocItemsCap = dense_items_cap(kNoAllocMaxN, kNoAllocMaxN);
+constexpr int64_t kNoAllocSlotsCap = dense_slots_cap(kNoAllocMaxN);
+constexpr size_t kNoAllocItems = ((size_t)kNoAllocItemsCap * sizeof(int4) + 255) / 256 * 256;
+constexpr size_t kNoAllocPartial =
+    ((size_t)kNoAllocSlotsCap * (PMMM_PMAX + 1) * (PMMM_PMAX + 1 + 1) * sizeof(float) + 255) /
+    256 * 256;
+constexpr size_t kNoAllocBytes = 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist +
+                                 kNoAllocSums + kNoAllocItems + kNoAllocPartial;
 static_assert(kNoAllocInts % 256 == 0 && kNoAllocRecs % 256 == 0 && kNoAllocHist % 256 == 0,
               "256-byte aligned regions");
 
@@ -585,6 +606,11 @@ static int far_noalloc(pmmm_plan_s *pl, int64_t n, const float *x, const float *
     pb.staged = b + 5 * kNoAllocInts + kNoAllocRecs;
     pb.count = (int *)(b + 5 * kNoAllocInts + 2 * kNoAllocRecs);
     pb.tile_sums = (int *)(b + 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist);
+    pb.items = (int4 *)(b + 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist + kNoAllocSums);
+    pb.partial = (float *)(b + 5 * kNoAllocInts + 2 * kNoAllocRecs + kNoAllocHist +
+                           kNoAllocSums + kNoAllocItems);
+    pb.items_cap = kNoAllocItemsCap;
+    pb.slots_cap = kNoAllocSlotsCap;
     pb.tile_row = nullptr;  // far field only
     if ((size_t)bin_hist_ints(n) * sizeof(int) > kNoAllocHist ||
         (size_t)bin_scan_tiles(n) * sizeof(int) > kNoAllocSums) {
@@ -680,10 +706,9 @@ static int multi_impl(pmmm_plan_s *pl, int64_t n, const float *x, const float *y
         b.scell = pl->scell;
         b.perm = pl->perm;
         b.flag = pl->small + 1;
-        b.dense_cells = pl->dense_cells;
-        b.dense_count = pl->small;
+        b.items = nullptr;        // the multi-charge P2M reduces every cell itself
+        b.small = pl->small;
         b.tile_sums = pl->tile_sums;
-        b.dense_threshold = kDenseThreshold;
         b.sorted = pl->sorted;
         b.recs = pl->staged;
         PMMM_HIP(launch_bin<float>(b, s));
@@ -819,9 +844,12 @@ static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, con
 struct BatchClass {
     pmmm_plan_s *plan = nullptr;    // transfer kernel, twiddles, constants
     std::vector<int> members;       // system indices in the caller's order
-    int *start = nullptr, *dense = nullptr, *small = nullptr;
+    int *start = nullptr, *small = nullptr;
     int *count = nullptr, *tile_sums = nullptr;   // radix-sort scratch, sized by max_np
-    int64_t hist_cap = -1;          // max_np the radix scratch holds
+    int4 *items = nullptr;          // dense P2M items, [ns][items_cap]
+    float *partial = nullptr;       // [ns][slots_cap][P + 1]
+    int64_t hist_cap = -1;          // max_np the radix scratch and the items hold
+    int64_t items_cap = 0, slots_cap = 0;
     void *M = nullptr, *spec = nullptr, *L = nullptr;
     double *qr2 = nullptr, *sums = nullptr;
     int64_t *d_prange = nullptr;    // [2 members]
@@ -869,7 +897,8 @@ static void batch_destroy(pmmm_batch_s *b) {
     for (auto &c : b->cls) {
         hipFree(c.count);
         hipFree(c.start);
-        hipFree(c.dense);
+        hipFree(c.items);
+        hipFree(c.partial);
         hipFree(c.tile_sums);
         hipFree(c.small);
         hipFree(c.M);
@@ -895,7 +924,6 @@ static int batch_alloc_class(BatchClass &c, hipStream_t s) {
     const Plan *pl = c.plan;
     const size_t ns = c.members.size(), K = pl->K, P = pl->P, t = pl->tsize;
     PMMM_HIP(hipMalloc(&c.start, sizeof(int) * (K + 1) * ns));
-    PMMM_HIP(hipMalloc(&c.dense, sizeof(int) * K * ns));
     PMMM_HIP(hipMalloc(&c.small, sizeof(int) * 8 * ns));
     PMMM_HIP(hipMalloc(&c.M, t * (P + 1) * K * ns));
     PMMM_HIP(hipMalloc(&c.spec, 2 * t * P * pl->n * pl->ncol * ns));
@@ -941,6 +969,8 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
     for (auto &c : b->cls) {
         const Plan *pl = c.plan;
         const int ns = (int)c.members.size();
+        const int group = group_for((double)c.tot_np / ((double)pl->K * ns));
+        const int dense_thr = dense_threshold_for(group);
         BinArgs bn{};
         bn.n = 0;
         bn.x = x;
@@ -957,10 +987,11 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         bn.scell = b->scell;
         bn.perm = b->perm;
         bn.flag = b->flag;
-        bn.dense_cells = c.dense;
-        bn.dense_count = c.small;
+        bn.items = c.items;
+        bn.items_cap = c.items_cap;
+        bn.small = c.small;
         bn.tile_sums = c.tile_sums;
-        bn.dense_threshold = kDenseThreshold;
+        bn.dense_threshold = dense_thr;
         bn.sorted = b->sorted;
         bn.recs = b->recs;
         bn.prange = c.d_prange;
@@ -970,13 +1001,14 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
         P2MArgs m{};
         m.p = pl->p;
         m.ncell = pl->n;
-        m.group = group_for((double)c.tot_np / ((double)pl->K * ns));
-        m.dense_blocks = dense_blocks_for(c.max_np);
-        m.zero_count = nullptr;
+        m.group = group;
         m.start = c.start;
-        m.dense_cells = c.dense;
-        m.dense_count = c.small;
-        m.dense_threshold = kDenseThreshold;
+        m.dense_threshold = dense_thr;
+        m.items = c.items;
+        m.items_cap = c.items_cap;
+        m.small = c.small;
+        m.partial = c.partial;
+        m.slots_cap = c.slots_cap;
         m.sorted = b->sorted;
         m.M = c.M;
         m.prange = c.d_prange;
@@ -1078,10 +1110,20 @@ static int batch_far(pmmm_batch_s *b, const int64_t *offsets, const float *x, co
                 const size_t ns = c.members.size();
                 hipFree(c.count);
                 hipFree(c.tile_sums);
+                hipFree(c.items);
+                hipFree(c.partial);
                 c.count = c.tile_sums = nullptr;
+                c.items = nullptr;
+                c.partial = nullptr;
                 c.hist_cap = -1;
+                const int64_t ic = dense_items_cap(c.max_np, c.plan->K);
+                const int64_t sc = dense_slots_cap(c.max_np);
                 PMMM_HIP(hipMalloc(&c.count, sizeof(int) * bin_hist_ints(c.max_np) * ns));
                 PMMM_HIP(hipMalloc(&c.tile_sums, sizeof(int) * bin_scan_tiles(c.max_np) * ns));
+                PMMM_HIP(hipMalloc(&c.items, sizeof(int4) * ic * ns));
+                PMMM_HIP(hipMalloc(&c.partial, sizeof(float) * sc * (c.plan->P + 1) * ns));
+                c.items_cap = ic;
+                c.slots_cap = sc;
                 c.hist_cap = c.max_np;
             }
         }

@@ -20,15 +20,15 @@
 //                 the permutation, the sorted records and, on request, each
 //                 particle's sorted slot
 //   k_rb_bounds   start of every cell by binary search among the sorted slots
-//                 of its last digit, and the list of cells above the dense
-//                 threshold
+//                 of its last digit, and the P2M work items of the cells
+//                 above the dense threshold (kDenseItem particles each)
 // Cell index: I = floor(r n / b) per axis, clamped to [0, n-1]; periodic
 // positions are first wrapped into the box (in cell units).
 //
 // Batches: blockIdx.y selects one of several independent systems on meshes of
 // the same size; prange[2s], prange[2s+1] bound system s's particles in the
 // caller's arrays (null: one system, particles [0, n)), and its per-system
-// arrays sit at fixed strides (start K + 1, dense list K, small 8,
+// arrays sit at fixed strides (start K + 1, items items_cap, small 8,
 // histograms bin_hist_ints(max_np), scan sums bin_scan_tiles(max_np)).
 #include "pmmm_internal.h"
 
@@ -74,8 +74,11 @@ constexpr size_t scatter_lds(int bits) {
     return scatter_region<T, R>(bits) + (size_t)(2 * (1 << bits) + 16) * sizeof(int);
 }
 
-__global__ void k_rb_reset_dense(int nsys, int *__restrict__ dense_count) {
-    for (int sy = threadIdx.x; sy < nsys; sy += blockDim.x) dense_count[(int64_t)sy * 8] = 0;
+__global__ void k_rb_reset_items(int nsys, int *__restrict__ small) {
+    for (int sy = threadIdx.x; sy < nsys; sy += blockDim.x) {
+        small[(int64_t)sy * 8] = 0;
+        small[(int64_t)sy * 8 + 3] = 0;
+    }
 }
 
 // Tile histogram of digit (key >> shift) & (2^bits - 1), written to
@@ -85,13 +88,17 @@ __global__ void __launch_bounds__(1024) k_rb_hist(
     const int64_t *__restrict__ prange, int64_t n, int first, const T *__restrict__ x,
     const T *__restrict__ y, const T *__restrict__ z, T inv_h, int nc, int periodic,
     const int *__restrict__ keys, int *__restrict__ hist, int64_t hist_ints, int tiles,
-    int shift, int bits, int *__restrict__ flag, int *__restrict__ dense_count) {
+    int shift, int bits, int *__restrict__ flag, int *__restrict__ small) {
     __shared__ int s_hist[kRadixBuckets];
     int64_t p0, np;
     sys_range(prange, n, p0, np);
     const int nb = 1 << bits, t = blockIdx.x;
     for (int d = threadIdx.x; d < nb; d += blockDim.x) s_hist[d] = 0;
-    if (first && t == 0 && threadIdx.x == 0) dense_count[(int64_t)blockIdx.y * 8] = 0;
+    if (first && t == 0 && threadIdx.x == 0) {
+        // item and partial-slot counts of this binning (filled by k_rb_bounds)
+        small[(int64_t)blockIdx.y * 8] = 0;
+        small[(int64_t)blockIdx.y * 8 + 3] = 0;
+    }
     __syncthreads();
     int kv[R];
     int out = 0;
@@ -396,18 +403,21 @@ __global__ void __launch_bounds__(1024) k_rb_scatter(
 // start[c] = first sorted slot of the system with cell >= c (relative to the
 // system's first particle), c = 0..K, searched among the slots whose last
 // digit equals c's (their range comes from the last pass's scanned
-// histogram); cells above the dense threshold are listed (in no particular
-// order: each dense cell is reduced by one block in a fixed order).
+// histogram).  A cell of more than dense_thr particles becomes J =
+// ceil(count / kDenseItem) P2M items {cell, j, J, first partial slot (J > 1)
+// or -1}; items and slots are reserved with atomics, so their positions vary
+// from call to call, but every item covers a fixed particle range and the
+// partials of a cell are added in item order, so the moments do not.
 __global__ void __launch_bounds__(256) k_rb_bounds(
     const int64_t *__restrict__ prange, int64_t n, int K, const int *__restrict__ skeys,
-    int *__restrict__ start, int dense_thr, int *__restrict__ dense_cells,
-    int *__restrict__ dense_count, const int *__restrict__ offs, int64_t hist_ints, int tiles,
+    int *__restrict__ start, int dense_thr, int4 *__restrict__ items, int64_t items_cap,
+    int *__restrict__ small, const int *__restrict__ offs, int64_t hist_ints, int tiles,
     int shift, int bits) {
     int64_t p0, np;
     sys_range(prange, n, p0, np);
     start += (int64_t)blockIdx.y * (K + 1);
-    dense_cells += (int64_t)blockIdx.y * K;
-    dense_count += (int64_t)blockIdx.y * 8;
+    if (items != nullptr) items += (int64_t)blockIdx.y * items_cap;
+    small += (int64_t)blockIdx.y * 8;
     offs += (int64_t)blockIdx.y * hist_ints;
     const int c = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
     const int nb = 1 << bits;
@@ -429,7 +439,13 @@ __global__ void __launch_bounds__(256) k_rb_bounds(
     int s1 = __shfl_down(s0, 1, 64);
     if (lane == 63 && c < K) s1 = lower(c + 1);
     if (c <= K) start[c] = s0;
-    if (c < K && s1 - s0 > dense_thr) dense_cells[atomicAdd(dense_count, 1)] = c;
+    if (items != nullptr && c < K && s1 - s0 > dense_thr) {
+        const int J = (s1 - s0 + kDenseItem - 1) / kDenseItem;
+        const int base = atomicAdd(small, J);
+        const int ps = J > 1 ? atomicAdd(small + 3, J) : -1;
+        for (int j = 0; j < J; ++j)
+            if (base + j < items_cap) items[base + j] = int4{c, j, J, ps};
+    }
 }
 
 // Digit widths of the passes for keys below K (at most kRadixMaxBits each,
@@ -465,7 +481,7 @@ static hipError_t radix_bin(const BinArgs &a, int K, int64_t maxn, hipStream_t s
         hipLaunchKernelGGL((k_rb_hist<T, R>), dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
                            first, (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
                            a.periodic, kin, a.count, hist_ints, tiles, shift, bits, a.flag,
-                           a.dense_count);
+                           a.small);
         const int64_t L = (int64_t)(1 << bits) * tiles;
         if (L <= kScanOneBlock) {
             hipLaunchKernelGGL(k_rb_scan1, dim3(1, nsys), dim3(1024), 0, s, L, hist_ints, a.count);
@@ -491,8 +507,8 @@ static hipError_t radix_bin(const BinArgs &a, int K, int64_t maxn, hipStream_t s
         if (!last) shift += bits;
     }
     hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s, a.prange,
-                       a.n, K, a.scell, a.start, a.dense_threshold, a.dense_cells, a.dense_count,
-                       a.count, hist_ints, tiles, shift, widths[passes - 1]);
+                       a.n, K, a.scell, a.start, a.dense_threshold, a.items, a.items_cap,
+                       a.small, a.count, hist_ints, tiles, shift, widths[passes - 1]);
     return hipGetLastError();
 }
 
@@ -501,12 +517,12 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const int64_t maxn = a.prange ? a.max_np : a.n;
     if (maxn == 0) {
-        // every system is empty: zero starts, and the dense count reset here
+        // every system is empty: zero starts, and the item counts reset here
         const int nsys = a.nsys > 0 ? a.nsys : 1;
-        hipLaunchKernelGGL(k_rb_reset_dense, dim3(1), dim3(64), 0, s, nsys, a.dense_count);
+        hipLaunchKernelGGL(k_rb_reset_items, dim3(1), dim3(64), 0, s, nsys, a.small);
         hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s,
-                           a.prange, a.n, K, a.scell, a.start, a.dense_threshold, a.dense_cells,
-                           a.dense_count, a.count, (int64_t)0, 1, 0, 1);
+                           a.prange, a.n, K, a.scell, a.start, a.dense_threshold, a.items,
+                           a.items_cap, a.small, a.count, (int64_t)0, 1, 0, 1);
         return hipGetLastError();
     }
     switch (bin_tile_items(maxn)) {

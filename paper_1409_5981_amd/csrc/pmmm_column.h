@@ -791,10 +791,12 @@ hipError_t column_launch_g(const FFTArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The streamed form at the plan's FFT size (64 or 128 points).
+// The streamed form at the plan's FFT size (64 or 128 points; FP64 plans
+// stop at 64).
 template <int PO, typename T, int RSP>
 hipError_t column_launch_g(const FFTArgs &a, hipStream_t s) {
-    if (a.nf == 128) return column_launch_g<PO, T, RSP, 7>(a, s);
+    if constexpr (sizeof(T) == 4)
+        if (a.nf == 128) return column_launch_g<PO, T, RSP, 7>(a, s);
     if (a.nf == 64) return column_launch_g<PO, T, RSP, 6>(a, s);
     return hipErrorInvalidValue;
 }

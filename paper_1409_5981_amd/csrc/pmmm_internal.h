@@ -488,7 +488,12 @@ struct BinArgs {
     void *recs;        // particle4<T>[n] records between passes
     int *start;        // [nsys][K + 1] first sorted slot of every cell (system-relative)
     int *flag;         // set when an open-boundary particle lies outside the box
-    int *dense_cells, *dense_count;
+    // [nsys][items_cap] dense-cell items {cell, chunk, chunks, first partial
+    // slot or -1} (or null: none built); small[8 s + 0] counts the items,
+    // small[8 s + 3] the partial slots of system s
+    int4 *items;
+    int64_t items_cap;
+    int *small;
     int *count;        // [nsys][bin_hist_ints(max_np)] radix histograms / offsets
     int *tile_sums;    // [nsys][bin_scan_tiles(max_np)] scan scratch
     int *pos;          // [n] sorted slot of each particle in the caller's order (or null)
@@ -524,12 +529,29 @@ constexpr int64_t bin_hist_ints(int64_t max_np) {
 }
 constexpr int64_t bin_scan_tiles(int64_t max_np) { return (bin_hist_ints(max_np) + 4095) / 4096; }
 
+// Dense cells (above the P2M threshold, never below kDenseMinThreshold) are
+// cut into items of kDenseItem sorted particles, one wave each; a cell of J
+// items (J > 1) leaves J partial sums that a second pass adds in item order.
+constexpr int kDenseItem = 512;
+constexpr int kDenseMinThreshold = 64;
+// Items of a system of up to max_np particles on K cells: each dense cell
+// gives at most count / kDenseItem + 1, and there are at most
+// max_np / (threshold + 1) dense cells.
+constexpr int64_t dense_items_cap(int64_t max_np, int64_t K) {
+    return max_np / kDenseItem + bin_min64(K, max_np / (kDenseMinThreshold + 1)) + 1;
+}
+// Partial slots: a split cell has count > kDenseItem and J < 2 count / kDenseItem.
+constexpr int64_t dense_slots_cap(int64_t max_np) { return 2 * max_np / kDenseItem + 1; }
+
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path
-    int dense_blocks;               // workgroups for the dense cells (0: n below the threshold)
-    int *zero_count;                // counts to reset for the next binning (or null)
-    const int *start, *dense_cells, *dense_count;
-    int dense_threshold;
+    const int *start;
+    int dense_threshold;            // cells above it are reduced as dense items
+    const int4 *items;              // dense items of the binning (see BinArgs)
+    int64_t items_cap;
+    const int *small;
+    float *partial;                 // [nsys][slots_cap][P + 1] sums of the items of split cells
+    int64_t slots_cap;
     const void *sorted;
     void *M;                        // [P + 1][K]: moments, then sum q |u|^2
     const int64_t *prange;          // batch (see BinArgs)

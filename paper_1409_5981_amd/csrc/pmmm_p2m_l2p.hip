@@ -18,109 +18,170 @@
 
 namespace pmmm {
 
-// Blocks [0, nlight) run the light path (G lanes per cell); the remaining
-// dense_blocks handle the listed dense cells, one workgroup per cell with
-// FP64 accumulation and a fixed-order reduction.  zero_count (when not
-// null) is reset for the next binning.
+// Sum of v[0..64) over the 64 lanes of a wave, scattered: on return lane L
+// holds in v[0] the total of component L.  Six exchange steps, each halving
+// the components a lane keeps (the lower half if its bit is clear, else the
+// upper half, the other half going to the partner lane), so 63 shuffles in
+// place of 6 per component; the pattern is fixed, so the sums are
+// reproducible.
+template <int H, typename A>
+__device__ __forceinline__ void wave_rs_step(A *v, int lane) {
+    if constexpr (H >= 1) {
+        const bool up = (lane & H) != 0;
+        static_for<0, H>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const A send = up ? v[i] : v[i + H];
+            const A keep = up ? v[i + H] : v[i];
+            v[i] = keep + __shfl_xor(send, H, 64);
+        });
+        wave_rs_step<H / 2, A>(v, lane);
+    }
+}
+
+// Light cells (at most dense_thr particles): a group of G lanes per cell
+// strides over its sorted particles and reduces with cross-lane shuffles.
 template <int PO, typename T, int G>
 __global__ void __launch_bounds__(256) k_p2m(int K, const int *__restrict__ start,
                                              const particle4<T> *__restrict__ sorted,
-                                             int dense_thr, const int *__restrict__ dense_cells,
-                                             const int *__restrict__ dense_count, int nlight,
-                                             T *__restrict__ M, int *__restrict__ zero_count,
+                                             int dense_thr, T *__restrict__ M,
                                              const int64_t *__restrict__ prange) {
     constexpr int P = nreal(PO);
+    constexpr int NV = P + 1;
     {
         // system blockIdx.y of a batch: its cell arrays and sorted particles
         const int64_t sy = blockIdx.y;
         start += sy * (K + 1);
-        dense_cells += sy * K;
-        dense_count += sy * 8;
-        M += sy * (P + 1) * K;
-        if (zero_count != nullptr) zero_count += sy * K;
+        M += sy * NV * K;
         if (prange != nullptr) sorted += prange[2 * sy];
     }
-    if ((int)blockIdx.x < nlight) {
-        const int gid = blockIdx.x * 256 + threadIdx.x;
-        if (zero_count != nullptr && gid < K) zero_count[gid] = 0;
-        const int cell = gid / G;
-        const int lane = gid & (G - 1);
-        int s0 = 0, s1 = 0;
-        bool write = false;
-        if (cell < K) {
-            s0 = start[cell];
-            s1 = start[cell + 1];
-            write = (s1 - s0) <= dense_thr;
-            if (!write) s1 = s0;
-        }
-        T acc[P + 1];
-#pragma unroll
-        for (int c = 0; c <= P; ++c) acc[c] = T(0);
-        // two particles per lane and round, both loads in flight together; a
-        // clamped second particle past the cell's end enters with charge 0
-        // (same summation order as one particle per round)
-        for (int s = s0 + lane; s < s1; s += 2 * G) {
-            const bool two = s + G < s1;
-            const particle4<T> r0 = sorted[s];
-            const particle4<T> r1 = sorted[two ? s + G : s];
-            const T q1 = two ? r1.q : T(0);
-            accumulate_regular<PO, T>(-r0.ux, -r0.uy, -r0.uz, r0.q, acc);  // q R(r_M - r_i)
-            acc[P] += r0.q * (r0.ux * r0.ux + r0.uy * r0.uy + r0.uz * r0.uz);
-            accumulate_regular<PO, T>(-r1.ux, -r1.uy, -r1.uz, q1, acc);
-            acc[P] += q1 * (r1.ux * r1.ux + r1.uy * r1.uy + r1.uz * r1.uz);
-        }
-#pragma unroll
-        for (int off = G / 2; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-        }
-        if (write) {
-#pragma unroll
-            for (int c = 0; c <= P; ++c)
-                if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
-        }
-        return;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int cell = gid / G;
+    const int lane = gid & (G - 1);
+    int s0 = 0, s1 = 0;
+    bool write = false;
+    if (cell < K) {
+        s0 = start[cell];
+        s1 = start[cell + 1];
+        write = (s1 - s0) <= dense_thr;
+        if (!write) s1 = s0;
     }
-    __shared__ double red[4][P + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int nd = *dense_count;
-    const int nblk = gridDim.x - nlight;
-    for (int d = blockIdx.x - nlight; d < nd; d += nblk) {
-        const int cell = dense_cells[d];
-        const int s0 = start[cell], s1 = start[cell + 1];
-        double acc[P + 1];
+    T acc[NV];
 #pragma unroll
-        for (int c = 0; c <= P; ++c) acc[c] = 0.0;
-        // four particles per thread and round, loads issued together; the
-        // per-thread order of the sum is unchanged (clamped extras enter with
-        // charge 0)
-        constexpr int U = 4;
-        for (int s = s0 + tid; s < s1; s += 256 * U) {
-            particle4<T> r[U];
+    for (int c = 0; c < NV; ++c) acc[c] = T(0);
+    // two particles per lane and round, both loads in flight together; a
+    // clamped second particle past the cell's end enters with charge 0
+    // (same summation order as one particle per round)
+    for (int s = s0 + lane; s < s1; s += 2 * G) {
+        const bool two = s + G < s1;
+        const particle4<T> r0 = sorted[s];
+        const particle4<T> r1 = sorted[two ? s + G : s];
+        const T q1 = two ? r1.q : T(0);
+        accumulate_regular<PO, T>(-r0.ux, -r0.uy, -r0.uz, r0.q, acc);  // q R(r_M - r_i)
+        acc[P] += r0.q * (r0.ux * r0.ux + r0.uy * r0.uy + r0.uz * r0.uz);
+        accumulate_regular<PO, T>(-r1.ux, -r1.uy, -r1.uz, q1, acc);
+        acc[P] += q1 * (r1.ux * r1.ux + r1.uy * r1.uy + r1.uz * r1.uz);
+    }
 #pragma unroll
-            for (int u = 0; u < U; ++u) r[u] = sorted[s + u * 256 < s1 ? s + u * 256 : s1 - 1];
+    for (int off = G / 2; off >= 1; off >>= 1) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double q = s + u * 256 < s1 ? (double)r[u].q : 0.0;
-                accumulate_regular<PO, double>(-(double)r[u].ux, -(double)r[u].uy,
-                                               -(double)r[u].uz, q, acc);
-                acc[P] += q * ((double)r[u].ux * r[u].ux + (double)r[u].uy * r[u].uy +
-                               (double)r[u].uz * r[u].uz);
+        for (int c = 0; c < NV; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    if (write) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            if ((c & (G - 1)) == lane) M[(int64_t)c * K + cell] = acc[c];
+    }
+}
+
+// Dense items of the binning, one wave each: the item's kDenseItem sorted
+// particles (eight per lane), a scattered wave sum per group of 64
+// components, then the moments written directly (a cell of one item) or as
+// the cell's partial sum of this item (added by k_p2m_combine in FP64).
+template <int PO, typename T>
+__global__ void __launch_bounds__(256) k_p2m_dense(int K, const int *__restrict__ start,
+                                                   const particle4<T> *__restrict__ sorted,
+                                                   const int4 *__restrict__ items,
+                                                   int64_t items_cap,
+                                                   const int *__restrict__ small,
+                                                   float *__restrict__ partial,
+                                                   int64_t slots_cap, T *__restrict__ M,
+                                                   const int64_t *__restrict__ prange) {
+    constexpr int P = nreal(PO);
+    constexpr int NV = P + 1;
+    constexpr int NG = (NV + 63) / 64;
+    {
+        const int64_t sy = blockIdx.y;
+        start += sy * (K + 1);
+        items += sy * items_cap;
+        small += sy * 8;
+        partial += sy * slots_cap * NV;
+        M += sy * NV * K;
+        if (prange != nullptr) sorted += prange[2 * sy];
+    }
+    const int lane = threadIdx.x & 63;
+    const int nitems = small[0] < items_cap ? small[0] : (int)items_cap;
+    const int nwaves = gridDim.x * 4;
+    for (int it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += nwaves) {
+        const int4 e = items[it];
+        const int cell = e.x, j = e.y, J = e.z, ps = e.w;
+        const int s0 = start[cell] + j * kDenseItem;
+        const int s1e = start[cell + 1];
+        const int s1 = s0 + kDenseItem < s1e ? s0 + kDenseItem : s1e;
+        constexpr int U = kDenseItem / 64;
+        particle4<T> r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + u * 64 + lane;
+            r[u] = sorted[s < s1 ? s : s1 - 1];
+        }
+        T acc[NG * 64];
+#pragma unroll
+        for (int c = 0; c < NG * 64; ++c) acc[c] = T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T q = s0 + u * 64 + lane < s1 ? r[u].q : T(0);
+            accumulate_regular<PO, T>(-r[u].ux, -r[u].uy, -r[u].uz, q, acc);
+            acc[P] += q * (r[u].ux * r[u].ux + r[u].uy * r[u].uy + r[u].uz * r[u].uz);
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            wave_rs_step<32, T>(acc + 64 * g, lane);
+            const int c = 64 * g + lane;
+            if (c < NV) {
+                if (J == 1) M[(int64_t)c * K + cell] = acc[64 * g];
+                else if (ps + j < slots_cap) partial[(int64_t)(ps + j) * NV + c] = (float)acc[64 * g];
             }
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int c = 0; c <= P; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+}
+
+// Moments of the cells split into several dense items: the partial sums of
+// items 0..J-1, added in that order in FP64.  One wave per split cell (found
+// at its item 0), lanes over the components.
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2m_combine(int K, int NV, const int4 *__restrict__ items,
+                                                     int64_t items_cap,
+                                                     const int *__restrict__ small,
+                                                     const float *__restrict__ partial,
+                                                     int64_t slots_cap, T *__restrict__ M) {
+    {
+        const int64_t sy = blockIdx.y;
+        items += sy * items_cap;
+        small += sy * 8;
+        partial += sy * slots_cap * NV;
+        M += sy * NV * K;
+    }
+    const int lane = threadIdx.x & 63;
+    const int nitems = small[0] < items_cap ? small[0] : (int)items_cap;
+    const int nwaves = gridDim.x * 4;
+    for (int it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += nwaves) {
+        const int4 e = items[it];
+        if (e.y != 0 || e.z < 2 || e.w < 0 || e.w + e.z > slots_cap) continue;
+        for (int c = lane; c < NV; c += 64) {
+            double acc = 0.0;
+            for (int k = 0; k < e.z; ++k) acc += (double)partial[(int64_t)(e.w + k) * NV + c];
+            M[(int64_t)c * K + e.x] = T(acc);
         }
-        if (lane == 0) {
-#pragma unroll
-            for (int c = 0; c <= P; ++c) red[wid][c] = acc[c];
-        }
-        __syncthreads();
-        for (int c = tid; c <= P; c += 256)
-            M[(int64_t)c * K + cell] = T(((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]);
-        __syncthreads();
     }
 }
 
@@ -243,18 +304,15 @@ template <int PO, typename T>
 static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
     const int K = a.ncell * a.ncell * a.ncell;
     const int G = a.group;
-    int nlight = (int)(((int64_t)K * G + 255) / 256);
-    if (a.zero_count && nlight * 256 < K) nlight = (K + 255) / 256;
-    const int grid = nlight + a.dense_blocks;
+    const int nlight = (int)(((int64_t)K * G + 255) / 256);
     const int nsys = a.nsys > 0 ? a.nsys : 1;
     const int *st = a.start;
     const particle4<T> *so = (const particle4<T> *)a.sorted;
     T *M = (T *)a.M;
 #define PMMM_P2M_G(GG)                                                                     \
     case GG:                                                                               \
-        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(grid, nsys), dim3(256), 0, s, K, st, so,\
-                           a.dense_threshold, a.dense_cells, a.dense_count, nlight, M,      \
-                           a.zero_count, a.prange);                                        \
+        hipLaunchKernelGGL((k_p2m<PO, T, GG>), dim3(nlight, nsys), dim3(256), 0, s, K, st, \
+                           so, a.dense_threshold, M, a.prange);                            \
         break;
     switch (G) {
         PMMM_P2M_G(4)
@@ -266,6 +324,16 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
             return hipErrorInvalidValue;
     }
 #undef PMMM_P2M_G
+    if (a.items != nullptr) {
+        // waves for the dense items: up to the capacity, at most 8192 (they loop)
+        const int64_t dwaves = a.items_cap < 8192 ? a.items_cap : 8192;
+        const int dblocks = (int)((dwaves + 3) / 4);
+        hipLaunchKernelGGL((k_p2m_dense<PO, T>), dim3(dblocks, nsys), dim3(256), 0, s, K, st, so,
+                           a.items, a.items_cap, a.small, a.partial, a.slots_cap, M, a.prange);
+        hipLaunchKernelGGL(k_p2m_combine<T>, dim3(dblocks < 256 ? dblocks : 256, nsys), dim3(256),
+                           0, s, K, nreal(PO) + 1, a.items, a.items_cap, a.small, a.partial,
+                           a.slots_cap, M);
+    }
     return hipGetLastError();
 }
 
