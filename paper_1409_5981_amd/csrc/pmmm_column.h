@@ -456,82 +456,6 @@ __global__ void __launch_bounds__(PO <= 6 ? 512 : 256, (PO == 7 && sizeof(T) == 
 // keeps their results in registers until every read of the moment spectra
 // is done; they then overwrite the spectra in place.
 //
-// LDS layout of the spectra: element e of row b at b * nf + cpos(b, e), the
-// low three bits of e flipped by bits 4..6 of e and bit 3 by the row's
-// parity.  For 128-point rows every access of the kernel -- 16 consecutive
-// elements of a row, or the FFT's (row, e) patterns of 16 lanes -- then
-// falls on 16 distinct 8-byte bank pairs, with no padding, so three blocks
-// share a CU (64- and 32-point rows keep some two- and four-way conflicts
-// in the first FFT pass).
-__device__ __forceinline__ constexpr int cpos(int row, int e) {
-    return e ^ (((e >> 4) & 7) | ((row & 1) << 3));
-}
-
-// In-place FFTs of nlines rows of N = 16 N2 points (N = 32, 64, 128) in the
-// layout above: 16-point register FFTs over n1 of x[n1 N2 + t2], twiddles
-// W_N^(t2 k1), then N2-point FFTs over t2.  The lanes of one row's items sit
-// in one wave, so each in-place pass needs no barrier between its reads and
-// writes (a wave's LDS operations complete in order; the asm statement keeps
-// the compiler from moving the writes up).  HALF: only the first N/2 inputs
-// are non-zero (forward) or only the first N/2 outputs are kept (inverse).
-template <typename T, bool INV, int N, bool HALF>
-__device__ __forceinline__ void fft_col(cplx<T> *buf, int nlines, const cplx<T> *tw, int tid,
-                                        int nthr) {
-    constexpr int N2 = N / 16, L2 = ilog2c(N2);
-    const int items = nlines * N2;
-    for (int it = tid; it < items; it += nthr) {
-        const int line = it >> L2, t2 = it & (N2 - 1);
-        cplx<T> *b = buf + line * N;
-        cplx<T> v[16];
-        static_for<0, 16>([&](auto in) {
-            constexpr int n1 = decltype(in)::value;
-            if constexpr (!INV && HALF && n1 >= 8) v[n1] = {T(0), T(0)};
-            else v[n1] = b[cpos(line, n1 * N2 + t2)];
-        });
-        fft_reg<16, INV, T>(v);
-        static_for<1, 16>([&](auto ik) {
-            constexpr int k1 = decltype(ik)::value;
-            const int e = t2 * k1;  // < N
-            cplx<T> w = e < N / 2 ? tw[e] : tw[e - N / 2];
-            if (e >= N / 2) {
-                w.re = -w.re;
-                w.im = -w.im;
-            }
-            if (INV) w.im = -w.im;
-            v[k1] = cmul(v[k1], w);
-        });
-        asm volatile("" ::: "memory");
-        static_for<0, 16>([&](auto ik) {
-            constexpr int k1 = decltype(ik)::value;
-            b[cpos(line, t2 * 16 + k1)] = v[k1];
-        });
-    }
-    __syncthreads();
-    for (int it = tid; it < nlines * 16; it += nthr) {
-        const int line = it >> 4, k1 = it & 15;
-        cplx<T> *b = buf + line * N;
-        cplx<T> u[N2];
-        static_for<0, N2>([&](auto it2) {
-            constexpr int t2 = decltype(it2)::value;
-            u[t2] = b[cpos(line, t2 * 16 + k1)];
-        });
-        fft_reg<N2, INV, T>(u);
-        asm volatile("" ::: "memory");
-        static_for<0, N2>([&](auto ik2) {
-            constexpr int k2 = decltype(ik2)::value;
-            if constexpr (!(INV && HALF && k2 >= N2 / 2)) b[cpos(line, k2 * 16 + k1)] = u[k2];
-        });
-    }
-    __syncthreads();
-}
-
-template <typename T, bool INV, int N>
-__device__ __forceinline__ void fft_col_rt(cplx<T> *buf, bool half, int nlines,
-                                           const cplx<T> *tw, int tid, int nthr) {
-    if (half) fft_col<T, INV, N, true>(buf, nlines, tw, tid, nthr);
-    else fft_col<T, INV, N, false>(buf, nlines, tw, tid, nthr);
-}
-
 // Next order >= from whose kernel values subset S needs (2 PO + 1: none).
 __host__ __device__ constexpr int next_order(int PO, int RS, int S, int from) {
     for (int NN = from; NN <= 2 * PO; ++NN)

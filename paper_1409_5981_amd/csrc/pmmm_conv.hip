@@ -235,6 +235,267 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
     }
 }
 
+// ------------------------------------------------- planes of 64 and 128
+// Same transforms for FFT sizes N = 64 and 128, one (plane z, component c)
+// per block of 256 threads, with register FFTs in four steps (fft_col) and
+// the open boundary's zero half pruned.  The row pairs live in swizzled LDS
+// rows xb[npair][N]; the y pass runs over chunks of up to 33 kx columns
+// through yb[N][CWS] (y-major, kx fastest, so the lanes of a wave take
+// consecutive kx: conflict-free in LDS and coalesced in memory): its first
+// step reads the row pairs straight from xb (unpacking the R2C of two real
+// rows), its second writes the spectrum to memory (forward) or into the
+// C2R row pairs (inverse).  Open: nin = N / 2 rows and columns in, and the
+// y and x transforms skip the zero half; periodic: nin = N.
+constexpr int kPlaneThreads = 256;
+constexpr int kPlaneChunk = 33;
+
+template <typename T>
+__device__ __forceinline__ cplx<T> tw_n(const cplx<T> *tw, int e, int N, bool inv) {
+    cplx<T> w = e < N / 2 ? tw[e] : tw[e - N / 2];
+    if (e >= N / 2) {
+        w.re = -w.re;
+        w.im = -w.im;
+    }
+    if (inv) w.im = -w.im;
+    return w;
+}
+
+template <typename T, int N, bool HALF>
+__global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd_n(const T *__restrict__ M,
+                                                               cplx<T> *__restrict__ spec,
+                                                               const cplx<T> *__restrict__ tw_g,
+                                                               int P,
+                                                               double *__restrict__ qr2_partial) {
+    constexpr int nin = HALF ? N / 2 : N, npair = nin / 2, nh = N / 2 + 1, N2 = N / 16;
+    constexpr int CWS = kPlaneChunk;  // odd row stride of yb
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cplx<T> *tw = (cplx<T> *)lds_raw;
+    cplx<T> *xb = tw + N / 2;
+    cplx<T> *yb = xb + npair * N;
+    const int z = blockIdx.x, tid = threadIdx.x;
+    {
+        const int64_t sy = blockIdx.z, K = (int64_t)nin * nin * nin;
+        M += sy * (P + 1) * K;
+        spec += sy * P * nin * N * nh;
+        if (qr2_partial != nullptr) qr2_partial += sy * nin;
+    }
+    if ((int)blockIdx.y == P) {
+        // blocks of the extra row: sum over plane z of the per-cell q|u|^2
+        // (component P of M), fixed-order reduction
+        __shared__ double red[kPlaneThreads / 64];
+        const T *pl = M + ((int64_t)P * nin + z) * nin * nin;
+        double acc = 0.0;
+        for (int idx = tid; idx < nin * nin; idx += kPlaneThreads) acc += (double)pl[idx];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kPlaneThreads / 64; ++w) t += red[w];
+            qr2_partial[z] = t;
+        }
+        return;
+    }
+    const int c = blockIdx.y;
+    const cplx<T> twv = tw_g[tid < N / 2 ? tid : 0];
+    const T *plane = M + ((int64_t)c * nin + z) * nin * nin;
+    // rows (2j, 2j+1) as one complex row; the loads of a batch are issued
+    // before their LDS stores
+    constexpr int NL = npair * nin;
+    constexpr int LB = (NL + kPlaneThreads - 1) / kPlaneThreads < 8
+                           ? (NL + kPlaneThreads - 1) / kPlaneThreads : 8;
+    for (int base = tid; base < NL; base += kPlaneThreads * LB) {
+        cplx<T> v[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int idx = base + u * kPlaneThreads < NL ? base + u * kPlaneThreads : NL - 1;
+            const int j = idx / nin, x = idx - j * nin;
+            v[u] = {plane[(2 * j) * nin + x], plane[(2 * j + 1) * nin + x]};
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int idx = base + u * kPlaneThreads;
+            if (idx < NL) {
+                const int j = idx / nin, x = idx - j * nin;
+                xb[j * N + cpos(j, x)] = v[u];
+            }
+        }
+    }
+    if (tid < N / 2) tw[tid] = twv;
+    __syncthreads();
+    fft_col<T, false, N, HALF>(xb, npair, tw, tid, kPlaneThreads);   // ends with a barrier
+    cplx<T> *out = spec + ((int64_t)c * nin + z) * N * nh;
+    for (int k0 = 0; k0 < nh; k0 += kPlaneChunk) {
+        const int cn = nh - k0 < kPlaneChunk ? nh - k0 : kPlaneChunk;
+        // y transforms, first step: 16-point FFTs over n1 of x[n1 N2 + t2]
+        for (int it = tid; it < cn * N2; it += kPlaneThreads) {
+            const int t2 = it / cn, kl = it - t2 * cn, k = k0 + kl;
+            cplx<T> v[16];
+            static_for<0, 16>([&](auto in) {
+                constexpr int n1 = decltype(in)::value;
+                if constexpr (HALF && n1 >= 8) {
+                    v[n1] = {T(0), T(0)};
+                } else {
+                    const int y = n1 * N2 + t2, j = y >> 1;
+                    const cplx<T> zk = xb[j * N + cpos(j, k & (N - 1))];
+                    const cplx<T> zm = xb[j * N + cpos(j, (N - k) & (N - 1))];
+                    if ((y & 1) == 0) v[n1] = {T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+                    else v[n1] = {T(0.5) * (zk.im + zm.im), T(-0.5) * (zk.re - zm.re)};
+                }
+            });
+            fft_reg<16, false, T>(v);
+            static_for<0, 16>([&](auto ik) {
+                constexpr int k1 = decltype(ik)::value;
+                const cplx<T> w = k1 == 0 ? cplx<T>{T(1), T(0)} : tw_n(tw, t2 * k1, N, false);
+                yb[(t2 * 16 + k1) * CWS + kl] = k1 == 0 ? v[k1] : cmul(v[k1], w);
+            });
+        }
+        __syncthreads();
+        // second step: N2-point FFTs over t2, spectrum rows y = k2 * 16 + k1
+        for (int it = tid; it < cn * 16; it += kPlaneThreads) {
+            const int k1 = it / cn, kl = it - k1 * cn;
+            cplx<T> u[N2];
+            static_for<0, N2>([&](auto it2) {
+                constexpr int t2 = decltype(it2)::value;
+                u[t2] = yb[(t2 * 16 + k1) * CWS + kl];
+            });
+            fft_reg<N2, false, T>(u);
+            static_for<0, N2>([&](auto ik2) {
+                constexpr int k2 = decltype(ik2)::value;
+                out[(k2 * 16 + k1) * nh + k0 + kl] = u[k2];
+            });
+        }
+        __syncthreads();   // yb is refilled by the next chunk
+    }
+}
+
+template <typename T, int N, bool HALF>
+__global__ void __launch_bounds__(kPlaneThreads) k_plane_inv_n(const cplx<T> *__restrict__ spec,
+                                                               T *__restrict__ L,
+                                                               const cplx<T> *__restrict__ tw_g,
+                                                               T scale, int P) {
+    constexpr int nout = HALF ? N / 2 : N, npair = nout / 2, nh = N / 2 + 1, N2 = N / 16;
+    constexpr int CWS = kPlaneChunk;
+    constexpr int K2 = HALF ? N2 / 2 : N2;   // y rows kept: k2 * 16 + k1 < nout
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cplx<T> *tw = (cplx<T> *)lds_raw;
+    cplx<T> *xb = tw + N / 2;
+    cplx<T> *yb = xb + npair * N;
+    const int z = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    {
+        const int64_t sy = blockIdx.z;
+        spec += sy * P * nout * N * nh;
+        L += sy * P * nout * nout * nout;
+    }
+    if (tid < N / 2) tw[tid] = tw_g[tid];
+    __syncthreads();
+    const cplx<T> *in = spec + ((int64_t)c * nout + z) * N * nh;
+    for (int k0 = 0; k0 < nh; k0 += kPlaneChunk) {
+        const int cn = nh - k0 < kPlaneChunk ? nh - k0 : kPlaneChunk;
+        // y inverse transforms, first step, straight from memory (lanes take
+        // consecutive kx)
+        for (int it = tid; it < cn * N2; it += kPlaneThreads) {
+            const int t2 = it / cn, kl = it - t2 * cn;
+            cplx<T> v[16];
+            static_for<0, 16>([&](auto in1) {
+                constexpr int n1 = decltype(in1)::value;
+                v[n1] = in[(n1 * N2 + t2) * nh + k0 + kl];
+            });
+            fft_reg<16, true, T>(v);
+            static_for<0, 16>([&](auto ik) {
+                constexpr int k1 = decltype(ik)::value;
+                const cplx<T> w = k1 == 0 ? cplx<T>{T(1), T(0)} : tw_n(tw, t2 * k1, N, true);
+                yb[(t2 * 16 + k1) * CWS + kl] = k1 == 0 ? v[k1] : cmul(v[k1], w);
+            });
+        }
+        __syncthreads();
+        // second step, rows y = k2 * 16 + k1 < nout, into the C2R row pairs:
+        // even rows y = 2j give A, odd rows B, and Z_j[k] = A[k] + i B[k],
+        // Z_j[N - k] = conj(A[k]) + i conj(B[k]) (0 < k < N/2); the even rows
+        // are written first, the odd ones added after a barrier
+        for (int parity = 0; parity < 2; ++parity) {
+            for (int it = tid; it < cn * 8; it += kPlaneThreads) {
+                const int kh = it / cn, kl = it - kh * cn, k1 = 2 * kh + parity, k = k0 + kl;
+                cplx<T> u[N2];
+                static_for<0, N2>([&](auto it2) {
+                    constexpr int t2 = decltype(it2)::value;
+                    u[t2] = yb[(t2 * 16 + k1) * CWS + kl];
+                });
+                fft_reg<N2, true, T>(u);
+                static_for<0, K2>([&](auto ik2) {
+                    constexpr int k2 = decltype(ik2)::value;
+                    const int j = (k2 * 16 + k1) >> 1;
+                    cplx<T> *row = xb + j * N;
+                    const cplx<T> a = u[k2];
+                    if (parity == 0) {
+                        row[cpos(j, k)] = a;
+                        if (k >= 1 && k < N / 2) row[cpos(j, N - k)] = {a.re, -a.im};
+                    } else {
+                        cplx<T> &zk = row[cpos(j, k)];
+                        zk = {zk.re - a.im, zk.im + a.re};
+                        if (k >= 1 && k < N / 2) {
+                            cplx<T> &zm = row[cpos(j, N - k)];
+                            zm = {zm.re + a.im, zm.im + a.re};
+                        }
+                    }
+                });
+            }
+            __syncthreads();
+        }
+    }
+    // x inverse transforms of the row pairs, the first nout outputs kept
+    fft_col<T, true, N, HALF>(xb, npair, tw, tid, kPlaneThreads);
+    T *plane = L + ((int64_t)c * nout + z) * nout * nout;
+    for (int idx = tid; idx < nout * nout; idx += kPlaneThreads) {
+        const int y = idx / nout, x = idx - y * nout, j = y >> 1;
+        const cplx<T> v = xb[j * N + cpos(j, x)];
+        plane[idx] = ((y & 1) ? v.im : v.re) * scale;
+    }
+}
+
+template <typename T, int N>
+static size_t plane_n_lds(bool half) {
+    const int npair = (half ? N / 2 : N) / 2;
+    return (size_t)(N / 2 + npair * N + N * kPlaneChunk) * sizeof(cplx<T>);
+}
+
+template <typename T, int N>
+static hipError_t plane_n_launch(const FFTArgs &a, int stage, hipStream_t s) {
+    const int P = nreal(a.p), n = a.n, nsys = a.nsys > 0 ? a.nsys : 1;
+    const bool half = a.open != 0;
+    const size_t lds = plane_n_lds<T, N>(half);
+    hipError_t e = hipSuccess;
+    if (stage == 0) {
+        const void *k = half ? (const void *)k_plane_fwd_n<T, N, true>
+                             : (const void *)k_plane_fwd_n<T, N, false>;
+        if (lds > 65536 && (e = set_max_lds(k, lds)) != hipSuccess) return e;
+        const int rows = half ? P : P + 1;   // periodic: one extra row of q|u|^2 sums
+        if (half)
+            hipLaunchKernelGGL((k_plane_fwd_n<T, N, true>), dim3(n, rows, nsys),
+                               dim3(kPlaneThreads), lds, s, (const T *)a.M, (cplx<T> *)a.spec,
+                               (const cplx<T> *)a.tw, P, nullptr);
+        else
+            hipLaunchKernelGGL((k_plane_fwd_n<T, N, false>), dim3(n, rows, nsys),
+                               dim3(kPlaneThreads), lds, s, (const T *)a.M, (cplx<T> *)a.spec,
+                               (const cplx<T> *)a.tw, P, a.qr2_partial);
+    } else {
+        const void *k = half ? (const void *)k_plane_inv_n<T, N, true>
+                             : (const void *)k_plane_inv_n<T, N, false>;
+        if (lds > 65536 && (e = set_max_lds(k, lds)) != hipSuccess) return e;
+        const T scale = T(1.0 / ((double)N * N * N));
+        if (half)
+            hipLaunchKernelGGL((k_plane_inv_n<T, N, true>), dim3(n, P, nsys), dim3(kPlaneThreads),
+                               lds, s, (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw,
+                               scale, P);
+        else
+            hipLaunchKernelGGL((k_plane_inv_n<T, N, false>), dim3(n, P, nsys), dim3(kPlaneThreads),
+                               lds, s, (const cplx<T> *)a.spec, (T *)a.L, (const cplx<T> *)a.tw,
+                               scale, P);
+    }
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------------- launcher
 static int ilog2(int v) {
     int l = 0;
@@ -285,6 +546,10 @@ hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
     const PlaneShape ps = plane_shape(n, nf, P, nsys, csz);
     const size_t lds_plane = ps.lds;
     hipError_t e = hipSuccess;
+    if (stage != 1 && (nf == 64 || nf == 128)) {
+        if (sizeof(T) == 8 && nf == 128) return hipErrorInvalidValue;
+        return nf == 64 ? plane_n_launch<T, 64>(a, stage, s) : plane_n_launch<T, 128>(a, stage, s);
+    }
     if (stage == 0) {
         e = ensure_lds(k_plane_fwd<T>, lds_plane);
         if (e != hipSuccess) return e;
