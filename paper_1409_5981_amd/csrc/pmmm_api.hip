@@ -872,7 +872,17 @@ struct pmmm_batch_s {
     int key_hits = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // classes run concurrently on side streams (default priority), forked
+    // from and joined back into the caller's stream with events
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+    std::vector<int> lane_of;       // side stream of each class (longest first, least loaded)
 };
+
+// Side streams of a batch: classes are independent (disjoint particle
+// ranges, their own meshes), so up to this many run at once.
+constexpr int kBatchStreams = 4;
 
 static bool same_class(const pmmm_params &a, const pmmm_params &b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.box[0] == b.box[0] &&
@@ -917,6 +927,9 @@ static void batch_destroy(pmmm_batch_s *b) {
     hipFree(b->recs);
     hipFree(b->flag);
     if (b->h_prange) hipHostFree(b->h_prange);
+    for (hipStream_t st : b->side) hipStreamDestroy(st);
+    for (hipEvent_t ev : b->join) hipEventDestroy(ev);
+    if (b->fork) hipEventDestroy(b->fork);
     delete b;
 }
 
@@ -963,10 +976,10 @@ static int batch_capacity(pmmm_batch_s *b, int64_t n) {
 }
 
 // Every launch of one batched far-field call, class by class.
-static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const float *z,
-                         const float *q, float *phi, float *gx, float *gy, float *gz,
-                         hipStream_t s) {
-    for (auto &c : b->cls) {
+static int class_enqueue(pmmm_batch_s *b, BatchClass &c, const float *x, const float *y,
+                         const float *z, const float *q, float *phi, float *gx, float *gy,
+                         float *gz, hipStream_t s) {
+    {
         const Plan *pl = c.plan;
         const int ns = (int)c.members.size();
         const int group = group_for((double)c.tot_np / ((double)pl->K * ns));
@@ -1052,6 +1065,57 @@ static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const 
     return PMMM_OK;
 }
 
+// Assign the classes to the side streams, longest first to the least loaded
+// (work ~ particles x expansion terms + mesh x terms).
+static void batch_plan_lanes(pmmm_batch_s *b) {
+    const int nl = (int)b->side.size();
+    b->lane_of.assign(b->cls.size(), 0);
+    if (nl < 2) return;
+    std::vector<int> order(b->cls.size());
+    std::vector<double> cost(b->cls.size()), load(nl, 0.0);
+    for (size_t i = 0; i < b->cls.size(); ++i) {
+        const BatchClass &c = b->cls[i];
+        order[i] = (int)i;
+        cost[i] = ((double)c.tot_np + 4.0 * (double)c.plan->K * c.members.size()) * c.plan->P;
+    }
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    for (int i : order) {
+        int best = 0;
+        for (int k = 1; k < nl; ++k)
+            if (load[k] < load[best]) best = k;
+        load[best] += cost[i];
+        b->lane_of[i] = best;
+    }
+}
+
+// Every launch of one batched far-field call: the classes on the side
+// streams, forked from and joined back into s (also under graph capture,
+// where the fork and join events make them parallel branches).
+static int batch_enqueue(pmmm_batch_s *b, const float *x, const float *y, const float *z,
+                         const float *q, float *phi, float *gx, float *gy, float *gz,
+                         hipStream_t s) {
+    if (b->side.size() < 2 || b->cls.size() < 2) {
+        for (auto &c : b->cls) {
+            const int rc = class_enqueue(b, c, x, y, z, q, phi, gx, gy, gz, s);
+            if (rc != PMMM_OK) return rc;
+        }
+        return PMMM_OK;
+    }
+    if (b->lane_of.size() != b->cls.size()) batch_plan_lanes(b);
+    PMMM_HIP(hipEventRecord(b->fork, s));
+    for (hipStream_t st : b->side) PMMM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+    for (size_t i = 0; i < b->cls.size(); ++i) {
+        const int rc = class_enqueue(b, b->cls[i], x, y, z, q, phi, gx, gy, gz,
+                                     b->side[b->lane_of[i]]);
+        if (rc != PMMM_OK) return rc;
+    }
+    for (size_t k = 0; k < b->side.size(); ++k) {
+        PMMM_HIP(hipEventRecord(b->join[k], b->side[k]));
+        PMMM_HIP(hipStreamWaitEvent(s, b->join[k], 0));
+    }
+    return PMMM_OK;
+}
+
 static int batch_far(pmmm_batch_s *b, const int64_t *offsets, const float *x, const float *y,
                      const float *z, const float *q, float *phi, float *gx, float *gy,
                      float *gz, void *stream) {
@@ -1128,6 +1192,7 @@ static int batch_far(pmmm_batch_s *b, const int64_t *offsets, const float *x, co
             }
         }
         b->offsets.assign(offsets, offsets + b->nsys + 1);
+        b->lane_of.clear();   // the classes' loads changed: reassign their streams
     }
     const std::vector<const void *> key = {x, y, z, q, phi, gx, gy, gz, (const void *)s};
     const bool graphs = b->use_graph && s != nullptr;
@@ -1309,6 +1374,19 @@ int pmmm_batch_create(int nsys, const pmmm_params *per_sys, void *stream, pmmm_b
         if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_prange, sizeof(int64_t) * 2 * nsys);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = hip_fail(e, "batch workspace");
+    }
+    if (rc == PMMM_OK && b->cls.size() > 1) {
+        const int nl = (int)b->cls.size() < kBatchStreams ? (int)b->cls.size() : kBatchStreams;
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (int k = 0; k < nl && e == hipSuccess; ++k) {
+            hipStream_t st = nullptr;
+            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e == hipSuccess) b->side.push_back(st);
+            hipEvent_t ev = nullptr;
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) b->join.push_back(ev);
+        }
+        if (e != hipSuccess) rc = hip_fail(e, "batch streams");
     }
     if (rc != PMMM_OK) {
         batch_destroy(b);
