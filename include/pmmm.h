@@ -244,7 +244,8 @@ int pmmm_plan_autotune(pmmm_plan plan, int64_t n, const void *x, const void *y, 
  * streamed from memory at each thread's frequency with one column per block
  * and each thread running 1, 2 or 4 of the four row subsets of the M2L
  * (less LDS per block, so several blocks share a compute unit; FFT meshes of
- * 64 and 128 points). */
+ * 64 and 128 points; four subsets per thread up to order 6, two up to order
+ * 8: beyond, their results would not fit the registers). */
 enum {
     PMMM_COLUMN_DEFAULT = 0,
     PMMM_COLUMN_TILE = 1,

@@ -429,6 +429,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.flag = pl->small + 1;
         b.items = mode != kNear ? pb.items : nullptr;
         b.items_cap = pb.items_cap;
+        b.slots_cap = pb.slots_cap;
         b.small = pl->small;
         b.pos = staged ? pb.pos : nullptr;
         b.tile_sums = pb.tile_sums;
@@ -1002,6 +1003,7 @@ static int class_enqueue(pmmm_batch_s *b, BatchClass &c, const float *x, const f
         bn.flag = b->flag;
         bn.items = c.items;
         bn.items_cap = c.items_cap;
+        bn.slots_cap = c.slots_cap;
         bn.small = c.small;
         bn.tile_sums = c.tile_sums;
         bn.dense_threshold = dense_thr;

@@ -78,6 +78,7 @@ __global__ void k_rb_reset_items(int nsys, int *__restrict__ small) {
     for (int sy = threadIdx.x; sy < nsys; sy += blockDim.x) {
         small[(int64_t)sy * 8] = 0;
         small[(int64_t)sy * 8 + 3] = 0;
+        small[(int64_t)sy * 8 + 4] = 0;
     }
 }
 
@@ -95,9 +96,11 @@ __global__ void __launch_bounds__(1024) k_rb_hist(
     const int nb = 1 << bits, t = blockIdx.x;
     for (int d = threadIdx.x; d < nb; d += blockDim.x) s_hist[d] = 0;
     if (first && t == 0 && threadIdx.x == 0) {
-        // item and partial-slot counts of this binning (filled by k_rb_bounds)
+        // item, partial-slot and split-cell counts of this binning (filled by
+        // k_rb_bounds)
         small[(int64_t)blockIdx.y * 8] = 0;
         small[(int64_t)blockIdx.y * 8 + 3] = 0;
+        small[(int64_t)blockIdx.y * 8 + 4] = 0;
     }
     __syncthreads();
     int kv[R];
@@ -405,14 +408,16 @@ __global__ void __launch_bounds__(1024) k_rb_scatter(
 // digit equals c's (their range comes from the last pass's scanned
 // histogram).  A cell of more than dense_thr particles becomes J =
 // ceil(count / kDenseItem) P2M items {cell, j, J, first partial slot (J > 1)
-// or -1}; items and slots are reserved with atomics, so their positions vary
-// from call to call, but every item covers a fixed particle range and the
-// partials of a cell are added in item order, so the moments do not.
+// or -1}, and a cell of J > 1 items is also listed as split {cell, J, first
+// slot}; items, slots and list entries are reserved with atomics, so their
+// positions vary from call to call, but every item covers a fixed particle
+// range and the partials of a cell are added in a fixed order, so the
+// moments do not.
 __global__ void __launch_bounds__(256) k_rb_bounds(
     const int64_t *__restrict__ prange, int64_t n, int K, const int *__restrict__ skeys,
     int *__restrict__ start, int dense_thr, int4 *__restrict__ items, int64_t items_cap,
-    int *__restrict__ small, const int *__restrict__ offs, int64_t hist_ints, int tiles,
-    int shift, int bits) {
+    int64_t splits_cap, int *__restrict__ small, const int *__restrict__ offs, int64_t hist_ints,
+    int tiles, int shift, int bits) {
     int64_t p0, np;
     sys_range(prange, n, p0, np);
     start += (int64_t)blockIdx.y * (K + 1);
@@ -444,7 +449,11 @@ __global__ void __launch_bounds__(256) k_rb_bounds(
         const int base = atomicAdd(small, J);
         const int ps = J > 1 ? atomicAdd(small + 3, J) : -1;
         for (int j = 0; j < J; ++j)
-            if (base + j < items_cap) items[base + j] = int4{c, j, J, ps};
+            if (base + j < items_cap - splits_cap) items[base + j] = int4{c, j, J, ps};
+        if (J > 1) {
+            const int si = atomicAdd(small + 4, 1);
+            if (si < splits_cap) items[items_cap - splits_cap + si] = int4{c, J, ps, 0};
+        }
     }
 }
 
@@ -508,7 +517,8 @@ static hipError_t radix_bin(const BinArgs &a, int K, int64_t maxn, hipStream_t s
     }
     hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s, a.prange,
                        a.n, K, a.scell, a.start, a.dense_threshold, a.items, a.items_cap,
-                       a.small, a.count, hist_ints, tiles, shift, widths[passes - 1]);
+                       dense_splits_cap_of(a.slots_cap), a.small, a.count, hist_ints, tiles, shift,
+                       widths[passes - 1]);
     return hipGetLastError();
 }
 
@@ -522,7 +532,8 @@ hipError_t launch_bin(const BinArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_rb_reset_items, dim3(1), dim3(64), 0, s, nsys, a.small);
         hipLaunchKernelGGL(k_rb_bounds, dim3((K + 1 + 255) / 256, nsys), dim3(256), 0, s,
                            a.prange, a.n, K, a.scell, a.start, a.dense_threshold, a.items,
-                           a.items_cap, a.small, a.count, (int64_t)0, 1, 0, 1);
+                           a.items_cap, dense_splits_cap_of(a.slots_cap), a.small, a.count,
+                           (int64_t)0, 1, 0, 1);
         return hipGetLastError();
     }
     switch (bin_tile_items(maxn)) {

@@ -730,8 +730,12 @@ hipError_t column_launch(const FFTArgs &a, hipStream_t s) {
     const int kind = a.col_kernel > 0 ? a.col_kernel : column_default_kernel(PO, a.nf, sizeof(T));
     switch (kind) {
         case PMMM_COLUMN_STREAM_1: return column_launch_g<PO, T, 1>(a, s);
-        case PMMM_COLUMN_STREAM_2: return column_launch_g<PO, T, 2>(a, s);
-        case PMMM_COLUMN_STREAM_4: return column_launch_g<PO, T, 4>(a, s);
+        case PMMM_COLUMN_STREAM_2:
+            if constexpr (PO < 9) return column_launch_g<PO, T, 2>(a, s);
+            return hipErrorInvalidValue;
+        case PMMM_COLUMN_STREAM_4:
+            if constexpr (PO < 7) return column_launch_g<PO, T, 4>(a, s);
+            return hipErrorInvalidValue;
         case PMMM_COLUMN_TILE: break;
         default: return hipErrorInvalidValue;
     }

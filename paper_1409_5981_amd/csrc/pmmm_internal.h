@@ -497,9 +497,8 @@ inline size_t column_g_lds(int p, int nf, size_t tsize) {
 // LDS for w columns per block, or streamed from memory with each thread
 // running 1, 2 or 4 row subsets (FFT meshes of 64 and 128 points).
 inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize);
-// Default form: the streamed kernel with two subsets per thread for FFT
-// meshes of 64 points and more (or wherever the staged tile does not fit),
-// else the staged tile.
+// Default form: the streamed kernel with two subsets per thread (one from
+// order 9 on) for FFT meshes of 64 points and more, else the staged tile.
 inline int column_default_kernel(int p, int nf, size_t tsize);
 
 // Widest shape that fits (w from 64 / nf down to 1).
@@ -522,6 +521,10 @@ inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize) {
         case PMMM_COLUMN_STREAM_1:
         case PMMM_COLUMN_STREAM_2:
         case PMMM_COLUMN_STREAM_4:
+            // more row subsets per thread hold more results in registers:
+            // four from order 7 and two from order 9 on would spill
+            if ((kind == PMMM_COLUMN_STREAM_4 && p >= 7) || (kind == PMMM_COLUMN_STREAM_2 && p >= 9))
+                return false;
             return (nf == 64 || nf == 128) && column_g_lds(p, nf, tsize) > 0;
         default: return false;
     }
@@ -530,6 +533,8 @@ inline bool column_kernel_fits(int kind, int p, int nf, size_t tsize) {
 inline int column_default_kernel(int p, int nf, size_t tsize) {
     if (nf >= 64 && column_kernel_fits(PMMM_COLUMN_STREAM_2, p, nf, tsize))
         return PMMM_COLUMN_STREAM_2;
+    if (nf >= 64 && column_kernel_fits(PMMM_COLUMN_STREAM_1, p, nf, tsize))
+        return PMMM_COLUMN_STREAM_1;
     if (column_kernel_fits(PMMM_COLUMN_TILE, p, nf, tsize)) return PMMM_COLUMN_TILE;
     if (column_kernel_fits(PMMM_COLUMN_STREAM_2, p, nf, tsize)) return PMMM_COLUMN_STREAM_2;
     return 0;
@@ -564,10 +569,11 @@ struct BinArgs {
     int *start;        // [nsys][K + 1] first sorted slot of every cell (system-relative)
     int *flag;         // set when an open-boundary particle lies outside the box
     // [nsys][items_cap] dense-cell items {cell, chunk, chunks, first partial
-    // slot or -1} (or null: none built); small[8 s + 0] counts the items,
-    // small[8 s + 3] the partial slots of system s
+    // slot or -1} followed by the split cells (or null: none built);
+    // small[8 s + 0] counts the items, small[8 s + 3] the partial slots and
+    // small[8 s + 4] the split cells of system s
     int4 *items;
-    int64_t items_cap;
+    int64_t items_cap, slots_cap;
     int *small;
     int *count;        // [nsys][bin_hist_ints(max_np)] radix histograms / offsets
     int *tile_sums;    // [nsys][bin_scan_tiles(max_np)] scan scratch
@@ -609,14 +615,20 @@ constexpr int64_t bin_scan_tiles(int64_t max_np) { return (bin_hist_ints(max_np)
 // items (J > 1) leaves J partial sums that a second pass adds in item order.
 constexpr int kDenseItem = 512;
 constexpr int kDenseMinThreshold = 64;
-// Items of a system of up to max_np particles on K cells: each dense cell
-// gives at most count / kDenseItem + 1, and there are at most
-// max_np / (threshold + 1) dense cells.
-constexpr int64_t dense_items_cap(int64_t max_np, int64_t K) {
-    return max_np / kDenseItem + bin_min64(K, max_np / (kDenseMinThreshold + 1)) + 1;
-}
 // Partial slots: a split cell has count > kDenseItem and J < 2 count / kDenseItem.
 constexpr int64_t dense_slots_cap(int64_t max_np) { return 2 * max_np / kDenseItem + 1; }
+// Split cells (two items or more): at most half the partial slots.
+constexpr int64_t dense_splits_cap(int64_t max_np) { return dense_slots_cap(max_np) / 2 + 1; }
+// The same from a partial-slot capacity (slots_cap = dense_slots_cap(n)).
+constexpr int64_t dense_splits_cap_of(int64_t slots_cap) { return slots_cap / 2 + 1; }
+// Table of a system of up to max_np particles on K cells: the items (each
+// dense cell gives at most count / kDenseItem + 1, and there are at most
+// max_np / (threshold + 1) dense cells), then the list of split cells
+// {cell, J, first partial slot} at offset items_cap - dense_splits_cap.
+constexpr int64_t dense_items_cap(int64_t max_np, int64_t K) {
+    return max_np / kDenseItem + bin_min64(K, max_np / (kDenseMinThreshold + 1)) + 1 +
+           dense_splits_cap(max_np);
+}
 
 struct P2MArgs {
     int p, ncell, group;            // lanes per cell in the light path

@@ -155,15 +155,19 @@ __global__ void __launch_bounds__(256) k_p2m_dense(int K, const int *__restrict_
     }
 }
 
-// Moments of the cells split into several dense items: the partial sums of
-// items 0..J-1, added in that order in FP64.  One wave per split cell (found
-// at its item 0), lanes over the components.
+// Moments of the cells split into several dense items: one block per split
+// cell; wave w adds the partial sums of items w, w + 4, ... in FP64 (eight
+// running sums, item k in sum (k / 4) mod 8, so eight loads are in flight),
+// then the waves' totals are added in order -- a fixed order, so the
+// moments are reproducible.  Lanes run over the components.
 template <typename T>
 __global__ void __launch_bounds__(256) k_p2m_combine(int K, int NV, const int4 *__restrict__ items,
                                                      int64_t items_cap,
                                                      const int *__restrict__ small,
                                                      const float *__restrict__ partial,
                                                      int64_t slots_cap, T *__restrict__ M) {
+    __shared__ double red[4][nreal(PMMM_PMAX) + 1];
+    const int64_t splits_cap = dense_splits_cap_of(slots_cap);
     {
         const int64_t sy = blockIdx.y;
         items += sy * items_cap;
@@ -171,17 +175,33 @@ __global__ void __launch_bounds__(256) k_p2m_combine(int K, int NV, const int4 *
         partial += sy * slots_cap * NV;
         M += sy * NV * K;
     }
-    const int lane = threadIdx.x & 63;
-    const int nitems = small[0] < items_cap ? small[0] : (int)items_cap;
-    const int nwaves = gridDim.x * 4;
-    for (int it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += nwaves) {
-        const int4 e = items[it];
-        if (e.y != 0 || e.z < 2 || e.w < 0 || e.w + e.z > slots_cap) continue;
+    const int4 *splits = items + items_cap - splits_cap;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nsplit = small[4] < splits_cap ? small[4] : (int)splits_cap;
+    for (int si = blockIdx.x; si < nsplit; si += gridDim.x) {
+        const int4 e = splits[si];
+        const int cell = e.x, J = e.y, ps = e.z;
+        const bool ok = ps >= 0 && ps + J <= slots_cap;
         for (int c = lane; c < NV; c += 64) {
-            double acc = 0.0;
-            for (int k = 0; k < e.z; ++k) acc += (double)partial[(int64_t)(e.w + k) * NV + c];
-            M[(int64_t)c * K + e.x] = T(acc);
+            const float *pc = partial + (int64_t)ps * NV + c;
+            double acc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+            for (int k0 = wid; ok && k0 < J; k0 += 32) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = k0 + 4 * u < J ? pc[(int64_t)(k0 + 4 * u) * NV] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[u] += (double)v[u];
+            }
+            red[wid][c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                          ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         }
+        __syncthreads();
+        for (int c = threadIdx.x; c < NV; c += 256)
+            if (ok) M[(int64_t)c * K + cell] = T((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
+        __syncthreads();
     }
 }
 
@@ -330,7 +350,10 @@ static hipError_t p2m_dispatch_g(const P2MArgs &a, hipStream_t s) {
         const int dblocks = (int)((dwaves + 3) / 4);
         hipLaunchKernelGGL((k_p2m_dense<PO, T>), dim3(dblocks, nsys), dim3(256), 0, s, K, st, so,
                            a.items, a.items_cap, a.small, a.partial, a.slots_cap, M, a.prange);
-        hipLaunchKernelGGL(k_p2m_combine<T>, dim3(dblocks < 256 ? dblocks : 256, nsys), dim3(256),
+        // one block per split cell, up to 2048 (they loop)
+        const int64_t nsplit = dense_splits_cap_of(a.slots_cap);
+        const int cblocks = (int)(nsplit < 2048 ? nsplit : 2048);
+        hipLaunchKernelGGL(k_p2m_combine<T>, dim3(cblocks, nsys), dim3(256),
                            0, s, K, nreal(PO) + 1, a.items, a.items_cap, a.small, a.partial,
                            a.slots_cap, M);
     }

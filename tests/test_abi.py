@@ -61,12 +61,13 @@ def test_workspace_grows_with_particles(lib):
     # 512 ints per tile, sized for the most tiles any count up to 2^20 uses
     # (2^20 - 1 particles in 1024 tiles of 1024), with one scan sum per 4096
     # and the dense-cell P2M items (16 bytes each: one per 512 particles plus
-    # one per cell of more than 64, at most n / 65 of them) and partial sums
-    # (2 n / 512 slots of P + 1 = 65 floats)
+    # one per cell of more than 64, at most n / 65 of them, then one entry per
+    # split cell, at most half the partial slots) and partial sums (2 n / 512
+    # slots of P + 1 = 65 floats)
     hist = 512 * 1024 - 512
     sums = 512 * 1024 // 4096 - 1
-    items = (1 << 20) // 512 + (1 << 20) // 65
     slots = 2 * (1 << 20) // 512
+    items = (1 << 20) // 512 + (1 << 20) // 65 + slots // 2
     assert (workspace_bytes(prm, 1 << 20) - workspace_bytes(prm, 0)
             == (1 << 20) * 52 + 4 * (1 << 14) + 4 * (hist + sums) + 16 * items + 4 * 65 * slots)
 
