@@ -245,7 +245,10 @@ __device__ __forceinline__ void fft_reg(cplx<T> *v) {
                 static_for<0, R / span>([&](auto ig) {
                     constexpr int i0 = decltype(ig)::value * span + j, i1 = i0 + half;
                     cplx<T> b = a[i1];
-                    if constexpr (k32 != 0) b = cmul(b, w32<T, INV, k32>());
+                    // W = -+i is a swap and a sign: no multiplications (a
+                    // product by the constant 0 does not fold in IEEE code)
+                    if constexpr (k32 == 8) b = INV ? cplx<T>{-b.im, b.re} : cplx<T>{b.im, -b.re};
+                    else if constexpr (k32 != 0) b = cmul(b, w32<T, INV, k32>());
                     a[i1] = {a[i0].re - b.re, a[i0].im - b.im};
                     a[i0] = {a[i0].re + b.re, a[i0].im + b.im};
                 });
