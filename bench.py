@@ -114,10 +114,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(stage, workload, src_hash):
+def load_traffic(stage, workload, src_hash, form=None):
     """HBM traffic of the dominant kernel from committed rocprofv3 counter
     runs (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration),
-    only if the kernel sources are unchanged since the counters were taken."""
+    only if the kernel sources are unchanged since the counters were taken.
+    A record may hold one figure per kernel form (the column stage's forms);
+    `form` picks it, the record's default form when None or "default"."""
     path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -125,6 +127,10 @@ def load_traffic(stage, workload, src_hash):
         rec = json.load(f)
     if rec.get("source_hash") != src_hash:
         return None
+    forms = rec.get("forms")
+    if forms:
+        key = form if form not in (None, "default") else rec.get("default_form")
+        return forms.get(key, {}).get("bytes_per_launch")
     return rec.get("bytes_per_launch")
 
 
@@ -399,8 +405,9 @@ def main():
     peak_alu = FP32_PEAK if prec == "f32" else FP64_PEAK
     bytes_k, flops_k = algorithmic_work(dominant, N, n, p, nf, tsize)
     roof = _roofline(t_k, bytes_k, flops_k, peak_alu)
-    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash())
-    roof["kernel"] = dominant
+    form = tuning.get("column_kernel") if (tuning and dominant == "column") else None
+    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash(), form)
+    roof["kernel"] = dominant if form in (None, "default") else f"{dominant} ({form})"
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
     roof["algorithmic_flops"] = flops_k
@@ -495,8 +502,9 @@ def bench_multi(args, workload):
     nprod = 6 if args.split == "f32" else 3
     bytes_k, flops_k, mfma_k = multi_stage_work(dominant, N, S, n, p, nprod)
     roof = _roofline(t_k, bytes_k, flops_k, FP32_PEAK, mfma_k)
-    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash())
-    roof["kernel"] = dominant
+    form = tuning.get("column_kernel") if (tuning and dominant == "column") else None
+    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash(), form)
+    roof["kernel"] = dominant if form in (None, "default") else f"{dominant} ({form})"
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
     roof["algorithmic_flops"] = flops_k

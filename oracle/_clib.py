@@ -25,6 +25,8 @@ def lib():
                                          ctypes.c_int, ctypes.c_double, ctypes.c_int, _D]
         L.ora_lower_gamma_half.argtypes = [ctypes.c_int, ctypes.c_double, _D]
         L.ora_direct.argtypes = [ctypes.c_int64, _D, _D, _D, _D]
+        L.ora_direct_at.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int64), _D, _D]
         L.ora_ewald.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, _D]
         L.ora_near.argtypes = [ctypes.c_int64, _D, _D, _I, ctypes.c_int, ctypes.c_double,

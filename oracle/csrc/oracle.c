@@ -292,6 +292,34 @@ void ora_direct(int64_t n, const double *pos, const double *q, double *phi, doub
     }
 }
 
+/* The rows idx[0..m) of ora_direct: potential and gradient at the listed
+ * particles from all other particles. */
+void ora_direct_at(int64_t n, const double *pos, const double *q, int64_t m, const int64_t *idx,
+                   double *phi, double *grad) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t i = idx[t];
+        double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+        double p = 0, gx = 0, gy = 0, gz = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double ri = 1.0 / sqrt(r2);
+            double qr = q[j] * ri;
+            p += qr;
+            double qr3 = qr * ri * ri;
+            gx -= qr3 * dx;
+            gy -= qr3 * dy;
+            gz -= qr3 * dz;
+        }
+        phi[t] = p;
+        grad[3 * t] = gx;
+        grad[3 * t + 1] = gy;
+        grad[3 * t + 2] = gz;
+    }
+}
+
 /* Ewald reference for a cubic periodic box (tin-foil, no k = 0 term):
  *   Phi_i = sum'_{n,j} q_j erfc(a|r_ij + b n|)/|r_ij + b n|
  *         + 1/(pi V) sum_{k != 0} exp(-(pi k/a)^2)/k^2 Re sum_j q_j e^{2 pi i k . r_ij}

@@ -5,6 +5,7 @@ Phi = sum_j q_j / |r - r_j| everywhere; returned gradients are grad Phi.
 """
 from __future__ import annotations
 
+import ctypes
 from math import ceil, erfc, pi, sqrt
 
 import numpy as np
@@ -21,6 +22,21 @@ def direct(pos, q):
     phi = np.empty(n)
     grad = np.empty((n, 3))
     _clib.lib().ora_direct(n, _clib.dptr(pos), _clib.dptr(q), _clib.dptr(phi), _clib.dptr(grad))
+    return phi, grad
+
+
+def direct_at(pos, q, idx):
+    """Rows idx of direct(pos, q): the open-boundary potential and gradient
+    at the listed particles from all other particles."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    m = len(idx)
+    phi = np.empty(m)
+    grad = np.empty((m, 3))
+    _clib.lib().ora_direct_at(len(q), _clib.dptr(pos), _clib.dptr(q), m,
+                              idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              _clib.dptr(phi), _clib.dptr(grad))
     return phi, grad
 
 

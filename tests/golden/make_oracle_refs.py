@@ -5,7 +5,8 @@ For each workload the oracle computes the moments from ALL particles and
 evaluates the far field on a seeded sample of 4096 particles; the sample
 indices and the values are stored in tests/golden/ref_<workload>.npz.  The
 ewald_* files hold the Ewald sum (exact periodic potential and gradient)
-of every particle of a workload on the same kind of sample.
+of every particle of a workload on the same kind of sample, the direct_*
+files the open-boundary direct sum.
 
     python tests/golden/make_oracle_refs.py [workload ...]
 """
@@ -82,11 +83,34 @@ def make_ewald(name: str) -> str:
     return path
 
 
+# Exact open-boundary references (direct sum, the oracle's O1) at a seeded
+# sample of the Plummer workload's particles, for the method error of its
+# total field.
+DIRECT = {
+    "direct_open_plummer_n4194304": lambda: inputs.plummer_sphere(),
+}
+
+
+def make_direct(name: str) -> str:
+    from oracle import exact
+    t0 = time.time()
+    ps = DIRECT[name]()
+    rng = np.random.Generator(np.random.PCG64(1234))
+    idx = np.sort(rng.choice(ps.n, size=SAMPLE, replace=False))
+    phi, grad = exact.direct_at(ps.pos, ps.q.astype(np.float64), idx)
+    path = os.path.join(HERE, f"ref_{name}.npz")
+    np.savez_compressed(path, idx=idx, phi=phi, grad=grad, n=ps.n)
+    print(f"{name}: {time.time() - t0:.0f} s -> {path}", flush=True)
+    return path
+
+
 def make(name: str) -> str:
     if name in MULTI:
         return make_multi(name)
     if name in EWALD:
         return make_ewald(name)
+    if name in DIRECT:
+        return make_direct(name)
     t0 = time.time()
     ps = JOBS[name]()
     cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=2)
@@ -101,5 +125,5 @@ def make(name: str) -> str:
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or list(JOBS) + list(MULTI) + list(EWALD)):
+    for nm in (sys.argv[1:] or list(JOBS) + list(MULTI) + list(EWALD) + list(DIRECT)):
         make(nm)

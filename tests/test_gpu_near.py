@@ -134,3 +134,20 @@ def test_total_periodic_vs_ewald(name, gen, n_cells, p):
     print(f"{name} ({n_cells}^3, p={p}, c=2, FP32): method error vs Ewald: "
           f"grad {eg:.3e} phi {ep:.3e} (worst-case bound {_errest(2, p):.1e})")
     assert eg < _errest(2, p) and ep < _errest(2, p)
+
+
+def test_total_plummer_vs_direct_sum():
+    """Open Plummer workload (2^22 particles, 64^3 cells, p = 6, FP32): the
+    total field against the direct sum (FP64 oracle O1, written by
+    tests/golden/make_oracle_refs.py) at 4096 sampled particles; the
+    method error is printed and bounded by eq. errest."""
+    ref = np.load(os.path.join(GOLDEN, "ref_direct_open_plummer_n4194304.npz"))
+    ps = inputs.plummer_sphere()
+    assert ps.n == int(ref["n"])
+    res, _ = _gpu(ps, "f32", "total")
+    idx = ref["idx"]
+    eg = exact.rel_rms(res["grad"][idx], ref["grad"])
+    ep = exact.rel_rms(res["phi"][idx], ref["phi"])
+    print(f"open Plummer 2^22 64^3 p=6 c=2 FP32: method error vs direct sum: "
+          f"grad {eg:.3e} phi {ep:.3e} (worst-case bound {_errest(2, 6):.1e})")
+    assert eg < _errest(2, 6) and ep < _errest(2, 6)

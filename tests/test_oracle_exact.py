@@ -82,3 +82,15 @@ def test_near_field_counts_only_near_cells():
         far = np.max(np.abs(I - I[i]), axis=1) > 1
         r = np.linalg.norm(pos[far] - pos[i], axis=1)
         assert abs(nphi[i] + np.sum(q[far] / r) - full[i]) < 1e-12 * np.sum(np.abs(q) / 0.01)
+
+
+def test_direct_at_is_rows_of_direct():
+    """direct_at(pos, q, idx) returns rows idx of the all-pairs sum."""
+    rng = np.random.default_rng(23)
+    pos = rng.random((700, 3))
+    q = rng.random(700) - 0.5
+    phi, g = exact.direct(pos, q)
+    idx = np.array([0, 5, 699, 123, 5])
+    p2, g2 = exact.direct_at(pos, q, idx)
+    assert np.allclose(p2, phi[idx], rtol=1e-14, atol=0)
+    assert np.allclose(g2, g[idx], rtol=1e-13, atol=1e-13 * np.abs(g).max())
