@@ -293,7 +293,7 @@ WORKLOADS = {
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=1 << 16,
                     help="particles of the oracle's particle stages in the CPU baseline")
@@ -400,6 +400,23 @@ def main():
 
     err = golden_error(workload, out, prec)
 
+    # the near field beside it (not part of the metric): median of a few
+    # pmmm_near calls and of a few pmmm_total calls (one binning for both)
+    near_t = []
+    for fn in (plan.near, plan.total):
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(x, y, z, q, out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        near_t.append(sorted(ts)[len(ts) // 2])
+    near_rec = {"near_ms": near_t[0], "total_ms": near_t[1],
+                "note": "pmmm_near_* and pmmm_total_* (far + near, one binning), median of 5 calls; "
+                        "not part of the far-field metric"}
+
     nf = 2 * n if boundary == "open" else n
     tsize = 4 if prec == "f32" else 8
     peak_alu = FP32_PEAK if prec == "f32" else FP64_PEAK
@@ -446,6 +463,7 @@ def main():
         "roofline": roof,
         "step_roofline": step_roof,
         "stage_us": {k: v * 1e3 for k, v in means.items()},
+        "near_field": near_rec,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -304,11 +304,17 @@ def test_column_kernel_forms(form, boundary, n_cells, p):
     from paper_1409_5981_amd._lib import PMMM_EINVAL, Plan, PMMMError
     ps = _small(30000, n_cells, p, boundary, 18, np.float32)
     plan = Plan(n_cells, p, boundary)
+    nf = 2 * n_cells if boundary == "open" else n_cells
+    fits = form == "tile" or (nf in (64, 128) and not (form == "stream4" and p >= 7))
     try:
         plan.set_tuning(column_kernel=form)
     except PMMMError as e:
-        assert e.code == PMMM_EINVAL
-        pytest.skip(f"the {form} form does not fit {boundary} {n_cells}^3 p={p} (refused as it should)")
+        # the streamed forms need 64- or 128-point columns: refused, and the
+        # plan keeps its default form
+        assert e.code == PMMM_EINVAL and not fits, (form, boundary, n_cells, p)
+        assert plan.tuning()["column_kernel"] == "default"
+        return
+    assert fits, (form, boundary, n_cells, p)
     res, _ = gpu_far(ps, "f32", plan=plan)
     key = (boundary, n_cells, p)
     if key not in _FORM_REFS:
