@@ -577,7 +577,7 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
     constexpr int logn = LOGN, nf = 1 << LOGN, nh = nf / 2 + 1, nhp = (nh + 3) & ~3, ls = nf;
     const bool half = 2 * nz == nf;
     cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *buf = tw + nf / 2;
+    cplx<T> *buf = tw + nf;
     // XCD-aware order: consecutive columns stay on one XCD (blocks are dealt
     // round-robin over the 8 XCDs)
     const int per_xcd = (ngroups + 7) / 8;
@@ -600,7 +600,6 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
     auto s_comp = [&](int u) { return s_b0 + u * s_db < P ? s_b0 + u * s_db : P - 1; };
     constexpr int SB = 2 * kColumnLoadBatch;
     {
-        const cplx<T> twv = tw_g[tid < nf / 2 ? tid : 0];   // nf/2 <= blockDim.x
         // the zero half of an open column is never read (pruned transform)
         if (s_live) {
             for (int u0 = 0; s_b0 + u0 * s_db < P; u0 += SB) {
@@ -616,7 +615,7 @@ __global__ void __launch_bounds__((kRowSplit / RSP) * 128, RSP == 2 ? (sizeof(T)
                 }
             }
         }
-        if (tid < nf / 2) tw[tid] = twv;
+        fill_twiddles<T>(tw, tw_g, nf, tid, nthr);
     }
     __syncthreads();
     fft_col_rt<T, false, nf>(buf, half, P, tw, tid, nthr);

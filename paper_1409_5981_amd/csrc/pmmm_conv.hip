@@ -249,13 +249,10 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
 constexpr int kPlaneThreads = 256;
 constexpr int kPlaneChunk = 33;
 
+// W_N^e (conjugate for the inverse) from the full-circle table.
 template <typename T>
-__device__ __forceinline__ cplx<T> tw_n(const cplx<T> *tw, int e, int N, bool inv) {
-    cplx<T> w = e < N / 2 ? tw[e] : tw[e - N / 2];
-    if (e >= N / 2) {
-        w.re = -w.re;
-        w.im = -w.im;
-    }
+__device__ __forceinline__ cplx<T> tw_n(const cplx<T> *tw, int e, bool inv) {
+    cplx<T> w = tw[e];
     if (inv) w.im = -w.im;
     return w;
 }
@@ -270,7 +267,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd_n(const T *__restri
     constexpr int CWS = kPlaneChunk;  // odd row stride of yb
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *xb = tw + N / 2;
+    cplx<T> *xb = tw + N;
     cplx<T> *yb = xb + npair * N;
     const int z = blockIdx.x, tid = threadIdx.x;
     {
@@ -298,7 +295,6 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd_n(const T *__restri
         return;
     }
     const int c = blockIdx.y;
-    const cplx<T> twv = tw_g[tid < N / 2 ? tid : 0];
     const T *plane = M + ((int64_t)c * nin + z) * nin * nin;
     // rows (2j, 2j+1) as one complex row; the loads of a batch are issued
     // before their LDS stores
@@ -322,7 +318,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd_n(const T *__restri
             }
         }
     }
-    if (tid < N / 2) tw[tid] = twv;
+    fill_twiddles<T>(tw, tw_g, N, tid, kPlaneThreads);
     __syncthreads();
     fft_col<T, false, N, HALF>(xb, npair, tw, tid, kPlaneThreads);   // ends with a barrier
     cplx<T> *out = spec + ((int64_t)c * nin + z) * N * nh;
@@ -347,7 +343,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_fwd_n(const T *__restri
             fft_reg<16, false, T>(v);
             static_for<0, 16>([&](auto ik) {
                 constexpr int k1 = decltype(ik)::value;
-                const cplx<T> w = k1 == 0 ? cplx<T>{T(1), T(0)} : tw_n(tw, t2 * k1, N, false);
+                const cplx<T> w = k1 == 0 ? cplx<T>{T(1), T(0)} : tw_n(tw, t2 * k1, false);
                 yb[(t2 * 16 + k1) * CWS + kl] = k1 == 0 ? v[k1] : cmul(v[k1], w);
             });
         }
@@ -380,7 +376,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv_n(const cplx<T> *__
     constexpr int K2 = HALF ? N2 / 2 : N2;   // y rows kept: k2 * 16 + k1 < nout
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cplx<T> *tw = (cplx<T> *)lds_raw;
-    cplx<T> *xb = tw + N / 2;
+    cplx<T> *xb = tw + N;
     cplx<T> *yb = xb + npair * N;
     const int z = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
     {
@@ -388,7 +384,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv_n(const cplx<T> *__
         spec += sy * P * nout * N * nh;
         L += sy * P * nout * nout * nout;
     }
-    if (tid < N / 2) tw[tid] = tw_g[tid];
+    fill_twiddles<T>(tw, tw_g, N, tid, kPlaneThreads);
     __syncthreads();
     const cplx<T> *in = spec + ((int64_t)c * nout + z) * N * nh;
     for (int k0 = 0; k0 < nh; k0 += kPlaneChunk) {
@@ -405,7 +401,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv_n(const cplx<T> *__
             fft_reg<16, true, T>(v);
             static_for<0, 16>([&](auto ik) {
                 constexpr int k1 = decltype(ik)::value;
-                const cplx<T> w = k1 == 0 ? cplx<T>{T(1), T(0)} : tw_n(tw, t2 * k1, N, true);
+                const cplx<T> w = k1 == 0 ? cplx<T>{T(1), T(0)} : tw_n(tw, t2 * k1, true);
                 yb[(t2 * 16 + k1) * CWS + kl] = k1 == 0 ? v[k1] : cmul(v[k1], w);
             });
         }
@@ -457,7 +453,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane_inv_n(const cplx<T> *__
 template <typename T, int N>
 static size_t plane_n_lds(bool half) {
     const int npair = (half ? N / 2 : N) / 2;
-    return (size_t)(N / 2 + npair * N + N * kPlaneChunk) * sizeof(cplx<T>);
+    return (size_t)(N + npair * N + N * kPlaneChunk) * sizeof(cplx<T>);
 }
 
 template <typename T, int N>

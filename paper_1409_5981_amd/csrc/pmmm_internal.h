@@ -357,11 +357,25 @@ __device__ __forceinline__ constexpr int cpos(int row, int e) {
 
 // In-place FFTs of nlines rows of N = 16 N2 points (N = 32, 64, 128) in the
 // layout above: 16-point register FFTs over n1 of x[n1 N2 + t2], twiddles
-// W_N^(t2 k1), then N2-point FFTs over t2.  The lanes of one row's items sit
+// W_N^(t2 k1) from a full-circle table tw[e] = exp(-2 pi i e / N), e < N
+// (see fill_twiddles), then N2-point FFTs over t2.  The lanes of one row's items sit
 // in one wave, so each in-place pass needs no barrier between its reads and
 // writes (a wave's LDS operations complete in order; the asm statement keeps
 // the compiler from moving the writes up).  HALF: only the first N/2 inputs
 // are non-zero (forward) or only the first N/2 outputs are kept (inverse).
+// Full-circle twiddle table tw[e] = exp(-2 pi i e / N), e < N, in LDS from
+// the half table tw_g[e], e < N/2 (tw[e + N/2] = -tw[e]); call with at least
+// N/2 threads, before the barrier that precedes the first use.
+template <typename T>
+__device__ __forceinline__ void fill_twiddles(cplx<T> *tw, const cplx<T> *__restrict__ tw_g,
+                                              int N, int tid, int nthr) {
+    for (int e = tid; e < N / 2; e += nthr) {
+        const cplx<T> w = tw_g[e];
+        tw[e] = w;
+        tw[e + N / 2] = {-w.re, -w.im};
+    }
+}
+
 template <typename T, bool INV, int N, bool HALF>
 __device__ __forceinline__ void fft_col(cplx<T> *buf, int nlines, const cplx<T> *tw, int tid,
                                         int nthr) {
@@ -379,12 +393,7 @@ __device__ __forceinline__ void fft_col(cplx<T> *buf, int nlines, const cplx<T> 
         fft_reg<16, INV, T>(v);
         static_for<1, 16>([&](auto ik) {
             constexpr int k1 = decltype(ik)::value;
-            const int e = t2 * k1;  // < N
-            cplx<T> w = e < N / 2 ? tw[e] : tw[e - N / 2];
-            if (e >= N / 2) {
-                w.re = -w.re;
-                w.im = -w.im;
-            }
+            cplx<T> w = tw[t2 * k1];  // full-circle table: t2 k1 < N
             if (INV) w.im = -w.im;
             v[k1] = cmul(v[k1], w);
         });
@@ -488,11 +497,12 @@ inline size_t column_lds_w(int p, int nf, size_t tsize, int w, int *rs_out) {
     return lds;
 }
 
-// LDS bytes of the streamed-kernel column variant (twiddles and one column's
-// spectra, rows of nf without padding; 0 if over 160 KB).
+// LDS bytes of the streamed-kernel column variant (the full-circle twiddle
+// table and one column's spectra, rows of nf without padding; 0 if over
+// 160 KB).
 inline size_t column_g_lds(int p, int nf, size_t tsize) {
     const size_t P = (size_t)(p + 1) * (p + 1);
-    const size_t lds = P * (size_t)nf * 2 * tsize + (size_t)nf / 2 * 2 * tsize;
+    const size_t lds = P * (size_t)nf * 2 * tsize + (size_t)nf * 2 * tsize;
     return lds > 160 * 1024 ? 0 : lds;
 }
 
