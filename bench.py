@@ -520,9 +520,8 @@ def bench_multi(args, workload):
     nprod = 6 if args.split == "f32" else 3
     bytes_k, flops_k, mfma_k = multi_stage_work(dominant, N, S, n, p, nprod)
     roof = _roofline(t_k, bytes_k, flops_k, FP32_PEAK, mfma_k)
-    form = tuning.get("column_kernel") if (tuning and dominant == "column") else None
-    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash(), form)
-    roof["kernel"] = dominant if form in (None, "default") else f"{dominant} ({form})"
+    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash())
+    roof["kernel"] = dominant
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
     roof["algorithmic_flops"] = flops_k
