@@ -12,9 +12,12 @@ Modules
   exact       exact references: direct O(N^2) sum, Ewald sum, near field
   expansions  single-centre transformations (P2M, M2P, M2L, L2P, L2L, M2M)
               of App. A.3 in complex form, used to pin the mesh pipeline
+  storage     per-order fixed-point coefficient records (Sec. 5.3) and the
+              complex composition of two real sets (App. D)
 
 Parity status: every function listed above is pinned by a CPU test under
 tests/test_oracle_*.py against values fixed by the paper (Table RSlm), by
 textbook mathematics (associated Legendre functions, Laplace's equation,
-addition theorems, the rock-salt Madelung constant) or by brute force.
+addition theorems, the rock-salt Madelung constant, the bit counts of
+Sec. 5.3) or by brute force.
 """
