@@ -417,6 +417,8 @@ def main():
                 "note": "pmmm_near_* and pmmm_total_* (far + near, one binning), median of 5 calls; "
                         "not part of the far-field metric"}
 
+    storage_rec = bench_storage(plan, p, stream) if prec == "f32" else None
+
     nf = 2 * n if boundary == "open" else n
     tsize = 4 if prec == "f32" else 8
     peak_alu = FP32_PEAK if prec == "f32" else FP64_PEAK
@@ -464,12 +466,69 @@ def main():
         "step_roofline": step_roof,
         "stage_us": {k: v * 1e3 for k, v in means.items()},
         "near_field": near_rec,
+        "coef_storage": storage_rec,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     if err is not None and not err["ok"]:
         print("error above the bound: the line is not a valid measurement", file=sys.stderr)
         sys.exit(3)
+
+
+def bench_storage(plan, p, stream, reps=50):
+    """Coefficient storage calls on the workload's own meshes (outside the
+    far-field metric): per-order fixed-point records of the local-expansion
+    mesh (Sec. 5.3) and the App. D composition of the local-expansion and
+    moment meshes.  The stream is held by a spin kernel while the calls are
+    queued, so the events time back-to-back kernels, not host launch gaps."""
+    import numpy as np
+    import torch
+    from paper_1409_5981_amd import _lib
+    P = (p + 1) ** 2
+    Lh = plan.mesh(_lib.PMMM_MESH_L).reshape(P, -1).astype(np.float32)
+    Mh = plan.mesh(_lib.PMMM_MESH_M).reshape(P, -1).astype(np.float32)
+    dev = torch.device("cuda")
+    L, M = torch.from_numpy(Lh).to(dev), torch.from_numpy(Mh).to(dev)
+    ncell = L.shape[1]
+    W = _lib.coef_record_words(p)
+    rec, ex = _lib.coef_pack(p, L, stream=stream)
+    back = _lib.coef_unpack(p, rec, ex, stream=stream)
+    comp = _lib.coef_compose(p, L, M, stream=stream)
+    sa, sb = _lib.coef_split(p, comp, stream=stream)
+    torch.cuda.synchronize()
+    d = (back - L).double()
+    rt_err = float(torch.sqrt((d * d).sum() / (L.double() ** 2).sum()))
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(20_000_000)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    fw, cw = 4 * P * ncell, 4 * W * ncell
+    cases = {
+        "pack_auto_units": (lambda: _lib.coef_pack(p, L, rec, ex, True, stream), 2 * fw + cw),
+        "pack_given_units": (lambda: _lib.coef_pack(p, L, rec, ex, False, stream), fw + cw),
+        "unpack": (lambda: _lib.coef_unpack(p, rec, ex, back, stream), cw + fw),
+        "compose": (lambda: _lib.coef_compose(p, L, M, comp, stream), 4 * fw),
+        "split": (lambda: _lib.coef_split(p, comp, sa, sb, stream), 4 * fw),
+    }
+    kern = {}
+    for name, (fn, nbytes) in cases.items():
+        t = timed(fn)
+        kern[name] = {"us": t * 1e6, "algorithmic_bytes": nbytes, "GB/s": nbytes / t / 1e9,
+                      "frac": nbytes / t / HBM_PEAK}
+    return {"mesh": f"local-expansion mesh of the workload, {P} x {ncell} float32",
+            "bits_per_cell": 3 * (p + 1) * (p + 2) * (2 * p + 3) // 6,
+            "record_bytes_per_cell": 4 * W, "float_bytes_per_cell": 4 * P,
+            "round_trip_rel_rms": rt_err, "calls": kern,
+            "note": "pmmm_coef_* calls (Sec. 5.3 records, App. D composite); not part of the "
+                    "far-field metric; HIP events over %d back-to-back calls each" % reps}
 
 
 def bench_multi(args, workload):

@@ -222,6 +222,56 @@ int pmmm_total_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
                    const double *z, const double *q, double *phi, double *gx, double *gy,
                    double *gz, void *stream);
 
+/* Per-order fixed-point records of a coefficient mesh (Sec. 5.3 and its
+ * footnote: an order-l coefficient carries 3 (p + 1 - l) bits, so a cell
+ * carries 3 (p+1)(p+2)(2p+3)/6 bits, 612 at p = 7).  These calls work on a
+ * caller's device arrays; no plan is involved.
+ *   coef     [(p+1)^2][ncell] float32, device, component-major in the real
+ *            storage of the meshes (index l(l+1)+m holds Re X_l^|m| for
+ *            m >= 0 and Im X_l^|m| for m < 0), e.g. a PMMM_MESH_M or
+ *            PMMM_MESH_L mesh;
+ *   records  [ncell][pmmm_coef_record_words(p)] uint32, device: each cell's
+ *            codes as b_l-bit two's-complement fields in real-storage order,
+ *            bit j of the record in bit j mod 32 of word j / 32, zero-padded;
+ *   exps     [p+1] int32, device: the unit of order l is 2^exps[l], shared
+ *            by all cells.
+ * code = rint(word / 2^e_l) (ties to even), clamped to +-(2^(b_l-1) - 1);
+ * NaN words are coded 0.  With flags = PMMM_COEF_AUTO_EXP the pack chooses
+ * and writes exps: the smallest power of two under which the largest |word|
+ * of the order rounds inside its range (0 for an all-zero order,
+ * PMMM_COEF_EXP_INVALID for an order holding a non-finite word, whose codes
+ * are then 0); with flags = 0 it reads the caller's exps.  Unpack writes
+ * code * 2^e_l (NaN for an order marked invalid).  The round trip is within
+ * half a unit per word for automatic units.  Both calls only enqueue work on
+ * `stream` (NULL: the default stream) and allocate nothing; ncell = 0 is a
+ * no-op apart from the automatic exps (all 0).
+ * Errors: PMMM_EINVAL for p outside 0..PMMM_PMAX, ncell outside 0..2^31,
+ * unknown flag bits or a null pointer that would be used; PMMM_EHIP if a
+ * launch fails. */
+#define PMMM_COEF_EXP_INVALID (-2147483647 - 1)
+enum { PMMM_COEF_AUTO_EXP = 1 };
+/* 32-bit words per cell record at order p, or -1 for p outside 0..PMMM_PMAX. */
+int pmmm_coef_record_words(int p);
+int pmmm_coef_pack_f32(int p, int64_t ncell, const float *coef, uint32_t *records, int32_t *exps,
+                       unsigned flags, void *stream);
+int pmmm_coef_unpack_f32(int p, int64_t ncell, const uint32_t *records, const int32_t *exps,
+                         float *coef, void *stream);
+
+/* Complex composition of two real coefficient sets (App. D).  a and b are
+ * [(p+1)^2][ncell] float32 meshes in the real storage above, each obeying
+ * X_l^{-m} = (-1)^m conj(X_l^m); c is [(p+1)^2][ncell] (re, im) float32
+ * pairs (8-byte aligned) holding C_l^m = A_l^m + i B_l^m at index l(l+1)+m
+ * for every -l <= m <= l.  By linearity, a transformation applied to C in
+ * complex arithmetic acts on both sets at once; pmmm_coef_split_f32 recovers
+ * the two real sets from such a composite (it reads C_l^m and C_l^{-m} only,
+ * and writes a and b in full).  Device pointers; the calls only enqueue work
+ * on `stream` and allocate nothing.  Errors: PMMM_EINVAL for p outside
+ * 0..PMMM_PMAX, ncell outside 0..2^31 or a null pointer (ncell > 0);
+ * PMMM_EHIP if a launch fails. */
+int pmmm_coef_compose_f32(int p, int64_t ncell, const float *a, const float *b, float *c,
+                          void *stream);
+int pmmm_coef_split_f32(int p, int64_t ncell, const float *c, float *a, float *b, void *stream);
+
 /* Launch-shape autotuner.  Runs the far field (pmmm_far_f32 or _f64 by the
  * plan's precision, same arguments and meaning) on the caller's particles,
  * timing with HIP events the P2M stage for each number of lanes per cell

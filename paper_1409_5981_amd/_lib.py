@@ -21,6 +21,8 @@ PMMM_F32, PMMM_F64, PMMM_BF16X3 = 0, 1, 2
 PMMM_MESH_M, PMMM_MESH_L, PMMM_MESH_GREEN = 0, 1, 2
 PMMM_PMAX = 10
 PMMM_NOALLOC_MAX_N = 1 << 18
+PMMM_COEF_EXP_INVALID = -(2 ** 31)
+PMMM_COEF_AUTO_EXP = 1
 
 #: every symbol include/pmmm.h declares
 EXPORTS = [
@@ -32,6 +34,8 @@ EXPORTS = [
     "pmmm_plan_autotune", "pmmm_plan_get_tuning", "pmmm_plan_set_tuning",
     "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
     "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
+    "pmmm_coef_record_words", "pmmm_coef_pack_f32", "pmmm_coef_unpack_f32",
+    "pmmm_coef_compose_f32", "pmmm_coef_split_f32",
     "pmmm_error_string", "pmmm_last_error",
 ]
 
@@ -133,6 +137,16 @@ def load():
     L.pmmm_batch_set_graphs.restype = ci
     L.pmmm_batch_sync_status.argtypes = [vp]
     L.pmmm_batch_sync_status.restype = ci
+    L.pmmm_coef_record_words.argtypes = [ci]
+    L.pmmm_coef_record_words.restype = ci
+    L.pmmm_coef_pack_f32.argtypes = [ci, i64, vp, vp, vp, ctypes.c_uint, vp]
+    L.pmmm_coef_pack_f32.restype = ci
+    L.pmmm_coef_unpack_f32.argtypes = [ci, i64, vp, vp, vp, vp]
+    L.pmmm_coef_unpack_f32.restype = ci
+    L.pmmm_coef_compose_f32.argtypes = [ci, i64, vp, vp, vp, vp]
+    L.pmmm_coef_compose_f32.restype = ci
+    L.pmmm_coef_split_f32.argtypes = [ci, i64, vp, vp, vp, vp]
+    L.pmmm_coef_split_f32.restype = ci
     L.pmmm_error_string.argtypes = [ci]
     L.pmmm_error_string.restype = ctypes.c_char_p
     L.pmmm_last_error.argtypes = []
@@ -427,3 +441,97 @@ class Batch:
 
     def sync_status(self):
         _check(load().pmmm_batch_sync_status(self._h))
+
+
+# ------------------------------------------------- coefficient storage calls
+def coef_record_words(p: int) -> int:
+    """32-bit words of one per-order fixed-point cell record at order p."""
+    w = load().pmmm_coef_record_words(int(p))
+    if w < 0:
+        raise ValueError(f"order {p} outside 0..{PMMM_PMAX}")
+    return int(w)
+
+
+def _coef_mesh_shape(p, coef):
+    if coef.dim() != 2 or coef.shape[0] != (p + 1) ** 2:
+        raise ValueError(f"coefficient mesh must have shape [(p+1)^2, ncell], got {tuple(coef.shape)}")
+    return int(coef.shape[1])
+
+
+def coef_pack(p: int, coef, records=None, exps=None, auto_exp: bool = True, stream=None):
+    """Per-order fixed-point records of a float32 mesh [(p+1)^2, ncell]
+    (pmmm_coef_pack_f32); returns (records [ncell, words] int32 holding the
+    uint32 bit patterns, exps [p+1] int32)."""
+    import torch
+    L = load()
+    ncell = _coef_mesh_shape(p, coef)
+    w = coef_record_words(p)
+    check_buffers((coef,), torch.float32, (p + 1) ** 2 * ncell, what="coef")
+    if records is None:
+        records = torch.empty((ncell, w), dtype=torch.int32, device=coef.device)
+    if exps is None:
+        if not auto_exp:
+            raise ValueError("caller units need exps")
+        exps = torch.empty(p + 1, dtype=torch.int32, device=coef.device)
+    check_buffers((records,), torch.int32, ncell * w, what="records", device=coef.device)
+    check_buffers((exps,), torch.int32, p + 1, what="exps", device=coef.device)
+    _check(L.pmmm_coef_pack_f32(int(p), ncell, coef.data_ptr(), records.data_ptr(), exps.data_ptr(),
+                                PMMM_COEF_AUTO_EXP if auto_exp else 0, _stream_handle(stream)))
+    return records, exps
+
+
+def coef_unpack(p: int, records, exps, out=None, stream=None):
+    """Float32 mesh [(p+1)^2, ncell] from per-order fixed-point records
+    (pmmm_coef_unpack_f32)."""
+    import torch
+    L = load()
+    w = coef_record_words(p)
+    if records.dim() != 2 or records.shape[1] != w:
+        raise ValueError(f"records must have shape [ncell, {w}], got {tuple(records.shape)}")
+    ncell = int(records.shape[0])
+    check_buffers((records,), torch.int32, ncell * w, what="records")
+    check_buffers((exps,), torch.int32, p + 1, what="exps", device=records.device)
+    if out is None:
+        out = torch.empty(((p + 1) ** 2, ncell), dtype=torch.float32, device=records.device)
+    check_buffers((out,), torch.float32, (p + 1) ** 2 * ncell, shape=((p + 1) ** 2, ncell),
+                  what="out", device=records.device)
+    _check(L.pmmm_coef_unpack_f32(int(p), ncell, records.data_ptr(), exps.data_ptr(), out.data_ptr(),
+                                  _stream_handle(stream)))
+    return out
+
+
+def coef_compose(p: int, a, b, out=None, stream=None):
+    """App. D composite [(p+1)^2, ncell, 2] (re, im) of two real float32
+    meshes [(p+1)^2, ncell] (pmmm_coef_compose_f32)."""
+    import torch
+    L = load()
+    ncell = _coef_mesh_shape(p, a)
+    P = (p + 1) ** 2
+    check_buffers((a, b), torch.float32, P * ncell, shape=(P, ncell), what="a, b")
+    if out is None:
+        out = torch.empty((P, ncell, 2), dtype=torch.float32, device=a.device)
+    check_buffers((out,), torch.float32, 2 * P * ncell, shape=(P, ncell, 2), what="out",
+                  device=a.device)
+    _check(L.pmmm_coef_compose_f32(int(p), ncell, a.data_ptr(), b.data_ptr(), out.data_ptr(),
+                                   _stream_handle(stream)))
+    return out
+
+
+def coef_split(p: int, c, a=None, b=None, stream=None):
+    """The two real float32 meshes [(p+1)^2, ncell] of an App. D composite
+    [(p+1)^2, ncell, 2] (pmmm_coef_split_f32)."""
+    import torch
+    L = load()
+    P = (p + 1) ** 2
+    if c.dim() != 3 or c.shape[0] != P or c.shape[2] != 2:
+        raise ValueError(f"composite must have shape [(p+1)^2, ncell, 2], got {tuple(c.shape)}")
+    ncell = int(c.shape[1])
+    check_buffers((c,), torch.float32, 2 * P * ncell, what="c")
+    if a is None:
+        a = torch.empty((P, ncell), dtype=torch.float32, device=c.device)
+    if b is None:
+        b = torch.empty((P, ncell), dtype=torch.float32, device=c.device)
+    check_buffers((a, b), torch.float32, P * ncell, shape=(P, ncell), what="a, b", device=c.device)
+    _check(L.pmmm_coef_split_f32(int(p), ncell, c.data_ptr(), a.data_ptr(), b.data_ptr(),
+                                 _stream_handle(stream)))
+    return a, b

@@ -115,3 +115,27 @@ def test_buffer_validation_before_any_call():
         check_buffers((ok,), f32, 10)
     with pytest.raises(ValueError, match="None"):
         check_buffers((None,), f32, 10)
+
+
+def test_coefficient_storage_calls_validate_on_host(lib):
+    """Record sizes agree with the oracle's bit layout (Sec. 5.3), and bad
+    orders, sizes, flags and pointers are refused before any GPU call."""
+    import ctypes
+    from oracle.storage import cell_words
+    for p in range(11):
+        assert lib.pmmm_coef_record_words(p) == cell_words(p)
+    assert lib.pmmm_coef_record_words(-1) == -1 and lib.pmmm_coef_record_words(11) == -1
+    dummy = ctypes.c_void_p(16)
+    EINVAL = 1
+    assert lib.pmmm_coef_pack_f32(11, 4, dummy, dummy, dummy, 1, None) == EINVAL
+    assert lib.pmmm_coef_pack_f32(3, -1, dummy, dummy, dummy, 1, None) == EINVAL
+    assert lib.pmmm_coef_pack_f32(3, 4, dummy, dummy, dummy, 2, None) == EINVAL
+    assert lib.pmmm_coef_pack_f32(3, 4, None, dummy, dummy, 1, None) == EINVAL
+    assert lib.pmmm_coef_pack_f32(3, 4, dummy, dummy, None, 1, None) == EINVAL
+    assert lib.pmmm_coef_unpack_f32(3, 4, None, dummy, dummy, None) == EINVAL
+    assert lib.pmmm_coef_unpack_f32(-1, 4, dummy, dummy, dummy, None) == EINVAL
+    assert lib.pmmm_coef_compose_f32(3, 4, dummy, None, dummy, None) == EINVAL
+    assert lib.pmmm_coef_compose_f32(3, (1 << 31) + 1, dummy, dummy, dummy, None) == EINVAL
+    assert lib.pmmm_coef_split_f32(12, 4, dummy, dummy, dummy, None) == EINVAL
+    assert lib.pmmm_coef_split_f32(3, 4, dummy, None, dummy, None) == EINVAL
+    assert lib.pmmm_coef_compose_f32(3, 0, None, None, None, None) == 0         # empty: nothing to do
