@@ -105,10 +105,17 @@ def multi_stage_work(stage, N, S, n, p, nprod):
     raise KeyError(stage)
 
 
-def kernel_source_hash():
+# Sources that build each stage's kernels (a traffic record stays valid while
+# they are unchanged); stages not listed hash every kernel source.
+STAGE_SOURCES = {
+    "column": ["pmmm_column.h", "pmmm_column_inst.hip", "pmmm_internal.h"],
+}
+
+
+def kernel_source_hash(stage=None):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1409_5981_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in STAGE_SOURCES.get(stage) or sorted(os.listdir(d)):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -425,7 +432,7 @@ def main():
     bytes_k, flops_k = algorithmic_work(dominant, N, n, p, nf, tsize)
     roof = _roofline(t_k, bytes_k, flops_k, peak_alu)
     form = tuning.get("column_kernel") if (tuning and dominant == "column") else None
-    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash(), form)
+    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash(dominant), form)
     roof["kernel"] = dominant if form in (None, "default") else f"{dominant} ({form})"
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
@@ -579,7 +586,7 @@ def bench_multi(args, workload):
     nprod = 6 if args.split == "f32" else 3
     bytes_k, flops_k, mfma_k = multi_stage_work(dominant, N, S, n, p, nprod)
     roof = _roofline(t_k, bytes_k, flops_k, FP32_PEAK, mfma_k)
-    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash())
+    roof["traffic"] = load_traffic(dominant, workload, kernel_source_hash(dominant))
     roof["kernel"] = dominant
     roof["kernel_us"] = t_k * 1e6
     roof["algorithmic_bytes"] = bytes_k
