@@ -80,6 +80,8 @@ def near(pos, q, cfg: Config):
     the (2c+1)^3 cells around each particle's cell; periodic meshes wrap the
     cell offset with the matching image shift."""
     I, _, _, wpos = cells(pos, cfg)
+    if cfg.shape is not None and len(set(cfg.dims)) > 1:
+        return _near_pairs(wpos, q, I, cfg.cutoff)
     wpos = np.ascontiguousarray(wpos, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
     ci = np.ascontiguousarray(I.astype(np.int32))
@@ -89,6 +91,25 @@ def near(pos, q, cfg: Config):
     _clib.lib().ora_near(n, _clib.dptr(wpos), _clib.dptr(q), _clib.iptr(ci), cfg.n, cfg.box,
                          cfg.cutoff, 1 if cfg.boundary == "periodic" else 0,
                          _clib.dptr(phi), _clib.dptr(grad))
+    return phi, grad
+
+
+def _near_pairs(pos, q, I, cutoff, chunk=512):
+    """Open-boundary near field by brute force over all pairs: the pairs
+    whose cells lie within the near cube, max_a |I_a - J_a| <= c."""
+    q = np.asarray(q, dtype=np.float64)
+    n = len(q)
+    phi = np.zeros(n)
+    grad = np.zeros((n, 3))
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        d = pos[s:e, None, :] - pos[None, :, :]            # r_i - r_j
+        r2 = np.sum(d * d, axis=2)
+        near = np.max(np.abs(I[s:e, None, :] - I[None, :, :]), axis=2) <= cutoff
+        near[np.arange(e - s), np.arange(s, e)] = False
+        w = np.where(near, q[None, :] / np.sqrt(np.where(near, r2, 1.0)), 0.0)
+        phi[s:e] = w.sum(axis=1)
+        grad[s:e] = -np.einsum("ij,ijk->ik", w / np.where(near, r2, 1.0), d)
     return phi, grad
 
 

@@ -14,6 +14,8 @@ physical units, with numpy's FFT as the transform primitive:
   5. m2l_wave     the real-matrix M2L (eq. realmatrix) with every real
                   coefficient replaced by its complex spectrum value
   6. local_mesh   inverse DFT (1/n_f^3), open: the [0, n)^3 octant
+                  (open meshes may have nx, ny, nz cells of one edge h: the
+                  zero padding and the octant are taken per axis)
   7. periodic_corrections
                   dipole, self and r^2 corrections (App. B, correction
                   procedure) and the charged-system terms
@@ -43,6 +45,24 @@ class Config:
     cutoff: int = 2        # near cube half-width c (27 cells: 1, 125 cells: 2)
     alpha: float | None = None   # periodic splitting parameter (default 1.5/b)
     images: int = 4        # lattice-sum radius: |r + n b| <= images b (real), |n| <= images (reciprocal)
+    shape: tuple | None = None   # open boundary: (nx, ny, nz) cells of edge h = box / nx; None: n^3
+
+    def __post_init__(self):
+        if self.shape is not None:
+            if self.boundary != "open":
+                raise ValueError("a non-cubic mesh needs the open boundary")
+            if tuple(self.shape)[0] != self.n:
+                raise ValueError("shape[0] must equal n (box is the x edge)")
+
+    @property
+    def dims(self) -> tuple:
+        """Cells per axis (x, y, z)."""
+        return tuple(self.shape) if self.shape is not None else (self.n, self.n, self.n)
+
+    @property
+    def extent(self) -> np.ndarray:
+        """Box edges (x, y, z): cubic cells of edge h."""
+        return self.h * np.asarray(self.dims, dtype=np.float64)
 
     @property
     def h(self) -> float:
@@ -68,16 +88,18 @@ def cells(pos, cfg: Config):
     pos = np.asarray(pos, dtype=np.float64)
     if cfg.boundary == "periodic":
         pos = pos - cfg.box * np.floor(pos / cfg.box)
-    elif np.any((pos < 0) | (pos >= cfg.box)):
-        raise ValueError("open boundary: particle outside [0, b)^3")
+    elif np.any((pos < 0) | (pos >= cfg.extent[None, :])):
+        raise ValueError("open boundary: particle outside the box")
     I = np.floor(pos / cfg.h).astype(np.int64)
-    I = np.clip(I, 0, cfg.n - 1)
+    I = np.clip(I, 0, np.asarray(cfg.dims)[None, :] - 1)
     centre = (I + 0.5) * cfg.h
     return I, centre, pos - centre, pos
 
 
-def linear_cell(I, n):
-    return (I[:, 2] * n + I[:, 1]) * n + I[:, 0]
+def linear_cell(I, dims):
+    """Cell index (z ny + y) nx + x; dims = (nx, ny, nz), or n for n^3."""
+    nx, ny, _ = (dims, dims, dims) if np.isscalar(dims) else dims
+    return (I[:, 2] * ny + I[:, 1]) * nx + I[:, 0]
 
 
 # ---------------------------------------------------------------- step 2
@@ -85,9 +107,10 @@ def p2m_mesh(pos, q, cfg: Config, chunk: int = 1 << 16):
     """Moment meshes M[P, z, y, x] (real storage) and the per-cell sums
     sum_k q_k |r_k^rel|^2 [z, y, x] used by the periodic correction."""
     P = nreal(cfg.p)
-    K = cfg.n ** 3
+    nx, ny, nz = cfg.dims
+    K = nx * ny * nz
     I, centre, rel, _ = cells(pos, cfg)
-    lin = linear_cell(I, cfg.n)
+    lin = linear_cell(I, cfg.dims)
     q = np.asarray(q, dtype=np.float64)
     M = np.zeros((P, K))
     for s in range(0, len(q), chunk):
@@ -98,21 +121,24 @@ def p2m_mesh(pos, q, cfg: Config, chunk: int = 1 << 16):
         for c in range(P):
             M[c] += np.bincount(lin[s:e], weights=Mr[:, c], minlength=K)
     qr2 = np.bincount(lin, weights=q * np.sum(rel * rel, axis=1), minlength=K)
-    n = cfg.n
-    return M.reshape(P, n, n, n), qr2.reshape(n, n, n)
+    return M.reshape(P, nz, ny, nx), qr2.reshape(nz, ny, nx)
 
 
 # ---------------------------------------------------------------- step 3
 def green_open(cfg: Config):
-    """Open-boundary transfer-kernel mesh on the (2n)^3 zero-padded mesh
-    (App. C, Fig. green): index d -> displacement d (d < n) or d - 2n
-    (d > n); the index-n planes and the near cube max|delta| <= c are zero;
-    elsewhere S_k^j(delta h) for orders k <= 2p, real storage."""
-    n, nf, p2 = cfg.n, 2 * cfg.n, 2 * cfg.p
-    d = np.arange(nf)
-    delta = np.where(d < n, d, d - nf)
-    DZ, DY, DX = np.meshgrid(delta, delta, delta, indexing="ij")
-    onplane = (d[:, None, None] == n) | (d[None, :, None] == n) | (d[None, None, :] == n)
+    """Open-boundary transfer-kernel mesh on the zero-padded mesh of twice
+    the cells per axis (App. C, Fig. green; per axis a of n_a cells): index
+    d -> displacement d (d < n_a) or d - 2 n_a (d > n_a); the index-n_a
+    planes and the near cube max|delta| <= c are zero; elsewhere
+    S_k^j(delta h) for orders k <= 2p, real storage, [Q, 2nz, 2ny, 2nx]."""
+    p2 = 2 * cfg.p
+    ax = []
+    for na in cfg.dims:
+        d = np.arange(2 * na)
+        ax.append((np.where(d < na, d, d - 2 * na), d == na))
+    (dx, px), (dy, py), (dz, pz) = ax
+    DZ, DY, DX = np.meshgrid(dz, dy, dx, indexing="ij")
+    onplane = pz[:, None, None] | py[None, :, None] | px[None, None, :]
     cheb = np.maximum(np.maximum(np.abs(DX), np.abs(DY)), np.abs(DZ))
     zero = onplane | (cheb <= cfg.cutoff)
     h = cfg.h
@@ -211,15 +237,17 @@ def local_mesh(M, cfg: Config, Gt=None):
     the [0, n)^3 octant of the (2n)^3 mesh and keep that octant of L."""
     if Gt is None:
         Gt = spectra(green(cfg))
-    n, nf = cfg.n, cfg.nf
+    nx, ny, nz = cfg.dims
     if cfg.boundary == "open":
-        Mp = np.zeros((M.shape[0], nf, nf, nf))
-        Mp[:, :n, :n, :n] = M
+        sf = (2 * nz, 2 * ny, 2 * nx)
+        Mp = np.zeros((M.shape[0],) + sf)
+        Mp[:, :nz, :ny, :nx] = M
     else:
+        sf = (nz, ny, nx)
         Mp = M
     Lt = m2l_wave(Gt, spectra(Mp), cfg.p)
-    L = np.fft.irfftn(Lt, s=(nf, nf, nf), axes=(-3, -2, -1))
-    return L[:, :n, :n, :n].copy()
+    L = np.fft.irfftn(Lt, s=sf, axes=(-3, -2, -1))
+    return L[:, :nz, :ny, :nx].copy()
 
 
 # ---------------------------------------------------------------- step 7
@@ -246,7 +274,7 @@ def l2p(L, pos, cfg: Config, chunk: int = 1 << 16):
     for grad Phi, at each particle from the local expansion of its cell."""
     p = cfg.p
     I, centre, rel, _ = cells(pos, cfg)
-    lin = linear_cell(I, cfg.n)
+    lin = linear_cell(I, cfg.dims)
     Lf = L.reshape(L.shape[0], -1)
     N = len(lin)
     phi = np.empty(N)

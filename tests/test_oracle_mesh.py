@@ -385,3 +385,76 @@ def test_open_rejects_outside_particles():
     cfg = pmmm.Config(n=4, p=2, boundary="open")
     with pytest.raises(ValueError):
         pmmm.cells(np.array([[0.5, 1.0, 0.5]]), cfg)
+
+
+# ------------------------------------------------- open meshes of nx x ny x nz cells
+def test_open_non_cubic_fft_convolution_equals_cell_pair_m2l():
+    """Steps 3-6 on an open 3 x 4 x 5 mesh of cubic cells equal the explicit
+    sum over cell pairs of eq. M2L outside the near cube (Sec. 1: the mesh
+    may be any product of three integers; App. C padding per axis)."""
+    dims = (3, 4, 5)
+    cfg = pmmm.Config(n=3, p=2, boundary="open", cutoff=1, box=0.75, shape=dims)
+    rng = np.random.default_rng(2)
+    pos = rng.random((300, 3)) * cfg.extent
+    q = rng.random(300) - 0.5
+    M, _ = pmmm.p2m_mesh(pos, q, cfg)
+    assert M.shape == (nreal(2), 5, 4, 3)
+    L = pmmm.local_mesh(M, cfg)
+    P, h = nreal(cfg.p), cfg.h
+    Mc = from_real(M.reshape(P, -1).T, cfg.p)
+    nx, ny, nz = dims
+    idx = np.array([[i % nx, (i // nx) % ny, i // (nx * ny)] for i in range(nx * ny * nz)])
+    cen = (idx + 0.5) * h
+    for I in range(len(idx)):
+        acc = np.zeros(Mc.shape[1], dtype=complex)
+        for J in range(len(idx)):
+            if np.max(np.abs(idx[I] - idx[J])) <= cfg.cutoff:
+                continue
+            acc += ex.m2l(cfg.p, Mc[J], cen[J], cen[I])
+        np.testing.assert_allclose(L.reshape(P, -1)[:, I], to_real(acc, cfg.p), rtol=1e-11,
+                                   atol=1e-11 * np.max(np.abs(L)))
+
+
+def test_open_non_cubic_equals_its_cubic_embedding():
+    """The open far field on an nx x ny x nz mesh equals the far field on the
+    cube of 8^3 equal cells holding it (the extra cells are empty and the
+    near cubes are the same), and a cubic shape equals the plain n^3 mesh."""
+    rng = np.random.default_rng(3)
+    h = 1.0 / 8
+    cfg = pmmm.Config(n=5, p=4, boundary="open", cutoff=2, box=5 * h, shape=(5, 8, 3))
+    pos = rng.random((500, 3)) * cfg.extent
+    q = rng.random(500) - 0.5
+    a = pmmm.far_field(pos, q, cfg)
+    b = pmmm.far_field(pos, q, pmmm.Config(n=8, p=4, boundary="open", cutoff=2, box=1.0))
+    assert exact.rel_rms(a.phi, b.phi) < 1e-12 and exact.rel_rms(a.grad, b.grad) < 1e-12
+    pos2 = rng.random((500, 3))
+    c = pmmm.far_field(pos2, q, pmmm.Config(n=8, p=4, boundary="open", shape=(8, 8, 8)))
+    d = pmmm.far_field(pos2, q, pmmm.Config(n=8, p=4, boundary="open"))
+    assert np.array_equal(c.phi, d.phi) and np.array_equal(c.grad, d.grad)
+
+
+def test_near_pairs_match_cell_near_field():
+    """The brute-force near field used for non-cubic meshes equals the
+    cell-list near field of the C oracle on a cubic mesh."""
+    pos, q = _rand(700, 9)
+    cfg = pmmm.Config(n=6, p=2, boundary="open", cutoff=2)
+    I, _, _, wpos = pmmm.cells(pos, cfg)
+    a = exact._near_pairs(wpos, q, I, cfg.cutoff)
+    b = exact.near(pos, q, cfg)
+    assert exact.rel_rms(a[0], b[0]) < 1e-13 and exact.rel_rms(a[1], b[1]) < 1e-13
+
+
+def test_open_non_cubic_total_field_matches_direct_sum():
+    """Far + near on a 12 x 6 x 9 mesh against the direct sum: the method
+    error at p = 6, c = 2 is of the size the cubic meshes give."""
+    rng = np.random.default_rng(5)
+    cfg = pmmm.Config(n=12, p=6, boundary="open", cutoff=2, box=1.0, shape=(12, 6, 9))
+    pos = rng.random((3000, 3)) * cfg.extent
+    q = rng.random(3000) - 0.5
+    q -= q.mean()
+    far = pmmm.far_field(pos, q, cfg)
+    nphi, ng = exact.near(pos, q, cfg)
+    dphi, dg = exact.direct(pos, q)
+    e = exact.rel_rms(far.grad + ng, dg)
+    print(f"12x6x9 open mesh, p = 6, c = 2: rel-RMS grad error {e:.2e}")
+    assert e < 1e-5
