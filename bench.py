@@ -184,7 +184,7 @@ def cpu_baseline_child(workload, n_sample):
     from oracle import pmmm as opm
     from paper_1409_5981_amd import inputs
     ps = inputs.make_workload(workload)
-    cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box)
+    cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, shape=ps.shape)
     t0 = time.perf_counter()
     Gt = opm.spectra(opm.green(cfg))
     t_green = time.perf_counter() - t0
@@ -228,7 +228,8 @@ def cpu_baseline_child(workload, n_sample):
         "sample": (f"FP64 oracle (numpy, single thread) on this host ({model}, {ncpu} logical CPUs): "
                    f"binning+P2M and L2P on {ns} randomly sampled particles of the workload "
                    f"({t_p2m:.1f} s + {t_l2p:.1f} s, scaled x{scale:.0f} to N={ps.n}), FFTs + "
-                   f"wave-space M2L + inverse FFTs once on the full {cfg.nf}^3 mesh "
+                   f"wave-space M2L + inverse FFTs once on the full "
+                   f"{'x'.join(str(2 * d if cfg.boundary == 'open' else d) for d in cfg.dims)} mesh "
                    f"({t_mesh:.1f} s); estimated {t_full:.1f} s per far-field call; "
                    f"transfer spectra precomputed ({t_green:.1f} s, not timed)"),
         "stage_seconds": {"p2m_sample": t_p2m, "mesh": t_mesh, "l2p_sample": t_l2p,
@@ -292,6 +293,7 @@ WORKLOADS = {
     "periodic_n32768_m16_p5": ("periodic", "f32"),
     "open_n4096_m8_p4_f64": ("open", "f64"),
     "periodic_n1048576_m32_p7": ("periodic", "f32"),
+    "open_n2097152_m48x40x32_p6": ("open", "f32"),
     "multi_periodic_n1048576_m32_p6_s64": ("periodic", "f32"),
     "batch_periodic_256sys": ("periodic", "f32"),
 }
@@ -355,7 +357,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     x, y, z, q = (torch.from_numpy(a).to(dev) for a in (ps.x, ps.y, ps.z, ps.q))
-    plan = Plan(n, p, boundary, cutoff=2, precision=prec, n_max=N)
+    plan = Plan(n, p, boundary, box=ps.box, cutoff=2, precision=prec, n_max=N, shape=ps.shape)
+    n = plan.n_mesh             # cells per axis of the computed mesh
     tdt = torch.float32 if prec == "f32" else torch.float64
     out = tuple(torch.empty(N, dtype=tdt, device=dev) for _ in range(4))
     # a dedicated stream (the legacy default stream adds implicit synchronisation)
@@ -463,7 +466,9 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": workload, "boundary": boundary, "n_particles": N,
-                   "cells": f"{n}^3", "fft_mesh": f"{nf}^3", "p": p, "cutoff": 2,
+                   "cells": (f"{n}^3" if ps.shape is None else
+                             "x".join(map(str, ps.shape)) + f" (computed in {n}^3)"),
+                   "fft_mesh": f"{nf}^3", "p": p, "cutoff": 2,
                    "tuning": tuning,
                    "parallelism": "single GPU"},
         "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],

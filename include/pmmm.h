@@ -2,8 +2,8 @@
  * pmmm.h -- C ABI of the MI355X (gfx950) PMMM far-field library.
  *
  * Particle mesh multipole method (Nitadori, arXiv:1409.5981).  Given N
- * particles with positions r_i and charges q_i in a box cut into K = n^3
- * uniform cubic cells, the library returns the FAR-FIELD potential
+ * particles with positions r_i and charges q_i in a box cut into
+ * K = nx ny nz uniform cubic cells, the library returns the FAR-FIELD potential
  *     Phi_i = sum over particles j outside the (2c+1)^3 cells around i of
  *             q_j / |r_i - r_j|      (periodic: over all images, Ewald sense)
  * and its gradient grad Phi_i, in the caller's input order (problem statement
@@ -36,8 +36,9 @@
  * below; pmmm_error_string() names a code and pmmm_last_error() returns the
  * last message recorded by the calling thread.  Argument errors are
  * detected on the host before anything is enqueued.  Open-boundary particles
- * outside [0, b)^3 are clamped into the border cells by the kernels and
- * raise a device flag that pmmm_plan_sync_status() reports as PMMM_EDOMAIN.
+ * outside the box [0, b_x) x [0, b_y) x [0, b_z) are clamped into the
+ * border cells of the computed mesh by the kernels and raise a device flag
+ * that pmmm_plan_sync_status() reports as PMMM_EDOMAIN.
  */
 #ifndef PMMM_H
 #define PMMM_H
@@ -68,16 +69,22 @@ typedef struct pmmm_plan_s *pmmm_plan;
 typedef struct pmmm_batch_s *pmmm_batch;
 
 /* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
- *   nx, ny, nz  cells per axis.  The library needs nx == ny == nz == n, a
- *               power of two with n >= 4 and an FFT mesh nf (2n open, n
- *               periodic) of at most 128 (FP32) or 64 (FP64); other meshes
- *               return PMMM_EUNSUPPORTED.
+ *   nx, ny, nz  cells per axis (the mesh may be any product of three
+ *               integers, Sec. 1).  Periodic meshes must be cubic powers of
+ *               two, nx == ny == nz == n >= 4 (other sizes would need
+ *               mixed-radix transforms: PMMM_EUNSUPPORTED).  Open meshes may
+ *               have any nx, ny, nz >= 1: the library computes on the
+ *               smallest power-of-two cube n^3 (n >= 4) of the same cells
+ *               that holds the box at its corner.  The open convolution is
+ *               linear, so the extra cells, which hold no particles, change
+ *               no result; they cost FFT and M2L work.  The FFT mesh nf (2n
+ *               open, n periodic) may be at most 128 (FP32) or 64 (FP64).
  *   box         edge lengths b of the box [0, b_x) x [0, b_y) x [0, b_z);
  *               cells must be cubic (b_a / n_a equal to 1e-12 relative).
  *   p           expansion order, 0 <= p <= PMMM_PMAX ((p+1)^2 coefficients);
  *               at p = 0 the far-field gradient is identically zero.
  *   cutoff      near-cell half width c: 1 (27 cells) or 2 (125 cells); 0 -> 2.
- *               Periodic meshes need n >= 2c + 1, open meshes n >= c + 2.
+ *               Periodic meshes need n >= 2c + 1.
  *   boundary    PMMM_OPEN or PMMM_PERIODIC.
  *   precision   PMMM_F32 (use pmmm_far_f32) or PMMM_F64 (pmmm_far_f64).
  *               PMMM_BF16X3 is an FP32 plan whose multi-charge M2L product
@@ -320,7 +327,10 @@ int pmmm_plan_set_tuning(pmmm_plan plan, const pmmm_tuning *in);
  * of this function; the flag is cleared. */
 int pmmm_plan_sync_status(pmmm_plan plan);
 
-/* Copy an internal mesh to host memory for inspection (synchronises):
+/* Copy an internal mesh to host memory for inspection (synchronises).  n
+ * is the computed mesh (for an open plan of nx x ny x nz cells, the
+ * power-of-two cube holding it; the caller's cells are the corner
+ * [0, nz) x [0, ny) x [0, nx)):
  *   PMMM_MESH_M      moments of the last call, [(p+1)^2][n][n][n] (z, y, x),
  *                    in CELL units (M_l scaled by 1/h^l), plan precision;
  *   PMMM_MESH_L      local expansions of the last call, same layout, in cell

@@ -191,11 +191,16 @@ def _check(rc: int):
 
 def make_params(n: int, p: int, boundary: str, box: float = 1.0, cutoff: int = 2,
                 precision: str = "f32", alpha: float = 0.0, images: int = 0,
-                n_max: int = 0) -> Params:
+                n_max: int = 0, shape=None) -> Params:
+    """n cells per axis and box edge `box`, or with shape = (nx, ny, nz)
+    (open boundary) nx = n cells along the x edge `box` and cubic cells."""
     prm = Params()
-    prm.nx = prm.ny = prm.nz = int(n)
+    dims = (int(n),) * 3 if shape is None else tuple(int(v) for v in shape)
+    if dims[0] != int(n):
+        raise ValueError("shape[0] must equal n")
+    prm.nx, prm.ny, prm.nz = dims
     for a in range(3):
-        prm.box[a] = float(box)
+        prm.box[a] = float(box) * dims[a] / dims[0]
     prm.p = int(p)
     prm.cutoff = int(cutoff)
     prm.boundary = PMMM_OPEN if boundary == "open" else PMMM_PERIODIC
@@ -221,12 +226,22 @@ class Plan:
 
     def __init__(self, n: int, p: int, boundary: str, box: float = 1.0, cutoff: int = 2,
                  precision: str = "f32", alpha: float = 0.0, images: int = 0, n_max: int = 0,
-                 stream=None):
+                 stream=None, shape=None):
         L = load()
-        self.params = make_params(n, p, boundary, box, cutoff, precision, alpha, images, n_max)
+        self.params = make_params(n, p, boundary, box, cutoff, precision, alpha, images, n_max,
+                                  shape)
         self.n, self.p, self.boundary, self.box = n, p, boundary, box
+        self.shape = (n, n, n) if shape is None else tuple(shape)
         self.cutoff, self.precision = cutoff, precision
-        self.nf = 2 * n if boundary == "open" else n
+        # cells per axis of the computed mesh: open meshes sit in the
+        # smallest power-of-two cube (at least 4) that holds them
+        nc = n
+        if boundary == "open":
+            nc = 4
+            while nc < max(self.shape):
+                nc *= 2
+        self.n_mesh = nc
+        self.nf = 2 * nc if boundary == "open" else nc
         self._h = ctypes.c_void_p()
         _check(L.pmmm_plan_create(ctypes.byref(self.params), _stream_handle(stream),
                                   ctypes.byref(self._h)))
@@ -372,7 +387,7 @@ class Plan:
         dt = np.float64 if self.precision == "f64" else np.float32
         buf = np.empty(nbytes // np.dtype(dt).itemsize, dtype=dt)
         _check(L.pmmm_plan_copy_mesh(self._h, which, buf.ctypes.data_as(ctypes.c_void_p), nbytes))
-        P, n, nf = (self.p + 1) ** 2, self.n, self.nf
+        P, n, nf = (self.p + 1) ** 2, self.n_mesh, self.nf
         if which in (PMMM_MESH_M, PMMM_MESH_L):
             return buf.reshape(P, n, n, n)
         Q = (2 * self.p + 1) ** 2

@@ -47,6 +47,7 @@ constexpr int64_t kStagedL2PMinN = int64_t(1) << 18;
 struct Plan {
     pmmm_params prm;
     int n, nf, p, P, Q, open, prec, cutoff, images;
+    int lim[3];               // cells per axis of the caller's box (open: a corner of n^3)
     int64_t K, ncol, ngreen;  // ngreen: stored transfer-kernel values
     double box, h, inv_h, alpha, alpha_cell;
     int device;
@@ -119,6 +120,19 @@ using namespace pmmm;
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Cells per axis of the mesh the library computes on.  A periodic mesh is
+// the caller's (cubic, power of two).  An open mesh of nx x ny x nz cubic
+// cells is computed on the smallest power-of-two cube of the same cells
+// that holds it (at least 4 per axis): the open convolution is linear, so
+// the extra cells, which hold no particles, change no result, and the near
+// cube of every cell is the same.
+static int mesh_cells(const pmmm_params *prm) {
+    if (prm->boundary != PMMM_OPEN) return prm->nx;
+    int n = 4;
+    while (n < prm->nx || n < prm->ny || n < prm->nz) n *= 2;
+    return n;
+}
+
 static int validate(const pmmm_params *prm, std::string &why) {
     if (!prm) {
         why = "params is NULL";
@@ -159,17 +173,15 @@ static int validate(const pmmm_params *prm, std::string &why) {
         why = "alpha, images and n_max must be non-negative";
         return PMMM_EINVAL;
     }
-    const int n = prm->nx;
+    const int n = mesh_cells(prm);
     if (prm->boundary == PMMM_PERIODIC && n < 2 * c + 1) {
         why = "periodic mesh needs n >= 2c + 1";
         return PMMM_EINVAL;
     }
-    if (prm->boundary == PMMM_OPEN && n < c + 2) {
-        why = "open mesh needs n >= c + 2";
-        return PMMM_EINVAL;
-    }
-    if (prm->nx != prm->ny || prm->nx != prm->nz || !is_pow2(n) || n < 4) {
-        why = "the library needs a cubic power-of-two mesh with n >= 4";
+    if (prm->boundary == PMMM_PERIODIC &&
+        (prm->nx != prm->ny || prm->nx != prm->nz || !is_pow2(n) || n < 4)) {
+        why = "periodic meshes must be cubic powers of two with n >= 4 (other sizes need "
+              "mixed-radix transforms)";
         return PMMM_EUNSUPPORTED;
     }
     const int nf = prm->boundary == PMMM_OPEN ? 2 * n : n;
@@ -188,7 +200,10 @@ static int validate(const pmmm_params *prm, std::string &why) {
 
 static void derive(Plan *pl, const pmmm_params *prm) {
     pl->prm = *prm;
-    pl->n = prm->nx;
+    pl->n = mesh_cells(prm);
+    pl->lim[0] = prm->nx;
+    pl->lim[1] = prm->ny;
+    pl->lim[2] = prm->nz;
     pl->open = prm->boundary == PMMM_OPEN;
     pl->nf = pl->open ? 2 * pl->n : pl->n;
     pl->p = prm->p;
@@ -203,7 +218,8 @@ static void derive(Plan *pl, const pmmm_params *prm) {
         const int64_t nh = pl->nf / 2 + 1, nhp = (nh + 3) & ~3;
         pl->ngreen = nh * nh * pl->Q * nhp;
     }
-    pl->box = prm->box[0];
+    // box: edge of the computed cube (the caller's, or its embedding)
+    pl->box = pl->n == prm->nx ? prm->box[0] : prm->box[0] / prm->nx * pl->n;
     pl->h = pl->box / pl->n;
     pl->inv_h = pl->n / pl->box;
     pl->alpha = prm->alpha == 0 ? 1.5 / pl->box : prm->alpha;
@@ -420,6 +436,7 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         b.ncell = pl->n;
         b.inv_h = pl->inv_h;
         b.periodic = !pl->open;
+        for (int a3 = 0; a3 < 3; ++a3) b.lim[a3] = pl->lim[a3];
         b.cell_of = pb.cell_of;
         b.slot = pb.slot;
         b.count = pb.count;
@@ -994,6 +1011,7 @@ static int class_enqueue(pmmm_batch_s *b, BatchClass &c, const float *x, const f
         bn.ncell = pl->n;
         bn.inv_h = pl->inv_h;
         bn.periodic = !pl->open;
+        for (int a3 = 0; a3 < 3; ++a3) bn.lim[a3] = pl->lim[a3];
         bn.cell_of = b->cell_of;
         bn.slot = b->slot;
         bn.count = c.count;

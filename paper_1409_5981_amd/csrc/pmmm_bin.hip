@@ -38,12 +38,12 @@ constexpr int kRadixBuckets = 1 << kRadixMaxBits;
 constexpr int kScanOneBlock = 16384;   // histograms up to this size: one-block scan
 
 template <typename T>
-__device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int periodic, int &ic, T &u,
-                                           int &outside) {
+__device__ __forceinline__ void cell_coord(T v, T inv_h, int n, int lim, int periodic, int &ic,
+                                           T &u, int &outside) {
     T s = v * inv_h;
     if (periodic) {
         s = s - T(n) * floor(s / T(n));
-    } else if (!(s >= T(0) && s < T(n))) {
+    } else if (!(s >= T(0) && s < T(lim))) {
         outside = 1;
     }
     int i = (int)floor(s);
@@ -87,7 +87,7 @@ __global__ void k_rb_reset_items(int nsys, int *__restrict__ small) {
 template <typename T, int R>
 __global__ void __launch_bounds__(1024) k_rb_hist(
     const int64_t *__restrict__ prange, int64_t n, int first, const T *__restrict__ x,
-    const T *__restrict__ y, const T *__restrict__ z, T inv_h, int nc, int periodic,
+    const T *__restrict__ y, const T *__restrict__ z, T inv_h, int nc, int3 lim, int periodic,
     const int *__restrict__ keys, int *__restrict__ hist, int64_t hist_ints, int tiles,
     int shift, int bits, int *__restrict__ flag, int *__restrict__ small) {
     __shared__ int s_hist[kRadixBuckets];
@@ -121,9 +121,9 @@ __global__ void __launch_bounds__(1024) k_rb_hist(
             const int64_t j = (int64_t)t * (1024 * R) + r * 1024 + threadIdx.x;
             int ix, iy, iz;
             T u;
-            cell_coord(xv[r], inv_h, nc, periodic, ix, u, out);
-            cell_coord(yv[r], inv_h, nc, periodic, iy, u, out);
-            cell_coord(zv[r], inv_h, nc, periodic, iz, u, out);
+            cell_coord(xv[r], inv_h, nc, lim.x, periodic, ix, u, out);
+            cell_coord(yv[r], inv_h, nc, lim.y, periodic, iy, u, out);
+            cell_coord(zv[r], inv_h, nc, lim.z, periodic, iz, u, out);
             kv[r] = j < np ? (iz * nc + iy) * nc + ix : -1;
         }
         if (out && np > 0) {
@@ -281,9 +281,9 @@ __global__ void __launch_bounds__(1024) k_rb_scatter(
         if (e < na) {
             if (first) {
                 int ix, iy, iz, out = 0;
-                cell_coord(x[i], inv_h, nc, periodic, ix, rec[r].ux, out);
-                cell_coord(y[i], inv_h, nc, periodic, iy, rec[r].uy, out);
-                cell_coord(z[i], inv_h, nc, periodic, iz, rec[r].uz, out);
+                cell_coord(x[i], inv_h, nc, nc, periodic, ix, rec[r].ux, out);
+                cell_coord(y[i], inv_h, nc, nc, periodic, iy, rec[r].uy, out);
+                cell_coord(z[i], inv_h, nc, nc, periodic, iz, rec[r].uz, out);
                 rec[r].q = q != nullptr ? q[i] : T(0);
                 key[r] = (iz * nc + iy) * nc + ix;
                 val[r] = (int)i;
@@ -481,6 +481,8 @@ static hipError_t radix_bin(const BinArgs &a, int K, int64_t maxn, hipStream_t s
     const int *kin = nullptr, *vin = nullptr;
     const particle4<T> *rin = nullptr;
     int shift = 0;
+    const int3 lim = make_int3(a.lim[0] > 0 ? a.lim[0] : a.ncell, a.lim[1] > 0 ? a.lim[1] : a.ncell,
+                               a.lim[2] > 0 ? a.lim[2] : a.ncell);
     for (int ps = 0; ps < passes; ++ps) {
         const int bits = widths[ps], first = ps == 0, last = ps == passes - 1;
         // alternate so that the last pass lands in (scell, perm, sorted)
@@ -489,7 +491,7 @@ static hipError_t radix_bin(const BinArgs &a, int K, int64_t maxn, hipStream_t s
         particle4<T> *ro = to_final ? rF : rA;
         hipLaunchKernelGGL((k_rb_hist<T, R>), dim3(tiles, nsys), dim3(1024), 0, s, a.prange, a.n,
                            first, (const T *)a.x, (const T *)a.y, (const T *)a.z, inv_h, a.ncell,
-                           a.periodic, kin, a.count, hist_ints, tiles, shift, bits, a.flag,
+                           lim, a.periodic, kin, a.count, hist_ints, tiles, shift, bits, a.flag,
                            a.small);
         const int64_t L = (int64_t)(1 << bits) * tiles;
         if (L <= kScanOneBlock) {

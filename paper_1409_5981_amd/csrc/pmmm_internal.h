@@ -574,6 +574,10 @@ struct BinArgs {
     int ncell;         // cells per axis
     double inv_h;      // n / b
     int periodic;
+    // open boundary: cells per axis (x, y, z) of the caller's box, which may
+    // be a corner of the ncell^3 mesh; a particle beyond it sets flag
+    // (0: ncell)
+    int lim[3] = {0, 0, 0};
     // [n] key/value/record ping-pong arrays of the radix sort; the sorted
     // cell, the permutation (caller index of every sorted slot) and the
     // sorted records end in scell, perm, sorted

@@ -26,6 +26,7 @@ __all__ = [
     "periodic_pm1",
     "periodic_pm1_blocks",
     "plummer_sphere",
+    "uniform_open_shape",
     "paper_accuracy_set",
     "batched_systems",
     "multi_charge_sets",
@@ -48,6 +49,7 @@ class ParticleSet:
     boundary: str  # "open" or "periodic"
     box: float = 1.0
     cutoff: int = 2
+    shape: tuple | None = None   # open: (nx, ny, nz) cells, n_cells = nx, box = x edge
 
     @property
     def n(self) -> int:
@@ -146,6 +148,22 @@ def plummer_sphere(n=1 << 22, n_cells=64, p=6, seed=4, scale=0.05,
                        n_cells, p, "open")
 
 
+def uniform_open_shape(n=1 << 21, dims=(48, 40, 32), p=6, edge=1.0 / 64, seed=8,
+                       dtype=np.float32) -> ParticleSet:
+    """Open box of dims cubic cells of edge ``edge`` (not a cube, not powers
+    of two), ``n`` uniform particles with neutral +/-1 charges.  Positions
+    are drawn in float64 and rounded to ``dtype``; a rounding that reaches
+    the box edge is moved one step inside."""
+    rng = _rng(seed)
+    ext = np.asarray(dims, dtype=np.float64) * edge
+    pos = (rng.random((n, 3)) * ext).astype(dtype)
+    top = ext.astype(dtype)
+    pos = np.where(pos >= top, np.nextafter(top, dtype(0)), pos)
+    q = neutral_pm1(rng, n, dtype)
+    return ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, int(dims[0]), p,
+                       "open", box=float(dims[0] * edge), shape=tuple(int(d) for d in dims))
+
+
 def paper_accuracy_set(n=16384, n_cells=8, p=4, boundary="open", cutoff=2,
                        seed=7, dtype=np.float64) -> ParticleSet:
     """The paper's accuracy-test recipe (Sec. 4): N uniform particles in a
@@ -195,6 +213,9 @@ WORKLOADS = {
                                  "periodic, N=2^20 uniform, neutral +/-1, 32^3 cells, p=7, FP32"),
     "open_plummer_n4194304_m64_p6": (plummer_sphere,
                                      "open, N=2^22 Plummer a=0.05, 64^3 cells (128^3 padded FFT), p=6, FP32"),
+    "open_n2097152_m48x40x32_p6": (uniform_open_shape,
+                                   "open, N=2^21 uniform, neutral +/-1, 48x40x32 cells of edge 1/64 "
+                                   "(computed in the 64^3 cube, 128^3 padded FFT), p=6, FP32"),
 }
 
 

@@ -31,6 +31,7 @@ JOBS = {
     "open_n4096_m8_p4_f64": inputs.open_equal_mass,
     "periodic_n1048576_m32_p7": inputs.periodic_pm1_blocks,
     "open_plummer_n4194304_m64_p6": inputs.plummer_sphere,
+    "open_n2097152_m48x40x32_p6": inputs.uniform_open_shape,
 }
 
 
@@ -113,7 +114,8 @@ def make(name: str) -> str:
         return make_direct(name)
     t0 = time.time()
     ps = JOBS[name]()
-    cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=2)
+    cfg = opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=2,
+                     shape=ps.shape)
     rng = np.random.Generator(np.random.PCG64(1234))
     idx = np.sort(rng.choice(ps.n, size=min(SAMPLE, ps.n), replace=False))
     res = opm.far_field(ps.pos, ps.q.astype(np.float64), cfg, eval_idx=idx)

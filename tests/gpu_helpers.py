@@ -16,7 +16,8 @@ def gpu_far(ps, precision="f32", cutoff=2, near=False, plan=None, alpha=0.0, ima
     npdt = np.float32 if precision == "f32" else np.float64
     if plan is None:
         plan = Plan(ps.n_cells, ps.p, ps.boundary, box=ps.box, cutoff=cutoff,
-                    precision=precision, alpha=alpha, images=images)
+                    precision=precision, alpha=alpha, images=images,
+                    shape=getattr(ps, "shape", None))
     dev = "cuda"
     x, y, z, q = (torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).to(dev)
                   for a in (ps.x, ps.y, ps.z, ps.q))

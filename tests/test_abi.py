@@ -50,6 +50,14 @@ def test_parameter_validation_on_host(lib):
     prm = make_params(8, 3, "open")
     prm.box[1] = 2.0                                                              # non-cubic cells
     assert workspace_bytes(prm, 10) == 0
+    # open meshes of any nx x ny x nz cubic cells sit in a power-of-two cube
+    assert workspace_bytes(make_params(12, 6, "open", shape=(12, 6, 9)), 10) > 0
+    assert workspace_bytes(make_params(3, 2, "open", box=0.75, shape=(3, 4, 5)), 10) > 0
+    assert workspace_bytes(make_params(33, 3, "open", shape=(33, 20, 17)), 10) > 0   # in 64^3
+    assert workspace_bytes(make_params(65, 3, "open", shape=(65, 3, 3)), 10) == 0    # 128^3: nf > 128
+    assert workspace_bytes(make_params(24, 3, "open", precision="f64"), 10) > 0     # in 32^3
+    assert workspace_bytes(make_params(8, 3, "periodic", shape=(8, 8, 4)), 10) == 0 # periodic: cubic
+    assert workspace_bytes(make_params(24, 3, "periodic"), 10) == 0                 # periodic: 2^k
 
 
 def test_workspace_grows_with_particles(lib):

@@ -1,0 +1,108 @@
+"""GPU parity on open meshes of nx x ny x nz cubic cells (any product of
+three integers, Sec. 1).  The library computes them on the power-of-two cube
+of the same cells that holds the box; the oracle computes them natively on
+the caller's mesh (App. C padding per axis), so these tests check both the
+kernels and the embedding.  Bounds: gpu_helpers.BOUNDS."""
+import numpy as np
+import pytest
+
+from gpu_helpers import assert_parity
+from oracle import exact
+from oracle import pmmm as opm
+from paper_1409_5981_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _set(dims, n, seed, dtype, clustered=False):
+    """n particles in the box of dims cubic cells, neutral +-1 charges;
+    clustered: half of them in a ball around one point.  The cell edge is a
+    power of two (the embedding cube has edge 1), so that r / h is exact in
+    FP32 and FP64 alike and both sides put every particle in the same cell."""
+    rng = np.random.default_rng(seed)
+    nc = 4
+    while nc < max(dims):
+        nc *= 2
+    box = dims[0] / nc
+    ext = np.asarray(dims, dtype=np.float64) / nc
+    pos = rng.random((n, 3)) * ext
+    if clustered:
+        k = n // 2
+        pos[:k] = 0.3 * ext + 0.05 * ext.min() * (rng.random((k, 3)) - 0.5)
+    q = inputs.neutral_pm1(rng, n, dtype)
+    return pos.astype(dtype), q, box
+
+
+def _gpu(pos, q, dims, p, box, precision, cutoff, mode="far"):
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    plan = Plan(dims[0], p, "open", box=box, cutoff=cutoff, precision=precision, shape=dims)
+    x, y, z = (torch.from_numpy(np.ascontiguousarray(pos[:, a])).to("cuda") for a in range(3))
+    qt = torch.from_numpy(np.ascontiguousarray(q)).to("cuda")
+    phi, gx, gy, gz = getattr(plan, mode)(x, y, z, qt)
+    torch.cuda.synchronize()
+    from paper_1409_5981_amd._lib import PMMMError
+    try:
+        plan.sync_status()
+        st = 0
+    except PMMMError as e:
+        st = e.code
+    return ({"phi": phi.double().cpu().numpy(),
+             "grad": torch.stack([gx, gy, gz], dim=1).double().cpu().numpy()}, plan, st)
+
+
+@pytest.mark.parametrize("dims,p,precision,cutoff,n", [
+    ((12, 6, 9), 6, "f32", 2, 3000),        # in 16^3
+    ((5, 8, 3), 4, "f64", 1, 1500),         # in 8^3
+    ((24, 24, 24), 5, "f32", 2, 8000),      # non-power-of-two cube, in 32^3
+    ((33, 20, 17), 3, "f32", 2, 6000),      # in 64^3: the 128-point transforms
+    ((1, 1, 1), 2, "f32", 1, 50),           # every cell is near: the far field is zero
+])
+def test_open_mesh_shapes_match_oracle(dims, p, precision, cutoff, n):
+    dt = np.float32 if precision == "f32" else np.float64
+    print(f"shape {dims} p={p} {precision} c={cutoff} n={n}", flush=True)
+    pos, q, box = _set(dims, n, sum(dims) + p, dt)
+    cfg = opm.Config(n=dims[0], p=p, boundary="open", box=box, cutoff=cutoff, shape=dims)
+    ref = opm.far_field(pos.astype(np.float64), q.astype(np.float64), cfg)
+    res, _, st = _gpu(pos, q, dims, p, box, precision, cutoff)
+    assert st == 0
+    if dims == (1, 1, 1):
+        # only FFT round-off of an all-masked convolution is left
+        scale = np.abs(q).sum() / (box / dims[0])
+        assert np.abs(res["phi"]).max() < 1e-6 * scale and np.abs(res["grad"]).max() < 1e-6 * scale
+        assert np.all(ref.phi == 0) and np.all(ref.grad == 0)
+        return
+    assert_parity(res, ref.phi, ref.grad, precision, f"open {dims} p={p}")
+
+
+def test_open_mesh_shape_clustered_total_field():
+    """Total field (far + near, one binning) on a 10 x 14 x 7 mesh with half
+    the particles in one cluster: against the oracle's far field plus its
+    brute-force near field, and within the method error of the direct sum."""
+    dims, p = (10, 14, 7), 5
+    pos, q, box = _set(dims, 4000, 7, np.float32, clustered=True)
+    cfg = opm.Config(n=dims[0], p=p, boundary="open", box=box, cutoff=2, shape=dims)
+    p64, q64 = pos.astype(np.float64), q.astype(np.float64)
+    far = opm.far_field(p64, q64, cfg)
+    nphi, ng = exact.near(p64, q64, cfg)
+    res, _, st = _gpu(pos, q, dims, p, box, "f32", 2, mode="total")
+    assert st == 0
+    assert_parity(res, far.phi + nphi, far.grad + ng, "f32", f"total {dims}")
+    dphi, dg = exact.direct(p64, q64)
+    e = exact.rel_rms(res["grad"], dg)
+    print(f"total field vs direct sum: rel-RMS grad {e:.2e}", flush=True)
+    assert e < 1e-4
+
+
+def test_particle_outside_the_caller_box_is_flagged():
+    """A particle inside the power-of-two cube but beyond the caller's ny
+    cells is outside the box: PMMM_EDOMAIN, as for any open plan."""
+    from paper_1409_5981_amd._lib import PMMM_EDOMAIN
+    dims = (12, 6, 9)
+    pos, q, box = _set(dims, 500, 3, np.float32)
+    h = box / dims[0]
+    _, _, st = _gpu(pos, q, dims, 3, box, "f32", 2)
+    assert st == 0
+    pos[17, 1] = np.float32(6.5 * h)           # y beyond 6 cells, inside the 16^3 cube
+    _, _, st = _gpu(pos, q, dims, 3, box, "f32", 2)
+    assert st == PMMM_EDOMAIN
