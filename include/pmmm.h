@@ -70,9 +70,11 @@ typedef struct pmmm_batch_s *pmmm_batch;
 
 /* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
  *   nx, ny, nz  cells per axis (the mesh may be any product of three
- *               integers, Sec. 1).  Periodic meshes must be cubic powers of
- *               two, nx == ny == nz == n >= 4 (other sizes would need
- *               mixed-radix transforms: PMMM_EUNSUPPORTED).  Open meshes may
+ *               integers, Sec. 1).  Periodic meshes must be cubic,
+ *               nx == ny == nz == n >= 2c + 1; a power-of-two n runs the
+ *               radix-2 transforms, any other n <= 64 runs direct DFTs along
+ *               each axis (same results up to rounding; batches and the
+ *               multi-charge call take powers of two only).  Open meshes may
  *               have any nx, ny, nz >= 1: the library computes on the
  *               smallest power-of-two cube n^3 (n >= 4) of the same cells
  *               that holds the box at its corner.  The open convolution is

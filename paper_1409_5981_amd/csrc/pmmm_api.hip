@@ -48,6 +48,8 @@ struct Plan {
     pmmm_params prm;
     int n, nf, p, P, Q, open, prec, cutoff, images;
     int lim[3];               // cells per axis of the caller's box (open: a corner of n^3)
+    int generic;              // periodic n not a power of two: direct-DFT stages
+    void *spec2 = nullptr;    // generic: M2L output spectra
     int64_t K, ncol, ngreen;  // ngreen: stored transfer-kernel values
     double box, h, inv_h, alpha, alpha_cell;
     int device;
@@ -178,10 +180,12 @@ static int validate(const pmmm_params *prm, std::string &why) {
         why = "periodic mesh needs n >= 2c + 1";
         return PMMM_EINVAL;
     }
-    if (prm->boundary == PMMM_PERIODIC &&
-        (prm->nx != prm->ny || prm->nx != prm->nz || !is_pow2(n) || n < 4)) {
-        why = "periodic meshes must be cubic powers of two with n >= 4 (other sizes need "
-              "mixed-radix transforms)";
+    if (prm->boundary == PMMM_PERIODIC && (prm->nx != prm->ny || prm->nx != prm->nz)) {
+        why = "periodic meshes must be cubic";
+        return PMMM_EUNSUPPORTED;
+    }
+    if (prm->boundary == PMMM_PERIODIC && !is_pow2(n) && n > kGenericMaxN) {
+        why = "periodic meshes whose edge is not a power of two are limited to 64 cells per axis";
         return PMMM_EUNSUPPORTED;
     }
     const int nf = prm->boundary == PMMM_OPEN ? 2 * n : n;
@@ -191,7 +195,7 @@ static int validate(const pmmm_params *prm, std::string &why) {
         return PMMM_EUNSUPPORTED;
     }
     // the column kernel keeps at least one column's spectra in LDS (160 KB per CU)
-    if (column_default_kernel(prm->p, nf, prm->precision == PMMM_F64 ? 8 : 4) == 0) {
+    if (is_pow2(n) && column_default_kernel(prm->p, nf, prm->precision == PMMM_F64 ? 8 : 4) == 0) {
         why = "order too high for this FFT mesh: one column's spectra exceed 160 KB of LDS";
         return PMMM_EUNSUPPORTED;
     }
@@ -204,6 +208,7 @@ static void derive(Plan *pl, const pmmm_params *prm) {
     pl->lim[0] = prm->nx;
     pl->lim[1] = prm->ny;
     pl->lim[2] = prm->nz;
+    pl->generic = !is_pow2(pl->n);
     pl->open = prm->boundary == PMMM_OPEN;
     pl->nf = pl->open ? 2 * pl->n : pl->n;
     pl->p = prm->p;
@@ -231,7 +236,8 @@ static size_t plan_bytes(const Plan *pl) {
     const size_t t = pl->tsize, c = 2 * t;
     size_t b = 0;
     b += (size_t)pl->ngreen * t;                         // green
-    b += (size_t)(pl->nf / 2) * c;                       // twiddles
+    b += (size_t)(pl->generic ? pl->nf : pl->nf / 2) * c; // twiddles
+    if (pl->generic) b += (size_t)pl->P * pl->n * pl->ncol * c;  // M2L output spectra
     b += (size_t)(pl->P + 1) * pl->K * t;                // M
     b += (size_t)pl->P * pl->n * pl->ncol * c;           // spectra
     b += (size_t)pl->P * pl->K * t;                      // L
@@ -302,6 +308,7 @@ static void destroy(Plan *pl) {
     hipFree(pl->tw);
     hipFree(pl->M);
     hipFree(pl->spec);
+    hipFree(pl->spec2);
     hipFree(pl->L);
     hipFree(pl->start);
     hipFree(pl->small);
@@ -322,14 +329,16 @@ static void destroy(Plan *pl) {
     delete static_cast<pmmm_plan_s *>(pl);
 }
 
+// Radix-2 twiddles e^(-2 pi i k / nf), k < nf/2; a generic plan keeps all nf
+// roots of unity for its direct DFTs.
 template <typename T>
 static int make_twiddles(Plan *pl, hipStream_t s) {
-    const int nf = pl->nf;
-    std::vector<cplx<T>> tw(nf / 2);
-    for (int k = 0; k < nf / 2; ++k)
+    const int nf = pl->nf, cnt = pl->generic ? nf : nf / 2;
+    std::vector<cplx<T>> tw(cnt);
+    for (int k = 0; k < cnt; ++k)
         tw[k] = {T(std::cos(2.0 * M_PI * k / nf)), T(-std::sin(2.0 * M_PI * k / nf))};
-    PMMM_HIP(hipMalloc(&pl->tw, sizeof(cplx<T>) * (nf / 2)));
-    PMMM_HIP(hipMemcpyAsync(pl->tw, tw.data(), sizeof(cplx<T>) * (nf / 2), hipMemcpyHostToDevice, s));
+    PMMM_HIP(hipMalloc(&pl->tw, sizeof(cplx<T>) * cnt));
+    PMMM_HIP(hipMemcpyAsync(pl->tw, tw.data(), sizeof(cplx<T>) * cnt, hipMemcpyHostToDevice, s));
     return PMMM_OK;
 }
 
@@ -338,6 +347,7 @@ static int alloc_plan(Plan *pl, hipStream_t s) {
     PMMM_HIP(hipMalloc(&pl->green, (size_t)pl->ngreen * t));
     PMMM_HIP(hipMalloc(&pl->M, (size_t)(pl->P + 1) * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
+    if (pl->generic) PMMM_HIP(hipMalloc(&pl->spec2, (size_t)pl->P * pl->n * pl->ncol * c));
     PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
     // [0] dense items, [1] domain flag, [2] near tiles, [3] partial slots
@@ -487,6 +497,8 @@ static int call_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, cons
         f.sums = pl->sums;
         f.col_w = pl->tune_col_w;
         f.col_kernel = pl->tune_col_kernel;
+        f.generic = pl->generic;
+        f.spec2 = pl->spec2;
         for (int st = 0; st < 3; ++st) {
             StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s, timed);
             PMMM_HIP(launch_conv_stage<T>(f, st, s));
@@ -802,7 +814,9 @@ static int autotune_impl(pmmm_plan_s *pl, int64_t n, const T *x, const T *y, con
                          const T *q, T *phi, T *gx, T *gy, T *gz, hipStream_t s) {
     // column candidates: (form, width)
     std::vector<std::pair<int, int>> cand;
-    {
+    if (pl->generic) {
+        cand.push_back({0, 0});     // one M2L kernel, no forms to choose from
+    } else {
         int wmax = 1, rs = 1;
         if (column_shape(pl->p, pl->nf, pl->tsize, &wmax, &rs) > 0) {
             cand.push_back({PMMM_COLUMN_TILE, wmax});
@@ -1362,6 +1376,11 @@ int pmmm_batch_create(int nsys, const pmmm_params *per_sys, void *stream, pmmm_b
         if (per_sys[i].precision == PMMM_F64) {
             set_error("batches run the FP32 pipeline (PMMM_F32 or PMMM_BF16X3 systems)");
             return PMMM_EINVAL;
+        }
+        if (per_sys[i].boundary == PMMM_PERIODIC && !is_pow2(per_sys[i].nx)) {
+            set_error("system " + std::to_string(i) +
+                      ": batches take periodic meshes of power-of-two edge only");
+            return PMMM_EUNSUPPORTED;
         }
     }
     hipStream_t s = (hipStream_t)stream;

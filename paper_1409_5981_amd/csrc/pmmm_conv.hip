@@ -535,6 +535,7 @@ static PlaneShape plane_shape(int n, int nf, int P, int nsys, size_t csz) {
 
 template <typename T>
 hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s) {
+    if (a.generic) return launch_generic_stage<T>(a, stage, s);
     const int P = nreal(a.p);
     const int nf = a.nf, logn = ilog2(nf), nh = nf / 2 + 1, n = a.n;
     const int nsys = a.nsys > 0 ? a.nsys : 1;

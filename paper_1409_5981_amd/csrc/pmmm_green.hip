@@ -313,8 +313,12 @@ hipError_t build_green(const GreenArgs &a, hipStream_t s) {
         hipFree(G);
         return e;
     }
-    std::vector<cplx<double>> twh(nf / 2 > 0 ? nf / 2 : 1);
-    for (int k = 0; k < nf / 2; ++k)
+    // power-of-two nf: the nf/2 twiddles of the radix-2 transform; any
+    // other nf: the nf roots of unity of the direct DFT
+    const bool pow2 = (nf & (nf - 1)) == 0;
+    const int ntw = pow2 ? (nf / 2 > 0 ? nf / 2 : 1) : nf;
+    std::vector<cplx<double>> twh(ntw);
+    for (int k = 0; k < ntw; ++k)
         twh[k] = {std::cos(2.0 * M_PI * k / nf), -std::sin(2.0 * M_PI * k / nf)};
     e = hipMalloc(&tw, sizeof(cplx<double>) * twh.size());
     if (e == hipSuccess)
@@ -358,15 +362,19 @@ hipError_t build_green(const GreenArgs &a, hipStream_t s) {
         const int64_t cnt = (int64_t)jc * npts;
         hipLaunchKernelGGL(k_to_complex, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                            cnt, G + (int64_t)j0 * npts, Gc);
-        for (int axis = 0; axis < 3; ++axis) {
+        for (int axis = 0; axis < 3 && e == hipSuccess; ++axis) {
             const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nf : (int64_t)nf * nf);
             const int64_t nlines = (int64_t)jc * nf * nf;
-            hipLaunchKernelGGL(k_line_fft, dim3((unsigned)((nlines + lpb - 1) / lpb)), dim3(64),
-                               lds, s, Gc, logn, nlines, stride, lpb, tw);
+            if (pow2)
+                hipLaunchKernelGGL(k_line_fft, dim3((unsigned)((nlines + lpb - 1) / lpb)),
+                                   dim3(64), lds, s, Gc, logn, nlines, stride, lpb, tw);
+            else
+                e = launch_line_dft_f64(Gc, nf, nlines, stride, tw, s);
         }
         const int nhp = ((nf / 2 + 1) + 3) & ~3;
         const int64_t tot = (int64_t)(nf / 2 + 1) * (nf / 2 + 1) * jc * nhp;
         const double shift = a.open ? 0.0 : -2.0 * a.alpha_cell / std::sqrt(M_PI);
+        if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_fold<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nf, Q,
                            j0, jc, Gc, shift, (T *)a.green_out);
         e = hipGetLastError();

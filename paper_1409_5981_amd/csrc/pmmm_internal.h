@@ -676,10 +676,22 @@ struct FFTArgs {
     int nsys;                       // batch of systems at fixed strides (1: one)
     int col_w;                      // columns per column-kernel block (0: largest that fits)
     int col_kernel;                 // PMMM_COLUMN_* form (0: column_default_kernel)
+    // periodic n not a power of two: direct DFTs, tw = cplx<T>[n] roots of
+    // unity e^(-2 pi i m / n), and the M2L output in spec2 (same size as spec)
+    int generic;
+    void *spec2;
 };
 // stage 0: forward plane FFTs, 1: column FFT + M2L + inverse, 2: inverse planes
 template <typename T>
 hipError_t launch_conv_stage(const FFTArgs &a, int stage, hipStream_t s);
+// The same three stages for a generic periodic mesh (n <= kGenericMaxN).
+constexpr int kGenericMaxN = 64;
+template <typename T>
+hipError_t launch_generic_stage(const FFTArgs &a, int stage, hipStream_t s);
+// In-place forward FP64 DFT of nlines lines of n points; line L starts at
+// (L / stride) * stride * n + (L % stride) and steps by stride (any n).
+hipError_t launch_line_dft_f64(cplx<double> *data, int n, int64_t nlines, int64_t stride,
+                               const cplx<double> *w, hipStream_t s);
 
 struct L2PArgs {
     int64_t n;

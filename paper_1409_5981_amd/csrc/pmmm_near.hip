@@ -78,7 +78,17 @@ struct NearSrc {
     T ux, yz[2], q;
 };
 
-template <typename T>
+// Cell-index arithmetic on rows of n cells: shifts for power-of-two n (POW2),
+// divisions otherwise.
+template <bool POW2>
+struct RowIdx {
+    int n, logn;
+    __device__ __forceinline__ int mul(int v) const { return POW2 ? v << logn : v * n; }
+    __device__ __forceinline__ int div(int v) const { return POW2 ? v >> logn : v / n; }  // v >= 0
+    __device__ __forceinline__ int mod(int v) const { return POW2 ? v & (n - 1) : v % n; }  // v >= 0
+};
+
+template <typename T, bool POW2>
 __global__ void __launch_bounds__(kNearTile) k_near(int n, int logn, int cutoff, int periodic,
                                                     const int *__restrict__ start,
                                                     const int *__restrict__ scell,
@@ -92,17 +102,18 @@ __global__ void __launch_bounds__(kNearTile) k_near(int n, int logn, int cutoff,
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
     if (t >= ntiles[0]) return;  // the whole (one-wave) block leaves
+    const RowIdx<POW2> ri{n, logn};
     const int r = tile_row[t];
-    const int row0 = start[r << logn], row1 = start[(r + 1) << logn];
+    const int row0 = start[ri.mul(r)], row1 = start[ri.mul(r + 1)];
     const int s0 = row0 + (t - tile_first[r]) * kNearTile;
     const int s1 = min(s0 + kNearTile, row1);
     const int s = s0 + lane;
     const bool live = s < s1;
     const int sc = live ? s : s1 - 1;
     const particle4<T> me = sorted[sc];
-    const int tx = scell[sc] & (n - 1);
-    const int xa = scell[s0] & (n - 1), xb = scell[s1 - 1] & (n - 1);  // sorted: xa <= xb
-    const int iz = r >> logn, iy = r & (n - 1);
+    const int tx = ri.mod(scell[sc]);
+    const int xa = ri.mod(scell[s0]), xb = ri.mod(scell[s1 - 1]);  // sorted: xa <= xb
+    const int iz = ri.div(r), iy = ri.mod(r);
     const int c = cutoff;
     // each chunk of at most 64 sources is summed in T, the chunk sums in FP64:
     // a target meets ~10^3 sources, and one long FP32 running sum would lose
@@ -112,15 +123,15 @@ __global__ void __launch_bounds__(kNearTile) k_near(int n, int logn, int cutoff,
         int jz = iz + dz;
         if (jz < 0 || jz >= n) {
             if (!periodic) continue;
-            jz &= n - 1;
+            jz += jz < 0 ? n : -n;      // |dz| <= c < n
         }
         for (int dy = -c; dy <= c; ++dy) {
             int jy = iy + dy;
             if (jy < 0 || jy >= n) {
                 if (!periodic) continue;
-                jy &= n - 1;
+                jy += jy < 0 ? n : -n;
             }
-            const int jrow = (jz << logn) | jy;
+            const int jrow = ri.mul(jz) + jy;
             // unwrapped x range of the sources, in pieces that do not wrap
             int lo = xa - c, hi = xb + c;
             if (!periodic) {
@@ -129,16 +140,16 @@ __global__ void __launch_bounds__(kNearTile) k_near(int n, int logn, int cutoff,
             }
             for (int u0 = lo; u0 <= hi;) {
                 // image shift of the piece holding u0: floor(u0 / n) n
-                const int shift = (u0 >= 0 ? (u0 >> logn) : -((n - 1 - u0) >> logn)) << logn;
+                const int shift = ri.mul(u0 >= 0 ? ri.div(u0) : -ri.div(n - 1 - u0));
                 const int x0 = u0 - shift;
                 const int x1 = hi - shift < n - 1 ? hi - shift : n - 1;
-                const int b0 = start[(jrow << logn) + x0], b1 = start[(jrow << logn) + x1 + 1];
+                const int b0 = start[ri.mul(jrow) + x0], b1 = start[ri.mul(jrow) + x1 + 1];
                 for (int c0 = b0; c0 < b1; c0 += kNearTile) {
                     const int cnt = b1 - c0 < kNearTile ? b1 - c0 : kNearTile;
                     {
                         const int js = c0 + lane < b1 ? c0 + lane : b1 - 1;
                         const particle4<T> so = sorted[js];
-                        const int sxu = (scell[js] & (n - 1)) + shift;
+                        const int sxu = ri.mod(scell[js]) + shift;
                         __syncthreads();  // the previous chunk has been read
                         // target - source displacement in y and z is
                         // (u_t - u_s) - (row offset): keep u_s + offset
@@ -201,14 +212,21 @@ template <typename T>
 hipError_t launch_near(const NearArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (a.ncell * a.ncell > 1024 * kNearRowsPerThread) return hipErrorInvalidValue;
+    const bool pow2 = (a.ncell & (a.ncell - 1)) == 0;
     const int logn = __builtin_ctz((unsigned)a.ncell);
     hipLaunchKernelGGL(k_near_tiles, dim3(1), dim3(1024), 0, s, a.ncell, a.start, a.tile_first,
                        a.tile_row, a.ntiles);
     const int64_t max_tiles = (a.n + kNearTile - 1) / kNearTile + (int64_t)a.ncell * a.ncell;
-    hipLaunchKernelGGL(k_near<T>, dim3((unsigned)max_tiles), dim3(kNearTile), 0, s, a.ncell, logn,
-                       a.cutoff, a.periodic, a.start, a.scell, (const particle4<T> *)a.sorted,
-                       a.tile_first, a.tile_row, a.ntiles, T(a.inv_h), (out4<T> *)a.staged,
-                       a.accumulate);
+    if (pow2)
+        hipLaunchKernelGGL((k_near<T, true>), dim3((unsigned)max_tiles), dim3(kNearTile), 0, s,
+                           a.ncell, logn, a.cutoff, a.periodic, a.start, a.scell,
+                           (const particle4<T> *)a.sorted, a.tile_first, a.tile_row, a.ntiles,
+                           T(a.inv_h), (out4<T> *)a.staged, a.accumulate);
+    else
+        hipLaunchKernelGGL((k_near<T, false>), dim3((unsigned)max_tiles), dim3(kNearTile), 0, s,
+                           a.ncell, logn, a.cutoff, a.periodic, a.start, a.scell,
+                           (const particle4<T> *)a.sorted, a.tile_first, a.tile_row, a.ntiles,
+                           T(a.inv_h), (out4<T> *)a.staged, a.accumulate);
     return hipGetLastError();
 }
 

@@ -44,7 +44,9 @@ def test_parameter_validation_on_host(lib):
     assert workspace_bytes(make_params(8, 10, "open"), 10) > 0                     # p = PMAX
     assert workspace_bytes(make_params(16, 9, "periodic"), 10) > 0
     assert workspace_bytes(make_params(64, 10, "open"), 10) > 0                    # streamed column kernel
-    assert workspace_bytes(make_params(12, 3, "periodic"), 10) == 0                # not 2^k
+    assert workspace_bytes(make_params(12, 3, "periodic"), 10) > 0                 # direct DFTs
+    assert workspace_bytes(make_params(9, 5, "periodic", cutoff=2), 10) > 0        # odd edge
+    assert workspace_bytes(make_params(65, 3, "periodic"), 10) == 0                # > 64, not 2^k
     assert workspace_bytes(make_params(128, 3, "open"), 10) == 0                   # nf > 128
     assert workspace_bytes(make_params(64, 3, "open", precision="f64"), 10) == 0   # nf > 64 (FP64)
     prm = make_params(8, 3, "open")
@@ -57,7 +59,7 @@ def test_parameter_validation_on_host(lib):
     assert workspace_bytes(make_params(65, 3, "open", shape=(65, 3, 3)), 10) == 0    # 128^3: nf > 128
     assert workspace_bytes(make_params(24, 3, "open", precision="f64"), 10) > 0     # in 32^3
     assert workspace_bytes(make_params(8, 3, "periodic", shape=(8, 8, 4)), 10) == 0 # periodic: cubic
-    assert workspace_bytes(make_params(24, 3, "periodic"), 10) == 0                 # periodic: 2^k
+    assert workspace_bytes(make_params(24, 3, "periodic"), 10) > 0                  # direct DFTs
 
 
 def test_workspace_grows_with_particles(lib):
@@ -147,3 +149,14 @@ def test_coefficient_storage_calls_validate_on_host(lib):
     assert lib.pmmm_coef_split_f32(12, 4, dummy, dummy, dummy, None) == EINVAL
     assert lib.pmmm_coef_split_f32(3, 4, dummy, None, dummy, None) == EINVAL
     assert lib.pmmm_coef_compose_f32(3, 0, None, None, None, None) == 0         # empty: nothing to do
+
+
+def test_batch_refuses_non_power_of_two_periodic_systems(lib):
+    """Batches run the radix-2 stage kernels only: a periodic system whose
+    edge is not a power of two is refused on the host (no GPU call)."""
+    import ctypes
+    from paper_1409_5981_amd._lib import Params, make_params
+    arr = (Params * 2)(make_params(16, 4, "periodic"), make_params(12, 4, "periodic"))
+    out = ctypes.c_void_p()
+    assert lib.pmmm_batch_create(2, arr, None, ctypes.byref(out)) == 5      # PMMM_EUNSUPPORTED
+    assert b"power-of-two" in lib.pmmm_last_error()

@@ -106,3 +106,80 @@ def test_particle_outside_the_caller_box_is_flagged():
     pos[17, 1] = np.float32(6.5 * h)           # y beyond 6 cells, inside the 16^3 cube
     _, _, st = _gpu(pos, q, dims, 3, box, "f32", 2)
     assert st == PMMM_EDOMAIN
+
+
+# ------------------------------------------- periodic meshes of any edge n
+def _pset(n, N, seed, dtype, charged=False):
+    """N uniform particles in a periodic box of n^3 cells whose edge h is a
+    power of two (FP32 and FP64 give every particle the same cell)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0
+    while h * n > 1.0:
+        h /= 2
+    box = n * h
+    pos = (rng.random((N, 3)) * box).astype(dtype)
+    pos = np.where(pos >= dtype(box), np.nextafter(dtype(box), dtype(0)), pos)
+    q = inputs.neutral_pm1(rng, N, dtype)
+    if charged:
+        q = (q + dtype(0.25)).astype(dtype)
+    return pos, q, box
+
+
+def _pgpu(pos, q, n, p, box, precision, cutoff, mode="far", autotune=False):
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    plan = Plan(n, p, "periodic", box=box, cutoff=cutoff, precision=precision)
+    x, y, z = (torch.from_numpy(np.ascontiguousarray(pos[:, a])).to("cuda") for a in range(3))
+    qt = torch.from_numpy(np.ascontiguousarray(q)).to("cuda")
+    if autotune:
+        plan.autotune(x, y, z, qt)
+    phi, gx, gy, gz = getattr(plan, mode)(x, y, z, qt)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    return {"phi": phi.double().cpu().numpy(),
+            "grad": torch.stack([gx, gy, gz], dim=1).double().cpu().numpy()}
+
+
+@pytest.mark.parametrize("n,p,precision,cutoff,N,charged", [
+    (6, 4, "f64", 2, 2000, False),
+    (12, 6, "f32", 2, 8000, False),
+    (9, 5, "f32", 2, 5000, False),          # odd edge: no Nyquist frequency
+    (20, 3, "f32", 1, 12000, False),
+    (10, 4, "f32", 2, 4000, True),          # charged system: the per-particle terms of App. B
+    (7, 7, "f64", 1, 1500, True),
+])
+def test_periodic_non_power_of_two_matches_oracle(n, p, precision, cutoff, N, charged):
+    dt = np.float32 if precision == "f32" else np.float64
+    print(f"periodic n={n} p={p} {precision} c={cutoff} N={N} charged={charged}", flush=True)
+    pos, q, box = _pset(n, N, 3 * n + p, dt, charged)
+    cfg = opm.Config(n=n, p=p, boundary="periodic", box=box, cutoff=cutoff)
+    ref = opm.far_field(pos.astype(np.float64), q.astype(np.float64), cfg)
+    res = _pgpu(pos, q, n, p, box, precision, cutoff)
+    assert_parity(res, ref.phi, ref.grad, precision, f"periodic n={n} p={p}")
+
+
+def test_periodic_non_power_of_two_total_field_and_ewald():
+    """Total field on a 12^3 periodic mesh: against the oracle's far + near
+    field, and within the method error of the Ewald sum."""
+    n, p = 12, 6
+    pos, q, box = _pset(n, 6000, 5, np.float32)
+    cfg = opm.Config(n=n, p=p, boundary="periodic", box=box, cutoff=2)
+    p64, q64 = pos.astype(np.float64), q.astype(np.float64)
+    far = opm.far_field(p64, q64, cfg)
+    nphi, ng = exact.near(p64, q64, cfg)
+    res = _pgpu(pos, q, n, p, box, "f32", 2, mode="total")
+    assert_parity(res, far.phi + nphi, far.grad + ng, "f32", "total periodic n=12")
+    ephi, eg = exact.ewald(p64, q64, box=box)
+    e = exact.rel_rms(res["grad"], eg)
+    print(f"periodic n=12 total field vs Ewald: rel-RMS grad {e:.2e}", flush=True)
+    assert e < 1e-4
+
+
+def test_periodic_non_power_of_two_autotune():
+    """The autotuner on a direct-DFT plan (P2M lanes only) keeps parity."""
+    n, p = 12, 4
+    pos, q, box = _pset(n, 6000, 8, np.float32)
+    cfg = opm.Config(n=n, p=p, boundary="periodic", box=box, cutoff=2)
+    ref = opm.far_field(pos.astype(np.float64), q.astype(np.float64), cfg)
+    res = _pgpu(pos, q, n, p, box, "f32", 2, autotune=True)
+    assert_parity(res, ref.phi, ref.grad, "f32", "periodic n=12 autotuned")
