@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import subprocess
@@ -55,7 +56,7 @@ def algorithmic_work(stage, N, n, p, nf, tsize=4):
     t = tsize
     P, Q, K = (p + 1) ** 2, (2 * p + 1) ** 2, n ** 3
     F = nf * nf * (nf // 2 + 1)
-    lg = 3 * (nf.bit_length() - 1)               # log2(nf^3)
+    lg = round(3 * math.log2(nf))                # log2(nf^3)
     harm = 4 * (p + 1) * (p + 2)
     fft = 5 * P * nf ** 3 * lg // 2              # one direction, real-to-complex
     if stage == "bin":
@@ -294,6 +295,7 @@ WORKLOADS = {
     "open_n4096_m8_p4_f64": ("open", "f64"),
     "periodic_n1048576_m32_p7": ("periodic", "f32"),
     "open_n2097152_m48x40x32_p6": ("open", "f32"),
+    "periodic_n1048576_m24_p6": ("periodic", "f32"),
     "multi_periodic_n1048576_m32_p6_s64": ("periodic", "f32"),
     "batch_periodic_256sys": ("periodic", "f32"),
 }

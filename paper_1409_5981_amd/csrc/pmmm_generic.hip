@@ -177,8 +177,10 @@ struct GenKernel {
     }
 };
 
-// One thread per frequency f = (kz n + ky) nh + kx: L~ = T(G~) M~ by
-// eq. realmatrix, output rows outer, from spec into spec2.
+// One thread per (output row (l, m >= 0), frequency): L~ = T(G~) M~ by
+// eq. realmatrix, from spec into spec2.  Thread t = ((row n + ky) nh + kx) n
+// + kz: consecutive threads take consecutive kz, whose folded transfer-kernel
+// values are contiguous; the spectrum index is f = (kz n + ky) nh + kx.
 template <typename T>
 __global__ __launch_bounds__(kGenThreads) void k_gen_m2l(const cplx<T> *__restrict__ spec,
                                                          cplx<T> *__restrict__ out,
@@ -187,9 +189,20 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_m2l(const cplx<T> *__restri
                                                          double *__restrict__ sums) {
     const int nh = n / 2 + 1, nhp = (nh + 3) & ~3, Q = (2 * p + 1) * (2 * p + 1);
     const int64_t nspec = (int64_t)n * n * nh;
-    const int64_t f = (int64_t)blockIdx.x * kGenThreads + threadIdx.x;
-    if (f >= nspec) return;
-    const int kx = (int)(f % nh), ky = (int)((f / nh) % n), kz = (int)(f / ((int64_t)nh * n));
+    const int nrows = (p + 1) * (p + 2) / 2;
+    const int64_t t = (int64_t)blockIdx.x * kGenThreads + threadIdx.x;
+    if (t >= nspec * nrows) return;
+    const int kz = (int)(t % n);
+    const int64_t rest = t / n;
+    const int kx = (int)(rest % nh), ky = (int)((rest / nh) % n);
+    int row = (int)(rest / ((int64_t)nh * n));
+    int l = 0;
+    while (row > l) {
+        row -= l + 1;
+        ++l;
+    }
+    const int m = row;
+    const int64_t f = ((int64_t)kz * n + ky) * nh + kx;
     GenKernel<T> G;
     G.g = green;
     G.nhp = nhp;
@@ -198,64 +211,60 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_m2l(const cplx<T> *__restri
     G.kz = G.fz ? n - kz : kz;
     G.colbase = ((int64_t)(G.fy ? n - ky : ky) * nh + kx) * Q;
     const cplx<T> *F = spec + f;
-    for (int l = 0; l <= p; ++l) {
-        for (int m = 0; m <= l; ++m) {
-            T are = T(0), aim = T(0), bre = T(0), bim = T(0);   // acc_re, acc_im (complex)
-            for (int lam = 0; lam <= p; ++lam) {
-                const int nn = l + lam;
-                T xr = T(0), xi = T(0), yr = T(0), yi = T(0);    // before the i^(nn mod 2) factor
-                {
-                    const cplx<T> M0 = F[(int64_t)(lam * (lam + 1)) * nspec];
-                    const T A = G.re_s(nn, -m), B = G.im_s(nn, -m);
-                    xr += A * M0.re;
-                    xi += A * M0.im;
-                    yr += B * M0.re;
-                    yi += B * M0.im;
-                }
-                for (int mu = 1; mu <= lam; ++mu) {
-                    const T sg = (mu & 1) ? T(-1) : T(1);
-                    const T A = G.re_s(nn, -(m + mu)), B = G.im_s(nn, -(m + mu));
-                    const T C = sg * G.re_s(nn, -(m - mu)), D = sg * G.im_s(nn, -(m - mu));
-                    const cplx<T> Mr = F[(int64_t)(lam * (lam + 1) + mu) * nspec];
-                    const cplx<T> Mi = F[(int64_t)(lam * (lam + 1) - mu) * nspec];
-                    xr += (A + C) * Mr.re - (B - D) * Mi.re;
-                    xi += (A + C) * Mr.im - (B - D) * Mi.im;
-                    yr += (B + D) * Mr.re + (A - C) * Mi.re;
-                    yi += (B + D) * Mr.im + (A - C) * Mi.im;
-                }
-                if (nn & 1) {       // times i
-                    are -= xi;
-                    aim += xr;
-                    bre -= yi;
-                    bim += yr;
-                } else {
-                    are += xr;
-                    aim += xi;
-                    bre += yr;
-                    bim += yi;
-                }
-            }
-            if (f == 0) {
-                // zero frequency: the uniform corrections of App. B times n^3
-                // (the box volume in cell units): L_0^0 += 2 pi/(3V) sum q|u|^2,
-                // L_1^0 += 4 pi/(3V) sum M_1^0, L_1^1 += 8 pi/(3V) conj(sum M_1^1)
-                const double pi = 3.14159265358979323846;
-                if (l == 0) {
-                    double qr2 = 0.0;
-                    for (int z = 0; z < n; ++z) qr2 += qr2_partial[z];
-                    are += T(2.0 * pi / 3.0 * qr2);
-                } else if (l == 1 && m == 0) {
-                    are += T(4.0 * pi / 3.0 * (double)F[(int64_t)2 * nspec].re);
-                } else if (l == 1 && m == 1) {
-                    are += T(8.0 * pi / 3.0 * (double)F[(int64_t)3 * nspec].re);
-                    bre += T(-8.0 * pi / 3.0 * (double)F[(int64_t)1 * nspec].re);
-                }
-            }
-            out[(int64_t)(l * (l + 1) + m) * nspec + f] = {are, aim};
-            if (m > 0) out[(int64_t)(l * (l + 1) - m) * nspec + f] = {bre, bim};
+    T are = T(0), aim = T(0), bre = T(0), bim = T(0);   // acc_re, acc_im (complex)
+    for (int lam = 0; lam <= p; ++lam) {
+        const int nn = l + lam;
+        T xr = T(0), xi = T(0), yr = T(0), yi = T(0);    // before the i^(nn mod 2) factor
+        {
+            const cplx<T> M0 = F[(int64_t)(lam * (lam + 1)) * nspec];
+            const T A = G.re_s(nn, -m), B = G.im_s(nn, -m);
+            xr += A * M0.re;
+            xi += A * M0.im;
+            yr += B * M0.re;
+            yi += B * M0.im;
+        }
+        for (int mu = 1; mu <= lam; ++mu) {
+            const T sg = (mu & 1) ? T(-1) : T(1);
+            const T A = G.re_s(nn, -(m + mu)), B = G.im_s(nn, -(m + mu));
+            const T C = sg * G.re_s(nn, -(m - mu)), D = sg * G.im_s(nn, -(m - mu));
+            const cplx<T> Mr = F[(int64_t)(lam * (lam + 1) + mu) * nspec];
+            const cplx<T> Mi = F[(int64_t)(lam * (lam + 1) - mu) * nspec];
+            xr += (A + C) * Mr.re - (B - D) * Mi.re;
+            xi += (A + C) * Mr.im - (B - D) * Mi.im;
+            yr += (B + D) * Mr.re + (A - C) * Mi.re;
+            yi += (B + D) * Mr.im + (A - C) * Mi.im;
+        }
+        if (nn & 1) {       // times i
+            are -= xi;
+            aim += xr;
+            bre -= yi;
+            bim += yr;
+        } else {
+            are += xr;
+            aim += xi;
+            bre += yr;
+            bim += yi;
         }
     }
-    if (f == 0) sums[0] = (double)F[0].re;      // total charge, for L2P
+    if (f == 0) {
+        // zero frequency: the uniform corrections of App. B times n^3
+        // (the box volume in cell units): L_0^0 += 2 pi/(3V) sum q|u|^2,
+        // L_1^0 += 4 pi/(3V) sum M_1^0, L_1^1 += 8 pi/(3V) conj(sum M_1^1)
+        const double pi = 3.14159265358979323846;
+        if (l == 0) {
+            double qr2 = 0.0;
+            for (int z = 0; z < n; ++z) qr2 += qr2_partial[z];
+            are += T(2.0 * pi / 3.0 * qr2);
+        } else if (l == 1 && m == 0) {
+            are += T(4.0 * pi / 3.0 * (double)F[(int64_t)2 * nspec].re);
+        } else if (l == 1 && m == 1) {
+            are += T(8.0 * pi / 3.0 * (double)F[(int64_t)3 * nspec].re);
+            bre += T(-8.0 * pi / 3.0 * (double)F[(int64_t)1 * nspec].re);
+        }
+    }
+    out[(int64_t)(l * (l + 1) + m) * nspec + f] = {are, aim};
+    if (m > 0) out[(int64_t)(l * (l + 1) - m) * nspec + f] = {bre, bim};
+    if (f == 0 && l == 0) sums[0] = (double)F[0].re;      // total charge, for L2P
 }
 
 template <typename T>
@@ -295,8 +304,8 @@ hipError_t launch_generic_stage(const FFTArgs &a, int stage, hipStream_t s) {
         return dft_c<T, false>(spec, n, P, plane, (int64_t)n * plane, plane, w, s);
     }
     if (stage == 1) {
-        const int64_t nspec = (int64_t)n * plane;
-        hipLaunchKernelGGL(k_gen_m2l<T>, dim3((unsigned)((nspec + kGenThreads - 1) / kGenThreads)),
+        const int64_t nthr = (int64_t)n * plane * ((a.p + 1) * (a.p + 2) / 2);
+        hipLaunchKernelGGL(k_gen_m2l<T>, dim3((unsigned)((nthr + kGenThreads - 1) / kGenThreads)),
                            dim3(kGenThreads), 0, s, (const cplx<T> *)spec, spec2,
                            (const T *)a.green, n, a.p, (const double *)a.qr2_partial, a.sums);
         return hipGetLastError();

@@ -27,6 +27,7 @@ __all__ = [
     "periodic_pm1_blocks",
     "plummer_sphere",
     "uniform_open_shape",
+    "periodic_pm1_edge",
     "paper_accuracy_set",
     "batched_systems",
     "multi_charge_sets",
@@ -164,6 +165,22 @@ def uniform_open_shape(n=1 << 21, dims=(48, 40, 32), p=6, edge=1.0 / 64, seed=8,
                        "open", box=float(dims[0] * edge), shape=tuple(int(d) for d in dims))
 
 
+def periodic_pm1_edge(n=1 << 20, n_cells=24, p=6, edge=1.0 / 32, seed=9,
+                      dtype=np.float32) -> ParticleSet:
+    """Periodic box of n_cells^3 cells of edge ``edge`` (an edge count that
+    is not a power of two), ``n`` uniform particles, neutral +/-1 charges.
+    Positions are drawn in float64 and rounded to ``dtype``; a rounding that
+    reaches the box edge is moved one step inside."""
+    rng = _rng(seed)
+    box = n_cells * edge
+    pos = (rng.random((n, 3)) * box).astype(dtype)
+    top = dtype(box)
+    pos = np.where(pos >= top, np.nextafter(top, dtype(0)), pos)
+    q = neutral_pm1(rng, n, dtype)
+    return ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, n_cells, p,
+                       "periodic", box=float(box))
+
+
 def paper_accuracy_set(n=16384, n_cells=8, p=4, boundary="open", cutoff=2,
                        seed=7, dtype=np.float64) -> ParticleSet:
     """The paper's accuracy-test recipe (Sec. 4): N uniform particles in a
@@ -213,6 +230,9 @@ WORKLOADS = {
                                  "periodic, N=2^20 uniform, neutral +/-1, 32^3 cells, p=7, FP32"),
     "open_plummer_n4194304_m64_p6": (plummer_sphere,
                                      "open, N=2^22 Plummer a=0.05, 64^3 cells (128^3 padded FFT), p=6, FP32"),
+    "periodic_n1048576_m24_p6": (periodic_pm1_edge,
+                                 "periodic, N=2^20 uniform, neutral +/-1, 24^3 cells of edge 1/32 "
+                                 "(direct DFTs), p=6, FP32"),
     "open_n2097152_m48x40x32_p6": (uniform_open_shape,
                                    "open, N=2^21 uniform, neutral +/-1, 48x40x32 cells of edge 1/64 "
                                    "(computed in the 64^3 cube, 128^3 padded FFT), p=6, FP32"),

@@ -32,6 +32,7 @@ JOBS = {
     "periodic_n1048576_m32_p7": inputs.periodic_pm1_blocks,
     "open_plummer_n4194304_m64_p6": inputs.plummer_sphere,
     "open_n2097152_m48x40x32_p6": inputs.uniform_open_shape,
+    "periodic_n1048576_m24_p6": inputs.periodic_pm1_edge,
 }
 
 

@@ -262,7 +262,8 @@ def test_binding_rejects_bad_outputs_on_device():
 
 @pytest.mark.parametrize("name,gen", [("periodic_n1048576_m32_p7", "periodic_pm1_blocks"),
                                       ("open_plummer_n4194304_m64_p6", "plummer_sphere"),
-                                      ("open_n2097152_m48x40x32_p6", "uniform_open_shape")])
+                                      ("open_n2097152_m48x40x32_p6", "uniform_open_shape"),
+                                      ("periodic_n1048576_m24_p6", "periodic_pm1_edge")])
 def test_full_size_sampled(name, gen):
     """Full-size workloads in the benchmark's launch configuration: the GPU
     evaluates all N particles; the FP64 oracle values of a seeded sample of
