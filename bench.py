@@ -309,6 +309,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16,
                     help="particles of the oracle's particle stages in the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: replay the repeated far-field call as a HIP graph (pmmm_plan_set_graphs); "
+                         "stage profiling makes the calls eager again, so only the step time changes")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS),
                     help="default: the largest single-GPU configuration; the others are the "
                          "remaining configurations")
@@ -375,6 +378,7 @@ def main():
         # plan-time choice of launch shapes on this workload (not timed)
         tuning = plan.autotune(x, y, z, q, out=out)
 
+    plan.set_graphs(bool(args.graphs))
     # warm-up; the second half also times every stage to pick the dominant kernel
     half = max(1, args.warmup // 2)
     far_stages = [s for s in STAGES if s != "near"]

@@ -30,7 +30,7 @@ EXPORTS = [
     "pmmm_far_f32", "pmmm_far_f64", "pmmm_far_multi_f32", "pmmm_far_f32_noalloc",
     "pmmm_near_f32", "pmmm_near_f64", "pmmm_total_f32", "pmmm_total_f64",
     "pmmm_plan_sync_status", "pmmm_plan_mesh_bytes", "pmmm_plan_copy_mesh",
-    "pmmm_plan_set_profiling", "pmmm_plan_read_profile",
+    "pmmm_plan_set_profiling", "pmmm_plan_read_profile", "pmmm_plan_set_graphs",
     "pmmm_plan_autotune", "pmmm_plan_get_tuning", "pmmm_plan_set_tuning",
     "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
     "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
@@ -114,6 +114,8 @@ def load():
     L.pmmm_plan_mesh_bytes.restype = cz
     L.pmmm_plan_copy_mesh.argtypes = [vp, ci, vp, cz]
     L.pmmm_plan_copy_mesh.restype = ci
+    L.pmmm_plan_set_graphs.argtypes = [vp, ci]
+    L.pmmm_plan_set_graphs.restype = ci
     L.pmmm_plan_set_profiling.argtypes = [vp, ctypes.c_uint]
     L.pmmm_plan_set_profiling.restype = ci
     L.pmmm_plan_read_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -362,6 +364,10 @@ class Plan:
     def set_tuning(self, column_kernel="default", column_width=0, p2m_lanes=0):
         t = Tuning(COLUMN_KERNELS[column_kernel], int(column_width), int(p2m_lanes))
         _check(load().pmmm_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def set_graphs(self, enable: bool):
+        """Replay repeated calls as a HIP graph (pmmm_plan_set_graphs)."""
+        _check(load().pmmm_plan_set_graphs(self._h, 1 if enable else 0))
 
     def set_profiling(self, stages):
         """Enable HIP-event timing for the named stages (see STAGES)."""

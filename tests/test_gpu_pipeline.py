@@ -379,3 +379,40 @@ def test_bitwise_reproducible_and_graph_replay(boundary, n_cells, p, N):
         assert all(torch.equal(a, b) for a, b in zip(ref, static_out)), f"replay {k}"
         plan.total(*t)                       # eager work on the plan between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["far", "total"])
+def test_plan_graph_replay_bitwise(mode):
+    """pmmm_plan_set_graphs: the second identical call captures, later ones
+    replay; every replay, with unrelated eager work and synchronisations in
+    between, is bitwise the eager result, and a replay after the positions
+    changed in place matches an eager call on the new positions."""
+    import torch
+    from paper_1409_5981_amd._lib import Plan
+    ps = inputs.periodic_pm1()
+    dev = "cuda"
+    x, y, z, q = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ps.x, ps.y, ps.z, ps.q))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ref_plan = Plan(ps.n_cells, ps.p, "periodic")
+        plan = Plan(ps.n_cells, ps.p, "periodic")
+        ref = [t.clone() for t in getattr(ref_plan, mode)(x, y, z, q)]
+        out = tuple(torch.empty_like(x) for _ in range(4))
+        plan.set_graphs(True)
+        for rep in range(5):
+            getattr(plan, mode)(x, y, z, q, out=out)
+            torch.cuda.synchronize()
+            junk = (torch.arange(4096, device=dev, dtype=torch.float32) * rep).sum()
+            torch.cuda.synchronize()
+            for a, b in zip(out, ref):
+                assert torch.equal(a, b), (mode, rep)
+        x.mul_(0.5)
+        y.mul_(0.5)
+        getattr(plan, mode)(x, y, z, q, out=out)          # same pointers: a replay
+        ref2 = [t.clone() for t in getattr(ref_plan, mode)(x, y, z, q)]
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref2):
+            assert torch.equal(a, b)
+        plan.set_graphs(False)
+        plan.sync_status()
+    del junk
