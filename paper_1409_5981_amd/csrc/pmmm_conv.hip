@@ -239,15 +239,19 @@ __global__ void __launch_bounds__(512) k_plane_inv(int nout, int logn,
 // Same transforms for FFT sizes N = 64 and 128, one (plane z, component c)
 // per block of 256 threads, with register FFTs in four steps (fft_col) and
 // the open boundary's zero half pruned.  The row pairs live in swizzled LDS
-// rows xb[npair][N]; the y pass runs over chunks of up to 33 kx columns
+// rows xb[npair][N]; the y pass runs over chunks of up to 17 kx columns
 // through yb[N][CWS] (y-major, kx fastest, so the lanes of a wave take
 // consecutive kx: conflict-free in LDS and coalesced in memory): its first
 // step reads the row pairs straight from xb (unpacking the R2C of two real
 // rows), its second writes the spectrum to memory (forward) or into the
 // C2R row pairs (inverse).  Open: nin = N / 2 rows and columns in, and the
 // y and x transforms skip the zero half; periodic: nin = N.
+// Chunks of 17 columns keep a 128-point block at 51 KB of LDS, three blocks
+// per CU (33 columns: 68 KB, two blocks, and the inverse planes 28% slower;
+// 5 columns: 39 KB, four blocks, but 13 chunks' barriers make both passes
+// about 60% slower).
 constexpr int kPlaneThreads = 256;
-constexpr int kPlaneChunk = 33;
+constexpr int kPlaneChunk = 17;
 
 // W_N^e (conjugate for the inverse) from the full-circle table.
 template <typename T>
