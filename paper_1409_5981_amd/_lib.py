@@ -405,7 +405,7 @@ class Plan:
 class Batch:
     """Independent systems in one call (pmmm_batch_*).  `systems` is a list
     of dicts with the Plan arguments (n, p, boundary, box, cutoff, alpha,
-    images); every system runs the FP32 pipeline."""
+    images, shape); every system runs the FP32 pipeline."""
 
     def __init__(self, systems, stream=None):
         L = load()
@@ -414,7 +414,8 @@ class Batch:
         for i, sy in enumerate(systems):
             arr[i] = make_params(sy["n"], sy["p"], sy.get("boundary", "periodic"),
                                  sy.get("box", 1.0), sy.get("cutoff", 2), "f32",
-                                 sy.get("alpha", 0.0), sy.get("images", 0))
+                                 sy.get("alpha", 0.0), sy.get("images", 0),
+                                 shape=sy.get("shape"))
         self._params = arr
         self._h = ctypes.c_void_p()
         _check(L.pmmm_batch_create(self.nsys, arr, _stream_handle(stream), ctypes.byref(self._h)))

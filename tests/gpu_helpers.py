@@ -77,7 +77,8 @@ def assert_parity(res, ref_phi, ref_grad, precision, what, bounds=None, idx=None
 
 
 def oracle_cfg(ps, cutoff=2):
-    return opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=cutoff)
+    return opm.Config(n=ps.n_cells, p=ps.p, boundary=ps.boundary, box=ps.box, cutoff=cutoff,
+                      shape=getattr(ps, "shape", None))
 
 
 def cell_unit_mesh(mesh, cfg, kind):

@@ -159,3 +159,26 @@ def test_batch_full_workload_sampled():
     for n in (8, 16, 32):
         pick.append(next(i for i, ps in enumerate(systems) if ps.n_cells == n))
     _check(systems, offs, phi, grad, which=pick, sample=1024)
+
+
+def test_batch_with_open_non_cubic_systems():
+    """Open systems of nx x ny x nz cells in a batch (computed in their
+    power-of-two cubes, box checked per axis) beside cubic ones, each against
+    the oracle run natively on its own mesh."""
+    from paper_1409_5981_amd._lib import Batch
+    rng = np.random.default_rng(41)
+    specs = [((12, 6, 9), 4), ((8, 8, 8), 3), ((5, 7, 3), 3), ((12, 6, 9), 4)]
+    systems = []
+    for dims, p in specs:
+        h = 1.0 / 16                          # a power of two: the same cells in FP32 and FP64
+        npart = int(rng.integers(500, 2500)) & ~1
+        ext = np.asarray(dims) * h
+        pos = (rng.random((npart, 3)) * ext).astype(np.float32)
+        pos = np.minimum(pos, np.nextafter(ext.astype(np.float32), np.float32(0)))
+        q = inputs.neutral_pm1(rng, npart)
+        systems.append(inputs.ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q,
+                                          dims[0], p, "open", box=dims[0] * h, shape=dims))
+    batch = Batch([{"n": ps.n_cells, "p": ps.p, "boundary": "open", "box": ps.box,
+                    "shape": ps.shape} for ps in systems])
+    offs, phi, grad = _run(batch, systems)
+    _check(systems, offs, phi, grad)

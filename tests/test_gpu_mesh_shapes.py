@@ -57,6 +57,7 @@ def _gpu(pos, q, dims, p, box, precision, cutoff, mode="far"):
     ((24, 24, 24), 5, "f32", 2, 8000),      # non-power-of-two cube, in 32^3
     ((33, 20, 17), 3, "f32", 2, 6000),      # in 64^3: the 128-point transforms
     ((1, 1, 1), 2, "f32", 1, 50),           # every cell is near: the far field is zero
+    ((32, 20, 10), 3, "f64", 2, 3000),      # FP64 at its largest FFT mesh, 64^3
 ])
 def test_open_mesh_shapes_match_oracle(dims, p, precision, cutoff, n):
     dt = np.float32 if precision == "f32" else np.float64
@@ -147,6 +148,7 @@ def _pgpu(pos, q, n, p, box, precision, cutoff, mode="far", autotune=False):
     (20, 3, "f32", 1, 12000, False),
     (10, 4, "f32", 2, 4000, True),          # charged system: the per-particle terms of App. B
     (7, 7, "f64", 1, 1500, True),
+    (6, 10, "f32", 2, 1000, False),         # the highest order
 ])
 def test_periodic_non_power_of_two_matches_oracle(n, p, precision, cutoff, N, charged):
     dt = np.float32 if precision == "f32" else np.float64
