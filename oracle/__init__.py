@@ -14,6 +14,8 @@ Modules
               of App. A.3 in complex form, used to pin the mesh pipeline
   storage     per-order fixed-point coefficient records (Sec. 5.3) and the
               complex composition of two real sets (App. D)
+  hierarchical  the two-level PMMM of Sec. 5.2: coarse PMMM plus the fine
+              level for the pairs whose coarse cells are near
 
 Parity status: every function listed above is pinned by a CPU test under
 tests/test_oracle_*.py against values fixed by the paper (Table RSlm), by
