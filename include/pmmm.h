@@ -67,6 +67,7 @@ enum { PMMM_MESH_M = 0, PMMM_MESH_L = 1, PMMM_MESH_GREEN = 2 };
 
 typedef struct pmmm_plan_s *pmmm_plan;
 typedef struct pmmm_batch_s *pmmm_batch;
+typedef struct pmmm_hier_s *pmmm_hier;
 
 /* Method parameters (Sec. 2.1, Sec. 3.2, App. B).
  *   nx, ny, nz  cells per axis (the mesh may be any product of three
@@ -230,6 +231,33 @@ int pmmm_total_f32(pmmm_plan plan, int64_t n, const float *x, const float *y, co
 int pmmm_total_f64(pmmm_plan plan, int64_t n, const double *x, const double *y,
                    const double *z, const double *q, double *phi, double *gx, double *gy,
                    double *gz, void *stream);
+
+/* Two-level hierarchical far field (Sec. 5.2).  `coarse` describes an open
+ * FP32 mesh, cubic with a power-of-two edge n (the other fields as for
+ * pmmm_plan_create); `refine` = r in {1, 2, 4, 8} cuts each coarse cell into
+ * r^3 fine cells (n r <= 128).  A pair of particles is counted by
+ *   the coarse PMMM   when their coarse cells are more than c apart;
+ *   the fine level    when their coarse cells are within c and their fine
+ *                     cells are not: eq. M2L from every such fine cell's
+ *                     moments to the fine cell's local expansion, summed
+ *                     directly over the fine cells of the (2c+1)^3 coarse
+ *                     neighbourhood (the paper evaluates the same sum as a
+ *                     local convolution), then eq. L2P;
+ *   the near field    when their fine cells are within c.
+ * pmmm_hier_far_f32 returns the first two parts, pmmm_hier_total_f32 all
+ * three; arguments, layouts, ownership and stream semantics as
+ * pmmm_far_f32 (the outputs are overwritten).  The fine level costs
+ * O(((2c+1) r)^3 (p+1)^4) per fine cell.  pmmm_hier_sync_status reports a
+ * particle outside the box as PMMM_EDOMAIN.  Errors: PMMM_EINVAL for a bad
+ * argument or refine, PMMM_EUNSUPPORTED for a mesh the hierarchy does not
+ * take, plus those of pmmm_plan_create and pmmm_far_f32. */
+int pmmm_hier_create(const pmmm_params *coarse, int refine, void *stream, pmmm_hier *out);
+void pmmm_hier_destroy(pmmm_hier h);
+int pmmm_hier_far_f32(pmmm_hier h, int64_t n, const float *x, const float *y, const float *z,
+                      const float *q, float *phi, float *gx, float *gy, float *gz, void *stream);
+int pmmm_hier_total_f32(pmmm_hier h, int64_t n, const float *x, const float *y, const float *z,
+                        const float *q, float *phi, float *gx, float *gy, float *gz, void *stream);
+int pmmm_hier_sync_status(pmmm_hier h);
 
 /* Per-order fixed-point records of a coefficient mesh (Sec. 5.3 and its
  * footnote: an order-l coefficient carries 3 (p + 1 - l) bits, so a cell

@@ -34,6 +34,8 @@ EXPORTS = [
     "pmmm_plan_autotune", "pmmm_plan_get_tuning", "pmmm_plan_set_tuning",
     "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
     "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
+    "pmmm_hier_create", "pmmm_hier_destroy", "pmmm_hier_far_f32", "pmmm_hier_total_f32",
+    "pmmm_hier_sync_status",
     "pmmm_coef_record_words", "pmmm_coef_pack_f32", "pmmm_coef_unpack_f32",
     "pmmm_coef_compose_f32", "pmmm_coef_split_f32",
     "pmmm_error_string", "pmmm_last_error",
@@ -139,6 +141,16 @@ def load():
     L.pmmm_batch_set_graphs.restype = ci
     L.pmmm_batch_sync_status.argtypes = [vp]
     L.pmmm_batch_sync_status.restype = ci
+    L.pmmm_hier_create.argtypes = [ctypes.POINTER(Params), ci, vp, ctypes.POINTER(vp)]
+    L.pmmm_hier_create.restype = ci
+    L.pmmm_hier_destroy.argtypes = [vp]
+    L.pmmm_hier_destroy.restype = None
+    for name in ("pmmm_hier_far_f32", "pmmm_hier_total_f32"):
+        f = getattr(L, name)
+        f.argtypes = [vp, i64] + [vp] * 8 + [vp]
+        f.restype = ci
+    L.pmmm_hier_sync_status.argtypes = [vp]
+    L.pmmm_hier_sync_status.restype = ci
     L.pmmm_coef_record_words.argtypes = [ci]
     L.pmmm_coef_record_words.restype = ci
     L.pmmm_coef_pack_f32.argtypes = [ci, i64, vp, vp, vp, ctypes.c_uint, vp]
@@ -463,6 +475,51 @@ class Batch:
 
     def sync_status(self):
         _check(load().pmmm_batch_sync_status(self._h))
+
+
+class Hier:
+    """Two-level hierarchical far field (pmmm_hier_*): an open FP32 coarse
+    mesh of n^3 cells refined by r per axis."""
+
+    def __init__(self, n: int, p: int, refine: int, box: float = 1.0, cutoff: int = 2,
+                 n_max: int = 0, stream=None):
+        L = load()
+        self.params = make_params(n, p, "open", box, cutoff, "f32", 0.0, 0, n_max)
+        self.n, self.p, self.refine, self.box, self.cutoff = n, p, refine, box, cutoff
+        self._h = ctypes.c_void_p()
+        _check(L.pmmm_hier_create(ctypes.byref(self.params), int(refine), _stream_handle(stream),
+                                  ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            load().pmmm_hier_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, x, y, z, q, out, stream):
+        import torch
+        n = x.numel()
+        check_buffers((x, y, z, q), torch.float32, n, what="x, y, z, q")
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(4))
+        check_buffers(out, torch.float32, n, what="out", device=x.device)
+        _check(fn(self._h, n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                  *[o.data_ptr() for o in out], _stream_handle(stream)))
+        return out
+
+    def far(self, x, y, z, q, out=None, stream=None):
+        return self._call(load().pmmm_hier_far_f32, x, y, z, q, out, stream)
+
+    def total(self, x, y, z, q, out=None, stream=None):
+        return self._call(load().pmmm_hier_total_f32, x, y, z, q, out, stream)
+
+    def sync_status(self):
+        _check(load().pmmm_hier_sync_status(self._h))
 
 
 # ------------------------------------------------- coefficient storage calls

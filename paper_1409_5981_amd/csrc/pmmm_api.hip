@@ -9,7 +9,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "pmmm_internal.h"
+#include "pmmm_hier.h"
 
 namespace pmmm {
 
@@ -50,6 +50,11 @@ struct Plan {
     int lim[3];               // cells per axis of the caller's box (open: a corner of n^3)
     int generic;              // periodic n not a power of two: direct-DFT stages
     void *spec2 = nullptr;    // generic: M2L output spectra
+    // fine plan of a hierarchy: no transfer kernel or spectra; its far
+    // stage is the local M2L over hier_table (margin hier_D, refinement hier_r)
+    bool no_transfer = false;
+    const float *hier_table = nullptr;
+    int hier_r = 0, hier_D = 0;
     int64_t K, ncol, ngreen;  // ngreen: stored transfer-kernel values
     double box, h, inv_h, alpha, alpha_cell;
     int device;
@@ -358,10 +363,12 @@ static int make_twiddles(Plan *pl, hipStream_t s) {
 
 static int alloc_plan(Plan *pl, hipStream_t s) {
     const size_t t = pl->tsize, c = 2 * t;
-    PMMM_HIP(hipMalloc(&pl->green, (size_t)pl->ngreen * t));
+    if (!pl->no_transfer) {
+        PMMM_HIP(hipMalloc(&pl->green, (size_t)pl->ngreen * t));
+        PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
+        if (pl->generic) PMMM_HIP(hipMalloc(&pl->spec2, (size_t)pl->P * pl->n * pl->ncol * c));
+    }
     PMMM_HIP(hipMalloc(&pl->M, (size_t)(pl->P + 1) * pl->K * t));
-    PMMM_HIP(hipMalloc(&pl->spec, (size_t)pl->P * pl->n * pl->ncol * c));
-    if (pl->generic) PMMM_HIP(hipMalloc(&pl->spec2, (size_t)pl->P * pl->n * pl->ncol * c));
     PMMM_HIP(hipMalloc(&pl->L, (size_t)pl->P * pl->K * t));
     PMMM_HIP(hipMalloc(&pl->start, sizeof(int) * (pl->K + 1)));
     // [0] dense items, [1] domain flag, [2] near tiles, [3] partial slots
@@ -386,7 +393,9 @@ static int group_for(double mean) {
 
 // What one call computes: the far field (pmmm_far_*), the near field alone
 // (pmmm_near_*) or both with one binning (pmmm_total_*).
-enum CallMode { kFar = 0, kNear = 1, kTotal = 2 };
+// kHierFine / kHierTotal: the fine level of a hierarchy (and its near field),
+// added into outputs that already hold the coarse far field
+enum CallMode { kFar = 0, kNear = 1, kTotal = 2, kHierFine = 3, kHierTotal = 4 };
 
 // Per-particle device buffers of one call: the plan's own (grown on demand)
 // or, for the allocation-free entry point, slices of the static scratch.
@@ -556,9 +565,23 @@ static int enqueue_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, c
         f.col_kernel = pl->tune_col_kernel;
         f.generic = pl->generic;
         f.spec2 = pl->spec2;
-        for (int st = 0; st < 3; ++st) {
-            StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s, timed);
-            PMMM_HIP(launch_conv_stage<T>(f, st, s));
+        if (mode == kHierFine || mode == kHierTotal) {
+            StageTimer t(pl, PMMM_STAGE_COLUMN, s, timed);
+            HierArgs h{};
+            h.p = pl->p;
+            h.nf = pl->n;
+            h.r = pl->hier_r;
+            h.cutoff = pl->cutoff;
+            h.D = pl->hier_D;
+            h.M = (const float *)pl->M;
+            h.L = (float *)pl->L;
+            h.table = pl->hier_table;
+            PMMM_HIP(launch_hier_m2l_f32(h, s));
+        } else {
+            for (int st = 0; st < 3; ++st) {
+                StageTimer t(pl, PMMM_STAGE_FFT_FWD + st, s, timed);
+                PMMM_HIP(launch_conv_stage<T>(f, st, s));
+            }
         }
         {
             StageTimer t(pl, PMMM_STAGE_L2P, s, timed);
@@ -585,16 +608,18 @@ static int enqueue_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, c
             PMMM_HIP(launch_l2p<T>(l, s));
             if (mode == kFar && staged)
                 PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz, 0, s));
+            if (mode == kHierFine)   // added to the coarse far field already in the outputs
+                PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz, 1, s));
         }
     }
-    if (mode != kFar) {
+    if (mode == kNear || mode == kTotal || mode == kHierTotal) {
         StageTimer t(pl, PMMM_STAGE_NEAR, s, timed);
         NearArgs a{};
         a.n = n;
         a.ncell = pl->n;
         a.cutoff = pl->cutoff;
         a.periodic = !pl->open;
-        a.accumulate = mode == kTotal ? 1 : 0;
+        a.accumulate = mode == kNear ? 0 : 1;
         a.start = pl->start;
         a.scell = pb.scell;
         a.sorted = pb.sorted;
@@ -605,7 +630,7 @@ static int enqueue_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, c
         a.staged = pb.staged;
         PMMM_HIP(launch_near<T>(a, s));
         PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz,
-                                     mode == kNear ? accumulate : 0, s));
+                                     mode == kNear ? accumulate : (mode == kHierTotal ? 1 : 0), s));
     }
     return PMMM_OK;
 }
@@ -1309,6 +1334,130 @@ static int batch_far(pmmm_batch_s *b, const int64_t *offsets, const float *x, co
     b->key = key;
     return batch_enqueue(b, x, y, z, q, phi, gx, gy, gz, s);
 }
+
+// ------------------------------------------------ two-level hierarchy
+struct pmmm_hier_s {
+    pmmm_plan_s *coarse = nullptr, *fine = nullptr;
+    float *table = nullptr;
+};
+
+static void hier_destroy(pmmm_hier_s *h) {
+    if (!h) return;
+    if (h->coarse) destroy(h->coarse);
+    if (h->fine) destroy(h->fine);
+    if (h->table) hipFree(h->table);
+    delete h;
+}
+
+// The fine plan: binning, P2M, L2P and the near field on the refined mesh,
+// no transfer kernel or spectra.
+static int fine_plan_create(const pmmm_params *coarse, int r, hipStream_t s, pmmm_plan_s **out) {
+    pmmm_params fp = *coarse;
+    fp.nx = fp.ny = fp.nz = coarse->nx * r;
+    pmmm_plan_s *pl = new pmmm_plan_s();
+    derive(pl, &fp);
+    pl->no_transfer = true;
+    hipError_t e = hipGetDevice(&pl->device);
+    int rc = e == hipSuccess ? PMMM_OK : hip_fail(e, "hipGetDevice");
+    if (rc == PMMM_OK) rc = alloc_plan(pl, s);
+    if (rc == PMMM_OK) rc = scratch_setup(pl->device);
+    if (rc == PMMM_OK && fp.n_max > 0) rc = ensure_capacity(pl, fp.n_max);
+    if (rc != PMMM_OK) {
+        destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return PMMM_OK;
+}
+
+extern "C" {
+
+int pmmm_hier_create(const pmmm_params *coarse, int refine, void *stream, pmmm_hier *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return PMMM_EINVAL;
+    }
+    *out = nullptr;
+    std::string why;
+    int rc = validate(coarse, why);
+    if (rc != PMMM_OK) {
+        set_error(why);
+        return rc;
+    }
+    if (coarse->boundary != PMMM_OPEN || coarse->precision != PMMM_F32 || coarse->nx != coarse->ny ||
+        coarse->nx != coarse->nz || !is_pow2(coarse->nx)) {
+        set_error("the hierarchy takes an open FP32 coarse mesh, cubic with a power-of-two edge");
+        return PMMM_EUNSUPPORTED;
+    }
+    if (refine != 1 && refine != 2 && refine != 4 && refine != 8) {
+        set_error("refine must be 1, 2, 4 or 8");
+        return PMMM_EINVAL;
+    }
+    if (coarse->nx * refine > 128) {
+        set_error("the fine mesh is limited to 128 cells per axis");
+        return PMMM_EUNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    pmmm_hier_s *h = new pmmm_hier_s();
+    rc = pmmm_plan_create(coarse, stream, &h->coarse);
+    if (rc == PMMM_OK) rc = fine_plan_create(coarse, refine, s, &h->fine);
+    if (rc == PMMM_OK) {
+        const int c = h->fine->cutoff, D = (c + 1) * refine - 1, W = 2 * D + 1;
+        const size_t bytes = sizeof(float) * (size_t)W * W * W * h->fine->Q;
+        hipError_t e = hipMalloc(&h->table, bytes);
+        if (e == hipSuccess) e = build_hier_table_f32(h->fine->p, c, D, h->table, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hierarchy table");
+        } else {
+            h->fine->hier_table = h->table;
+            h->fine->hier_r = refine;
+            h->fine->hier_D = D;
+        }
+    }
+    if (rc != PMMM_OK) {
+        hier_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return PMMM_OK;
+}
+
+void pmmm_hier_destroy(pmmm_hier h) { hier_destroy(h); }
+
+int pmmm_hier_far_f32(pmmm_hier h, int64_t n, const float *x, const float *y, const float *z,
+                      const float *q, float *phi, float *gx, float *gy, float *gz, void *stream) {
+    if (!h) {
+        set_error("hierarchy is NULL");
+        return PMMM_EINVAL;
+    }
+    int rc = call_impl<float>(h->coarse, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+    if (rc != PMMM_OK || n == 0) return rc;
+    return call_impl<float>(h->fine, kHierFine, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+}
+
+int pmmm_hier_total_f32(pmmm_hier h, int64_t n, const float *x, const float *y, const float *z,
+                        const float *q, float *phi, float *gx, float *gy, float *gz, void *stream) {
+    if (!h) {
+        set_error("hierarchy is NULL");
+        return PMMM_EINVAL;
+    }
+    int rc = call_impl<float>(h->coarse, kFar, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+    if (rc != PMMM_OK || n == 0) return rc;
+    return call_impl<float>(h->fine, kHierTotal, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
+}
+
+int pmmm_hier_sync_status(pmmm_hier h) {
+    if (!h) {
+        set_error("hierarchy is NULL");
+        return PMMM_EINVAL;
+    }
+    const int rc = pmmm_plan_sync_status(h->coarse);
+    const int rf = pmmm_plan_sync_status(h->fine);
+    return rc != PMMM_OK ? rc : rf;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -22,7 +22,7 @@
 #include <vector>
 #include <cmath>
 
-#include "pmmm_internal.h"
+#include "pmmm_hier.h"
 
 namespace pmmm {
 
@@ -387,6 +387,37 @@ hipError_t build_green(const GreenArgs &a, hipStream_t s) {
     if (kvec) hipFree(kvec);
     if (table) hipFree(table);
     return e;
+}
+
+// Fine-level table of the hierarchical far field (one thread per offset).
+__global__ void k_hier_table(int lmax, int cutoff, int D, float *__restrict__ out) {
+    const int W = 2 * D + 1, Q = (lmax + 1) * (lmax + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)W * W * W) return;
+    const int dx = (int)(t % W) - D, dy = (int)((t / W) % W) - D, dz = (int)(t / ((int64_t)W * W)) - D;
+    float *o = out + t * Q;
+    int cheb = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+    cheb = cheb > abs(dz) ? cheb : abs(dz);
+    if (cheb <= cutoff) {
+        for (int j = 0; j < Q; ++j) o[j] = 0.0f;
+        return;
+    }
+    double sre[kMaxTri], sim[kMaxTri];
+    singular_tri(lmax, (double)dx, (double)dy, (double)dz, sre, sim);
+    for (int l = 0; l <= lmax; ++l) {
+        o[l * (l + 1)] = (float)sre[tri_idx(l, 0)];
+        for (int m = 1; m <= l; ++m) {
+            o[l * (l + 1) + m] = (float)sre[tri_idx(l, m)];
+            o[l * (l + 1) - m] = (float)sim[tri_idx(l, m)];
+        }
+    }
+}
+
+hipError_t build_hier_table_f32(int p, int cutoff, int D, float *out, hipStream_t s) {
+    const int64_t W = 2 * D + 1, cnt = W * W * W;
+    hipLaunchKernelGGL(k_hier_table, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, s, 2 * p,
+                       cutoff, D, out);
+    return hipGetLastError();
 }
 
 template hipError_t build_green<float>(const GreenArgs &, hipStream_t);

@@ -1,0 +1,111 @@
+// Fine level of the two-level hierarchical far field (Sec. 5.2).  The
+// coarse PMMM counts the pairs of particles whose coarse cells are more than
+// c apart; the fine level counts those whose coarse cells are within c but
+// whose fine cells are not: the local expansion of fine cell I gathers
+// eq. M2L of the moments of every such fine cell J, in the real-matrix form
+// of eq. realmatrix with the real values of S at the displacement I - J
+// (cell units), read from a table over the margin |d_a| <= D = (c + 1) r - 1.
+// The sum is taken directly, cell pair by cell pair (the paper's local FFT
+// convolution computes the same sum).
+#include "pmmm_hier.h"
+
+namespace pmmm {
+namespace {
+
+constexpr int kHierThreads = 256;
+
+// Values of the table row of one offset, as the real-storage components of
+// Re S_nn^k / Im S_nn^k for any -nn <= k <= nn (conjugate relation).
+struct HierRow {
+    const float *g;
+    __device__ __forceinline__ float at(int nn, int k) const { return g[nn * (nn + 1) + k]; }
+    __device__ __forceinline__ float re_s(int nn, int k) const {
+        if (k > nn || -k > nn) return 0.0f;
+        if (k >= 0) return at(nn, k);
+        return ((-k) & 1) ? -at(nn, -k) : at(nn, -k);
+    }
+    __device__ __forceinline__ float im_s(int nn, int k) const {
+        if (k == 0 || k > nn || -k > nn) return 0.0f;
+        if (k > 0) return at(nn, -k);
+        return ((-k) & 1) ? at(nn, k) : -at(nn, k);
+    }
+};
+
+// Thread = (output row (l, m >= 0), target fine cell I), I fastest.
+__global__ __launch_bounds__(kHierThreads) void k_hier_m2l(const float *__restrict__ M,
+                                                           float *__restrict__ L,
+                                                           const float *__restrict__ table,
+                                                           int nf, int r, int cutoff, int D,
+                                                           int p) {
+    const int64_t K = (int64_t)nf * nf * nf;
+    const int nrows = (p + 1) * (p + 2) / 2, Q = (2 * p + 1) * (2 * p + 1), W = 2 * D + 1;
+    const int64_t t = (int64_t)blockIdx.x * kHierThreads + threadIdx.x;
+    if (t >= K * nrows) return;
+    const int64_t I = t % K;
+    int row = (int)(t / K);
+    int l = 0;
+    while (row > l) {
+        row -= l + 1;
+        ++l;
+    }
+    const int m = row;
+    const int ix = (int)(I % nf), iy = (int)((I / nf) % nf), iz = (int)(I / ((int64_t)nf * nf));
+    const int nc = nf / r;
+    int lo[3], hi[3];
+    const int ii[3] = {ix, iy, iz};
+    for (int a = 0; a < 3; ++a) {
+        const int C = ii[a] / r;
+        lo[a] = (C - cutoff > 0 ? C - cutoff : 0) * r;
+        hi[a] = (C + cutoff < nc - 1 ? C + cutoff : nc - 1) * r + r - 1;
+    }
+    // each source cell's terms are summed in FP32, the ~10^3 source sums in
+    // FP64: the contributions of a neutral neighbourhood largely cancel, and
+    // one long FP32 running sum would lose that many roundings
+    double are = 0.0, aim = 0.0;
+    for (int jz = lo[2]; jz <= hi[2]; ++jz) {
+        const int dz = iz - jz;
+        for (int jy = lo[1]; jy <= hi[1]; ++jy) {
+            const int dy = iy - jy;
+            for (int jx = lo[0]; jx <= hi[0]; ++jx) {
+                const int dx = ix - jx;
+                int cheb = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+                cheb = cheb > abs(dz) ? cheb : abs(dz);
+                if (cheb <= cutoff) continue;               // fine near cube: direct sum
+                const HierRow G{table + (((int64_t)(dz + D) * W + (dy + D)) * W + (dx + D)) * Q};
+                const float *MJ = M + ((int64_t)jz * nf + jy) * nf + jx;
+                float sre = 0.0f, sim = 0.0f;
+                for (int lam = 0; lam <= p; ++lam) {
+                    const int nn = l + lam;
+                    const float M0 = MJ[(int64_t)(lam * (lam + 1)) * K];
+                    sre += G.re_s(nn, -m) * M0;
+                    sim += G.im_s(nn, -m) * M0;
+                    for (int mu = 1; mu <= lam; ++mu) {
+                        const float sg = (mu & 1) ? -1.0f : 1.0f;
+                        const float A = G.re_s(nn, -(m + mu)), B = G.im_s(nn, -(m + mu));
+                        const float C = sg * G.re_s(nn, -(m - mu)), Dv = sg * G.im_s(nn, -(m - mu));
+                        const float Mr = MJ[(int64_t)(lam * (lam + 1) + mu) * K];
+                        const float Mi = MJ[(int64_t)(lam * (lam + 1) - mu) * K];
+                        sre += (A + C) * Mr - (B - Dv) * Mi;
+                        sim += (B + Dv) * Mr + (A - C) * Mi;
+                    }
+                }
+                are += (double)sre;
+                aim += (double)sim;
+            }
+        }
+    }
+    L[(int64_t)(l * (l + 1) + m) * K + I] = (float)are;
+    if (m > 0) L[(int64_t)(l * (l + 1) - m) * K + I] = (float)aim;
+}
+
+}  // namespace
+
+hipError_t launch_hier_m2l_f32(const HierArgs &a, hipStream_t s) {
+    const int64_t K = (int64_t)a.nf * a.nf * a.nf, nrows = (a.p + 1) * (a.p + 2) / 2;
+    const int64_t nthr = K * nrows;
+    hipLaunchKernelGGL(k_hier_m2l, dim3((unsigned)((nthr + kHierThreads - 1) / kHierThreads)),
+                       dim3(kHierThreads), 0, s, a.M, a.L, a.table, a.nf, a.r, a.cutoff, a.D, a.p);
+    return hipGetLastError();
+}
+
+}  // namespace pmmm
