@@ -298,6 +298,7 @@ WORKLOADS = {
     "periodic_n1048576_m24_p6": ("periodic", "f32"),
     "multi_periodic_n1048576_m32_p6_s64": ("periodic", "f32"),
     "batch_periodic_256sys": ("periodic", "f32"),
+    "hier_open_n1048576_m16r2_p4_c1": ("open", "f32"),
 }
 
 
@@ -356,6 +357,8 @@ def main():
         return bench_multi(args, workload)
     if workload.startswith("batch_"):
         return bench_batch(args, workload)
+    if workload.startswith("hier_"):
+        return bench_hier(args, workload)
     boundary, prec = WORKLOADS[workload]
     ps = inputs.make_workload(workload)
     N, n, p = ps.n, ps.n_cells, ps.p
@@ -719,6 +722,90 @@ def bench_batch(args, workload):
         "config": {"workload": workload, "systems": len(systems), "n_particles": N,
                    "classes": batch.classes, "meshes": meshes, "cutoff": 2,
                    "parallelism": "single GPU"},
+        "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],
+                    "max": step_ms[-1], "events": K},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_hier(args, workload):
+    """Two-level hierarchical far field (pmmm_hier_far_f32, Sec. 5.2): 2^20
+    uniform particles with neutral +/-1 charges in the unit box, coarse 16^3
+    open mesh refined by 2 (fine 32^3), p = 4, c = 1.  One step is one call.
+    The roofline takes the fine level's algorithmic work, one real (P x P)
+    eq. M2L product per pair of fine cells whose coarse cells are near and
+    fine cells are not, over the whole call's time (a lower bound for the
+    fine kernel alone)."""
+    import numpy as np
+    import torch
+    from paper_1409_5981_amd import inputs
+    from paper_1409_5981_amd._lib import Hier
+
+    N, n, r, p, c = 1 << 20, 16, 2, 4, 1
+    rng = np.random.Generator(np.random.PCG64(10))
+    x, y, z = inputs.uniform_positions(rng, N, np.float32)
+    q = inputs.neutral_pm1(rng, N, np.float32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    xt, yt, zt, qt = (torch.from_numpy(a).to(dev) for a in (x, y, z, q))
+    h = Hier(n, p, r, cutoff=c, n_max=N)
+    out = tuple(torch.empty(N, dtype=torch.float32, device=dev) for _ in range(4))
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(stream)
+    for _ in range(max(3, args.warmup)):
+        h.far(xt, yt, zt, qt, out=out, stream=stream)
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(K):
+        h.far(xt, yt, zt, qt, out=out, stream=stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h.sync_status()
+    step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(K))
+    t_med = step_ms[len(step_ms) // 2] / 1e3
+    # pairs of fine cells handled by the fine level, counted exactly
+    nf = n * r
+    cells = np.arange(nf)
+    per_axis = {}                 # offset d -> targets i with source i - d in a near coarse cell
+    for d in range(-((c + 1) * r - 1), (c + 1) * r):
+        i = cells[max(0, d):min(nf, nf + d)]
+        per_axis[d] = int(np.sum(np.abs(i // r - (i - d) // r) <= c))
+    D = (c + 1) * r - 1
+    pairs = 0
+    for dz in range(-D, D + 1):
+        for dy in range(-D, D + 1):
+            for dx in range(-D, D + 1):
+                if max(abs(dx), abs(dy), abs(dz)) <= c:
+                    continue
+                pairs += per_axis[dx] * per_axis[dy] * per_axis[dz]
+    P = (p + 1) ** 2
+    flops = 2 * P * P * pairs
+    roof = {"bound": "alu", "achieved": flops / t_med / 1e12, "peak": FP32_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": flops / t_med / FP32_PEAK, "traffic": None,
+            "kernel": "whole hierarchical call (fine-level flops)", "algorithmic_flops": flops,
+            "fine_pairs": pairs}
+    rec = {
+        "metric": "particles/s, two-level hierarchical PMMM far field",
+        "value": N * K / el,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": max(3, args.warmup),
+        "ms_per_step": el / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "n_particles": N, "coarse": f"{n}^3", "refine": r,
+                   "fine": f"{nf}^3", "p": p, "cutoff": c, "parallelism": "single GPU"},
         "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],
                     "max": step_ms[-1], "events": K},
         "roofline": roof,
