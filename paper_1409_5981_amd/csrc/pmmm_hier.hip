@@ -116,78 +116,88 @@ __device__ __forceinline__ float im_s_c(const float *g) {
     else return -g[NN * (NN + 1) + KK];
 }
 
-// One thread per target fine cell, every output row at once: per source
+// A group of `split` lanes per target fine cell, every output row at once:
+// the lanes of a group take the cell's source cells in turn, and per source
 // cell the moments and the table row are read once and the (P x P) product
 // of eq. realmatrix is unrolled at compile time (order PO).  Per-source sums
-// in FP32, the sum over sources in FP64.
+// in FP32, the sums over sources and over the group's lanes in FP64.
+// split is a power of two <= 64 (several lanes per cell fill the chip's
+// SIMDs when a fine mesh has few cells for a kernel of this register size).
 constexpr int kHierCellThreads = 64;
 template <int PO>
 __global__ __launch_bounds__(kHierCellThreads) void k_hier_m2l_cell(
     const float *__restrict__ M, float *__restrict__ L, const float *__restrict__ table, int nf,
-    int r, int cutoff, int D) {
+    int r, int cutoff, int D, int split) {
     constexpr int P = nreal(PO), Q = nreal(2 * PO);
     const int64_t K = (int64_t)nf * nf * nf;
-    const int64_t I = (int64_t)blockIdx.x * kHierCellThreads + threadIdx.x;
-    if (I >= K) return;
+    const int part = (int)threadIdx.x & (split - 1);
+    const int64_t I = ((int64_t)blockIdx.x * kHierCellThreads + threadIdx.x) / split;
+    const bool active = I < K;
     const int W = 2 * D + 1;
-    const int ix = (int)(I % nf), iy = (int)((I / nf) % nf), iz = (int)(I / ((int64_t)nf * nf));
+    const int64_t Ic = active ? I : 0;
+    const int ix = (int)(Ic % nf), iy = (int)((Ic / nf) % nf), iz = (int)(Ic / ((int64_t)nf * nf));
     const int nc = nf / r;
-    int lo[3], hi[3];
+    int lo[3], w[3];
     const int ii[3] = {ix, iy, iz};
     for (int a = 0; a < 3; ++a) {
         const int C = ii[a] / r;
         lo[a] = (C - cutoff > 0 ? C - cutoff : 0) * r;
-        hi[a] = (C + cutoff < nc - 1 ? C + cutoff : nc - 1) * r + r - 1;
+        w[a] = (C + cutoff < nc - 1 ? C + cutoff : nc - 1) * r + r - lo[a];
     }
+    const int count = active ? w[0] * w[1] * w[2] : 0;
     double acc[P];
     static_for<0, P>([&](auto ia) { acc[decltype(ia)::value] = 0.0; });
-    for (int jz = lo[2]; jz <= hi[2]; ++jz) {
-        const int dz = iz - jz;
-        for (int jy = lo[1]; jy <= hi[1]; ++jy) {
-            const int dy = iy - jy;
-            for (int jx = lo[0]; jx <= hi[0]; ++jx) {
-                const int dx = ix - jx;
-                int cheb = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
-                cheb = cheb > abs(dz) ? cheb : abs(dz);
-                if (cheb <= cutoff) continue;
-                const float *g = table + (((int64_t)(dz + D) * W + (dy + D)) * W + (dx + D)) * Q;
-                const float *MJ = M + ((int64_t)jz * nf + jy) * nf + jx;
-                float mj[P];
-                static_for<0, P>([&](auto ia) {
-                    constexpr int a = decltype(ia)::value;
-                    mj[a] = MJ[(int64_t)a * K];
-                });
-                static_for<0, PO + 1>([&](auto il) {
-                    constexpr int l = decltype(il)::value;
-                    static_for<0, l + 1>([&](auto im) {
-                        constexpr int m = decltype(im)::value;
-                        float sre = 0.0f, sim = 0.0f;
-                        static_for<0, PO + 1>([&](auto ilam) {
-                            constexpr int lam = decltype(ilam)::value;
-                            constexpr int nn = l + lam;
-                            const float M0 = mj[lam * (lam + 1)];
-                            sre += re_s_c<nn, -m>(g) * M0;
-                            if constexpr (m > 0) sim += im_s_c<nn, -m>(g) * M0;
-                            static_for<1, lam + 1>([&](auto imu) {
-                                constexpr int mu = decltype(imu)::value;
-                                constexpr float sg = (mu & 1) ? -1.0f : 1.0f;
-                                const float A = re_s_c<nn, -(m + mu)>(g);
-                                const float B = im_s_c<nn, -(m + mu)>(g);
-                                const float C = sg * re_s_c<nn, -(m - mu)>(g);
-                                const float Dv = sg * im_s_c<nn, -(m - mu)>(g);
-                                const float Mr = mj[lam * (lam + 1) + mu];
-                                const float Mi = mj[lam * (lam + 1) - mu];
-                                sre += (A + C) * Mr - (B - Dv) * Mi;
-                                if constexpr (m > 0) sim += (B + Dv) * Mr + (A - C) * Mi;
-                            });
-                        });
-                        acc[l * (l + 1) + m] += (double)sre;
-                        if constexpr (m > 0) acc[l * (l + 1) - m] += (double)sim;
+    for (int sidx = part; sidx < count; sidx += split) {
+        const int jx = lo[0] + sidx % w[0];
+        const int t = sidx / w[0];
+        const int jy = lo[1] + t % w[1];
+        const int jz = lo[2] + t / w[1];
+        const int dx = ix - jx, dy = iy - jy, dz = iz - jz;
+        int cheb = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+        cheb = cheb > abs(dz) ? cheb : abs(dz);
+        if (cheb <= cutoff) continue;
+        const float *g = table + (((int64_t)(dz + D) * W + (dy + D)) * W + (dx + D)) * Q;
+        const float *MJ = M + ((int64_t)jz * nf + jy) * nf + jx;
+        float mj[P];
+        static_for<0, P>([&](auto ia) {
+            constexpr int a = decltype(ia)::value;
+            mj[a] = MJ[(int64_t)a * K];
+        });
+        static_for<0, PO + 1>([&](auto il) {
+            constexpr int l = decltype(il)::value;
+            static_for<0, l + 1>([&](auto im) {
+                constexpr int m = decltype(im)::value;
+                float sre = 0.0f, sim = 0.0f;
+                static_for<0, PO + 1>([&](auto ilam) {
+                    constexpr int lam = decltype(ilam)::value;
+                    constexpr int nn = l + lam;
+                    const float M0 = mj[lam * (lam + 1)];
+                    sre += re_s_c<nn, -m>(g) * M0;
+                    if constexpr (m > 0) sim += im_s_c<nn, -m>(g) * M0;
+                    static_for<1, lam + 1>([&](auto imu) {
+                        constexpr int mu = decltype(imu)::value;
+                        constexpr float sg = (mu & 1) ? -1.0f : 1.0f;
+                        const float A = re_s_c<nn, -(m + mu)>(g);
+                        const float B = im_s_c<nn, -(m + mu)>(g);
+                        const float C = sg * re_s_c<nn, -(m - mu)>(g);
+                        const float Dv = sg * im_s_c<nn, -(m - mu)>(g);
+                        const float Mr = mj[lam * (lam + 1) + mu];
+                        const float Mi = mj[lam * (lam + 1) - mu];
+                        sre += (A + C) * Mr - (B - Dv) * Mi;
+                        if constexpr (m > 0) sim += (B + Dv) * Mr + (A - C) * Mi;
                     });
                 });
-            }
-        }
+                acc[l * (l + 1) + m] += (double)sre;
+                if constexpr (m > 0) acc[l * (l + 1) - m] += (double)sim;
+            });
+        });
     }
+    for (int off = 1; off < split; off <<= 1)
+        static_for<0, P>([&](auto ia) {
+            constexpr int a = decltype(ia)::value;
+            acc[a] += __shfl_xor(acc[a], off, kHierCellThreads);
+        });
+    if (!active || part != 0) return;
     static_for<0, P>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
         L[(int64_t)a * K + I] = (float)acc[a];
@@ -201,10 +211,15 @@ hipError_t hier_cell_dispatch(const HierArgs &a, hipStream_t s) {
     } else {
         if (a.p != PO) return hier_cell_dispatch<PO + 1>(a, s);
         const int64_t K = (int64_t)a.nf * a.nf * a.nf;
+        // Lanes per cell: enough waves for four per SIMD (256 CUs x 4
+        // SIMDs), at most 8.
+        int split = 1;
+        while (split < 8 && K * split < (int64_t)4 * 1024 * kHierCellThreads) split <<= 1;
+        const int64_t nthr = K * split;
         hipLaunchKernelGGL(k_hier_m2l_cell<PO>,
-                           dim3((unsigned)((K + kHierCellThreads - 1) / kHierCellThreads)),
+                           dim3((unsigned)((nthr + kHierCellThreads - 1) / kHierCellThreads)),
                            dim3(kHierCellThreads), 0, s, a.M, a.L, a.table, a.nf, a.r, a.cutoff,
-                           a.D);
+                           a.D, split);
         return hipGetLastError();
     }
 }
