@@ -13,7 +13,7 @@ namespace pmmm {
 namespace {
 
 constexpr int kHierThreads = 256;
-constexpr int kHierCellMaxP = 4;
+constexpr int kHierCellMaxP = 7;
 
 // Values of the table row of one offset, as the real-storage components of
 // Re S_nn^k / Im S_nn^k for any -nn <= k <= nn (conjugate relation).
@@ -116,19 +116,30 @@ __device__ __forceinline__ float im_s_c(const float *g) {
     else return -g[NN * (NN + 1) + KK];
 }
 
-// A group of `split` lanes per target fine cell, every output row at once:
-// the lanes of a group take the cell's source cells in turn, and per source
-// cell the moments and the table row are read once and the (P x P) product
-// of eq. realmatrix is unrolled at compile time (order PO).  Per-source sums
-// in FP32, the sums over sources and over the group's lanes in FP64.
-// split is a power of two <= 64 (several lanes per cell fill the chip's
-// SIMDs when a fine mesh has few cells for a kernel of this register size).
+// Output orders of the row groups of the per-cell kernel: group g takes the
+// orders [hier_cut(PO, g), hier_cut(PO, g + 1)).  Up to order 4 one group
+// holds every row; above it the rows are shared out so that a lane's FP64
+// sums and the moments it holds stay within the register file.
+__host__ __device__ constexpr int hier_ngroups(int po) { return po <= 4 ? 1 : po - 3; }
+__host__ __device__ constexpr int hier_cut(int po, int g) {
+    return g == 0 ? 0 : g == hier_ngroups(po) ? po + 1 : (g == 1 ? 4 : g == 2 ? 6 : 7);
+}
+
+// A group of `split` lanes per target fine cell and row group: the lanes of
+// a group take the cell's source cells in turn, and per source cell the
+// moments and the table row are read once and the rows of orders
+// [LA, LE) of the (P x P) product of eq. realmatrix are unrolled at compile
+// time (order PO).  Per-source sums in FP32, the sums over sources and over
+// the group's lanes in FP64.  split is a power of two <= 64 (several lanes
+// per cell fill the chip's SIMDs when a fine mesh has few cells for a kernel
+// of this register size).
 constexpr int kHierCellThreads = 64;
-template <int PO>
-__global__ __launch_bounds__(kHierCellThreads) void k_hier_m2l_cell(
-    const float *__restrict__ M, float *__restrict__ L, const float *__restrict__ table, int nf,
-    int r, int cutoff, int D, int split) {
+template <int PO, int LA, int LE>
+__device__ __forceinline__ void hier_cell_rows(const float *__restrict__ M, float *__restrict__ L,
+                                               const float *__restrict__ table, int nf, int r,
+                                               int cutoff, int D, int split) {
     constexpr int P = nreal(PO), Q = nreal(2 * PO);
+    constexpr int A0 = LA * LA, NA = LE * LE - A0;
     const int64_t K = (int64_t)nf * nf * nf;
     const int part = (int)threadIdx.x & (split - 1);
     const int64_t I = ((int64_t)blockIdx.x * kHierCellThreads + threadIdx.x) / split;
@@ -145,8 +156,8 @@ __global__ __launch_bounds__(kHierCellThreads) void k_hier_m2l_cell(
         w[a] = (C + cutoff < nc - 1 ? C + cutoff : nc - 1) * r + r - lo[a];
     }
     const int count = active ? w[0] * w[1] * w[2] : 0;
-    double acc[P];
-    static_for<0, P>([&](auto ia) { acc[decltype(ia)::value] = 0.0; });
+    double acc[NA];
+    static_for<0, NA>([&](auto ia) { acc[decltype(ia)::value] = 0.0; });
     for (int sidx = part; sidx < count; sidx += split) {
         const int jx = lo[0] + sidx % w[0];
         const int t = sidx / w[0];
@@ -163,7 +174,7 @@ __global__ __launch_bounds__(kHierCellThreads) void k_hier_m2l_cell(
             constexpr int a = decltype(ia)::value;
             mj[a] = MJ[(int64_t)a * K];
         });
-        static_for<0, PO + 1>([&](auto il) {
+        static_for<LA, LE>([&](auto il) {
             constexpr int l = decltype(il)::value;
             static_for<0, l + 1>([&](auto im) {
                 constexpr int m = decltype(im)::value;
@@ -187,20 +198,33 @@ __global__ __launch_bounds__(kHierCellThreads) void k_hier_m2l_cell(
                         if constexpr (m > 0) sim += (B + Dv) * Mr + (A - C) * Mi;
                     });
                 });
-                acc[l * (l + 1) + m] += (double)sre;
-                if constexpr (m > 0) acc[l * (l + 1) - m] += (double)sim;
+                acc[l * (l + 1) + m - A0] += (double)sre;
+                if constexpr (m > 0) acc[l * (l + 1) - m - A0] += (double)sim;
             });
         });
     }
     for (int off = 1; off < split; off <<= 1)
-        static_for<0, P>([&](auto ia) {
+        static_for<0, NA>([&](auto ia) {
             constexpr int a = decltype(ia)::value;
             acc[a] += __shfl_xor(acc[a], off, kHierCellThreads);
         });
     if (!active || part != 0) return;
-    static_for<0, P>([&](auto ia) {
+    static_for<0, NA>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
-        L[(int64_t)a * K + I] = (float)acc[a];
+        L[(int64_t)(A0 + a) * K + I] = (float)acc[a];
+    });
+}
+
+// blockIdx.y selects the row group.
+template <int PO>
+__global__ __launch_bounds__(kHierCellThreads) void k_hier_m2l_cell(
+    const float *__restrict__ M, float *__restrict__ L, const float *__restrict__ table, int nf,
+    int r, int cutoff, int D, int split) {
+    static_for<0, hier_ngroups(PO)>([&](auto ig) {
+        constexpr int gi = decltype(ig)::value;
+        if (blockIdx.y == gi)
+            hier_cell_rows<PO, hier_cut(PO, gi), hier_cut(PO, gi + 1)>(M, L, table, nf, r, cutoff,
+                                                                        D, split);
     });
 }
 
@@ -211,13 +235,14 @@ hipError_t hier_cell_dispatch(const HierArgs &a, hipStream_t s) {
     } else {
         if (a.p != PO) return hier_cell_dispatch<PO + 1>(a, s);
         const int64_t K = (int64_t)a.nf * a.nf * a.nf;
-        // Lanes per cell: enough waves for four per SIMD (256 CUs x 4
-        // SIMDs), at most 8.
+        constexpr int NG = hier_ngroups(PO);
+        // Lanes per cell and row group: enough waves for four per SIMD
+        // (256 CUs x 4 SIMDs), at most 8.
         int split = 1;
-        while (split < 8 && K * split < (int64_t)4 * 1024 * kHierCellThreads) split <<= 1;
+        while (split < 8 && K * NG * split < (int64_t)4 * 1024 * kHierCellThreads) split <<= 1;
         const int64_t nthr = K * split;
         hipLaunchKernelGGL(k_hier_m2l_cell<PO>,
-                           dim3((unsigned)((nthr + kHierCellThreads - 1) / kHierCellThreads)),
+                           dim3((unsigned)((nthr + kHierCellThreads - 1) / kHierCellThreads), NG),
                            dim3(kHierCellThreads), 0, s, a.M, a.L, a.table, a.nf, a.r, a.cutoff,
                            a.D, split);
         return hipGetLastError();
