@@ -495,9 +495,12 @@ template <typename T>
 static int enqueue_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, const T *y,
                         const T *z, const T *q, T *phi, T *gx, T *gy, T *gz, int accumulate,
                         const PBuf &pb, bool timed, hipStream_t s) {
-    // near and total calls, and large far-field calls, leave their results
-    // in sorted order (16-byte records) and send them back in one pass
+    // near and total calls, and large far-field calls, stage their results
+    // as 16-byte records and send them to the outputs in one pass: in
+    // sorted order (with each particle's sorted slot from the binning) when
+    // the near field adds to them, else at the caller's indices
     const bool staged = mode != kFar || n >= kStagedL2PMinN;
+    const bool sorted_stage = mode == kNear || mode == kTotal || mode == kHierTotal;
     const int group = pl->tune_group > 0 ? pl->tune_group : group_for((double)n / (double)pl->K);
     const int dense_thr = dense_threshold_for(group);
 
@@ -524,7 +527,7 @@ static int enqueue_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, c
         b.items_cap = pb.items_cap;
         b.slots_cap = pb.slots_cap;
         b.small = pl->small;
-        b.pos = staged ? pb.pos : nullptr;
+        b.pos = sorted_stage ? pb.pos : nullptr;
         b.tile_sums = pb.tile_sums;
         b.dense_threshold = dense_thr;
         b.sorted = pb.sorted;
@@ -603,13 +606,13 @@ static int enqueue_impl(pmmm_plan_s *pl, CallMode mode, int64_t n, const T *x, c
             l.gz = gz;
             if (staged) {
                 l.staged = pb.staged;
-                l.pos = pb.pos;
+                l.pos = sorted_stage ? pb.pos : nullptr;
             }
             PMMM_HIP(launch_l2p<T>(l, s));
             if (mode == kFar && staged)
-                PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz, 0, s));
+                PMMM_HIP(launch_unpermute<T>(n, nullptr, pb.staged, phi, gx, gy, gz, 0, s));
             if (mode == kHierFine)   // added to the coarse far field already in the outputs
-                PMMM_HIP(launch_unpermute<T>(n, pb.pos, pb.staged, phi, gx, gy, gz, 1, s));
+                PMMM_HIP(launch_unpermute<T>(n, nullptr, pb.staged, phi, gx, gy, gz, 1, s));
         }
     }
     if (mode == kNear || mode == kTotal || mode == kHierTotal) {

@@ -703,8 +703,9 @@ struct L2PArgs {
     double alpha_cell;              // alpha h
     double inv_h;                   // 1 / h in the caller's length unit
     void *phi, *gx, *gy, *gz;
-    void *staged;                   // out4<T>[n] in sorted order, or null: scatter directly
-    const int *pos;                 // [n] sorted slot per caller index (with staged)
+    void *staged;                   // out4<T>[n] results, or null: scatter directly
+    const int *pos;                 // with staged: [n] sorted slot per caller index, and the
+                                    // records in sorted order; null: records at caller indices
     const int64_t *prange;          // batch (see BinArgs)
     int nsys;
     int64_t max_np;
@@ -712,8 +713,8 @@ struct L2PArgs {
 template <typename T>
 hipError_t launch_l2p(const L2PArgs &a, hipStream_t s);
 
-// Sorted-order results back to the caller's order (out[i] = or +=
-// staged[pos[i]]).
+// Staged results into the caller's outputs (out[i] = or += staged[pos[i]],
+// or staged[i] when pos is null).
 template <typename T>
 hipError_t launch_unpermute(int64_t n, const int *pos, const void *staged, void *phi, void *gx,
                             void *gy, void *gz, int accumulate, hipStream_t s);

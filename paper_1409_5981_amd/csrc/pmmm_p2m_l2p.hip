@@ -11,9 +11,11 @@
 //              periodic system (App. B, correction procedure; the uniform
 //              corrections are already in L); results rescaled to the
 //              caller's units and scattered to input order -- for large N
-//              written in sorted order instead (16-byte stores) and sent
-//              back by k_unpermute, one 16-byte gather per particle in place
-//              of four scattered 4-byte stores.
+//              as one 16-byte record per particle instead, at the caller's
+//              index (or in sorted order when the near field adds to it),
+//              which k_unpermute splits into the four outputs (after a
+//              16-byte gather in the sorted case), in place of four
+//              scattered 4-byte stores.
 #include "pmmm_internal.h"
 
 namespace pmmm {
@@ -216,6 +218,7 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
                                              T *__restrict__ gx_out, T *__restrict__ gy_out,
                                              T *__restrict__ gz_out,
                                              out4<T> *__restrict__ staged,
+                                             int staged_caller,
                                              const int64_t *__restrict__ prange) {
     constexpr int P = nreal(PO);
     int64_t p0, np;
@@ -282,8 +285,10 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
     }
     const T ih2 = inv_h * inv_h;
     if (staged != nullptr) {
-        // sorted order, one 16-byte store; k_unpermute sends it back
-        staged[s] = out4<T>{ph * inv_h, gx * ih2, gy * ih2, gz * ih2};
+        // one 16-byte store, in sorted order (the near field adds to it
+        // there) or at the caller's index; k_unpermute writes the outputs
+        staged[staged_caller ? (int64_t)perm[s] : s] =
+            out4<T>{ph * inv_h, gx * ih2, gy * ih2, gz * ih2};
         return;
     }
     const int i = perm[s];
@@ -294,7 +299,8 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
 }
 
 // Results back to the caller's order: particle i reads its sorted slot's
-// record (one 16-byte gather) and writes the four outputs coalesced.
+// record (one 16-byte gather; pos null: the records are in the caller's
+// order already) and writes the four outputs coalesced.
 template <typename T>
 __global__ void __launch_bounds__(256) k_unpermute(int64_t n, const int *__restrict__ pos,
                                                    const out4<T> *__restrict__ staged,
@@ -303,8 +309,8 @@ __global__ void __launch_bounds__(256) k_unpermute(int64_t n, const int *__restr
                                                    int accumulate) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int g = pos[i];
-    if (g < 0 || (int64_t)g >= n) return;  // only reachable with inconsistent counts
+    const int64_t g = pos != nullptr ? (int64_t)pos[i] : i;
+    if (g < 0 || g >= n) return;  // only reachable with inconsistent counts
     const out4<T> v = staged[g];
     if (accumulate) {
         phi_out[i] += v.phi;
@@ -387,7 +393,8 @@ static hipError_t l2p_launch(const L2PArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_l2p<PO, T>), dim3(blocks, nsys), dim3(256), 0, s, a.n, K, a.periodic,
                        (const particle4<T> *)a.sorted, a.scell, a.perm, (const T *)a.L,
                        a.sums, T(a.alpha_cell), T(a.inv_h), (T *)a.phi,
-                       (T *)a.gx, (T *)a.gy, (T *)a.gz, (out4<T> *)a.staged, a.prange);
+                       (T *)a.gx, (T *)a.gy, (T *)a.gz, (out4<T> *)a.staged,
+                       a.pos == nullptr ? 1 : 0, a.prange);
     if (a.staged != nullptr && a.prange != nullptr) return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -396,7 +403,7 @@ template <typename T>
 hipError_t launch_unpermute(int64_t n, const int *pos, const void *staged, void *phi, void *gx,
                             void *gy, void *gz, int accumulate, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    if (pos == nullptr || staged == nullptr) return hipErrorInvalidValue;
+    if (staged == nullptr) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_unpermute<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pos,
                        (const out4<T> *)staged, (T *)phi, (T *)gx, (T *)gy, (T *)gz, accumulate);
     return hipGetLastError();
