@@ -299,6 +299,7 @@ WORKLOADS = {
     "multi_periodic_n1048576_m32_p6_s64": ("periodic", "f32"),
     "batch_periodic_256sys": ("periodic", "f32"),
     "hier_open_n1048576_m16r2_p4_c1": ("open", "f32"),
+    "hier_total_plummer_n4194304_m64r2_p4_c1": ("open", "f32"),
 }
 
 
@@ -336,7 +337,7 @@ def main():
         sys.exit(2)
 
     workload = args.workload
-    single = not (workload.startswith("multi_") or workload.startswith("batch_"))
+    single = not workload.startswith(("multi_", "batch_", "hier_"))
     cpu_proc = None
     if single and not args.no_cpu_baseline:
         # the oracle runs on the host beside the GPU measurement
@@ -730,10 +731,58 @@ def bench_batch(args, workload):
     print(json.dumps(rec), flush=True)
 
 
+def _near_pairs(x, y, z, nc, c):
+    """Ordered pairs i != j whose cells (nc^3 over the unit box) are within c
+    of each other (Chebyshev): the near field's pair count."""
+    import numpy as np
+    idx = [np.clip((np.asarray(a, dtype=np.float64) * nc).astype(np.int64), 0, nc - 1)
+           for a in (x, y, z)]
+    cnt = np.bincount((idx[2] * nc + idx[1]) * nc + idx[0], minlength=nc ** 3)
+    cnt = cnt.reshape(nc, nc, nc).astype(np.float64)
+    pad = np.pad(cnt, c)
+    tot = 0.0
+    for dz in range(-c, c + 1):
+        for dy in range(-c, c + 1):
+            for dx in range(-c, c + 1):
+                tot += float(np.sum(cnt * pad[c + dz:c + dz + nc, c + dy:c + dy + nc,
+                                              c + dx:c + dx + nc]))
+    return int(tot) - len(idx[0])
+
+
+def _fine_pairs(n, r, c):
+    """Pairs of fine cells (target, source) whose coarse cells are within c
+    and fine cells are not: the fine level's eq. M2L products, counted
+    exactly."""
+    import numpy as np
+    nf = n * r
+    cells = np.arange(nf)
+    D = (c + 1) * r - 1
+    per_axis = {}                 # offset d -> targets i with source i - d in a near coarse cell
+    for d in range(-D, D + 1):
+        i = cells[max(0, d):min(nf, nf + d)]
+        per_axis[d] = int(np.sum(np.abs(i // r - (i - d) // r) <= c))
+    pairs = 0
+    for dz in range(-D, D + 1):
+        for dy in range(-D, D + 1):
+            for dx in range(-D, D + 1):
+                if max(abs(dx), abs(dy), abs(dz)) <= c:
+                    continue
+                pairs += per_axis[dx] * per_axis[dy] * per_axis[dz]
+    return pairs
+
+
 def bench_hier(args, workload):
-    """Two-level hierarchical far field (pmmm_hier_far_f32, Sec. 5.2): 2^20
-    uniform particles with neutral +/-1 charges in the unit box, coarse 16^3
-    open mesh refined by 2 (fine 32^3), p = 4, c = 1.  One step is one call.
+    """Two-level hierarchical PMMM (pmmm_hier_*, Sec. 5.2).  One step is one
+    call.
+      hier_open_n1048576_m16r2_p4_c1: the far field of 2^20 uniform
+        particles with neutral +/-1 charges in the unit box, coarse 16^3
+        open mesh refined by 2 (fine 32^3), p = 4, c = 1;
+      hier_total_plummer_n4194304_m64r2_p4_c1: the total field (far + near)
+        of the 2^22-particle Plummer sphere of the default workload, coarse
+        64^3 refined by 2 (fine 128^3), p = 4, c = 1, beside the total field
+        of the uniform 64^3 plan at the same p and c on the same particles
+        (the clustered case the hierarchy is for: the near field shrinks
+        with the finer cells).
     The roofline takes the fine level's algorithmic work, one real (P x P)
     eq. M2L product per pair of fine cells whose coarse cells are near and
     fine cells are not, over the whole call's time (a lower bound for the
@@ -741,12 +790,20 @@ def bench_hier(args, workload):
     import numpy as np
     import torch
     from paper_1409_5981_amd import inputs
-    from paper_1409_5981_amd._lib import Hier
+    from paper_1409_5981_amd._lib import Hier, Plan
 
-    N, n, r, p, c = 1 << 20, 16, 2, 4, 1
-    rng = np.random.Generator(np.random.PCG64(10))
-    x, y, z = inputs.uniform_positions(rng, N, np.float32)
-    q = inputs.neutral_pm1(rng, N, np.float32)
+    total = workload.startswith("hier_total_")
+    if total:
+        ps = inputs.plummer_sphere()
+        x, y, z, q = ps.x, ps.y, ps.z, ps.q
+        N, n, r, p, c = ps.n, 64, 2, 4, 1
+        K, W = min(args.steps, 10), min(args.warmup, 2)
+    else:
+        N, n, r, p, c = 1 << 20, 16, 2, 4, 1
+        rng = np.random.Generator(np.random.PCG64(10))
+        x, y, z = inputs.uniform_positions(rng, N, np.float32)
+        q = inputs.neutral_pm1(rng, N, np.float32)
+        K, W = args.steps, max(3, args.warmup)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     xt, yt, zt, qt = (torch.from_numpy(a).to(dev) for a in (x, y, z, q))
@@ -755,49 +812,63 @@ def bench_hier(args, workload):
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
     torch.cuda.set_stream(stream)
-    for _ in range(max(3, args.warmup)):
-        h.far(xt, yt, zt, qt, out=out, stream=stream)
+    call = h.total if total else h.far
+    for _ in range(W):
+        call(xt, yt, zt, qt, out=out, stream=stream)
     torch.cuda.synchronize()
-    K = args.steps
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(K):
-        h.far(xt, yt, zt, qt, out=out, stream=stream)
+        call(xt, yt, zt, qt, out=out, stream=stream)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     h.sync_status()
     step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(K))
     t_med = step_ms[len(step_ms) // 2] / 1e3
-    # pairs of fine cells handled by the fine level, counted exactly
     nf = n * r
-    cells = np.arange(nf)
-    per_axis = {}                 # offset d -> targets i with source i - d in a near coarse cell
-    for d in range(-((c + 1) * r - 1), (c + 1) * r):
-        i = cells[max(0, d):min(nf, nf + d)]
-        per_axis[d] = int(np.sum(np.abs(i // r - (i - d) // r) <= c))
-    D = (c + 1) * r - 1
-    pairs = 0
-    for dz in range(-D, D + 1):
-        for dy in range(-D, D + 1):
-            for dx in range(-D, D + 1):
-                if max(abs(dx), abs(dy), abs(dz)) <= c:
-                    continue
-                pairs += per_axis[dx] * per_axis[dy] * per_axis[dz]
+    pairs = _fine_pairs(n, r, c)
     P = (p + 1) ** 2
     flops = 2 * P * P * pairs
     roof = {"bound": "alu", "achieved": flops / t_med / 1e12, "peak": FP32_PEAK / 1e12,
             "unit": "TFLOP/s", "frac": flops / t_med / FP32_PEAK, "traffic": None,
             "kernel": "whole hierarchical call (fine-level flops)", "algorithmic_flops": flops,
             "fine_pairs": pairs}
+    extra = {}
+    if total:
+        # the uniform plan's total field on the same particles, and how
+        # closely the two agree (the same method error, other cells)
+        hout = [o.double().cpu().numpy() for o in out]
+        plan = Plan(n, p, "open", cutoff=c, n_max=N)
+        uout = tuple(torch.empty(N, dtype=torch.float32, device=dev) for _ in range(4))
+        plan.total(xt, yt, zt, qt, out=uout, stream=stream)
+        torch.cuda.synchronize()
+        ut = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.total(xt, yt, zt, qt, out=uout, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ut.append(e0.elapsed_time(e1))
+        plan.sync_status()
+        u = [o.double().cpu().numpy() for o in uout]
+        gh, gu = np.stack(hout[1:], 1), np.stack(u[1:], 1)
+        extra = {"uniform_total_ms": sorted(ut)[1], "hier_total_ms": step_ms[len(step_ms) // 2],
+                 "speedup_vs_uniform": sorted(ut)[1] / step_ms[len(step_ms) // 2],
+                 "near_pairs_hier": _near_pairs(x, y, z, nf, c),
+                 "near_pairs_uniform": _near_pairs(x, y, z, n, c),
+                 "grad_rel_rms_hier_vs_uniform":
+                     float(np.sqrt(np.sum((gh - gu) ** 2) / np.sum(gu ** 2)))}
     rec = {
-        "metric": "particles/s, two-level hierarchical PMMM far field",
+        "metric": ("particles/s, two-level hierarchical PMMM total field (far + near)" if total
+                   else "particles/s, two-level hierarchical PMMM far field"),
         "value": N * K / el,
         "unit": "particles/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": max(3, args.warmup),
+        "warmup": W,
         "ms_per_step": el / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -809,6 +880,7 @@ def bench_hier(args, workload):
         "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0],
                     "max": step_ms[-1], "events": K},
         "roofline": roof,
+        **extra,
         "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
