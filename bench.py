@@ -37,6 +37,9 @@ if ROOT not in sys.path:
 METRIC = "particles/s, PMMM far field (P2M+FFT M2L+L2P) at rel. RMS force err <=1e-6"
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector
+# FP32 operations of one near-field pair (k_near): the offset (4), r^2 (5),
+# rsq (1), q/r and the potential sum (2), 1/r^3 (2), three gradient FMAs (6)
+NEAR_FLOPS_PER_PAIR = 20
 FP64_PEAK = 78.6e12
 BF16_PEAK = 2.5e15           # FLOP/s, MI355X dense BF16 matrix cores
 MULTI_METRIC = ("particle x charge-set evaluations/s, PMMM far field of many charge sets "
@@ -837,6 +840,14 @@ def bench_hier(args, workload):
             "fine_pairs": pairs}
     extra = {}
     if total:
+        # the near field's pairs on the fine mesh at NEAR_FLOPS_PER_PAIR
+        # FP32 operations each, with the fine level's products, over the
+        # whole call (the near field takes most of it)
+        near_h = _near_pairs(x, y, z, nf, c)
+        work = flops + NEAR_FLOPS_PER_PAIR * near_h
+        roof.update({"achieved": work / t_med / 1e12, "frac": work / t_med / FP32_PEAK,
+                     "kernel": "whole hierarchical total call (near-field pairs and fine-level flops)",
+                     "algorithmic_flops": work, "near_pairs": near_h})
         # the uniform plan's total field on the same particles, and how
         # closely the two agree (the same method error, other cells)
         hout = [o.double().cpu().numpy() for o in out]
@@ -857,7 +868,7 @@ def bench_hier(args, workload):
         gh, gu = np.stack(hout[1:], 1), np.stack(u[1:], 1)
         extra = {"uniform_total_ms": sorted(ut)[1], "hier_total_ms": step_ms[len(step_ms) // 2],
                  "speedup_vs_uniform": sorted(ut)[1] / step_ms[len(step_ms) // 2],
-                 "near_pairs_hier": _near_pairs(x, y, z, nf, c),
+                 "near_pairs_hier": near_h,
                  "near_pairs_uniform": _near_pairs(x, y, z, n, c),
                  "grad_rel_rms_hier_vs_uniform":
                      float(np.sqrt(np.sum((gh - gu) ** 2) / np.sum(gu ** 2)))}
