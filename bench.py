@@ -786,10 +786,11 @@ def bench_hier(args, workload):
         of the uniform 64^3 plan at the same p and c on the same particles
         (the clustered case the hierarchy is for: the near field shrinks
         with the finer cells).
-    The roofline takes the fine level's algorithmic work, one real (P x P)
-    eq. M2L product per pair of fine cells whose coarse cells are near and
-    fine cells are not, over the whole call's time (a lower bound for the
-    fine kernel alone)."""
+    The far-field line's roofline takes the fine level's algorithmic work,
+    one real (P x P) eq. M2L product per pair of fine cells whose coarse
+    cells are near and fine cells are not, over that kernel's own time (HIP
+    events around it); the total-field line's takes the near-field pairs
+    and those products over the whole call."""
     import numpy as np
     import torch
     from paper_1409_5981_amd import inputs
@@ -830,14 +831,25 @@ def bench_hier(args, workload):
     h.sync_status()
     step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(K))
     t_med = step_ms[len(step_ms) // 2] / 1e3
+    # the fine level's kernel alone: HIP events around it on the call's
+    # stream, in calls of their own after the timed ones
+    h.set_profiling(["column"])
+    h.read_profile(1)
+    for _ in range(min(K, 20)):
+        call(xt, yt, zt, qt, out=out, stream=stream)
+    torch.cuda.synchronize()
+    fms, fcnt = h.read_profile(1)["column"]
+    h.set_profiling([])
+    t_fine = fms / max(fcnt, 1) / 1e3
     nf = n * r
     pairs = _fine_pairs(n, r, c)
     P = (p + 1) ** 2
     flops = 2 * P * P * pairs
-    roof = {"bound": "alu", "achieved": flops / t_med / 1e12, "peak": FP32_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": flops / t_med / FP32_PEAK, "traffic": None,
-            "kernel": "whole hierarchical call (fine-level flops)", "algorithmic_flops": flops,
-            "fine_pairs": pairs}
+    roof = {"bound": "alu", "achieved": flops / t_fine / 1e12, "peak": FP32_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": flops / t_fine / FP32_PEAK, "traffic": None,
+            "kernel": "fine-level eq. M2L sums (k_hier_m2l_cell)", "kernel_us": t_fine * 1e6,
+            "algorithmic_flops": flops, "fine_pairs": pairs,
+            "call_frac": flops / t_med / FP32_PEAK}
     extra = {}
     if total:
         # the near field's pairs on the fine mesh at NEAR_FLOPS_PER_PAIR
@@ -847,7 +859,9 @@ def bench_hier(args, workload):
         work = flops + NEAR_FLOPS_PER_PAIR * near_h
         roof.update({"achieved": work / t_med / 1e12, "frac": work / t_med / FP32_PEAK,
                      "kernel": "whole hierarchical total call (near-field pairs and fine-level flops)",
-                     "algorithmic_flops": work, "near_pairs": near_h})
+                     "algorithmic_flops": work, "near_pairs": near_h,
+                     "fine_frac": flops / t_fine / FP32_PEAK})
+        roof.pop("call_frac")
         # the uniform plan's total field on the same particles, and how
         # closely the two agree (the same method error, other cells)
         hout = [o.double().cpu().numpy() for o in out]

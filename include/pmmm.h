@@ -258,6 +258,14 @@ int pmmm_hier_far_f32(pmmm_hier h, int64_t n, const float *x, const float *y, co
 int pmmm_hier_total_f32(pmmm_hier h, int64_t n, const float *x, const float *y, const float *z,
                         const float *q, float *phi, float *gx, float *gy, float *gz, void *stream);
 int pmmm_hier_sync_status(pmmm_hier h);
+/* Per-stage timing of a hierarchy's two levels, as pmmm_plan_set_profiling /
+ * pmmm_plan_read_profile: the mask applies to both levels; level 0 reads the
+ * coarse PMMM's stages, level 1 the fine level's (binning, P2M, the fine
+ * eq. M2L sums as PMMM_STAGE_COLUMN, L2P and the near field).  Errors:
+ * PMMM_EINVAL for a NULL hierarchy or another level, plus those of
+ * pmmm_plan_read_profile. */
+int pmmm_hier_set_profiling(pmmm_hier h, unsigned mask);
+int pmmm_hier_read_profile(pmmm_hier h, int level, double *ms, int64_t *count, int reset);
 
 /* Per-order fixed-point records of a coefficient mesh (Sec. 5.3 and its
  * footnote: an order-l coefficient carries 3 (p + 1 - l) bits, so a cell

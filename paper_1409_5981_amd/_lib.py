@@ -35,7 +35,7 @@ EXPORTS = [
     "pmmm_batch_create", "pmmm_batch_destroy", "pmmm_batch_far_f32", "pmmm_batch_classes",
     "pmmm_batch_set_graphs", "pmmm_batch_sync_status",
     "pmmm_hier_create", "pmmm_hier_destroy", "pmmm_hier_far_f32", "pmmm_hier_total_f32",
-    "pmmm_hier_sync_status",
+    "pmmm_hier_sync_status", "pmmm_hier_set_profiling", "pmmm_hier_read_profile",
     "pmmm_coef_record_words", "pmmm_coef_pack_f32", "pmmm_coef_unpack_f32",
     "pmmm_coef_compose_f32", "pmmm_coef_split_f32",
     "pmmm_error_string", "pmmm_last_error",
@@ -151,6 +151,11 @@ def load():
         f.restype = ci
     L.pmmm_hier_sync_status.argtypes = [vp]
     L.pmmm_hier_sync_status.restype = ci
+    L.pmmm_hier_set_profiling.argtypes = [vp, ctypes.c_uint]
+    L.pmmm_hier_set_profiling.restype = ci
+    L.pmmm_hier_read_profile.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ci]
+    L.pmmm_hier_read_profile.restype = ci
     L.pmmm_coef_record_words.argtypes = [ci]
     L.pmmm_coef_record_words.restype = ci
     L.pmmm_coef_pack_f32.argtypes = [ci, i64, vp, vp, vp, ctypes.c_uint, vp]
@@ -520,6 +525,22 @@ class Hier:
 
     def sync_status(self):
         _check(load().pmmm_hier_sync_status(self._h))
+
+    def set_profiling(self, stages):
+        """Enable HIP-event timing of the named stages (see STAGES) on both
+        levels; the fine level's eq. M2L sums are its "column" stage."""
+        mask = 0
+        for st in stages:
+            mask |= 1 << STAGES.index(st)
+        _check(load().pmmm_hier_set_profiling(self._h, mask))
+
+    def read_profile(self, level, reset=True):
+        """{stage: (total ms, timed launches)} of level 0 (coarse) or 1
+        (fine) since the last reset."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        _check(load().pmmm_hier_read_profile(self._h, int(level), ms, cnt, int(bool(reset))))
+        return {st: (ms[i], cnt[i]) for i, st in enumerate(STAGES)}
 
 
 # ------------------------------------------------- coefficient storage calls

@@ -1450,6 +1450,23 @@ int pmmm_hier_total_f32(pmmm_hier h, int64_t n, const float *x, const float *y, 
     return call_impl<float>(h->fine, kHierTotal, n, x, y, z, q, phi, gx, gy, gz, 0, stream);
 }
 
+int pmmm_hier_set_profiling(pmmm_hier h, unsigned mask) {
+    if (!h) {
+        set_error("hierarchy is NULL");
+        return PMMM_EINVAL;
+    }
+    const int rc = pmmm_plan_set_profiling(h->coarse, mask);
+    return rc != PMMM_OK ? rc : pmmm_plan_set_profiling(h->fine, mask);
+}
+
+int pmmm_hier_read_profile(pmmm_hier h, int level, double *ms, int64_t *count, int reset) {
+    if (!h || (level != 0 && level != 1)) {
+        set_error(!h ? "hierarchy is NULL" : "level must be 0 (coarse) or 1 (fine)");
+        return PMMM_EINVAL;
+    }
+    return pmmm_plan_read_profile(level == 0 ? h->coarse : h->fine, ms, count, reset);
+}
+
 int pmmm_hier_sync_status(pmmm_hier h) {
     if (!h) {
         set_error("hierarchy is NULL");

@@ -143,3 +143,32 @@ def test_hier_refine_eight_total_field_vs_direct_sum():
     e = exact.rel_rms(res["grad"], dg)
     print(f"hier r=8 total field vs direct sum: rel-RMS grad {e:.2e}", flush=True)
     assert e < 5e-3
+
+
+def test_hier_stage_profiling():
+    """pmmm_hier_set_profiling / _read_profile: the fine level's eq. M2L sums
+    are timed as its column stage, the coarse PMMM's stages on level 0, and
+    another level is rejected."""
+    import torch
+    from paper_1409_5981_amd._lib import Hier, PMMMError
+    pos, q = _set(2000, 41)
+    h = Hier(4, 3, 2, cutoff=1)
+    x, y, z = (torch.from_numpy(np.ascontiguousarray(pos[:, a])).cuda() for a in range(3))
+    qt = torch.from_numpy(q).cuda()
+    h.set_profiling(["bin", "column", "l2p"])
+    for _ in range(3):
+        h.far(x, y, z, qt)
+    torch.cuda.synchronize()
+    fine, coarse = h.read_profile(1), h.read_profile(0)
+    for prof in (fine, coarse):
+        for st in ("bin", "column", "l2p"):
+            ms, cnt = prof[st]
+            assert cnt == 3 and ms > 0.0
+        assert prof["p2m"] == (0.0, 0)
+    assert h.read_profile(1)["column"] == (0.0, 0)      # reset by the read before
+    h.set_profiling([])
+    h.far(x, y, z, qt)
+    torch.cuda.synchronize()
+    assert h.read_profile(1)["column"] == (0.0, 0)
+    with pytest.raises(PMMMError):
+        h.read_profile(2)
