@@ -125,6 +125,9 @@ __host__ __device__ constexpr int hier_cut(int po, int g) {
     return g == 0 ? 0 : g == hier_ngroups(po) ? po + 1 : (g == 1 ? 4 : g == 2 ? 6 : 7);
 }
 
+// Index of output row (l, m >= 0) in l-major order.
+__host__ __device__ constexpr int hier_row(int l, int m) { return l * (l + 1) / 2 + m; }
+
 // A group of `split` lanes per target fine cell and row group: the lanes of
 // a group take the cell's source cells in turn, and per source cell the
 // moments and the table row are read once and the rows of orders
@@ -140,6 +143,7 @@ __device__ __forceinline__ void hier_cell_rows(const float *__restrict__ M, floa
                                                int cutoff, int D, int split) {
     constexpr int P = nreal(PO), Q = nreal(2 * PO);
     constexpr int A0 = LA * LA, NA = LE * LE - A0;
+    constexpr int NR = hier_row(LE, 0) - hier_row(LA, 0);   // rows (l, m >= 0), LA <= l < LE
     const int64_t K = (int64_t)nf * nf * nf;
     const int part = (int)threadIdx.x & (split - 1);
     const int64_t I = ((int64_t)blockIdx.x * kHierCellThreads + threadIdx.x) / split;
@@ -174,32 +178,65 @@ __device__ __forceinline__ void hier_cell_rows(const float *__restrict__ M, floa
             constexpr int a = decltype(ia)::value;
             mj[a] = MJ[(int64_t)a * K];
         });
+        // FP32 sums of this source, one per output row (l, m >= 0); the
+        // coefficient sums of a (nn, m, mu) are formed once and serve every
+        // split nn = l + lambda
+        float sre[NR], sim[NR];
+        static_for<0, NR>([&](auto ir) {
+            sre[decltype(ir)::value] = 0.0f;
+            sim[decltype(ir)::value] = 0.0f;
+        });
+        static_for<LA, LE + PO>([&](auto inn) {
+            constexpr int nn = decltype(inn)::value;
+            static_for<0, (nn < LE - 1 ? nn : LE - 1) + 1>([&](auto im) {
+                constexpr int m = decltype(im)::value;
+                static_for<0, (nn < PO ? nn : PO) + 1>([&](auto imu) {
+                    constexpr int mu = decltype(imu)::value;
+                    // splits l + lambda = nn with LA <= l < LE, m <= l,
+                    // mu <= lambda <= PO
+                    constexpr int l_lo0 = nn - PO > LA ? nn - PO : LA;
+                    constexpr int l_lo = l_lo0 > m ? l_lo0 : m;
+                    constexpr int l_hi0 = nn - mu < LE - 1 ? nn - mu : LE - 1;
+                    if constexpr (l_lo <= l_hi0) {
+                        if constexpr (mu == 0) {
+                            const float a0 = re_s_c<nn, -m>(g);
+                            const float b0 = im_s_c<nn, -m>(g);
+                            static_for<l_lo, l_hi0 + 1>([&](auto il) {
+                                constexpr int l = decltype(il)::value;
+                                constexpr int lam = nn - l;
+                                constexpr int row = hier_row(l, m) - hier_row(LA, 0);
+                                const float M0 = mj[lam * (lam + 1)];
+                                sre[row] += a0 * M0;
+                                if constexpr (m > 0) sim[row] += b0 * M0;
+                            });
+                        } else {
+                            constexpr float sg = (mu & 1) ? -1.0f : 1.0f;
+                            const float A = re_s_c<nn, -(m + mu)>(g);
+                            const float B = im_s_c<nn, -(m + mu)>(g);
+                            const float C = sg * re_s_c<nn, -(m - mu)>(g);
+                            const float Dv = sg * im_s_c<nn, -(m - mu)>(g);
+                            const float s1 = A + C, s2 = B - Dv, s3 = B + Dv, s4 = A - C;
+                            static_for<l_lo, l_hi0 + 1>([&](auto il) {
+                                constexpr int l = decltype(il)::value;
+                                constexpr int lam = nn - l;
+                                constexpr int row = hier_row(l, m) - hier_row(LA, 0);
+                                const float Mr = mj[lam * (lam + 1) + mu];
+                                const float Mi = mj[lam * (lam + 1) - mu];
+                                sre[row] += s1 * Mr - s2 * Mi;
+                                if constexpr (m > 0) sim[row] += s3 * Mr + s4 * Mi;
+                            });
+                        }
+                    }
+                });
+            });
+        });
         static_for<LA, LE>([&](auto il) {
             constexpr int l = decltype(il)::value;
             static_for<0, l + 1>([&](auto im) {
                 constexpr int m = decltype(im)::value;
-                float sre = 0.0f, sim = 0.0f;
-                static_for<0, PO + 1>([&](auto ilam) {
-                    constexpr int lam = decltype(ilam)::value;
-                    constexpr int nn = l + lam;
-                    const float M0 = mj[lam * (lam + 1)];
-                    sre += re_s_c<nn, -m>(g) * M0;
-                    if constexpr (m > 0) sim += im_s_c<nn, -m>(g) * M0;
-                    static_for<1, lam + 1>([&](auto imu) {
-                        constexpr int mu = decltype(imu)::value;
-                        constexpr float sg = (mu & 1) ? -1.0f : 1.0f;
-                        const float A = re_s_c<nn, -(m + mu)>(g);
-                        const float B = im_s_c<nn, -(m + mu)>(g);
-                        const float C = sg * re_s_c<nn, -(m - mu)>(g);
-                        const float Dv = sg * im_s_c<nn, -(m - mu)>(g);
-                        const float Mr = mj[lam * (lam + 1) + mu];
-                        const float Mi = mj[lam * (lam + 1) - mu];
-                        sre += (A + C) * Mr - (B - Dv) * Mi;
-                        if constexpr (m > 0) sim += (B + Dv) * Mr + (A - C) * Mi;
-                    });
-                });
-                acc[l * (l + 1) + m - A0] += (double)sre;
-                if constexpr (m > 0) acc[l * (l + 1) - m - A0] += (double)sim;
+                constexpr int row = hier_row(l, m) - hier_row(LA, 0);
+                acc[l * (l + 1) + m - A0] += (double)sre[row];
+                if constexpr (m > 0) acc[l * (l + 1) - m - A0] += (double)sim[row];
             });
         });
     }
