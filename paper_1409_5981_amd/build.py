@@ -34,9 +34,11 @@ def _newest_header() -> float:
     return max(os.path.getmtime(h) for h in hdrs)
 
 
-# The column-stage unit is compiled once per (order, precision): the orders
-# are the slowest part of the build, and apart they compile in parallel.
+# The column-stage unit is compiled once per (order, precision) and the
+# hierarchy's fine-level unit once per order: the orders are the slowest part
+# of the build, and apart they compile in parallel.
 COLUMN_UNIT = "pmmm_column_inst.hip"
+HIER_UNIT = "pmmm_hier_inst.hip"
 PMAX = 10
 
 
@@ -50,11 +52,17 @@ def _units() -> list[tuple[str, str, list[str]]]:
                 for t in ("float", "double"):
                     units.append((src, f"{base}_p{p}_{t}",
                                   [f"-DPMMM_COLUMN_ORDER={p}", f"-DPMMM_COLUMN_T={t}"]))
+        elif os.path.basename(src) == HIER_UNIT:
+            for p in range(PMAX, -1, -1):
+                units.append((src, f"{base}_p{p}", [f"-DPMMM_HIER_ORDER={p}"]))
         else:
             units.append((src, base, []))
+
     # high orders first, then the largest other units
-    units.sort(key=lambda u: (-int(u[1].split("_p")[1].split("_")[0]) - 100
-                              if u[0].endswith(COLUMN_UNIT) else -os.path.getsize(u[0]) / 1e6))
+    def order(u):
+        return int(u[1].split("_p")[-1].split("_")[0])
+    units.sort(key=lambda u: (-order(u) - 100 if u[0].endswith((COLUMN_UNIT, HIER_UNIT))
+                              else -os.path.getsize(u[0]) / 1e6))
     return units
 
 

@@ -20,4 +20,9 @@ struct HierArgs {
 };
 hipError_t launch_hier_m2l_f32(const HierArgs &a, hipStream_t s);
 
+// The fine-level kernel of one order (pmmm_hier_cell.h; instantiated for
+// 0 <= PO <= PMMM_PMAX by pmmm_hier_inst.hip).
+template <int PO>
+hipError_t hier_cell_launch(const HierArgs &a, hipStream_t s);
+
 }  // namespace pmmm

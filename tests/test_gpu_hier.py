@@ -34,11 +34,11 @@ def _run(n, p, r, c, pos, q, mode="far"):
     return {"phi": phi.double().cpu().numpy(), "grad": torch.stack([gx, gy, gz], 1).double().cpu().numpy()}
 
 
-# p = 3, 4: the unrolled kernel with one row group; 5, 6, 7: two to four row
-# groups; 8: the per-row kernel.
+# p = 3, 4: the fine-level kernel with one row group; 5 to 10: two to seven
+# row groups.
 @pytest.mark.parametrize("n,p,r,c,N", [(4, 4, 2, 1, 3000), (4, 3, 2, 2, 3000), (4, 3, 4, 1, 4000),
                                        (8, 5, 2, 2, 6000), (4, 6, 2, 1, 3000), (4, 7, 2, 1, 3000),
-                                       (4, 8, 2, 1, 2000)])
+                                       (4, 8, 2, 1, 2000), (4, 10, 2, 1, 2000)])
 def test_hier_far_matches_oracle(n, p, r, c, N):
     print(f"hier coarse {n}^3 p={p} r={r} c={c} N={N}", flush=True)
     pos, q = _set(N, 10 * n + r + c)
