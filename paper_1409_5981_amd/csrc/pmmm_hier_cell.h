@@ -121,8 +121,8 @@ __device__ __forceinline__ void hier_cell_rows(const float *__restrict__ M, floa
                                 constexpr int lam = nn - l;
                                 constexpr int row = hier_row(l, m) - hier_row(LA, 0);
                                 const float M0 = mj[lam * (lam + 1)];
-                                sre[row] += a0 * M0;
-                                if constexpr (m > 0) sim[row] += b0 * M0;
+                                sre[row] = __builtin_fmaf(a0, M0, sre[row]);
+                                if constexpr (m > 0) sim[row] = __builtin_fmaf(b0, M0, sim[row]);
                             });
                         } else {
                             constexpr float sg = (mu & 1) ? -1.0f : 1.0f;
@@ -137,8 +137,15 @@ __device__ __forceinline__ void hier_cell_rows(const float *__restrict__ M, floa
                                 constexpr int row = hier_row(l, m) - hier_row(LA, 0);
                                 const float Mr = mj[lam * (lam + 1) + mu];
                                 const float Mi = mj[lam * (lam + 1) - mu];
-                                sre[row] += s1 * Mr - s2 * Mi;
-                                if constexpr (m > 0) sim[row] += s3 * Mr + s4 * Mi;
+                                // one FMA per multiply-add into the running
+                                // sums (a - b inside += would cost a product,
+                                // an FMA and an add)
+                                sre[row] = __builtin_fmaf(s1, Mr, sre[row]);
+                                sre[row] = __builtin_fmaf(-s2, Mi, sre[row]);
+                                if constexpr (m > 0) {
+                                    sim[row] = __builtin_fmaf(s3, Mr, sim[row]);
+                                    sim[row] = __builtin_fmaf(s4, Mi, sim[row]);
+                                }
                             });
                         }
                     }
