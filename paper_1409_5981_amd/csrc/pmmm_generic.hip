@@ -52,8 +52,11 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_dft_c(cplx<T> *__restrict__
             int m = 0;                          // (j k) mod n
             for (int j = 0; j < n; ++j) {
                 const cplx<T> x = buf[j * kGenTile + ii], t = w[m];
-                re += x.re * t.re - x.im * t.im;
-                im += x.re * t.im + x.im * t.re;
+                // one FMA per multiply-add into the running sums
+                re = fma(x.re, t.re, re);
+                re = fma(-x.im, t.im, re);
+                im = fma(x.re, t.im, im);
+                im = fma(x.im, t.re, im);
                 m += k;
                 if (m >= n) m -= n;
             }
@@ -218,10 +221,10 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_m2l(const cplx<T> *__restri
         {
             const cplx<T> M0 = F[(int64_t)(lam * (lam + 1)) * nspec];
             const T A = G.re_s(nn, -m), B = G.im_s(nn, -m);
-            xr += A * M0.re;
-            xi += A * M0.im;
-            yr += B * M0.re;
-            yi += B * M0.im;
+            xr = fma(A, M0.re, xr);
+            xi = fma(A, M0.im, xi);
+            yr = fma(B, M0.re, yr);
+            yi = fma(B, M0.im, yi);
         }
         for (int mu = 1; mu <= lam; ++mu) {
             const T sg = (mu & 1) ? T(-1) : T(1);
@@ -229,10 +232,16 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_m2l(const cplx<T> *__restri
             const T C = sg * G.re_s(nn, -(m - mu)), D = sg * G.im_s(nn, -(m - mu));
             const cplx<T> Mr = F[(int64_t)(lam * (lam + 1) + mu) * nspec];
             const cplx<T> Mi = F[(int64_t)(lam * (lam + 1) - mu) * nspec];
-            xr += (A + C) * Mr.re - (B - D) * Mi.re;
-            xi += (A + C) * Mr.im - (B - D) * Mi.im;
-            yr += (B + D) * Mr.re + (A - C) * Mi.re;
-            yi += (B + D) * Mr.im + (A - C) * Mi.im;
+            // one FMA per multiply-add into the running sums
+            const T ac = A + C, bd = B - D, bpd = B + D, amc = A - C;
+            xr = fma(ac, Mr.re, xr);
+            xr = fma(-bd, Mi.re, xr);
+            xi = fma(ac, Mr.im, xi);
+            xi = fma(-bd, Mi.im, xi);
+            yr = fma(bpd, Mr.re, yr);
+            yr = fma(amc, Mi.re, yr);
+            yi = fma(bpd, Mr.im, yi);
+            yi = fma(amc, Mi.im, yi);
         }
         if (nn & 1) {       // times i
             are -= xi;

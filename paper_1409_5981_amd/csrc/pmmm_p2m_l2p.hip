@@ -238,43 +238,60 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t n, int K, int periodic,
     const T qtot_term = periodic ? T(sums[0] * 3.14159265358979323846 / (3.0 * (double)K)) : T(0);
     T R[P];
     regular_harmonics<PO, T>(r.ux, r.uy, r.uz, R);
-    // Phi = sum_l [L_l^0 R_l^0 + 2 sum_{m>0} Re(L_l^m R_l^m)]
-    T ph = T(0);
+    // Phi = sum_l [L_l^0 R_l^0 + 2 sum_{m>0} Re(L_l^m R_l^m)]; every
+    // multiply-add below is one FMA into a running sum (a product difference
+    // inside += would cost a product, an FMA and an add), and the m > 0 terms
+    // are summed apart so that the factor 2 is applied once
+    T ph = T(0), ph2 = T(0);
 #pragma unroll
     for (int l = 0; l <= PO; ++l) {
-        ph += Lc[ridx(l, 0)] * R[ridx(l, 0)];
+        ph = fma(Lc[ridx(l, 0)], R[ridx(l, 0)], ph);
 #pragma unroll
-        for (int m = 1; m <= l; ++m)
-            ph += T(2) * (Lc[ridx(l, m)] * R[ridx(l, m)] - Lc[ridx(l, -m)] * R[ridx(l, -m)]);
+        for (int m = 1; m <= l; ++m) {
+            ph2 = fma(Lc[ridx(l, m)], R[ridx(l, m)], ph2);
+            ph2 = fma(-Lc[ridx(l, -m)], R[ridx(l, -m)], ph2);
+        }
     }
+    ph = fma(T(2), ph2, ph);
     // L'_1^0 and L'_1^1 (eq. L2L with destination order one)
-    T d0 = T(0), d1re = T(0), d1im = T(0);
+    T d0 = T(0), d02 = T(0), d1re = T(0), d1im = T(0);
 #pragma unroll
     for (int lam = 1; lam <= PO; ++lam) {
         const int k = lam - 1;
-        d0 += Lc[ridx(lam, 0)] * R[ridx(k, 0)];
+        d0 = fma(Lc[ridx(lam, 0)], R[ridx(k, 0)], d0);
 #pragma unroll
-        for (int mu = 1; mu <= k; ++mu)
-            d0 += T(2) * (Lc[ridx(lam, mu)] * R[ridx(k, mu)] - Lc[ridx(lam, -mu)] * R[ridx(k, -mu)]);
+        for (int mu = 1; mu <= k; ++mu) {
+            d02 = fma(Lc[ridx(lam, mu)], R[ridx(k, mu)], d02);
+            d02 = fma(-Lc[ridx(lam, -mu)], R[ridx(k, -mu)], d02);
+        }
         // + sum_{mu=1..lam} L_lam^mu R_k^{mu-1}
 #pragma unroll
         for (int mu = 1; mu <= lam; ++mu) {
             const T lre = Lc[ridx(lam, mu)], lim = Lc[ridx(lam, -mu)];
             const T rre = R[ridx(k, mu - 1)];
-            const T rim = (mu - 1 > 0) ? R[ridx(k, -(mu - 1))] : T(0);
-            d1re += lre * rre - lim * rim;
-            d1im += lre * rim + lim * rre;
+            d1re = fma(lre, rre, d1re);
+            d1im = fma(lim, rre, d1im);
+            if (mu - 1 > 0) {
+                const T rim = R[ridx(k, -(mu - 1))];
+                d1re = fma(-lim, rim, d1re);
+                d1im = fma(lre, rim, d1im);
+            }
         }
         // - sum_{nu=0..lam-2} conj(L_lam^nu R_k^{nu+1})
 #pragma unroll
         for (int nu = 0; nu <= lam - 2; ++nu) {
             const T lre = Lc[ridx(lam, nu)];
-            const T lim = (nu > 0) ? Lc[ridx(lam, -nu)] : T(0);
             const T rre = R[ridx(k, nu + 1)], rim = R[ridx(k, -(nu + 1))];
-            d1re -= lre * rre - lim * rim;
-            d1im += lre * rim + lim * rre;  // minus the conjugate's imaginary part
+            d1re = fma(-lre, rre, d1re);
+            d1im = fma(lre, rim, d1im);  // minus the conjugate's imaginary part
+            if (nu > 0) {
+                const T lim = Lc[ridx(lam, -nu)];
+                d1re = fma(lim, rim, d1re);
+                d1im = fma(lim, rre, d1im);
+            }
         }
     }
+    d0 = fma(T(2), d02, d0);
     T gx = -d1re, gy = d1im, gz = d0;
     if (periodic) {
         const T u2 = r.ux * r.ux + r.uy * r.uy + r.uz * r.uz;
